@@ -1,0 +1,171 @@
+"""Seeded synthetic inputs for the staggered-grid Stokes velocity smoother.
+
+This module only *builds input fields*; it holds none of the smoother's,
+residual's or multigrid's arithmetic.  Both the CPU oracle (tests) and the
+HIP path (tests, bench) are fed from here.
+
+Grid convention (paper Sec. 2.1, staggered grid of Fig. 1; unit square, y up):
+  * cell (i, j), 0 <= i < nx, 0 <= j < ny, centre ((i+1/2)dx, (j+1/2)dy):
+    carries the cell viscosity eta_c (the paper's eta_P) and the pressure p;
+  * node (i, j), 0 <= i <= nx, 0 <= j <= ny, at (i dx, j dy): eta_n (eta_B);
+  * vx(i, j) at (i dx, (j+1/2)dy): array shape (ny, nx+1);
+  * vy(i, j) at ((i+1/2)dx, j dy): array shape (ny+1, nx);
+  * density rho lives with vy (Fig. 1 caption), so fy has the vy shape.
+
+Problem family: the sinker benchmark of Sec. 5.1 (stiff, dense circular
+inclusions in a weaker medium, gravity pointing down), made non-dimensional.
+Right-hand side: with y up and gravity (0, -|g|), the momentum balance
+div(sigma') - grad p + rho g = 0 gives f = -rho g, i.e. fx = 0, fy = +rho|g|.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Problem:
+    nx: int
+    ny: int
+    dx: float
+    dy: float
+    eta_c: np.ndarray          # (ny, nx)
+    eta_n: np.ndarray          # (ny+1, nx+1)
+    fx: np.ndarray             # (ny, nx+1)
+    fy: np.ndarray             # (ny+1, nx)
+    meta: dict = field(default_factory=dict)
+
+    def zeros_v(self):
+        return (np.zeros((self.ny, self.nx + 1)), np.zeros((self.ny + 1, self.nx)))
+
+
+def _inside(x, y, sinkers):
+    m = np.zeros(np.broadcast(x, y).shape, dtype=bool)
+    for (cx, cy, r) in sinkers:
+        m |= (x - cx) ** 2 + (y - cy) ** 2 <= r * r
+    return m
+
+
+def nodal_harmonic(eta_c: np.ndarray) -> np.ndarray:
+    """Nodal viscosity: harmonic mean of the 1, 2 or 4 cells touching a node.
+
+    Input construction only (how eta_B is obtained from eta_P is not fixed by
+    the paper; the harmonic rule is the workload's stated choice)."""
+    ny, nx = eta_c.shape
+    inv = 1.0 / eta_c
+    s = np.zeros((ny + 1, nx + 1))
+    n = np.zeros((ny + 1, nx + 1))
+    for oj in (0, 1):
+        for oi in (0, 1):
+            s[oj:oj + ny, oi:oi + nx] += inv
+            n[oj:oj + ny, oi:oi + nx] += 1.0
+    return n / s
+
+
+def sinker_problem(nx: int, ny: int, sinkers, eta_in: float, eta_out,
+                   rho_in: float = 1.1, rho_out: float = 1.0, g: float = 1.0,
+                   meta: dict | None = None) -> Problem:
+    """Fields for circular inclusions ``sinkers = [(cx, cy, r), ...]``.
+
+    ``eta_out`` is a scalar or a (ny, nx) background array."""
+    dx, dy = 1.0 / nx, 1.0 / ny
+    xc = (np.arange(nx) + 0.5) * dx
+    yc = (np.arange(ny) + 0.5) * dy
+    X, Y = np.meshgrid(xc, yc)
+    ins = _inside(X, Y, sinkers)
+    bg = np.broadcast_to(np.asarray(eta_out, dtype=np.float64), (ny, nx))
+    eta_c = np.where(ins, eta_in, bg).astype(np.float64)
+    eta_n = nodal_harmonic(eta_c)
+    # density sampled at the vy points ((i+1/2)dx, j dy)
+    Xv, Yv = np.meshgrid(xc, np.arange(ny + 1) * dy)
+    rho = np.where(_inside(Xv, Yv, sinkers), rho_in, rho_out)
+    fy = (rho * g).astype(np.float64)
+    fx = np.zeros((ny, nx + 1))
+    return Problem(nx, ny, dx, dy, eta_c, eta_n, fx, fy, dict(meta or {}))
+
+
+# --------------------------------------------------------------------------
+# The workloads (non-dimensional sinker family, Sec. 5.1 / Sec. 6.1 shapes)
+# --------------------------------------------------------------------------
+
+def centred_sinker(n: int = 64) -> Problem:
+    """One centred sinker, r = 0.1, eta 1e3 inside / 1 outside, rho 1.1 / 1.0."""
+    return sinker_problem(n, n, [(0.5, 0.5, 0.1)], 1e3, 1.0,
+                          meta=dict(workload="centred_sinker", n=n))
+
+
+def random_sinkers(n: int, count: int, seed: int, eta_in: float = 1e6,
+                   eta_out=1.0, rmin: float = 0.02, rmax: float = 0.08) -> Problem:
+    """``count`` sinkers, centres U[0.1,0.9]^2, radii U[rmin, rmax]."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.1, 0.9, size=(count, 2))
+    r = rng.uniform(rmin, rmax, size=count)
+    sinkers = [(float(c[k, 0]), float(c[k, 1]), float(r[k])) for k in range(count)]
+    return sinker_problem(n, n, sinkers, eta_in, eta_out,
+                          meta=dict(workload="random_sinkers", n=n, count=count, seed=seed))
+
+
+def smoother_workload(n: int = 4096, seed: int = 2) -> Problem:
+    """8 seeded sinkers, eta 1e6 / 1, harmonic nodal eta (smoother throughput)."""
+    return random_sinkers(n, 8, seed)
+
+
+def lognormal_background_workload(n: int = 8192, seed: int = 4, count: int = 16) -> Problem:
+    """16 sinkers of eta 1e6 over an i.i.d. per-cell background
+    log10(eta) ~ U(-2, 4) (multigrid / refinement workload)."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.1, 0.9, size=(count, 2))
+    r = rng.uniform(0.02, 0.08, size=count)
+    bg = 10.0 ** rng.uniform(-2.0, 4.0, size=(n, n))
+    sinkers = [(float(c[k, 0]), float(c[k, 1]), float(r[k])) for k in range(count)]
+    return sinker_problem(n, n, sinkers, 1e6, bg,
+                          meta=dict(workload="lognormal_background", n=n, count=count, seed=seed))
+
+
+def instance_problem(n: int, rng: np.random.Generator) -> Problem:
+    """One request/instance: sinker count U{1..8}, contrast 10^U(2,6)."""
+    count = int(rng.integers(1, 9))
+    contrast = float(10.0 ** rng.uniform(2.0, 6.0))
+    c = rng.uniform(0.1, 0.9, size=(count, 2))
+    r = rng.uniform(0.02, 0.08, size=count)
+    sinkers = [(float(c[k, 0]), float(c[k, 1]), float(r[k])) for k in range(count)]
+    return sinker_problem(n, n, sinkers, contrast, 1.0,
+                          meta=dict(workload="instance", n=n, count=count, contrast=contrast))
+
+
+def batch_mix(seed: int = 5, sizes=((256, 28), (512, 20), (1024, 12), (2048, 4))):
+    """Uneven mix of independent sinker problems (default: 64 instances)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for n, cnt in sizes:
+        for _ in range(cnt):
+            out.append(instance_problem(n, rng))
+    order = rng.permutation(len(out))
+    return [out[k] for k in order]
+
+
+def random_velocity(p: Problem, seed: int, scale: float = 1.0):
+    """Random velocity state with Dirichlet wall entries set to 0."""
+    rng = np.random.default_rng(seed)
+    vx = rng.standard_normal((p.ny, p.nx + 1)) * scale
+    vy = rng.standard_normal((p.ny + 1, p.nx)) * scale
+    vx[:, 0] = 0.0
+    vx[:, -1] = 0.0
+    vy[0, :] = 0.0
+    vy[-1, :] = 0.0
+    return vx, vy
+
+
+def random_pressure(p: Problem, seed: int, scale: float = 1.0):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((p.ny, p.nx)) * scale
+
+
+def random_shifts(n_outer: int, tile_x: int, tile_y: int, seed: int) -> np.ndarray:
+    """Explicit tile shifts (sx, sy) per outer iteration, int32 (n_outer, 2)."""
+    rng = np.random.default_rng(seed)
+    s = np.empty((n_outer, 2), dtype=np.int32)
+    s[:, 0] = rng.integers(0, tile_x, size=n_outer)
+    s[:, 1] = rng.integers(0, tile_y, size=n_outer)
+    return s
