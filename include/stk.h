@@ -1,0 +1,178 @@
+/*
+ * stk.h — C ABI of the MI355X (gfx950) matrix-free velocity smoother library
+ * for the 2D staggered-grid variable-viscosity Stokes equations.
+ *
+ * Source of the mathematics: Ferrari, Puentener, Sotoudeh, Viebig, "3D Blocking
+ * for Matrix-free Smoothers in 2D Variable-Viscosity Stokes Equations"
+ * (arXiv:2509.19061):
+ *   Sec. 2.1  Cauchy-form Stokes equations and the staggered grid (Fig. 1),
+ *   Sec. 3.1  saddle-point system, velocity subsystem M v + G p = f,
+ *   Sec. 3.2  inexact Uzawa with a matrix-free geometric multigrid velocity
+ *             solve whose smoothing dominates the cost,
+ *   Sec. 4    loop fusion, spatial blocking, RAS-type temporal blocking (Alg. 2),
+ *   Sec. 5    the five smoothers and the energy residual norms (Sec. 5.4).
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions shared by every call
+ * ---------------------------------------------------------------------------
+ * Grid: nx x ny cells of size dx x dy.  Cell (i,j), 0<=i<nx, 0<=j<ny, carries
+ * eta_c (the paper's eta_P) and the pressure p; node (i,j), 0<=i<=nx,
+ * 0<=j<=ny, carries eta_n (eta_B).  vx(i,j) sits on the left face of cell
+ * (i,j) and vy(i,j) on its bottom face; fx lives with vx and fy with vy.
+ *
+ * Memory layout: every field is a row-major array with x fastest and ONE
+ * common row stride `ld` (elements, >= nx+1); element (i,j) is at
+ * base[j*ld + i].  Used extents (rows x columns):
+ *     vx, fx : ny     x (nx+1)        vy, fy : (ny+1) x nx
+ *     eta_c, p : ny   x nx            eta_n  : (ny+1) x (nx+1)
+ * Nothing outside the used extents is read or written.  dtype STK_F64 means
+ * every field is double, STK_F32 float.  All field pointers are DEVICE
+ * pointers owned by the caller; the library never frees or retains them
+ * beyond the call (an stk_mg copies what it keeps).
+ *
+ * Boundary conditions: free-slip walls.  The wall velocities vx(0,.),
+ * vx(nx,.), vy(.,0), vy(.,ny) are Dirichlet 0: they are read as 0 whatever
+ * they hold, and every call that writes a velocity writes 0 there.  The shear
+ * stress vanishes at boundary nodes.
+ *
+ * Operator (A = -M is symmetric positive definite):
+ *   txx = 2 eta_c (vx(i+1,j)-vx(i,j))/dx,  tyy = 2 eta_c (vy(i,j+1)-vy(i,j))/dy,
+ *   txy = eta_n ((vx(i,j)-vx(i,j-1))/dy + (vy(i,j)-vy(i-1,j))/dx) at interior nodes,
+ *   (Mv)_x = d(txx)/dx + d(txy)/dy,  (Mv)_y = d(txy)/dx + d(tyy)/dy (centred).
+ *   Right-hand side for fixed pressure: b = f - G p, (Gp)_x = -(p(i,j)-p(i-1,j))/dx,
+ *   (Gp)_y = -(p(i,j)-p(i,j-1))/dy; p == NULL means p = 0.
+ *
+ * Asynchrony: calls enqueue work on the context's HIP stream and return
+ * without waiting, except where a host result is produced (noted per call).
+ * Errors: every call returns an stk status; on error nothing has been
+ * enqueued and no caller array has been modified; stk_last_error() gives a
+ * thread-local message.  No exception crosses the ABI.
+ */
+#ifndef STK_H
+#define STK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    STK_OK = 0,
+    STK_EINVAL = -1,        /* invalid argument (message names it)                       */
+    STK_ENOMEM = -2,        /* device allocation failed                                  */
+    STK_EHIP = -3,          /* a HIP runtime call failed (message has the HIP error)     */
+    STK_ENOTCONV = -4,      /* solve hit max_iters; results and the achieved residual are written */
+    STK_ENONFINITE = -5,    /* a norm came out NaN/Inf (outputs are still written)       */
+    STK_EUNSUPPORTED = -6   /* valid but not supported here (e.g. tile+halo beyond LDS)  */
+};
+
+typedef enum { STK_F64 = 0, STK_F32 = 1 } stk_dtype;
+
+/* The smoothers of Sec. 5 (list (i)-(v)).  Blocked fused Jacobi is
+ * STK_RAS_JACOBI with k = 1, halo = 0. */
+typedef enum {
+    STK_JACOBI = 0,        /* damped Jacobi, separate vx and vy passes (Sec. 5 (ii))            */
+    STK_JACOBI_FUSED = 1,  /* damped Jacobi, vx and vy in one pass (Sec. 4.1, Sec. 5 (iii))     */
+    STK_RAS_JACOBI = 2,    /* Jacobi with RAS-type temporal blocking (Sec. 4.3, Alg. 2, Sec. 5 (v)) */
+    STK_RBGS = 3           /* red-black Gauss-Seidel (Sec. 5 (i))                                */
+} stk_variant;
+
+typedef struct {
+    int nx, ny;     /* cells, each >= 2                                   */
+    int64_t ld;     /* common row stride in elements, >= nx + 1           */
+    double dx, dy;  /* cell size, > 0                                     */
+} stk_grid;
+
+/* Options of stk_smooth.  Fill with stk_smooth_opts_default(); a NULL
+ * options pointer means the defaults. */
+typedef struct {
+    double omega;          /* damping, in (0, 2); 0 = variant default (0.7 Jacobi forms, 1.0 RBGS) */
+    int tile_x, tile_y;    /* RAS owned tile in cells (default 64 x 64)                            */
+    int halo;              /* RAS overlap h in cells, >= 0; -1 (default) = k                        */
+    int k;                 /* RAS inner sweeps per outer iteration (T_inner of Alg. 2), default 4   */
+    const int32_t* shifts; /* HOST array, 2 ints (sx, sy) per outer iteration, reduced mod the tile;
+                              NULL (default) = drawn from `seed` (stk_ras_shifts)                    */
+    uint64_t seed;         /* seed of the shift stream when shifts == NULL (default 0)              */
+    int last_partial;      /* 1 (default): the last outer iteration runs only the remaining sweeps,
+                              so exactly `sweeps` sweeps happen; 0: ceil(sweeps/k) full outer
+                              iterations as Alg. 2 writes it                                         */
+} stk_smooth_opts;
+
+typedef struct stk_ctx stk_ctx;
+typedef struct stk_mg stk_mg;
+
+/* ------------------------------------------------------------ context -- */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  The context owns scratch
+ * (ping-pong velocity buffers, folded right-hand sides, reduction partials),
+ * grown on demand and freed by stk_ctx_destroy.  Not thread-safe: one host
+ * thread per context at a time. */
+int stk_ctx_create(stk_ctx** out, int device, void* hip_stream);
+int stk_ctx_destroy(stk_ctx* ctx);
+int stk_ctx_set_stream(stk_ctx* ctx, void* hip_stream);
+/* Block until the context's stream has drained. */
+int stk_ctx_sync(stk_ctx* ctx);
+/* Bytes of device scratch the context currently holds. */
+int stk_ctx_scratch_bytes(const stk_ctx* ctx, size_t* bytes);
+/* Thread-local message of the last failing call on this thread. */
+const char* stk_last_error(void);
+
+void stk_smooth_opts_default(stk_smooth_opts* o);
+
+/* -------------------------------------------------------------- smooth -- */
+
+/* `sweeps` smoothing sweeps of `variant` on M v = f - G p (Sec. 3.1), in
+ * place on (vx, vy).  Jacobi forms: v <- v + omega (b - M v)/diag(M) from the
+ * old iterate (split and fused give the same values).  RBGS: the sets vx-red,
+ * vx-black, vy-red, vy-black (colour (i+j) mod 2, red = 0) relaxed in that
+ * order.  RAS (Alg. 2 with snapshot semantics): per outer iteration the tile
+ * grid is cut at positions congruent to the shift modulo the tile size (edge
+ * tiles partial); every tile copies the current field on its tile grown by
+ * `halo` cells (clipped to the domain) plus a one-cell frozen ring, runs k
+ * Jacobi sweeps there, and writes back its owned cells only; all tiles read
+ * the same snapshot, so the result is deterministic.  With halo >= k-1 this
+ * equals k Jacobi sweeps exactly.  sweeps = 0 is a no-op.  Asynchronous.
+ * Errors: STK_EINVAL (bad sizes/pointers/options), STK_EUNSUPPORTED (RAS
+ * tile plus halo exceeding the LDS budget), STK_ENOMEM, STK_EHIP. */
+int stk_smooth(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, void* vx, void* vy, const void* p,
+               const void* eta_c, const void* eta_n, const void* fx, const void* fy, int sweeps,
+               stk_variant variant, const stk_smooth_opts* opts);
+
+/* Shift stream of RAS outer iterations: for t = 0..n_outer-1, sx = (z >> 32)
+ * mod tile_x and sy = (z' >> 32) mod tile_y where z, z' are consecutive
+ * SplitMix64 outputs from `seed` (Steele, Lea & Flood 2014).  Alg. 2 draws a
+ * random shift per outer iteration.  `out` is a host array of 2*n_outer. */
+int stk_ras_shifts(uint64_t seed, int n_outer, int tile_x, int tile_y, int32_t* out);
+
+/* ------------------------------------------------------------ residual -- */
+
+/* rx, ry <- r_v = b - M v on the unknowns (0 on walls); rp (nullable) <-
+ * r_p = -D v per cell, (Dv) = (vx(i+1,j)-vx(i,j))/dx + (vy(i,j+1)-vy(i,j))/dy
+ * (Sec. 5.4).  With fx = fy = 0 and p = NULL this is -M v.  Output arrays use
+ * the same layout and dtype as the inputs and must not alias them.
+ * Asynchronous. */
+int stk_residual(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* p,
+                 const void* eta_c, const void* eta_n, const void* fx, const void* fy, void* rx, void* ry,
+                 void* rp);
+
+/* Energy residual norms of Sec. 5.4, accumulated in FP64 for both dtypes:
+ *   out[0] N_v = sum over unknowns r_v^2 / diag(-M)
+ *   out[1] N_p = sum over cells r_p^2 eta_c / (2/dx^2 + 2/dy^2)
+ *   out[2] N_f = sum over unknowns f^2 / diag(-M)
+ *   out[3] E   = sqrt((N_v + N_p) / N_f)     (global relative energy residual)
+ *   out[4] E_v = sqrt(N_v / N_f)             (velocity part)
+ * `out` is a HOST array of 5 doubles.  The reduction order is fixed (bitwise
+ * reproducible run to run).  Synchronises the context's stream.
+ * STK_ENONFINITE if any value is NaN/Inf (e.g. N_f = 0); out is still written. */
+int stk_energy_norm(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy,
+                    const void* p, const void* eta_c, const void* eta_n, const void* fx, const void* fy,
+                    double out[5]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STK_H */

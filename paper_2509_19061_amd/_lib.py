@@ -1,0 +1,73 @@
+"""ctypes binding of ``libstk.so`` (include/stk.h): argument marshalling only.
+
+Every compute step runs in the HIP library.  If the library is not built
+this module raises at import time — there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstk.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+JACOBI, JACOBI_FUSED, RAS_JACOBI, RBGS = 0, 1, 2, 3
+VARIANTS = {"jacobi": JACOBI, "jacobi_fused": JACOBI_FUSED, "ras": RAS_JACOBI, "rbgs": RBGS}
+
+
+class StkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"stk error {code}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("ld", C.c_int64), ("dx", C.c_double), ("dy", C.c_double)]
+
+
+class SmoothOpts(C.Structure):
+    _fields_ = [("omega", C.c_double), ("tile_x", C.c_int), ("tile_y", C.c_int), ("halo", C.c_int), ("k", C.c_int),
+                ("shifts", C.POINTER(C.c_int32)), ("seed", C.c_uint64), ("last_partial", C.c_int)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2509_19061_amd.build` "
+                      "(there is no CPU fallback)")
+
+lib = C.CDLL(LIB_PATH)
+
+_P = C.c_void_p
+_I = C.c_int
+_G = C.POINTER(Grid)
+
+_SIGS = {
+    "stk_ctx_create": ([C.POINTER(_P), _I, _P], _I),
+    "stk_ctx_destroy": ([_P], _I),
+    "stk_ctx_set_stream": ([_P, _P], _I),
+    "stk_ctx_sync": ([_P], _I),
+    "stk_ctx_scratch_bytes": ([_P, C.POINTER(C.c_size_t)], _I),
+    "stk_last_error": ([], C.c_char_p),
+    "stk_smooth_opts_default": ([C.POINTER(SmoothOpts)], None),
+    "stk_smooth": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _I, _I, C.POINTER(SmoothOpts)], _I),
+    "stk_ras_shifts": ([C.c_uint64, _I, _I, _I, C.POINTER(C.c_int32)], _I),
+    "stk_residual": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I),
+    "stk_energy_norm": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_double)], _I),
+}
+
+
+def _bind(sigs):
+    for name, (args, res) in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+
+
+_bind(_SIGS)
+
+
+def check(rc):
+    if rc != OK:
+        raise StkError(rc, lib.stk_last_error().decode())
+    return rc

@@ -1,0 +1,76 @@
+// Internal declarations of the stk HIP library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "stk.h"
+
+struct stk_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int lds_max = 0;  // bytes of LDS one workgroup may use on this device
+    int num_cu = 0;
+    // Scratch slots, grown on demand (device memory).
+    enum { S_VX = 0, S_VY, S_BX, S_BY, S_PART, S_RED, S_NSLOT };
+    void* slot[S_NSLOT] = {};
+    size_t slot_bytes[S_NSLOT] = {};
+    double* host_red = nullptr;  // pinned host landing buffer for reductions
+};
+
+namespace stk {
+
+int set_error(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+#define STK_HIP(call)                                      \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return stk::hip_fail(e_, #call); \
+    } while (0)
+#define STK_TRY(call)              \
+    do {                           \
+        int rc_ = (call);          \
+        if (rc_ != STK_OK) return rc_; \
+    } while (0)
+
+// Make sure slot `s` of the context holds at least `bytes`; returns its pointer.
+int scratch(stk_ctx* ctx, int s, size_t bytes, void** out);
+// Make `ctx->device` current.
+int use_device(stk_ctx* ctx);
+
+int check_grid(const stk_grid* g);
+size_t elem_size(stk_dtype dt);
+// Bytes spanned by a field of `rows` rows of the grid's stride.
+inline size_t field_bytes(const stk_grid* g, int rows, stk_dtype dt) { return (size_t)rows * (size_t)g->ld * elem_size(dt); }
+
+// ---- kernel launchers (defined in the .hip files) ---------------------------
+struct FieldPtrs {
+    const void* eta_c;
+    const void* eta_n;
+    const void* bx;  // right-hand side at vx points (f folded with p, or fx)
+    const void* by;
+};
+
+int launch_fold_rhs(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* fx, const void* fy, const void* p,
+                    void* bx, void* by);
+int launch_jacobi_fused(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega,
+                        const void* vx, const void* vy, void* ox, void* oy);
+int launch_jacobi_split(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega,
+                        const void* vx, const void* vy, void* ox, void* oy);
+int launch_rbgs(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega, void* vx, void* vy);
+// RAS outer iteration; returns STK_EUNSUPPORTED when the tile does not fit.
+int ras_lds_bytes(stk_dtype dt, const stk_grid* g, int tile_x, int tile_y, int halo, size_t* bytes);
+int launch_ras(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega, int tile_x,
+               int tile_y, int halo, int kt, int sx, int sy, const void* vx, const void* vy, void* ox, void* oy);
+int launch_copy_velocity(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, void* ox,
+                         void* oy);
+int launch_residual(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* p,
+                    const void* eta_c, const void* eta_n, const void* fx, const void* fy, void* rx, void* ry,
+                    void* rp);
+// Energy partial sums -> 3 doubles in device memory `dst` (N_v, N_p, N_f).
+int launch_energy(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* p,
+                  const void* eta_c, const void* eta_n, const void* fx, const void* fy, double* dst);
+
+}  // namespace stk
