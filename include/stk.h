@@ -147,6 +147,17 @@ int stk_smooth(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, void* vx, void* vy
  * random shift per outer iteration.  `out` is a host array of 2*n_outer. */
 int stk_ras_shifts(uint64_t seed, int n_outer, int tile_x, int tile_y, int32_t* out);
 
+/* One RAS outer iteration (Alg. 2, snapshot form) out of place, with an
+ * explicit shift: (ox, oy) <- kt Jacobi sweeps per tile as in stk_smooth,
+ * with b = (bx, by) the already-folded right-hand side (b = f - G p, 0 on
+ * walls; pass fx, fy when p = 0).  Every velocity entry of (ox, oy) in the
+ * used extents is written (walls 0); (vx, vy) are not modified.  Outputs
+ * must not alias inputs.  kt = 0 copies.  For callers that manage their own
+ * ping-pong buffers.  Asynchronous; errors as stk_smooth. */
+int stk_ras_outer(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* eta_c,
+                  const void* eta_n, const void* bx, const void* by, void* ox, void* oy, double omega, int tile_x,
+                  int tile_y, int halo, int kt, int sx, int sy);
+
 /* ------------------------------------------------------------ residual -- */
 
 /* rx, ry <- r_v = b - M v on the unknowns (0 on walls); rp (nullable) <-

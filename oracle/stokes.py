@@ -43,8 +43,14 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = None
+        L.or_num_threads.argtypes = []
+        L.or_num_threads.restype = I
         _lib = L
     return _lib
+
+
+def num_threads():
+    return int(lib().or_num_threads())
 
 
 def _p(a):

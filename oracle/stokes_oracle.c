@@ -30,9 +30,13 @@
  * M is symmetric negative definite (Sec. 5.4); d = diag(-M) > 0.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads the OpenMP loops use (for reporting the CPU baseline's core count). */
+int or_num_threads(void) { return omp_get_max_threads(); }
 
 typedef struct {
     int nx, ny;

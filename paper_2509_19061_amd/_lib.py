@@ -52,6 +52,7 @@ _SIGS = {
     "stk_smooth_opts_default": ([C.POINTER(SmoothOpts)], None),
     "stk_smooth": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _I, _I, C.POINTER(SmoothOpts)], _I),
     "stk_ras_shifts": ([C.c_uint64, _I, _I, _I, C.POINTER(C.c_int32)], _I),
+    "stk_ras_outer": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double, _I, _I, _I, _I, _I, _I], _I),
     "stk_residual": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I),
     "stk_energy_norm": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_double)], _I),
 }

@@ -14,7 +14,7 @@ from . import _lib as L
 from ._lib import (EHIP, EINVAL, ENOMEM, ENONFINITE, ENOTCONV, EUNSUPPORTED, F32, F64, JACOBI, JACOBI_FUSED, OK,
                    RAS_JACOBI, RBGS, VARIANTS, Grid, SmoothOpts, StkError, check)
 
-__all__ = ["Context", "Grid", "SmoothOpts", "StkError", "smooth", "residual", "energy_norm", "ras_shifts",
+__all__ = ["Context", "Grid", "SmoothOpts", "StkError", "smooth", "ras_outer", "residual", "energy_norm", "ras_shifts",
            "smooth_opts", "F64", "F32", "JACOBI", "JACOBI_FUSED", "RAS_JACOBI", "RBGS", "VARIANTS", "OK", "EINVAL",
            "ENOMEM", "EHIP", "ENOTCONV", "ENONFINITE", "EUNSUPPORTED", "dtype_code", "torch_dtype"]
 
@@ -105,6 +105,14 @@ def smooth(ctx, dt, grid, vx, vy, p, eta_c, eta_n, fx, fy, sweeps, variant, opts
                            _ptr(eta_n, dt), _ptr(fx, dt), _ptr(fy, dt), int(sweeps), int(variant),
                            C.byref(opts) if opts is not None else None))
     del keep
+
+
+def ras_outer(ctx, dt, grid, vx, vy, eta_c, eta_n, bx, by, ox, oy, omega=0.7, tile_x=64, tile_y=64, halo=4, kt=4,
+              sx=0, sy=0):
+    dt = dtype_code(dt)
+    check(L.lib.stk_ras_outer(ctx.handle, dt, C.byref(grid), _ptr(vx, dt), _ptr(vy, dt), _ptr(eta_c, dt),
+                              _ptr(eta_n, dt), _ptr(bx, dt), _ptr(by, dt), _ptr(ox, dt), _ptr(oy, dt), float(omega),
+                              int(tile_x), int(tile_y), int(halo), int(kt), int(sx), int(sy)))
 
 
 def residual(ctx, dt, grid, vx, vy, p, eta_c, eta_n, fx, fy, rx, ry, rp=None):

@@ -218,6 +218,7 @@ int stk_smooth(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, void* vx, void* vy
         f.by = by;
     }
     if (variant == STK_RBGS) {
+        STK_TRY(launch_zero_walls(ctx, dt, g, vx, vy));
         for (int s = 0; s < sweeps; ++s) STK_TRY(launch_rbgs(ctx, dt, g, f, omega, vx, vy));
         return STK_OK;
     }
@@ -254,6 +255,25 @@ int stk_smooth(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, void* vx, void* vy
     }
     if (cx != vx) STK_TRY(launch_copy_velocity(ctx, dt, g, cx, cy, vx, vy));
     return STK_OK;
+}
+
+int stk_ras_outer(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* eta_c,
+                  const void* eta_n, const void* bx, const void* by, void* ox, void* oy, double omega, int tile_x,
+                  int tile_y, int halo, int kt, int sx, int sy) {
+    if (!ctx) return set_error(STK_EINVAL, "ctx is NULL");
+    STK_TRY(check_dtype(dt));
+    STK_TRY(check_grid(g));
+    if (!vx || !vy || !eta_c || !eta_n || !bx || !by || !ox || !oy)
+        return set_error(STK_EINVAL, "vx, vy, eta_c, eta_n, bx, by, ox, oy must be non-NULL");
+    if (ox == vx || oy == vy || ox == vy || oy == vx) return set_error(STK_EINVAL, "outputs alias the inputs");
+    if (!(omega > 0.0 && omega < 2.0)) return set_error(STK_EINVAL, "omega must be in (0, 2)");
+    if (tile_x < 1 || tile_y < 1 || halo < 0 || kt < 0 || tile_x > (1 << 20) || tile_y > (1 << 20) || halo > (1 << 20))
+        return set_error(STK_EINVAL, "bad tile/halo/kt");
+    STK_TRY(use_device(ctx));
+    FieldPtrs f{eta_c, eta_n, bx, by};
+    sx = ((sx % tile_x) + tile_x) % tile_x;
+    sy = ((sy % tile_y) + tile_y) % tile_y;
+    return launch_ras(ctx, dt, g, f, omega, tile_x, tile_y, halo, kt, sx, sy, vx, vy, ox, oy);
 }
 
 int stk_residual(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* p,

@@ -106,6 +106,22 @@ __global__ __launch_bounds__(BX* BY) void k_copy_velocity(int nx, int ny, int64_
     if (i < nx) oy[k] = is_vy_unknown(nx, ny, i, j) ? vy[k] : T(0);
 }
 
+// Zero the Dirichlet wall entries of a velocity in place (in-place smoothers
+// never touch them otherwise).
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_walls(int nx, int ny, int64_t ld, T* __restrict__ vx,
+                                                    T* __restrict__ vy) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < ny) {
+        vx[(int64_t)t * ld] = T(0);
+        vx[(int64_t)t * ld + nx] = T(0);
+    }
+    if (t < nx) {
+        vy[t] = T(0);
+        vy[(int64_t)ny * ld + t] = T(0);
+    }
+}
+
 // ------------------------------------------------------------------- RAS --
 // One outer iteration of RAS-type temporal blocking (Alg. 2), snapshot form.
 // Workgroup = one tile.  Tile (tx, ty) owns cells [x0,x1) x [y0,y1), cut at
@@ -290,6 +306,19 @@ int launch_jacobi_split(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const Fie
         hipLaunchKernelGGL(k_jacobi_y<float>, grid, block, 0, ctx->stream, gg, (const float*)vx, (const float*)vy,
                            (float*)oy);
     }
+    STK_HIP(hipGetLastError());
+    return STK_OK;
+}
+
+int launch_zero_walls(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, void* vx, void* vy) {
+    const int n = std::max(g->nx, g->ny);
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (dt == STK_F64)
+        hipLaunchKernelGGL(k_zero_walls<double>, grid, block, 0, ctx->stream, g->nx, g->ny, g->ld, (double*)vx,
+                           (double*)vy);
+    else
+        hipLaunchKernelGGL(k_zero_walls<float>, grid, block, 0, ctx->stream, g->nx, g->ny, g->ld, (float*)vx,
+                           (float*)vy);
     STK_HIP(hipGetLastError());
     return STK_OK;
 }

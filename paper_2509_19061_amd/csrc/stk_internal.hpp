@@ -59,6 +59,7 @@ int launch_jacobi_fused(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const Fie
                         const void* vx, const void* vy, void* ox, void* oy);
 int launch_jacobi_split(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega,
                         const void* vx, const void* vy, void* ox, void* oy);
+int launch_zero_walls(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, void* vx, void* vy);
 int launch_rbgs(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega, void* vx, void* vy);
 // RAS outer iteration; returns STK_EUNSUPPORTED when the tile does not fit.
 int ras_lds_bytes(stk_dtype dt, const stk_grid* g, int tile_x, int tile_y, int halo, size_t* bytes);

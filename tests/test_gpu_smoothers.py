@@ -263,3 +263,22 @@ def test_full_size_4096_ras_one_outer_iteration_vs_oracle(ctx):
     gx, gy = gpu_smooth(ctx, p, torch.float64, "ras", 8, **kw)
     ox, oy = S.smooth(p, *p.zeros_v(), p.fx, p.fy, None, 8, "ras", **kw)
     assert normwise(gx, ox) <= TOL64 and normwise(gy, oy) <= TOL64
+
+
+@pytest.mark.parametrize("kt,h", [(4, 4), (3, 1), (0, 2)])
+def test_ras_outer_entry_point_out_of_place(ctx, kt, h):
+    from paper_2509_19061_amd import api, fields
+    p = ragged_problem(150, 110, 28, 1e5)
+    vx0, vy0 = I.random_velocity(p, 29, 1e-3)
+    dp = fields.DeviceProblem(p, torch.float64)
+    vx, vy = dp.velocity(vx0, vy0)
+    ox, oy = dp.field(np.full((p.ny + 1, p.nx + 1), 7.0)), dp.field(np.full((p.ny + 1, p.nx + 1), 7.0))
+    api.ras_outer(ctx, torch.float64, dp.grid, vx, vy, dp.eta_c, dp.eta_n, dp.fx, dp.fy, ox, oy, 0.7, 48, 40, h, kt,
+                  17, 33)
+    torch.cuda.synchronize()
+    bx, by = S.rhs(p, p.fx, p.fy)
+    rx, ry = S.ras_outer(p, bx, by, 0.7, 48, 40, h, kt, 17, 33, vx0, vy0)
+    assert normwise(dp.get_vx(ox), rx) <= TOL64 and normwise(dp.get_vy(oy), ry) <= TOL64
+    # inputs untouched, walls of the output written
+    assert np.array_equal(dp.get_vx(vx), vx0) and np.array_equal(dp.get_vy(vy), vy0)
+    assert np.all(dp.get_vx(ox)[:, [0, -1]] == 0) and np.all(dp.get_vy(oy)[[0, -1], :] == 0)
