@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -96,6 +97,10 @@ int stk_ctx_create(stk_ctx** out, int device, void* hip_stream) {
     (void)hipDeviceGetAttribute(&b, hipDeviceAttributeSharedMemPerBlockOptin, device);
     c->lds_max = a > b ? a : b;
     (void)hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (const char* rk = std::getenv("STK_RAS_KERNEL")) {
+        if (!std::strcmp(rk, "window")) c->ras_kernel = 1;
+        else if (!std::strcmp(rk, "stream")) c->ras_kernel = 2;
+    }
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->host_red), 64 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;

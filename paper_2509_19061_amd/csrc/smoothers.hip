@@ -223,12 +223,12 @@ template <typename T, int MAXC>
 int launch_ras_t(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, int Tx, int Ty, int h, int kt, int sx, int sy,
                  const T* vx, const T* vy, T* ox, T* oy) {
     const size_t lds = ras_bytes<T>(g, Tx, Ty, h);
-    static bool attr_set[64] = {};
+    static size_t attr_set[64] = {};
     const int dev = ctx->device < 64 ? ctx->device : 63;
-    if (!attr_set[dev]) {
+    if (lds > attr_set[dev]) {
         STK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ras<T, MAXC>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, ctx->lds_max));
-        attr_set[dev] = true;
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set[dev] = lds;
     }
     const dim3 grid((unsigned)((g->nx + Tx - 1) / Tx + 1), (unsigned)((g->ny + Ty - 1) / Ty + 1));
     hipLaunchKernelGGL((k_ras<T, MAXC>), grid, dim3(RAS_NT), lds, ctx->stream, gg, vx, vy, ox, oy, Tx, Ty, h, kt, sx,
@@ -356,6 +356,14 @@ int launch_ras(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f
     if (lds > (size_t)ctx->lds_max)
         return set_error(STK_EUNSUPPORTED, "RAS tile %dx%d with halo %d needs %zu bytes of LDS (limit %d)", tile_x,
                          tile_y, halo, lds, ctx->lds_max);
+    if (ctx->ras_kernel != 1) {
+        bool done = false;
+        STK_TRY(launch_ras_stream(ctx, dt, g, f, omega, tile_x, tile_y, halo, kt, sx, sy, vx, vy, ox, oy, &done));
+        if (done) return STK_OK;
+        if (ctx->ras_kernel == 2)
+            return set_error(STK_EUNSUPPORTED, "streaming RAS kernel cannot take tile %dx%d, halo %d, k %d", tile_x,
+                             tile_y, halo, kt);
+    }
     if (dt == STK_F64) return launch_ras_dispatch<double>(ctx, g, f, omega, tile_x, tile_y, halo, kt, sx, sy, vx, vy, ox, oy);
     return launch_ras_dispatch<float>(ctx, g, f, omega, tile_x, tile_y, halo, kt, sx, sy, vx, vy, ox, oy);
 }

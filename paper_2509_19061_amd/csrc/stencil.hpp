@@ -45,34 +45,11 @@ __device__ __forceinline__ T ldenh(const Grid<T>& g, int i, int j) {
     return (i >= 1 && i <= g.nx - 1 && j >= 1 && j <= g.ny - 1) ? g.en[(int64_t)j * g.ld + i] : T(0);
 }
 
-// New vx(i,j).  vc = vx(i,j); vl/vr = vx(i-1/i+1, j); vb/vt = vx(i, j-1/j+1);
-// ybc/ybl = vy(i/i-1, j); ytc/ytl = vy(i/i-1, j+1); ecl/ecr = eta_c(i-1/i, j);
-// enb/ent = eta_n(i, j/j+1) (0 on boundary nodes).
+// The damped Jacobi step from the operator value m = (Mv) at the unknown and
+// g = omega / diag(-M): v' = v - g (b - m).  Every kernel ends in this call.
 template <typename T>
-__device__ __forceinline__ T jac_vx(T vc, T vl, T vr, T vb, T vt, T ybc, T ybl, T ytc, T ytl, T ecl, T ecr, T enb,
-                                    T ent, T b, T omega, T idx, T idy) {
-    const T txr = T(2) * ecr * (vr - vc) * idx;
-    const T txl = T(2) * ecl * (vc - vl) * idx;
-    const T sxt = ent * ((vt - vc) * idy + (ytc - ytl) * idx);
-    const T sxb = enb * ((vc - vb) * idy + (ybc - ybl) * idx);
-    const T m = (txr - txl) * idx + (sxt - sxb) * idy;
-    const T d = T(2) * (ecl + ecr) * (idx * idx) + (enb + ent) * (idy * idy);
-    return vc - (omega / d) * (b - m);
-}
-
-// New vy(i,j).  vc = vy(i,j); vl/vr = vy(i-1/i+1, j); vb/vt = vy(i, j-1/j+1);
-// xlc/xrc = vx(i/i+1, j); xlb/xrb = vx(i/i+1, j-1); ecb/ect = eta_c(i, j-1/j);
-// enl/enr = eta_n(i/i+1, j) (0 on boundary nodes).
-template <typename T>
-__device__ __forceinline__ T jac_vy(T vc, T vl, T vr, T vb, T vt, T xlc, T xrc, T xlb, T xrb, T ecb, T ect, T enl,
-                                    T enr, T b, T omega, T idx, T idy) {
-    const T tyt = T(2) * ect * (vt - vc) * idy;
-    const T tyb = T(2) * ecb * (vc - vb) * idy;
-    const T syr = enr * ((xrc - xrb) * idy + (vr - vc) * idx);
-    const T syl = enl * ((xlc - xlb) * idy + (vc - vl) * idx);
-    const T m = (tyt - tyb) * idy + (syr - syl) * idx;
-    const T d = T(2) * (ecb + ect) * (idy * idy) + (enl + enr) * (idx * idx);
-    return vc - (omega / d) * (b - m);
+__device__ __forceinline__ T jac_step(T vc, T g, T b, T m) {
+    return vc - g * (b - m);
 }
 
 // (M v)_x and (M v)_y in the same expression order (residual kernels).
@@ -101,6 +78,28 @@ __device__ __forceinline__ T diag_x(T ecl, T ecr, T enb, T ent, T idx, T idy) {
 template <typename T>
 __device__ __forceinline__ T diag_y(T ecb, T ect, T enl, T enr, T idx, T idy) {
     return T(2) * (ecb + ect) * (idy * idy) + (enl + enr) * (idx * idx);
+}
+
+// New vx(i,j).  vc = vx(i,j); vl/vr = vx(i-1/i+1, j); vb/vt = vx(i, j-1/j+1);
+// ybc/ybl = vy(i/i-1, j); ytc/ytl = vy(i/i-1, j+1); ecl/ecr = eta_c(i-1/i, j);
+// enb/ent = eta_n(i, j/j+1) (0 on boundary nodes).
+template <typename T>
+__device__ __forceinline__ T jac_vx(T vc, T vl, T vr, T vb, T vt, T ybc, T ybl, T ytc, T ytl, T ecl, T ecr, T enb,
+                                    T ent, T b, T omega, T idx, T idy) {
+    const T m = mv_x<T>(vc, vl, vr, vb, vt, ybc, ybl, ytc, ytl, ecl, ecr, enb, ent, idx, idy);
+    const T g = omega / diag_x<T>(ecl, ecr, enb, ent, idx, idy);
+    return jac_step<T>(vc, g, b, m);
+}
+
+// New vy(i,j).  vc = vy(i,j); vl/vr = vy(i-1/i+1, j); vb/vt = vy(i, j-1/j+1);
+// xlc/xrc = vx(i/i+1, j); xlb/xrb = vx(i/i+1, j-1); ecb/ect = eta_c(i, j-1/j);
+// enl/enr = eta_n(i/i+1, j) (0 on boundary nodes).
+template <typename T>
+__device__ __forceinline__ T jac_vy(T vc, T vl, T vr, T vb, T vt, T xlc, T xrc, T xlb, T xrb, T ecb, T ect, T enl,
+                                    T enr, T b, T omega, T idx, T idy) {
+    const T m = mv_y<T>(vc, vl, vr, vb, vt, xlc, xrc, xlb, xrb, ecb, ect, enl, enr, idx, idy);
+    const T g = omega / diag_y<T>(ecb, ect, enl, enr, idx, idy);
+    return jac_step<T>(vc, g, b, m);
 }
 
 // Gather-and-update at (i,j) straight from global memory (walls read as 0).

@@ -13,6 +13,7 @@ struct stk_ctx {
     hipStream_t stream = nullptr;
     int lds_max = 0;  // bytes of LDS one workgroup may use on this device
     int num_cu = 0;
+    int ras_kernel = 0;  // 0 auto (streaming when it fits), 1 LDS window only, 2 streaming only
     // Scratch slots, grown on demand (device memory).
     enum { S_VX = 0, S_VY, S_BX, S_BY, S_PART, S_RED, S_NSLOT };
     void* slot[S_NSLOT] = {};
@@ -65,6 +66,10 @@ int launch_rbgs(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& 
 int ras_lds_bytes(stk_dtype dt, const stk_grid* g, int tile_x, int tile_y, int halo, size_t* bytes);
 int launch_ras(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega, int tile_x,
                int tile_y, int halo, int kt, int sx, int sy, const void* vx, const void* vy, void* ox, void* oy);
+// Streaming RAS kernel; *done = false when the configuration does not fit it.
+int launch_ras_stream(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega, int tile_x,
+                      int tile_y, int halo, int kt, int sx, int sy, const void* vx, const void* vy, void* ox, void* oy,
+                      bool* done);
 int launch_copy_velocity(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, void* ox,
                          void* oy);
 int launch_residual(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* p,

@@ -26,6 +26,28 @@ def ctx():
     c.close()
 
 
+def _forced_ctx(kind):
+    import os
+    from paper_2509_19061_amd import api
+    old = os.environ.get("STK_RAS_KERNEL")
+    os.environ["STK_RAS_KERNEL"] = kind
+    try:
+        return api.Context(0)
+    finally:
+        if old is None:
+            del os.environ["STK_RAS_KERNEL"]
+        else:
+            os.environ["STK_RAS_KERNEL"] = old
+
+
+@pytest.fixture(scope="module", params=["window", "stream"])
+def ras_ctx(request):
+    """Contexts pinned to one RAS kernel (LDS window / streaming)."""
+    c = _forced_ctx(request.param)
+    yield c
+    c.close()
+
+
 def ragged_problem(nx=200, ny=150, seed=11, contrast=1e6):
     rng = np.random.default_rng(seed)
     count = 6
@@ -70,12 +92,12 @@ def test_centred_sinker_energy_history_fp64(ctx):
 
 # ------------------------------------------------- several tiles, ragged --
 @pytest.mark.parametrize("k,h", [(2, 2), (4, 4), (8, 8), (4, 1), (3, 0), (1, 0), (5, 2)])
-def test_ras_ragged_tiles_fp64(ctx, k, h):
+def test_ras_ragged_tiles_fp64(ras_ctx, k, h):
     p = ragged_problem()
     vx0, vy0 = I.random_velocity(p, 3, 1e-3)
     shifts = I.random_shifts(10, 64, 48, 7)
     kw = dict(tile_x=64, tile_y=48, k=k, halo=h)
-    gx, gy = gpu_smooth(ctx, p, torch.float64, "ras", 10, vx0, vy0, shifts=shifts, **kw)
+    gx, gy = gpu_smooth(ras_ctx, p, torch.float64, "ras", 10, vx0, vy0, shifts=shifts, **kw)
     ox, oy = S.smooth(p, vx0, vy0, p.fx, p.fy, None, 10, "ras", shifts=shifts, **kw)
     assert normwise(gx, ox) <= TOL64 and normwise(gy, oy) <= TOL64
 
@@ -90,7 +112,8 @@ def test_global_smoothers_ragged_with_pressure_fp64(ctx, variant):
     assert normwise(gx, ox) <= TOL64 and normwise(gy, oy) <= TOL64
 
 
-def test_ras_with_pressure_and_literal_outer_count_fp64(ctx):
+def test_ras_with_pressure_and_literal_outer_count_fp64(ras_ctx):
+    ctx = ras_ctx
     p = ragged_problem(97, 130, 13, 1e3)
     vx0, vy0 = I.random_velocity(p, 6, 1e-2)
     pr = I.random_pressure(p, 7)
@@ -101,14 +124,19 @@ def test_ras_with_pressure_and_literal_outer_count_fp64(ctx):
     assert normwise(gx, ox) <= TOL64 and normwise(gy, oy) <= TOL64
 
 
-def test_ras_with_enough_overlap_is_bitwise_fused_jacobi(ctx):
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_ras_with_enough_overlap_is_bitwise_fused_jacobi(ctx, ras_ctx, dtype):
     """RAS(h >= k-1) computes exactly Jacobi^k; the kernels share one update
     expression, so the GPU results agree bit for bit."""
     p = ragged_problem()
     vx0, vy0 = I.random_velocity(p, 9, 1e-3)
-    rx, ry = gpu_smooth(ctx, p, torch.float64, "ras", 12, vx0, vy0, tile_x=64, tile_y=64, k=4, halo=3, seed=5)
-    jx, jy = gpu_smooth(ctx, p, torch.float64, "jacobi_fused", 12, vx0, vy0)
-    sx, sy = gpu_smooth(ctx, p, torch.float64, "jacobi", 12, vx0, vy0)
+    if dtype == torch.float32:
+        p = I.Problem(p.nx, p.ny, p.dx, p.dy, as_dtype(p.eta_c, dtype), as_dtype(p.eta_n, dtype),
+                      as_dtype(p.fx, dtype), as_dtype(p.fy, dtype))
+        vx0, vy0 = as_dtype(vx0, dtype), as_dtype(vy0, dtype)
+    rx, ry = gpu_smooth(ras_ctx, p, dtype, "ras", 12, vx0, vy0, tile_x=64, tile_y=64, k=4, halo=3, seed=5)
+    jx, jy = gpu_smooth(ctx, p, dtype, "jacobi_fused", 12, vx0, vy0)
+    sx, sy = gpu_smooth(ctx, p, dtype, "jacobi", 12, vx0, vy0)
     assert np.array_equal(rx, jx) and np.array_equal(ry, jy)
     assert np.array_equal(sx, jx) and np.array_equal(sy, jy)
 
@@ -126,7 +154,8 @@ def test_deterministic_run_to_run(ctx, variant):
 # ------------------------------------------------------------------- FP32 --
 @pytest.mark.parametrize("variant,k", [("jacobi", 1), ("jacobi_fused", 1), ("rbgs", 1), ("ras", 2), ("ras", 4),
                                        ("ras", 8)])
-def test_fp32_one_step_against_fp64_oracle(ctx, variant, k):
+def test_fp32_one_step_against_fp64_oracle(ras_ctx, variant, k):
+    ctx = ras_ctx
     p = ragged_problem(200, 150, 14, 1e6)
     # an FP64 state a few sweeps in, rounded to FP32 (inputs identical on both sides)
     bx, by = S.rhs(p, p.fx, p.fy)
@@ -254,14 +283,15 @@ def test_fp64_nonfinite_norm_reported(ctx):
 
 
 # ----------------------------------------------------- full-size workload --
-def test_full_size_4096_ras_one_outer_iteration_vs_oracle(ctx):
+@pytest.mark.parametrize("k", [2, 4, 8])
+def test_full_size_4096_ras_one_outer_iteration_vs_oracle(ctx, k):
     """The benchmark's workload (4096^2, 8 sinkers, eta 1e6/1, T = 64, h = k = 8):
     one outer iteration compared with the oracle over the whole field."""
     p = I.smoother_workload(4096, 2)
     shifts = I.random_shifts(1, 64, 64, 3)
-    kw = dict(tile_x=64, tile_y=64, k=8, halo=8, shifts=shifts)
-    gx, gy = gpu_smooth(ctx, p, torch.float64, "ras", 8, **kw)
-    ox, oy = S.smooth(p, *p.zeros_v(), p.fx, p.fy, None, 8, "ras", **kw)
+    kw = dict(tile_x=64, tile_y=64, k=k, halo=k, shifts=shifts)
+    gx, gy = gpu_smooth(ctx, p, torch.float64, "ras", k, **kw)
+    ox, oy = S.smooth(p, *p.zeros_v(), p.fx, p.fy, None, k, "ras", **kw)
     assert normwise(gx, ox) <= TOL64 and normwise(gy, oy) <= TOL64
 
 
@@ -282,3 +312,26 @@ def test_ras_outer_entry_point_out_of_place(ctx, kt, h):
     # inputs untouched, walls of the output written
     assert np.array_equal(dp.get_vx(vx), vx0) and np.array_equal(dp.get_vy(vy), vy0)
     assert np.all(dp.get_vx(ox)[:, [0, -1]] == 0) and np.all(dp.get_vy(oy)[[0, -1], :] == 0)
+
+
+def test_ras_streaming_tall_tiles_and_many_tiles_per_workgroup(ras_ctx):
+    """Tiles stacked in one workgroup (streamed without draining), small tiles
+    so that workgroups hold several, rectangular tiles, thin halo."""
+    p = ragged_problem(301, 257, 30, 1e6)
+    vx0, vy0 = I.random_velocity(p, 31, 1e-3)
+    for (tx, ty, k, h) in [(16, 8, 3, 1), (40, 24, 4, 0), (64, 64, 6, 2), (13, 29, 2, 2)]:
+        shifts = I.random_shifts(4, tx, ty, tx + ty)
+        kw = dict(tile_x=tx, tile_y=ty, k=k, halo=h, shifts=shifts)
+        gx, gy = gpu_smooth(ras_ctx, p, torch.float64, "ras", 2 * k + 1, vx0, vy0, **kw)
+        ox, oy = S.smooth(p, vx0, vy0, p.fx, p.fy, None, 2 * k + 1, "ras", **kw)
+        assert normwise(gx, ox) <= TOL64 and normwise(gy, oy) <= TOL64, (tx, ty, k, h)
+
+
+def test_ras_large_k_falls_back_to_window_kernel(ctx):
+    p = ragged_problem(150, 140, 32, 1e3)
+    vx0, vy0 = I.random_velocity(p, 33, 1e-3)
+    shifts = I.random_shifts(2, 64, 64, 34)
+    kw = dict(tile_x=64, tile_y=64, k=16, halo=2, shifts=shifts)
+    gx, gy = gpu_smooth(ctx, p, torch.float64, "ras", 20, vx0, vy0, **kw)
+    ox, oy = S.smooth(p, vx0, vy0, p.fx, p.fy, None, 20, "ras", **kw)
+    assert normwise(gx, ox) <= TOL64 and normwise(gy, oy) <= TOL64
