@@ -182,6 +182,82 @@ int stk_energy_norm(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* v
                     const void* p, const void* eta_c, const void* eta_n, const void* fx, const void* fy,
                     double out[5]);
 
+/* ----------------------------------------------------------- multigrid -- */
+
+/* Geometric multigrid for the velocity block (Sec. 3.2: the velocity update
+ * of the inexact Uzawa scheme is solved approximately with a matrix-free
+ * geometric multigrid whose smoothing dominates the cost; Sec. 5.2 runs one
+ * V-cycle per Uzawa cycle).  The paper gives no transfer operators; this
+ * library coarsens by 2 in x and y while min(nx, ny) > coarsest and both are
+ * even, prolongs bilinearly per component (linear across faces, 3/4-1/4 along
+ * them, mirrored at the free-slip walls), restricts with R = P^T / 4, uses
+ * Galerkin coarse operators M_c = R M P (stored as 31 coefficients per coarse
+ * unknown, 62 * (ny_c+1) * ld_c words per coarse level; the finest level is
+ * matrix-free), smooths with damped Jacobi (bit-identical to RAS with
+ * halo >= k - 1) and solves the coarsest level exactly in FP64 (dense inverse
+ * of -M_c built at setup). */
+typedef struct {
+    int nu1, nu2;      /* pre / post smoothing sweeps per level (default 2, 2)                 */
+    double omega;      /* Jacobi damping (default 0.7)                                          */
+    int coarsest;      /* stop coarsening at min(nx, ny) <= coarsest (default 8)                */
+    double inner_tol;  /* FP32_REFINED: energy-norm reduction of each inner FP32 solve (1e-3)   */
+    int inner_max;     /* FP32_REFINED: max inner iterations per refinement step (default 60)   */
+} stk_mg_opts;
+
+typedef enum {
+    STK_SOLVE_F64 = 0,         /* flexible CG in FP64, preconditioned by one FP64 V-cycle per iteration */
+    STK_SOLVE_F32_REFINED = 1  /* FP64 iterative refinement: FP64 residual and update, each correction
+                                  solved by flexible CG in FP32 with FP32 V-cycles (coarsest grid FP64) */
+} stk_solve_mode;
+
+typedef struct {
+    int iterations;        /* F64: Krylov iterations; F32_REFINED: refinement steps                 */
+    int inner_iterations;  /* F32_REFINED: total FP32 Krylov iterations (F64: = iterations)         */
+    int converged;         /* final true E_v <= tol                                                 */
+    double ev;             /* final E_v = sqrt(N_v / N_f) from a freshly computed FP64 residual     */
+    double nf;             /* N_f = sum f^2 / diag(-M)                                              */
+    double seconds;        /* host wall time of the call                                            */
+} stk_report;
+
+void stk_mg_opts_default(stk_mg_opts* o);
+
+/* Build the hierarchy for grid g from DEVICE FP64 viscosities in g's layout.
+ * The handle copies what it keeps and owns every level buffer until
+ * stk_mg_destroy.  STK_EUNSUPPORTED if the coarsest level would exceed 4096
+ * unknowns (choose nx, ny divisible by a power of two).  Synchronises. */
+int stk_mg_create(stk_ctx* ctx, stk_mg** out, const stk_grid* g, const double* eta_c, const double* eta_n,
+                  const stk_mg_opts* opts);
+int stk_mg_destroy(stk_mg* mg);
+/* Levels, coarsest-grid unknowns and device bytes currently held. */
+int stk_mg_info(const stk_mg* mg, int* levels, int* coarse_unknowns, size_t* bytes);
+/* Device bytes a hierarchy for g needs when solving in `mode` (0 F64, 1 F32_REFINED),
+ * including the solver's vectors: the admission figure of a serving loop. */
+int stk_mg_footprint(const stk_grid* g, const stk_mg_opts* opts, int mode, size_t* bytes);
+
+/* One V(nu1, nu2)-cycle for M v = b on the finest level, in place on (vx, vy);
+ * device arrays in the layout of the grid given at creation, dtype dt (FP32
+ * uses FP32 copies of the viscosities and coarse stencils; the coarsest solve
+ * is FP64).
+ * Asynchronous. */
+int stk_mg_vcycle(stk_mg* mg, stk_dtype dt, void* vx, void* vy, const void* bx, const void* by);
+
+/* Solve M v = f - G p to the velocity energy residual E_v = sqrt(N_v / N_f)
+ * <= tol (Sec. 5.4), starting from (vx, vy) (device FP64, in/out).  p may be
+ * NULL.  At most max_iters Krylov iterations (F64) or refinement steps
+ * (F32_REFINED).  STK_ENOTCONV if the final E_v > tol (the iterate and the
+ * report are still written).  Synchronises. */
+int stk_mg_solve(stk_mg* mg, stk_solve_mode mode, double* vx, double* vy, const double* p, const double* fx,
+                 const double* fy, double tol, int max_iters, stk_report* rep);
+
+/* The same for n independent instances (distinct handles on one context):
+ * every level kernel is ONE launch across all instances (work-list of
+ * (instance, block)); instances stop individually; one host synchronisation
+ * per iteration reads all convergence flags.  Arrays of n pointers; p may be
+ * NULL or hold NULL entries; reps may be NULL. */
+int stk_mg_solve_batch(stk_ctx* ctx, int n, stk_mg* const* mgs, stk_solve_mode mode, double* const* vx,
+                       double* const* vy, const double* const* p, const double* const* fx, const double* const* fy,
+                       double tol, int max_iters, stk_report* reps);
+
 #ifdef __cplusplus
 }
 #endif

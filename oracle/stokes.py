@@ -35,7 +35,6 @@ def lib():
             "or_rbgs": [I, I, D, D, P, P, P, P, D, P, P],
             "or_ras": [I, I, D, D, P, P, P, P, D, I, I, I, I, I, I, P, P, P, P],
             "or_energy": [I, I, D, D, P, P, P, P, P, P, P, P],
-            "or_coarsen_eta": [I, I, P, P, P],
             "or_prolong_add": [I, I, P, P, P, P],
             "or_restrict": [I, I, P, P, P, P],
         }
@@ -206,15 +205,6 @@ def smooth(g, vx, vy, fx, fy, p, sweeps, variant, omega=None, tile_x=64, tile_y=
 
 
 # ---------------------------------------------------------------- transfers --
-
-def coarsen_eta(g):
-    assert g.nx % 2 == 0 and g.ny % 2 == 0
-    NX, NY = g.nx // 2, g.ny // 2
-    ec = _f(g.eta_c, (g.ny, g.nx))
-    ecc, enc = np.empty((NY, NX)), np.empty((NY + 1, NX + 1))
-    lib().or_coarsen_eta(g.nx, g.ny, _p(ec), _p(ecc), _p(enc))
-    return ecc, enc
-
 
 def prolong_add(nx, ny, cx, cy, fx, fy):
     NX, NY = nx // 2, ny // 2

@@ -414,30 +414,8 @@ void or_energy(int nx, int ny, double dx, double dy, const double* ec, const dou
  * = fine cells {2I,2I+1} x {2J,2J+1}; bilinear prolongation per component
  * (linear between coarse faces normal to the face, weights 3/4, 1/4 between
  * neighbouring coarse rows/columns tangentially, mirrored at walls); and
- * restriction R = P^T / 4. */
-
-/* Coarse viscosities: eta_c = mean of the 4 children; eta_n = harmonic mean of
- * the 1, 2 or 4 coarse cells touching the node. */
-void or_coarsen_eta(int nx, int ny, const double* ec, double* ecc, double* enc) {
-    int NX = nx / 2, NY = ny / 2;
-    for (int J = 0; J < NY; ++J)
-        for (int I = 0; I < NX; ++I)
-            ecc[(long)J * NX + I] = 0.25 * (ec[(long)(2 * J) * nx + 2 * I] + ec[(long)(2 * J) * nx + 2 * I + 1] +
-                                            ec[(long)(2 * J + 1) * nx + 2 * I] + ec[(long)(2 * J + 1) * nx + 2 * I + 1]);
-    for (int J = 0; J <= NY; ++J)
-        for (int I = 0; I <= NX; ++I) {
-            double s = 0.0;
-            int n = 0;
-            for (int oj = -1; oj <= 0; ++oj)
-                for (int oi = -1; oi <= 0; ++oi) {
-                    int ci = I + oi, cj = J + oj;
-                    if (ci < 0 || ci >= NX || cj < 0 || cj >= NY) continue;
-                    s += 1.0 / ecc[(long)cj * NX + ci];
-                    ++n;
-                }
-            enc[(long)J * (NX + 1) + I] = n / s;
-        }
-}
+ * restriction R = P^T / 4.  Coarse operators are Galerkin products
+ * (oracle/mg.py). */
 
 /* Weights of the fine position f (index along one axis) on coarse positions.
  * normal=1: fine faces along their normal (n+1 faces on n cells): even f sits

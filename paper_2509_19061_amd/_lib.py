@@ -32,6 +32,18 @@ class SmoothOpts(C.Structure):
                 ("shifts", C.POINTER(C.c_int32)), ("seed", C.c_uint64), ("last_partial", C.c_int)]
 
 
+class MgOpts(C.Structure):
+    _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("omega", C.c_double), ("coarsest", C.c_int),
+                ("inner_tol", C.c_double), ("inner_max", C.c_int)]
+
+
+class Report(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("inner_iterations", C.c_int), ("converged", C.c_int), ("ev", C.c_double),
+                ("nf", C.c_double), ("seconds", C.c_double)]
+
+
+SOLVE_F64, SOLVE_F32_REFINED = 0, 1
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2509_19061_amd.build` "
                       "(there is no CPU fallback)")
@@ -55,6 +67,15 @@ _SIGS = {
     "stk_ras_outer": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double, _I, _I, _I, _I, _I, _I], _I),
     "stk_residual": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I),
     "stk_energy_norm": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_double)], _I),
+    "stk_mg_opts_default": ([C.POINTER(MgOpts)], None),
+    "stk_mg_create": ([_P, C.POINTER(_P), _G, _P, _P, C.POINTER(MgOpts)], _I),
+    "stk_mg_destroy": ([_P], _I),
+    "stk_mg_info": ([_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(C.c_size_t)], _I),
+    "stk_mg_footprint": ([_G, C.POINTER(MgOpts), _I, C.POINTER(C.c_size_t)], _I),
+    "stk_mg_vcycle": ([_P, _I, _P, _P, _P, _P], _I),
+    "stk_mg_solve": ([_P, _I, _P, _P, _P, _P, _P, C.c_double, _I, C.POINTER(Report)], _I),
+    "stk_mg_solve_batch": ([_P, _I, C.POINTER(_P), _I, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P),
+                            C.POINTER(_P), C.c_double, _I, C.POINTER(Report)], _I),
 }
 
 

@@ -5,18 +5,25 @@ only checks and marshals them.  See ``include/stk.h`` for the semantics.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import sys
+import weakref
 
 import numpy as np
 import torch
 
 from . import _lib as L
 from ._lib import (EHIP, EINVAL, ENOMEM, ENONFINITE, ENOTCONV, EUNSUPPORTED, F32, F64, JACOBI, JACOBI_FUSED, OK,
-                   RAS_JACOBI, RBGS, VARIANTS, Grid, SmoothOpts, StkError, check)
+                   RAS_JACOBI, RBGS, SOLVE_F32_REFINED, SOLVE_F64, VARIANTS, Grid, MgOpts, Report, SmoothOpts,
+                   StkError, check)
 
 __all__ = ["Context", "Grid", "SmoothOpts", "StkError", "smooth", "ras_outer", "residual", "energy_norm", "ras_shifts",
            "smooth_opts", "F64", "F32", "JACOBI", "JACOBI_FUSED", "RAS_JACOBI", "RBGS", "VARIANTS", "OK", "EINVAL",
-           "ENOMEM", "EHIP", "ENOTCONV", "ENONFINITE", "EUNSUPPORTED", "dtype_code", "torch_dtype"]
+           "ENOMEM", "EHIP", "ENOTCONV", "ENONFINITE", "EUNSUPPORTED", "dtype_code", "torch_dtype", "MG", "mg_opts",
+           "mg_footprint", "mg_solve_batch", "SOLVE_F64", "SOLVE_F32_REFINED", "MODES"]
+
+MODES = {"f64": SOLVE_F64, "f32_refined": SOLVE_F32_REFINED}
 
 
 def dtype_code(dt):
@@ -47,15 +54,35 @@ def _ptr(t, dt=None):
     return t.data_ptr()
 
 
+# Live handles, released at interpreter exit while the HIP runtime is still up
+# (a destructor that ran during finalisation would call into a torn-down runtime).
+_LIVE_CONTEXTS = weakref.WeakSet()
+
+
+def _close_all():
+    for c in list(_LIVE_CONTEXTS):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_all)
+
+
 class Context:
-    """stk_ctx bound to a device and a HIP stream (default: torch's current)."""
+    """stk_ctx bound to a device and a HIP stream (default: torch's current).
+
+    Closing a context first closes the multigrid handles built on it."""
 
     def __init__(self, device: int = 0, stream=None):
         self.device = device
         self.handle = C.c_void_p()
+        self._mgs = weakref.WeakSet()
         s = stream if stream is not None else torch.cuda.current_stream(device)
         sp = s.cuda_stream if hasattr(s, "cuda_stream") else s
         check(L.lib.stk_ctx_create(C.byref(self.handle), device, C.c_void_p(sp)))
+        _LIVE_CONTEXTS.add(self)
 
     def set_stream(self, stream):
         sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
@@ -70,11 +97,15 @@ class Context:
         return n.value
 
     def close(self):
+        for m in list(self._mgs):
+            m.close()
         if self.handle:
             L.lib.stk_ctx_destroy(self.handle)
             self.handle = C.c_void_p()
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -137,3 +168,86 @@ def ras_shifts(seed, n_outer, tile_x, tile_y):
     check(L.lib.stk_ras_shifts(C.c_uint64(seed), int(n_outer), int(tile_x), int(tile_y),
                                out.ctypes.data_as(C.POINTER(C.c_int32))))
     return out.reshape(n_outer, 2)
+
+
+# ------------------------------------------------------------------ multigrid --
+
+def mg_opts(nu1=2, nu2=2, omega=0.7, coarsest=8, inner_tol=1e-3, inner_max=60):
+    o = MgOpts()
+    L.lib.stk_mg_opts_default(C.byref(o))
+    o.nu1, o.nu2, o.omega, o.coarsest = int(nu1), int(nu2), float(omega), int(coarsest)
+    o.inner_tol, o.inner_max = float(inner_tol), int(inner_max)
+    return o
+
+
+def _mode(mode):
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def _report(r):
+    return dict(iterations=r.iterations, inner_iterations=r.inner_iterations, converged=bool(r.converged),
+                ev=r.ev, nf=r.nf, seconds=r.seconds)
+
+
+def mg_footprint(grid, mode="f64", **opts):
+    n = C.c_size_t()
+    check(L.lib.stk_mg_footprint(C.byref(grid), C.byref(mg_opts(**opts)), _mode(mode), C.byref(n)))
+    return n.value
+
+
+class MG:
+    """stk_mg handle: hierarchy built from FP64 device viscosities (copied)."""
+
+    def __init__(self, ctx, grid, eta_c, eta_n, **opts):
+        self.ctx = ctx
+        self.grid = grid
+        self.handle = C.c_void_p()
+        if not ctx.handle:
+            raise ValueError("context is closed")
+        check(L.lib.stk_mg_create(ctx.handle, C.byref(self.handle), C.byref(grid), _ptr(eta_c, F64),
+                                  _ptr(eta_n, F64), C.byref(mg_opts(**opts))))
+        ctx._mgs.add(self)
+
+    def info(self):
+        lv, cn, b = C.c_int(), C.c_int(), C.c_size_t()
+        check(L.lib.stk_mg_info(self.handle, C.byref(lv), C.byref(cn), C.byref(b)))
+        return dict(levels=lv.value, coarse_unknowns=cn.value, bytes=b.value)
+
+    def vcycle(self, dt, vx, vy, bx, by):
+        dt = dtype_code(dt)
+        check(L.lib.stk_mg_vcycle(self.handle, dt, _ptr(vx, dt), _ptr(vy, dt), _ptr(bx, dt), _ptr(by, dt)))
+
+    def solve(self, mode, vx, vy, p, fx, fy, tol=1e-8, max_iters=500, allow_notconv=False):
+        r = Report()
+        rc = L.lib.stk_mg_solve(self.handle, _mode(mode), _ptr(vx, F64), _ptr(vy, F64), _ptr(p, F64),
+                                _ptr(fx, F64), _ptr(fy, F64), float(tol), int(max_iters), C.byref(r))
+        if not (allow_notconv and rc == ENOTCONV):
+            check(rc)
+        return _report(r)
+
+    def close(self):
+        if self.handle:
+            L.lib.stk_mg_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mg_solve_batch(ctx, mgs, mode, vx, vy, p, fx, fy, tol=1e-8, max_iters=500, allow_notconv=False):
+    """Solve len(mgs) independent instances together (lists of device tensors)."""
+    n = len(mgs)
+    arr = lambda xs, dt=F64: (C.c_void_p * n)(*[_ptr(x, dt) for x in xs])
+    hs = (C.c_void_p * n)(*[m.handle.value for m in mgs])
+    reps = (Report * n)()
+    pp = None if p is None else arr(p)
+    rc = L.lib.stk_mg_solve_batch(ctx.handle, n, hs, _mode(mode), arr(vx), arr(vy), pp, arr(fx), arr(fy),
+                                  float(tol), int(max_iters), reps)
+    if not (allow_notconv and rc == ENOTCONV):
+        check(rc)
+    return [_report(r) for r in reps]

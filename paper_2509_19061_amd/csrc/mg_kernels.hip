@@ -1,0 +1,656 @@
+// Multigrid and Krylov kernels for gfx950, batched over independent
+// instances (one launch per (level, kernel) serves every instance).
+//
+// Geometric multigrid for the velocity block (paper Sec. 3.2, Sec. 5.2); the
+// paper does not print the transfers, so these follow the stated reading:
+// coarsening by 2, bilinear prolongation per velocity component (linear
+// between coarse faces along the face normal, weights 3/4 and 1/4 between
+// neighbouring coarse rows tangentially, mirrored at the free-slip walls),
+// restriction R = P^T / 4, Galerkin coarse operators stored as 31-point
+// stencils (coarse_stencil.hpp); the finest level is matrix-free.
+//
+// Launch shape: a flat grid of 256-thread blocks; block b belongs to the
+// instance i with pre[i] <= b < pre[i+1] and covers a 64 x 4 patch of that
+// instance's (nx+1) x (ny+1) index box.
+#include "coarse_stencil.hpp"
+#include "mg_internal.hpp"
+#include "stencil.hpp"
+
+namespace stk {
+namespace {
+
+constexpr int BX = 64, BY = 4, NT = BX * BY;
+
+__device__ __forceinline__ int find_inst(const int* __restrict__ pre, int n, int b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// (instance, i, j) of this thread for a box of (nx+1) x (ny+1) indices
+#define STK_BATCH_INDEX(JOBS, PRE, N, NXF, NYF)                                     \
+    const int inst = find_inst(PRE, N, (int)blockIdx.x);                             \
+    const auto& J = JOBS[inst];                                                      \
+    const int lb = (int)blockIdx.x - PRE[inst];                                      \
+    const int gxb = (NXF(J) + 1 + BX - 1) / BX;                                      \
+    const int i = (lb % gxb) * BX + (int)(threadIdx.x % BX);                         \
+    const int j = (lb / gxb) * BY + (int)(threadIdx.x / BX);
+
+#define FINE_NX(J) (J).nx
+#define FINE_NY(J) (J).ny
+#define COARSE_NX(J) (J).cnx
+#define COARSE_NY(J) (J).cny
+
+template <typename T>
+__device__ __forceinline__ Grid<T> job_grid(const LevelJob<T>& J, const T* bx, const T* by, T omega) {
+    Grid<T> g;
+    g.ec = J.ec;
+    g.en = J.en;
+    g.bx = bx;
+    g.by = by;
+    g.ld = J.ld;
+    g.nx = J.nx;
+    g.ny = J.ny;
+    g.idx = J.idx;
+    g.idy = J.idy;
+    g.omega = omega;
+    return g;
+}
+
+// ---------------------------------------------------------------- smoother --
+// One damped Jacobi sweep (dir 0: v -> w, dir 1: w -> v), the shared update.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_jacobi(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
+                                                  int n, T omega, int dir) {
+    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    if (i > J.nx || j > J.ny) return;
+    const Grid<T> g = job_grid(J, J.bx, J.by, omega);
+    const T* sx = dir ? J.wx : J.vx;
+    const T* sy = dir ? J.wy : J.vy;
+    T* dx_ = dir ? J.vx : J.wx;
+    T* dy_ = dir ? J.vy : J.wy;
+    const int64_t k = (int64_t)j * J.ld + i;
+    if (J.st) {  // stored Galerkin stencil: m = M v = -(A v), g = omega / A_ii
+        for (int a = 0; a < 2; ++a) {
+            if (a == 0 ? j >= J.ny : i >= J.nx) continue;
+            T out = T(0);
+            if (a == 0 ? is_vx_unknown(J.nx, J.ny, i, j) : is_vy_unknown(J.nx, J.ny, i, j)) {
+                T d;
+                const T av = stencil_av<T>(J.st, J.plane, a, sx, sy, J.ld, J.nx, J.ny, i, j, d);
+                out = jac_step<T>((a == 0 ? sx : sy)[k], omega / d, (a == 0 ? J.bx : J.by)[k], -av);
+            }
+            (a == 0 ? dx_ : dy_)[k] = out;
+        }
+        return;
+    }
+    if (j < J.ny) dx_[k] = is_vx_unknown(J.nx, J.ny, i, j) ? jac_vx_global(g, sx, sy, i, j) : T(0);
+    if (i < J.nx) dy_[k] = is_vy_unknown(J.nx, J.ny, i, j) ? jac_vy_global(g, sx, sy, i, j) : T(0);
+}
+
+// ---------------------------------------------------------------- residual --
+// r = b - M v on the unknowns (0 on walls).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_residual(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
+                                                    int n) {
+    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    if (i > J.nx || j > J.ny) return;
+    const int nx = J.nx, ny = J.ny;
+    const int64_t ld = J.ld, k = (int64_t)j * ld + i;
+    if (J.st) {  // r = b - M v = b + A v
+        for (int a = 0; a < 2; ++a) {
+            if (a == 0 ? j >= ny : i >= nx) continue;
+            T r = T(0);
+            if (a == 0 ? is_vx_unknown(nx, ny, i, j) : is_vy_unknown(nx, ny, i, j)) {
+                T d;
+                r = (a == 0 ? J.bx : J.by)[k] + stencil_av<T>(J.st, J.plane, a, J.vx, J.vy, ld, nx, ny, i, j, d);
+            }
+            (a == 0 ? J.rx : J.ry)[k] = r;
+        }
+        return;
+    }
+    auto VX = [&](int a, int b) { return ldvx<T>(J.vx, ld, nx, ny, a, b); };
+    auto VY = [&](int a, int b) { return ldvy<T>(J.vy, ld, nx, ny, a, b); };
+    auto ENH = [&](int a, int b) { return (a >= 1 && a <= nx - 1 && b >= 1 && b <= ny - 1) ? J.en[(int64_t)b * ld + a] : T(0); };
+    if (j < ny) {
+        T r = T(0);
+        if (is_vx_unknown(nx, ny, i, j))
+            r = J.bx[k] - mv_x<T>(VX(i, j), VX(i - 1, j), VX(i + 1, j), VX(i, j - 1), VX(i, j + 1), VY(i, j),
+                                  VY(i - 1, j), VY(i, j + 1), VY(i - 1, j + 1), J.ec[k - 1], J.ec[k], ENH(i, j),
+                                  ENH(i, j + 1), J.idx, J.idy);
+        J.rx[k] = r;
+    }
+    if (i < nx) {
+        T r = T(0);
+        if (is_vy_unknown(nx, ny, i, j))
+            r = J.by[k] - mv_y<T>(VY(i, j), VY(i - 1, j), VY(i + 1, j), VY(i, j - 1), VY(i, j + 1), VX(i, j),
+                                  VX(i + 1, j), VX(i, j - 1), VX(i + 1, j - 1), J.ec[k - ld], J.ec[k], ENH(i, j),
+                                  ENH(i + 1, j), J.idx, J.idy);
+        J.ry[k] = r;
+    }
+}
+
+// --------------------------------------------------------------- transfers --
+// Weights of a fine index f on coarse indices along one axis (see header):
+// normal axis: f even -> f/2 (1); f odd -> (f-1)/2, (f+1)/2 (1/2 each).
+// tangential axis: J = f/2 with 3/4, neighbour J-1 (f even) or J+1 (f odd)
+// with 1/4, the neighbour mirrored onto J outside [0, nc).
+__device__ __forceinline__ int w_normal(int f, int* c, double* w) {
+    if ((f & 1) == 0) { c[0] = f >> 1; w[0] = 1.0; return 1; }
+    c[0] = (f - 1) >> 1; w[0] = 0.5;
+    c[1] = (f + 1) >> 1; w[1] = 0.5;
+    return 2;
+}
+__device__ __forceinline__ int w_tangent(int f, int nc, int* c, double* w) {
+    const int J = f >> 1, nb = (f & 1) ? J + 1 : J - 1;
+    if (nb < 0 || nb >= nc) { c[0] = J; w[0] = 1.0; return 1; }
+    c[0] = J; w[0] = 0.75;
+    c[1] = nb; w[1] = 0.25;
+    return 2;
+}
+
+// coarse rhs = R r = P^T r / 4, gathered per coarse unknown from the fine
+// unknowns that prolongate from it.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
+                                                    int n) {
+    STK_BATCH_INDEX(jobs, pre, n, COARSE_NX, COARSE_NY)
+    const int NX = J.cnx, NY = J.cny, nx = J.nx, ny = J.ny;
+    if (i > NX || j > NY) return;
+    const int64_t ld = J.ld, cld = J.cld, k = (int64_t)j * cld + i;
+    if (j < NY) {  // coarse vx(I=i, J=j)
+        double s = 0.0;
+        if (i >= 1 && i <= NX - 1) {
+            for (int fi = 2 * i - 1; fi <= 2 * i + 1; ++fi) {
+                int ci[2];
+                double wi[2];
+                const int nci = w_normal(fi, ci, wi);
+                double wn = 0.0;
+                for (int a = 0; a < nci; ++a) wn += ci[a] == i ? wi[a] : 0.0;
+                for (int fj = 2 * j - 1; fj <= 2 * j + 2; ++fj) {
+                    if (fj < 0 || fj >= ny) continue;
+                    int cj[2];
+                    double wj[2];
+                    const int ncj = w_tangent(fj, NY, cj, wj);
+                    double wt = 0.0;
+                    for (int b = 0; b < ncj; ++b) wt += cj[b] == j ? wj[b] : 0.0;
+                    if (wn != 0.0 && wt != 0.0) s += 0.25 * wn * wt * (double)J.rx[(int64_t)fj * ld + fi];
+                }
+            }
+        }
+        J.cbx[k] = T(s);
+    }
+    if (i < NX) {  // coarse vy(I=i, J=j)
+        double s = 0.0;
+        if (j >= 1 && j <= NY - 1) {
+            for (int fj = 2 * j - 1; fj <= 2 * j + 1; ++fj) {
+                int cj[2];
+                double wj[2];
+                const int ncj = w_normal(fj, cj, wj);
+                double wn = 0.0;
+                for (int b = 0; b < ncj; ++b) wn += cj[b] == j ? wj[b] : 0.0;
+                for (int fi = 2 * i - 1; fi <= 2 * i + 2; ++fi) {
+                    if (fi < 0 || fi >= nx) continue;
+                    int ci[2];
+                    double wi[2];
+                    const int nci = w_tangent(fi, NX, ci, wi);
+                    double wt = 0.0;
+                    for (int a = 0; a < nci; ++a) wt += ci[a] == i ? wi[a] : 0.0;
+                    if (wn != 0.0 && wt != 0.0) s += 0.25 * wn * wt * (double)J.ry[(int64_t)fj * ld + fi];
+                }
+            }
+        }
+        J.cby[k] = T(s);
+    }
+}
+
+// coarse iterate = 0 (the coarse problem is solved for the correction from 0)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_zero_coarse(const LevelJob<T>* __restrict__ jobs,
+                                                       const int* __restrict__ pre, int n) {
+    STK_BATCH_INDEX(jobs, pre, n, COARSE_NX, COARSE_NY)
+    if (i > J.cnx || j > J.cny) return;
+    const int64_t k = (int64_t)j * J.cld + i;
+    if (j < J.cny) J.cvx[k] = T(0);
+    if (i < J.cnx) J.cvy[k] = T(0);
+}
+
+// v += P e_c on the fine unknowns.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_prolong(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
+                                                   int n) {
+    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    const int nx = J.nx, ny = J.ny, NX = J.cnx, NY = J.cny;
+    if (i > nx || j > ny) return;
+    const int64_t k = (int64_t)j * J.ld + i, cld = J.cld;
+    if (is_vx_unknown(nx, ny, i, j)) {
+        int ci[2], cj[2];
+        double wi[2], wj[2];
+        const int a = w_normal(i, ci, wi), b = w_tangent(j, NY, cj, wj);
+        double s = 0.0;
+        for (int p = 0; p < a; ++p)
+            for (int q = 0; q < b; ++q) {
+                const int I = ci[p], JJ = cj[q];
+                const double c = (I >= 1 && I <= NX - 1) ? (double)J.cvx[(int64_t)JJ * cld + I] : 0.0;
+                s += wi[p] * wj[q] * c;
+            }
+        J.vx[k] = J.vx[k] + T(s);
+    }
+    if (is_vy_unknown(nx, ny, i, j)) {
+        int ci[2], cj[2];
+        double wi[2], wj[2];
+        const int a = w_tangent(i, NX, ci, wi), b = w_normal(j, cj, wj);
+        double s = 0.0;
+        for (int p = 0; p < a; ++p)
+            for (int q = 0; q < b; ++q) {
+                const int I = ci[p], JJ = cj[q];
+                const double c = (JJ >= 1 && JJ <= NY - 1) ? (double)J.cvy[(int64_t)JJ * cld + I] : 0.0;
+                s += wi[p] * wj[q] * c;
+            }
+        J.vy[k] = J.vy[k] + T(s);
+    }
+}
+
+// ------------------------------------------------------------ coarsest grid --
+// One workgroup per instance: dense FP64 solve x = A^{-1} (-b) of the coarsest
+// problem (A = -M assembled and inverted on the host at setup), gathered from
+// and scattered to the level layout through the unknown index map.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_mg_coarse(const CoarseJob<T>* __restrict__ jobs) {
+    extern __shared__ double rhs[];
+    const CoarseJob<T>& J = jobs[blockIdx.x];
+    const int nu = J.n;
+    for (int q = threadIdx.x; q < nu; q += blockDim.x) {
+        const int code = J.map[q];  // (component << 30) | (j * ld + i) offset
+        const int off = code & 0x3fffffff;
+        rhs[q] = -(double)((code >> 30) ? J.by[off] : J.bx[off]);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nu; q += blockDim.x) {
+        const double* row = J.ainv + (int64_t)q * nu;
+        double s = 0.0;
+        for (int c = 0; c < nu; ++c) s += row[c] * rhs[c];
+        const int code = J.map[q];
+        const int off = code & 0x3fffffff;
+        if (code >> 30) J.vy[off] = T(s); else J.vx[off] = T(s);
+    }
+}
+
+// w -> v copy of the level iterate (after an odd number of sweeps)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_copy_wv(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
+                                                   int n) {
+    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    if (i > J.nx || j > J.ny) return;
+    const int64_t k = (int64_t)j * J.ld + i;
+    if (j < J.ny) J.vx[k] = J.wx[k];
+    if (i < J.nx) J.vy[k] = J.wy[k];
+}
+
+// --------------------------------------------------------- Krylov vectors --
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ void block_sum2(double a0, double a1, double* part) {
+    __shared__ double red[2][NT / 64];
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][w] = a0;
+        red[1][w] = a1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double s = 0.0;
+        for (int q = 0; q < NT / 64; ++q) s += red[threadIdx.x][q];
+        part[2 * blockIdx.x + threadIdx.x] = s;
+    }
+}
+
+// diag(-M) at vx(i,j) / vy(i,j) from the FP64 viscosities (unknowns only)
+__device__ __forceinline__ double dgx(const VecJob& J, int i, int j) {
+    const int64_t ld = J.ld, k = (int64_t)j * ld + i;
+    const double enb = (j >= 1 && j <= J.ny - 1) ? J.en[k] : 0.0;
+    const double ent = (j + 1 <= J.ny - 1) ? J.en[k + ld] : 0.0;
+    return diag_x<double>(J.ec[k - 1], J.ec[k], enb, ent, J.idx, J.idy);
+}
+__device__ __forceinline__ double dgy(const VecJob& J, int i, int j) {
+    const int64_t ld = J.ld, k = (int64_t)j * ld + i;
+    const double enl = (i >= 1 && i <= J.nx - 1) ? J.en[k] : 0.0;
+    const double enr = (i + 1 <= J.nx - 1) ? J.en[k + 1] : 0.0;
+    return diag_y<double>(J.ec[k - ld], J.ec[k], enl, enr, J.idx, J.idy);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, const int* __restrict__ pre, int n,
+                                            int op, const FcgState* __restrict__ st, double* __restrict__ part) {
+    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    double a0 = 0.0, a1 = 0.0;
+    if (i <= J.nx && j <= J.ny && st[inst].active) {
+        const int64_t k = (int64_t)j * J.ld + i;
+        const double al = st[inst].alpha, be = st[inst].beta;
+        for (int c = 0; c < 2; ++c) {
+            const bool u = c == 0 ? is_vx_unknown(J.nx, J.ny, i, j) : is_vy_unknown(J.nx, J.ny, i, j);
+            const bool inbox = c == 0 ? j < J.ny : i < J.nx;
+            if (!inbox) continue;
+            T* X = static_cast<T*>(J.v[VS_X][c]);
+            T* R = static_cast<T*>(J.v[VS_R][c]);
+            T* Z = static_cast<T*>(J.v[VS_Z][c]);
+            T* P = static_cast<T*>(J.v[VS_P][c]);
+            T* Q = static_cast<T*>(J.v[VS_Q][c]);
+            switch (op) {
+                case OP_PQ:
+                    if (u) a0 += (double)P[k] * (double)Q[k];
+                    break;
+                case OP_UPDATE:
+                    if (u) {
+                        X[k] = T((double)X[k] + al * (double)P[k]);
+                        const T r = T((double)R[k] + al * (double)Q[k]);
+                        R[k] = r;
+                        a0 += (double)r * (double)r / (c == 0 ? dgx(J, i, j) : dgy(J, i, j));
+                    }
+                    break;
+                case OP_RZ_ZQ:
+                    if (u) {
+                        a0 += (double)R[k] * (double)Z[k];
+                        a1 += (double)Z[k] * (double)Q[k];
+                    }
+                    break;
+                case OP_XPBY:
+                    P[k] = u ? T((double)Z[k] + be * (double)P[k]) : T(0);
+                    break;
+                case OP_RNORM:
+                    if (u) a0 += (double)R[k] * (double)R[k] / (c == 0 ? dgx(J, i, j) : dgy(J, i, j));
+                    break;
+                case OP_FNORM: {
+                    const double* F = static_cast<const double*>(J.v[VS_F][c]);
+                    if (u) a0 += F[k] * F[k] / (c == 0 ? dgx(J, i, j) : dgy(J, i, j));
+                    break;
+                }
+                case OP_INIT_P:
+                    P[k] = u ? Z[k] : T(0);
+                    if (u) a0 += (double)R[k] * (double)Z[k];
+                    break;
+                case OP_ZERO_Z:
+                    Z[k] = T(0);
+                    break;
+                default:  // OP_ZERO_X
+                    X[k] = T(0);
+                    break;
+            }
+        }
+    }
+    block_sum2(a0, a1, part);
+}
+
+// slot src (FP64) -> slot dst (float), or src (float) -> dst (FP64)
+__global__ __launch_bounds__(NT) void k_vec_cast(const VecJob* __restrict__ jobs, const int* __restrict__ pre, int n,
+                                                 const FcgState* __restrict__ st, int src, int dst, int to_f32) {
+    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    if (i > J.nx || j > J.ny || !st[inst].active) return;
+    const int64_t k = (int64_t)j * J.ld + i;
+    for (int c = 0; c < 2; ++c) {
+        if (c == 0 ? j >= J.ny : i >= J.nx) continue;
+        if (to_f32)
+            static_cast<float*>(J.v[dst][c])[k] = (float)static_cast<const double*>(J.v[src][c])[k];
+        else
+            static_cast<double*>(J.v[dst][c])[k] = (double)static_cast<const float*>(J.v[src][c])[k];
+    }
+}
+
+// X64 += (double) X  (X = the FP32 correction of the refinement step)
+__global__ __launch_bounds__(NT) void k_vec_add_x64(const VecJob* __restrict__ jobs, const int* __restrict__ pre,
+                                                    int n, const FcgState* __restrict__ st) {
+    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    if (i > J.nx || j > J.ny || !st[inst].active) return;
+    const int64_t k = (int64_t)j * J.ld + i;
+    for (int c = 0; c < 2; ++c) {
+        if (c == 0 ? j >= J.ny : i >= J.nx) continue;
+        double* x = static_cast<double*>(J.v[VS_X64][c]);
+        x[k] = x[k] + (double)static_cast<const float*>(J.v[VS_X][c])[k];
+    }
+}
+
+// R64 = B64 - M X64 in FP64 with sum R64^2 / d
+__global__ __launch_bounds__(NT) void k_vec_res64(const VecJob* __restrict__ jobs, const int* __restrict__ pre, int n,
+                                                  const FcgState* __restrict__ st, double* __restrict__ part) {
+    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    double a0 = 0.0;
+    if (i <= J.nx && j <= J.ny && st[inst].active) {
+        const int nx = J.nx, ny = J.ny;
+        const int64_t ld = J.ld, k = (int64_t)j * ld + i;
+        const double* vx = static_cast<const double*>(J.v[VS_X64][0]);
+        const double* vy = static_cast<const double*>(J.v[VS_X64][1]);
+        auto VX = [&](int a, int b) { return ldvx<double>(vx, ld, nx, ny, a, b); };
+        auto VY = [&](int a, int b) { return ldvy<double>(vy, ld, nx, ny, a, b); };
+        auto ENH = [&](int a, int b) { return (a >= 1 && a <= nx - 1 && b >= 1 && b <= ny - 1) ? J.en[(int64_t)b * ld + a] : 0.0; };
+        if (j < ny) {
+            double r = 0.0;
+            if (is_vx_unknown(nx, ny, i, j)) {
+                const double m = mv_x<double>(VX(i, j), VX(i - 1, j), VX(i + 1, j), VX(i, j - 1), VX(i, j + 1), VY(i, j),
+                                              VY(i - 1, j), VY(i, j + 1), VY(i - 1, j + 1), J.ec[k - 1], J.ec[k],
+                                              ENH(i, j), ENH(i, j + 1), J.idx, J.idy);
+                r = static_cast<const double*>(J.v[VS_B64][0])[k] - m;
+                a0 += r * r / dgx(J, i, j);
+            }
+            static_cast<double*>(J.v[VS_R64][0])[k] = r;
+        }
+        if (i < nx) {
+            double r = 0.0;
+            if (is_vy_unknown(nx, ny, i, j)) {
+                const double m = mv_y<double>(VY(i, j), VY(i - 1, j), VY(i + 1, j), VY(i, j - 1), VY(i, j + 1), VX(i, j),
+                                              VX(i + 1, j), VX(i, j - 1), VX(i + 1, j - 1), J.ec[k - ld], J.ec[k],
+                                              ENH(i, j), ENH(i + 1, j), J.idx, J.idy);
+                r = static_cast<const double*>(J.v[VS_B64][1])[k] - m;
+                a0 += r * r / dgy(J, i, j);
+            }
+            static_cast<double*>(J.v[VS_R64][1])[k] = r;
+        }
+    }
+    block_sum2(a0, 0.0, part);
+}
+
+// per-instance sums of the per-block partials, fixed order
+__global__ __launch_bounds__(256) void k_inst_sums(const int* __restrict__ pre, const double* __restrict__ part,
+                                                   double* __restrict__ sums) {
+    const int inst = blockIdx.x;
+    const int b0 = pre[inst], b1 = pre[inst + 1];
+    __shared__ double red[2][256 / 64];
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = b0 + (int)threadIdx.x; b < b1; b += 256) {
+        s0 += part[2 * b];
+        s1 += part[2 * b + 1];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s0;
+        red[1][threadIdx.x >> 6] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double s = 0.0;
+        for (int q = 0; q < 256 / 64; ++q) s += red[threadIdx.x][q];
+        sums[2 * inst + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_fcg_scalars(FcgState* __restrict__ st, const double* __restrict__ sums, int n, int phase,
+                              double factor) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    FcgState& s = st[q];
+    const double s0 = sums[2 * q], s1 = sums[2 * q + 1];
+    switch (phase) {
+        case PH_NF:  // N_f and the outer stop threshold
+            s.nf = s0;
+            s.thr = factor * s0;
+            break;
+        case PH_NV0:  // start of an inner solve: relative threshold
+            s.nv = s0;
+            s.nv0 = s0;
+            s.thr = factor * s0;
+            s.active = s.active && s0 > s.thr;
+            break;
+        case PH_NV:
+            if (s.active) {
+                s.nv = s0;
+                s.active = s0 > s.thr;
+            }
+            break;
+        case PH_INIT:
+            if (s.active) s.gamma = -s0;
+            break;
+        case PH_ALPHA:
+            if (s.active) {
+                s.pq = s0;
+                s.alpha = (s0 != 0.0) ? s.gamma / s0 : 0.0;
+            }
+            break;
+        case PH_THR:  // outer threshold from the stored N_f
+            s.thr = factor * s.nf;
+            break;
+        default: {  // PH_BETA: rho = -r, gamma' = rho.z, beta = -alpha (z.q) / gamma
+            if (s.active) {
+                const double gnew = -s0;
+                s.rz = s0;
+                s.zq = s1;
+                s.beta = (s.gamma != 0.0) ? -s.alpha * s1 / s.gamma : 0.0;
+                s.gamma = gnew;
+            }
+        }
+    }
+}
+
+inline dim3 nblk(int blocks) { return dim3((unsigned)blocks); }
+
+}  // namespace
+}  // namespace stk
+
+namespace stk {
+
+#define STK_LAUNCH_CHECK() STK_HIP(hipGetLastError())
+
+template <typename T>
+int mg_jacobi(stk_ctx* ctx, const Batch& b, double omega, int dir) {
+    if (!b.n) return STK_OK;
+    hipLaunchKernelGGL(k_mg_jacobi<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
+                       static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n, T(omega), dir);
+    STK_LAUNCH_CHECK();
+    return STK_OK;
+}
+template <typename T>
+int mg_copy_wv(stk_ctx* ctx, const Batch& b) {
+    if (!b.n) return STK_OK;
+    hipLaunchKernelGGL(k_mg_copy_wv<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
+                       static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n);
+    STK_LAUNCH_CHECK();
+    return STK_OK;
+}
+template <typename T>
+int mg_residual(stk_ctx* ctx, const Batch& b) {
+    if (!b.n) return STK_OK;
+    hipLaunchKernelGGL(k_mg_residual<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
+                       static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n);
+    STK_LAUNCH_CHECK();
+    return STK_OK;
+}
+template <typename T>
+int mg_restrict(stk_ctx* ctx, const Batch& b) {
+    if (!b.n) return STK_OK;
+    hipLaunchKernelGGL(k_mg_restrict<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
+                       static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n);
+    STK_LAUNCH_CHECK();
+    return STK_OK;
+}
+template <typename T>
+int mg_zero_coarse(stk_ctx* ctx, const Batch& b) {
+    if (!b.n) return STK_OK;
+    hipLaunchKernelGGL(k_mg_zero_coarse<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
+                       static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n);
+    STK_LAUNCH_CHECK();
+    return STK_OK;
+}
+template <typename T>
+int mg_prolong(stk_ctx* ctx, const Batch& b) {
+    if (!b.n) return STK_OK;
+    hipLaunchKernelGGL(k_mg_prolong<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
+                       static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n);
+    STK_LAUNCH_CHECK();
+    return STK_OK;
+}
+template <typename T>
+int mg_coarse(stk_ctx* ctx, const void* jobs, int n, int max_unknowns) {
+    if (!n) return STK_OK;
+    hipLaunchKernelGGL(k_mg_coarse<T>, dim3(n), dim3(256), (size_t)max_unknowns * sizeof(double), ctx->stream,
+                       static_cast<const CoarseJob<T>*>(jobs));
+    STK_LAUNCH_CHECK();
+    return STK_OK;
+}
+template int mg_jacobi<double>(stk_ctx*, const Batch&, double, int);
+template int mg_jacobi<float>(stk_ctx*, const Batch&, double, int);
+template int mg_copy_wv<double>(stk_ctx*, const Batch&);
+template int mg_copy_wv<float>(stk_ctx*, const Batch&);
+template int mg_residual<double>(stk_ctx*, const Batch&);
+template int mg_residual<float>(stk_ctx*, const Batch&);
+template int mg_restrict<double>(stk_ctx*, const Batch&);
+template int mg_restrict<float>(stk_ctx*, const Batch&);
+template int mg_zero_coarse<double>(stk_ctx*, const Batch&);
+template int mg_zero_coarse<float>(stk_ctx*, const Batch&);
+template int mg_prolong<double>(stk_ctx*, const Batch&);
+template int mg_prolong<float>(stk_ctx*, const Batch&);
+template int mg_coarse<double>(stk_ctx*, const void*, int, int);
+template int mg_coarse<float>(stk_ctx*, const void*, int, int);
+
+template <typename T>
+int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* part, double* sums) {
+    if (!b.n) return STK_OK;
+    hipLaunchKernelGGL(k_vec<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const VecJob*>(b.jobs), b.pre,
+                       b.n, op, st, part);
+    STK_LAUNCH_CHECK();
+    if (sums) return inst_sums(ctx, b, part, sums);
+    return STK_OK;
+}
+template int vec_op<double>(stk_ctx*, const Batch&, int, const FcgState*, double*, double*);
+template int vec_op<float>(stk_ctx*, const Batch&, int, const FcgState*, double*, double*);
+
+int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums) {
+    hipLaunchKernelGGL(k_inst_sums, dim3(b.n), dim3(256), 0, ctx->stream, b.pre, part, sums);
+    STK_LAUNCH_CHECK();
+    return STK_OK;
+}
+
+int vec_cast_st(stk_ctx* ctx, const Batch& b, const FcgState* st, int src, int dst, int to_f32) {
+    if (!b.n) return STK_OK;
+    hipLaunchKernelGGL(k_vec_cast, dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const VecJob*>(b.jobs), b.pre,
+                       b.n, st, src, dst, to_f32);
+    STK_LAUNCH_CHECK();
+    return STK_OK;
+}
+int vec_add_x64_st(stk_ctx* ctx, const Batch& b, const FcgState* st) {
+    if (!b.n) return STK_OK;
+    hipLaunchKernelGGL(k_vec_add_x64, dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const VecJob*>(b.jobs),
+                       b.pre, b.n, st);
+    STK_LAUNCH_CHECK();
+    return STK_OK;
+}
+int vec_residual64_st(stk_ctx* ctx, const Batch& b, const FcgState* st, double* part, double* sums) {
+    if (!b.n) return STK_OK;
+    hipLaunchKernelGGL(k_vec_res64, dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const VecJob*>(b.jobs), b.pre,
+                       b.n, st, part);
+    STK_LAUNCH_CHECK();
+    return inst_sums(ctx, b, part, sums);
+}
+int fcg_scalars(stk_ctx* ctx, FcgState* st, const double* sums, int n, int phase, double factor) {
+    if (!n) return STK_OK;
+    hipLaunchKernelGGL(k_fcg_scalars, dim3((n + 63) / 64), dim3(64), 0, ctx->stream, st, sums, n, phase, factor);
+    STK_LAUNCH_CHECK();
+    return STK_OK;
+}
+
+}  // namespace stk

@@ -1,0 +1,227 @@
+"""GPU multigrid V-cycle and Krylov solves vs the CPU oracle (oracle/mg.py).
+
+V-cycle: the GPU and oracle hierarchies are built independently from the same
+viscosities; they differ only in rounding, including the coarsest solve (GPU:
+dense inverse, oracle: Cholesky solve), whose error is amplified by the
+coarse condition number, hence the V-cycle tolerance TOL_V below.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import as_dtype, normwise
+from oracle import dense as Dn
+from oracle import mg as OM
+from oracle import stokes as S
+from paper_2509_19061_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL_V = 1e-11
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2509_19061_amd import api
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def sinkers(nx, ny, seed, contrast):
+    rng = np.random.default_rng(seed)
+    cnt = 3
+    c = rng.uniform(0.15, 0.85, size=(cnt, 2))
+    r = rng.uniform(0.05, 0.12, size=cnt)
+    return I.sinker_problem(nx, ny, [(float(c[k, 0]), float(c[k, 1]), float(r[k])) for k in range(cnt)],
+                            contrast, 1.0)
+
+
+def gpu_mg(ctx, p, dtype=torch.float64, **opts):
+    from paper_2509_19061_amd import api, fields
+    dp64 = fields.DeviceProblem(p, torch.float64)
+    m = api.MG(ctx, dp64.grid, dp64.eta_c, dp64.eta_n, **opts)
+    dp = dp64 if dtype == torch.float64 else fields.DeviceProblem(p, dtype)
+    return m, dp
+
+
+@pytest.mark.parametrize("nx,ny,contrast", [(64, 64, 1.0), (64, 64, 1e2), (96, 64, 1e4), (50, 36, 1e3)])
+def test_vcycle_fp64_matches_oracle(ctx, nx, ny, contrast):
+    p = sinkers(nx, ny, nx + ny, contrast)
+    levels = OM.hierarchy(p, coarsest=8)
+    m, dp = gpu_mg(ctx, p)
+    assert m.info()["levels"] == len(levels)
+    vx0, vy0 = I.random_velocity(p, 1, 1e-2)
+    rx, ry = I.random_velocity(p, 2, 1.0)  # an arbitrary right-hand side
+    vx, vy = dp.velocity(vx0, vy0)
+    m.vcycle(torch.float64, vx, vy, dp.field(rx), dp.field(ry))
+    torch.cuda.synchronize()
+    ox, oy = OM.vcycle(levels, 0, vx0, vy0, rx, ry)
+    assert normwise(dp.get_vx(vx), ox) <= TOL_V and normwise(dp.get_vy(vy), oy) <= TOL_V
+
+
+def test_vcycle_odd_nu_and_more_sweeps(ctx):
+    p = sinkers(64, 64, 5, 1e2)
+    levels = OM.hierarchy(p, coarsest=8)
+    m, dp = gpu_mg(ctx, p, nu1=3, nu2=1, omega=0.6)
+    rx, ry = I.random_velocity(p, 3, 1.0)
+    vx, vy = dp.velocity()
+    m.vcycle(torch.float64, vx, vy, dp.field(rx), dp.field(ry))
+    torch.cuda.synchronize()
+    ox, oy = OM.vcycle(levels, 0, *p.zeros_v(), rx, ry, nu1=3, nu2=1, omega=0.6)
+    assert normwise(dp.get_vx(vx), ox) <= TOL_V and normwise(dp.get_vy(vy), oy) <= TOL_V
+
+
+def test_vcycle_fp32_against_fp64_oracle(ctx):
+    p = sinkers(128, 128, 7, 1e3)
+    levels = OM.hierarchy(p, coarsest=8)
+    m, dp = gpu_mg(ctx, p, dtype=torch.float32)
+    rx, ry = I.random_velocity(p, 4, 1.0)
+    rx, ry = as_dtype(rx, torch.float32), as_dtype(ry, torch.float32)
+    vx, vy = dp.velocity()
+    m.vcycle(torch.float32, vx, vy, dp.field(rx), dp.field(ry))
+    torch.cuda.synchronize()
+    ox, oy = OM.vcycle(levels, 0, *p.zeros_v(), rx, ry)
+    # FP32 smoothing on every level; the viscosities are rounded to FP32 on the GPU side
+    assert normwise(dp.get_vx(vx), ox) <= 2e-5 and normwise(dp.get_vy(vy), oy) <= 2e-5
+
+
+def energy_error(p, x, y, sx, sy):
+    A, d = Dn.assemble(p)
+    e = d.pack(x, y) - d.pack(sx, sy)
+    s = d.pack(sx, sy)
+    return np.sqrt(e @ A @ e / (s @ A @ s))
+
+
+@pytest.mark.parametrize("contrast", [1.0, 1e3, 1e6])
+def test_fp64_solve_matches_oracle_krylov(ctx, contrast):
+    from paper_2509_19061_amd import api
+    p = sinkers(64, 64, 9, contrast)
+    levels = OM.hierarchy(p, coarsest=8)
+    ox, oy, hist = OM.pcg(levels, p.fx, p.fy, tol=1e-10, max_iters=500)
+    m, dp = gpu_mg(ctx, p)
+    vx, vy = dp.velocity()
+    rep = m.solve("f64", vx, vy, None, dp.fx, dp.fy, tol=1e-10, max_iters=500)
+    assert rep["converged"] and rep["ev"] <= 1e-10
+    # same Krylov method on the same preconditioner: same iteration count (+-1 at the threshold)
+    assert abs(rep["iterations"] - (len(hist) - 1)) <= 1, (rep, len(hist))
+    gx, gy = dp.get_vx(vx), dp.get_vy(vy)
+    assert normwise(gx, ox) <= 1e-7 and normwise(gy, oy) <= 1e-7
+    # the GPU's own report agrees with the oracle's energy norm of its result
+    assert S.energy(p, gx, gy, p.fx, p.fy)[4] == pytest.approx(rep["ev"], rel=1e-6)
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32_refined"])
+def test_solve_recovers_known_discrete_solution(ctx, mode):
+    """Constant viscosity: v* = (sin pi x cos pi y, -cos pi x sin pi y) satisfies
+    -M v* = lam v*, so b = -lam v* has the exact discrete solution v*."""
+    n = 128
+    h = 1.0 / n
+    eta = 2.5
+    p = I.Problem(n, n, h, h, np.full((n, n), eta), np.full((n + 1, n + 1), eta), None, None)
+    xn, yc = np.arange(n + 1) * h, (np.arange(n) + 0.5) * h
+    xc, yn = (np.arange(n) + 0.5) * h, np.arange(n + 1) * h
+    sx = np.sin(np.pi * xn)[None, :] * np.cos(np.pi * yc)[:, None]
+    sy = -np.cos(np.pi * xc)[None, :] * np.sin(np.pi * yn)[:, None]
+    sx[:, [0, -1]] = 0.0
+    sy[[0, -1], :] = 0.0
+    lam = 8 * eta * np.sin(np.pi * h / 2) ** 2 / h ** 2
+    p.fx, p.fy = -lam * sx, -lam * sy
+    m, dp = gpu_mg(ctx, p)
+    vx, vy = dp.velocity()
+    rep = m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=1e-9, max_iters=200)
+    assert rep["converged"]
+    assert normwise(dp.get_vx(vx), sx) <= 1e-8 and normwise(dp.get_vy(vy), sy) <= 1e-8
+
+
+@pytest.mark.parametrize("contrast", [1e2, 1e6])
+def test_refined_solve_reaches_tolerance_and_matches_fp64_oracle(ctx, contrast):
+    p = sinkers(128, 96, 11, contrast)
+    levels = OM.hierarchy(p, coarsest=8)
+    ox, oy, hist = OM.pcg(levels, p.fx, p.fy, tol=1e-12, max_iters=2000)
+    m, dp = gpu_mg(ctx, p)
+    vx, vy = dp.velocity()
+    rep = m.solve("f32_refined", vx, vy, None, dp.fx, dp.fy, tol=1e-8, max_iters=50)
+    assert rep["converged"] and rep["ev"] <= 1e-8 and rep["iterations"] >= 1
+    gx, gy = dp.get_vx(vx), dp.get_vy(vy)
+    assert S.energy(p, gx, gy, p.fx, p.fy)[4] <= 1.01e-8
+    err = max(normwise(gx, ox), normwise(gy, oy))
+    assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32_refined"])
+def test_high_contrast_256_solve_matches_oracle(ctx, mode):
+    """Eight sinkers at viscosity contrast 1e6 on 256^2, solved to E_v <= 1e-8.
+    The oracle solves to 1e-9 (its FP64 floor here is ~2e-10); on the CPU an
+    oracle result at 1e-8 lies within 5e-9 of it in the relative energy norm,
+    so 5e-8 bounds a correct GPU result at 1e-8 with a 10x margin."""
+    from oracle import sparse as SP
+    p = I.random_sinkers(256, 8, 40, eta_in=1e6)
+    levels = OM.hierarchy(p, coarsest=8)
+    ox, oy, hist = OM.pcg(levels, p.fx, p.fy, tol=1e-9, max_iters=600)
+    assert hist[-1] <= 1e-9
+    m, dp = gpu_mg(ctx, p)
+    vx, vy = dp.velocity()
+    rep = m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=1e-8, max_iters=600)
+    assert rep["converged"] and rep["ev"] <= 1e-8
+    gx, gy = dp.get_vx(vx), dp.get_vy(vy)
+    assert S.energy(p, gx, gy, p.fx, p.fy)[4] <= 1.01e-8
+    A = levels[0].A
+    e = SP.pack(p.nx, p.ny, gx, gy) - SP.pack(p.nx, p.ny, ox, oy)
+    s_ = SP.pack(p.nx, p.ny, ox, oy)
+    assert np.sqrt(e @ (A @ e) / (s_ @ (A @ s_))) <= 5e-8
+
+
+def test_solve_with_pressure_and_initial_guess(ctx):
+    p = sinkers(64, 64, 13, 1e2)
+    pr = I.random_pressure(p, 14, 0.1)
+    x0 = I.random_velocity(p, 15, 1e-3)
+    levels = OM.hierarchy(p, coarsest=8)
+    ox, oy, _ = OM.pcg(levels, p.fx, p.fy, p=pr, tol=1e-11, max_iters=500, x0=x0)
+    m, dp = gpu_mg(ctx, p)
+    vx, vy = dp.velocity(*x0)
+    rep = m.solve("f64", vx, vy, dp.field(pr), dp.fx, dp.fy, tol=1e-11, max_iters=500)
+    assert rep["converged"]
+    assert normwise(dp.get_vx(vx), ox) <= 1e-8 and normwise(dp.get_vy(vy), oy) <= 1e-8
+    assert S.energy(p, dp.get_vx(vx), dp.get_vy(vy), p.fx, p.fy, pr)[4] <= 1.01e-11
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32_refined"])
+def test_batch_each_result_same_alone_and_in_mix(ctx, mode):
+    from paper_2509_19061_amd import api
+    probs = [sinkers(64, 64, 20, 1e3), sinkers(128, 128, 21, 1e5), sinkers(96, 64, 22, 1e2),
+             sinkers(32, 32, 23, 1e4)]
+    built = [gpu_mg(ctx, q) for q in probs]
+    alone = []
+    for (m, dp) in built:
+        vx, vy = dp.velocity()
+        rep = m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=1e-8, max_iters=300)
+        alone.append((dp.get_vx(vx), dp.get_vy(vy), rep))
+    vs = [dp.velocity() for (_, dp) in built]
+    reps = api.mg_solve_batch(ctx, [m for (m, _) in built], mode, [v[0] for v in vs], [v[1] for v in vs], None,
+                              [dp.fx for (_, dp) in built], [dp.fy for (_, dp) in built], tol=1e-8, max_iters=300)
+    for (m, dp), v, a, r in zip(built, vs, alone, reps):
+        assert r["converged"] and r["iterations"] == a[2]["iterations"]
+        assert np.array_equal(dp.get_vx(v[0]), a[0]) and np.array_equal(dp.get_vy(v[1]), a[1])
+        assert r["ev"] == a[2]["ev"]
+
+
+def test_mg_errors(ctx):
+    from paper_2509_19061_amd import api, fields
+    p = sinkers(101, 101, 30, 1e2)
+    dp = fields.DeviceProblem(p, torch.float64)
+    with pytest.raises(api.StkError) as e:
+        api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n)
+    assert e.value.code == api.EUNSUPPORTED
+    with pytest.raises(api.StkError) as e:
+        api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n, nu1=0, nu2=0)
+    assert e.value.code == api.EINVAL
+    q = sinkers(64, 64, 31, 1e4)
+    m, dq = gpu_mg(ctx, q)
+    vx, vy = dq.velocity()
+    rep = m.solve("f64", vx, vy, None, dq.fx, dq.fy, tol=1e-12, max_iters=2, allow_notconv=True)
+    assert not rep["converged"] and rep["ev"] > 1e-12
+    with pytest.raises(api.StkError) as e:
+        m.solve("f64", vx, vy, None, dq.fx, dq.fy, tol=1e-12, max_iters=2)
+    assert e.value.code == api.ENOTCONV
+    assert api.mg_footprint(dq.grid, "f32_refined") > 0

@@ -1,8 +1,11 @@
 """Pins of the oracle's multigrid pieces (no GPU).
 
-The paper gives no transfer operators (Sec. 3.2, Sec. 5.2); the oracle's
-reading is pinned by: exactness of the bilinear prolongation on linear
-fields, R = P^T/4 as an adjoint pair, the V-cycle being a symmetric linear
+The paper gives no transfer or coarse operators (Sec. 3.2, Sec. 5.2); the
+oracle's reading is pinned by: exactness of the bilinear prolongation on
+linear fields, R = P^T/4 as an adjoint pair, the sparse P / A agreeing with
+the C stencil and transfers, second-order consistency of the Galerkin coarse
+operator with the continuous viscous operator, the coarse correction being
+the energy-orthogonal projection, the V-cycle being a symmetric linear
 operator with the exact discrete solution as fixed point, and the Krylov
 solve agreeing with a dense direct solve.
 """
@@ -13,6 +16,7 @@ import pytest
 
 from oracle import dense as Dn
 from oracle import mg
+from oracle import sparse as SP
 from oracle import stokes as S
 from paper_2509_19061_amd import inputs as I
 
@@ -56,17 +60,97 @@ def test_restriction_is_quarter_prolongation_transpose():
     assert cx[0, 0] == 0.0 and cx[0, -1] == 0.0
 
 
-def test_coarse_viscosity_rules():
-    rng = np.random.default_rng(3)
-    ec = 10 ** rng.uniform(-2, 4, (8, 10))
-    g = SimpleNamespace(nx=10, ny=8, eta_c=ec)
-    ecc, enc = S.coarsen_eta(g)
-    assert ecc[1, 2] == pytest.approx(np.mean(ec[2:4, 4:6]), rel=1e-15)
-    # a node touching 4 coarse cells: harmonic mean; a corner touches 1
-    assert enc[2, 2] == pytest.approx(4 / np.sum(1 / ecc[1:3, 1:3]), rel=1e-14)
-    assert enc[0, 0] == ecc[0, 0]
-    const = S.coarsen_eta(SimpleNamespace(nx=10, ny=8, eta_c=np.full((8, 10), 7.0)))
-    assert np.all(const[0] == 7.0) and np.allclose(const[1], 7.0, rtol=1e-15)
+def test_sparse_forms_match_the_stencil_and_the_transfers():
+    p = I.random_sinkers(24, 3, 8, eta_in=1e4)
+    A = SP.operator_matrix(p)
+    Ad, d = Dn.assemble(p)
+    assert np.abs(A.toarray() - Ad).max() <= 1e-12 * np.abs(Ad).max()
+    vx, vy = I.random_velocity(p, 9)
+    mx, my = S.apply(p, vx, vy)
+    av = A @ SP.pack(p.nx, p.ny, vx, vy)
+    assert np.abs(av + SP.pack(p.nx, p.ny, mx, my)).max() <= 1e-12 * np.abs(av).max()
+    nx, ny = 16, 12
+    P = SP.prolongation_matrix(nx, ny)
+    ex, ey = I.random_velocity(SimpleNamespace(nx=nx // 2, ny=ny // 2), 10)
+    fx, fy = S.prolong_add(nx, ny, ex, ey, np.zeros((ny, nx + 1)), np.zeros((ny + 1, nx)))
+    assert np.abs(P @ SP.pack(nx // 2, ny // 2, ex, ey) - SP.pack(nx, ny, fx, fy)).max() <= 1e-15
+    rx, ry = I.random_velocity(SimpleNamespace(nx=nx, ny=ny), 11)
+    cx, cy = S.restrict(nx, ny, rx, ry)
+    assert np.abs(0.25 * (P.T @ SP.pack(nx, ny, rx, ry)) - SP.pack(nx // 2, ny // 2, cx, cy)).max() <= 1e-15
+
+
+def _smooth_field(n):
+    """v = (sin(pi x) sin^2(pi y), sin^2(pi x) sin(pi y)) on an n x n grid (free-slip
+    compatible) and M v for eta = 1: (Mv)_x = 2 vx_xx + vx_yy + vy_xy, (Mv)_y likewise."""
+    a, h = np.pi, 1.0 / n
+    X, Y = np.meshgrid(np.arange(n + 1) * h, (np.arange(n) + 0.5) * h)
+    vx = np.sin(a * X) * np.sin(a * Y) ** 2
+    mx = (-2 * a * a * np.sin(a * X) * np.sin(a * Y) ** 2 + 2 * a * a * np.sin(a * X) * np.cos(2 * a * Y)
+          + 2 * a * a * np.sin(a * X) * np.cos(a * X) * np.cos(a * Y))
+    X, Y = np.meshgrid((np.arange(n) + 0.5) * h, np.arange(n + 1) * h)
+    vy = np.sin(a * X) ** 2 * np.sin(a * Y)
+    my = (-2 * a * a * np.sin(a * X) ** 2 * np.sin(a * Y) + 2 * a * a * np.cos(2 * a * X) * np.sin(a * Y)
+          + 2 * a * a * np.sin(a * Y) * np.cos(a * Y) * np.cos(a * X))
+    return vx, vy, mx, my
+
+
+def test_galerkin_coarse_operator_is_second_order_consistent():
+    """M_c = P^T M P / 4 on the coarse grid approximates the continuous operator
+    to O(h^2) up to the walls: pins the 1/4 scaling, the weights and the product."""
+    errs = []
+    for n in (64, 128):
+        g = SimpleNamespace(nx=n, ny=n, dx=1 / n, dy=1 / n, eta_c=np.ones((n, n)), eta_n=np.ones((n + 1, n + 1)))
+        C = mg.hierarchy(g, coarsest=n // 2 - 1)[1]
+        N = n // 2
+        vx, vy, mx, my = _smooth_field(N)
+        ax, ay = SP.unpack(N, N, -(C.A @ SP.pack(N, N, vx, vy)))
+        scale = max(np.abs(mx).max(), np.abs(my).max())
+        errs.append(max(np.abs(ax - mx)[:, 1:-1].max(), np.abs(ay - my)[1:-1, :].max()) / scale)
+    assert errs[1] <= 3e-3 and errs[0] / errs[1] >= 3.5, errs
+
+
+def test_coarse_correction_is_the_energy_orthogonal_projection():
+    p = _problem(32, 12, 1e5)
+    levels = mg.hierarchy(p, coarsest=8)
+    A, P, C = levels[0].A, levels[0].P, levels[1].A
+    rng = np.random.default_rng(13)
+    x, c = rng.standard_normal(A.shape[0]), rng.standard_normal(A.shape[0])
+    xc = np.linalg.solve(C.toarray(), 0.25 * (P.T @ (c - A @ x)))
+    x1 = x + P @ xc
+    r1 = P.T @ (c - A @ x1)
+    assert np.abs(r1).max() <= 1e-9 * np.abs(P.T @ (c - A @ x)).max()
+    # ... hence it minimises the energy error over the coarse space
+    sol = np.linalg.solve(A.toarray(), c)
+    def energy(y):
+        return (y - sol) @ (A @ (y - sol))
+    for k in range(3):
+        assert energy(x1) <= energy(x1 + P @ rng.standard_normal(C.shape[0]) * 10.0 ** -k)
+    assert np.allclose(C.toarray(), C.toarray().T, rtol=0, atol=1e-12 * np.abs(C).max())
+
+
+def test_galerkin_couplings_stay_in_fixed_windows():
+    """Every coarse level couples an unknown only within the same offset windows
+    (vx->vx 3x5, vx->vy 4x4, vy->vx 4x4, vy->vy 5x3: 31 entries per row)."""
+    rng = np.random.default_rng(14)
+    nx, ny = 48, 32
+    en = np.zeros((ny + 1, nx + 1))
+    en[1:-1, 1:-1] = 10 ** rng.uniform(0, 3, (ny - 1, nx - 1))
+    g = SimpleNamespace(nx=nx, ny=ny, dx=1 / nx, dy=1 / ny, eta_c=10 ** rng.uniform(0, 3, (ny, nx)), eta_n=en)
+    win = {(0, 0): (-1, 1, -2, 2), (0, 1): (-2, 1, -1, 2), (1, 0): (-1, 2, -2, 1), (1, 1): (-2, 2, -1, 1)}
+    for L in mg.hierarchy(g, coarsest=4)[1:]:
+        nvx, vxid, vyid = SP.numbering(L.nx, L.ny)
+        pos = np.zeros((SP.n_unknowns(L.nx, L.ny), 3), int)
+        for comp, ids in ((0, vxid), (1, vyid)):
+            jj, ii = np.nonzero(ids >= 0)
+            pos[ids[jj, ii]] = np.stack([np.full(len(ii), comp), ii, jj], 1)
+        A = L.A.tocoo()
+        nz = A.data != 0
+        a, b = pos[A.row[nz]], pos[A.col[nz]]
+        for key, (x0, x1, y0, y1) in win.items():
+            m = (a[:, 0] == key[0]) & (b[:, 0] == key[1])
+            dx, dy = b[m, 1] - a[m, 1], b[m, 2] - a[m, 2]
+            assert dx.min() >= x0 and dx.max() <= x1 and dy.min() >= y0 and dy.max() <= y1, (L.nx, key)
+        assert np.bincount(A.row[nz]).max() <= 31
 
 
 def _problem(n, seed, contrast):
