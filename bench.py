@@ -10,8 +10,21 @@ Value: GLUP/s = cells x sweeps / step time (HIP events on the stream).
 Also reported: every smoother variant at 100 sweeps (Jacobi split, fused,
 RBGS, RAS k = 2, 4, 8), the dominant kernel's roofline (RAS outer-iteration
 kernel timed per launch with HIP events; algorithmic bytes = one round trip
-of vx, vy, eta_c, eta_n, bx, by read and vx, vy written per launch), and the
-CPU oracle timed on this host on a bounded sample of the same workload.
+of vx, vy, eta_c, eta_n, bx, by read and vx, vy written per launch), the CPU
+oracle timed on this host on a bounded sample of the same workload, and the
+multigrid solves:
+  * "solve": 16 sinkers (eta 1e6) over a smooth background with log10(eta)
+    uniform on [-2, 4] (contrast up to 1e8), 2048^2 cells, solved to
+    E_v <= 1e-8 by FP64 flexible CG preconditioned by an FP64 V-cycle and by
+    an FP32 V-cycle (mixed precision, FP64 refinement loop); each result's E_v is
+    recomputed from scratch by the library's FP64 energy-norm call, and the two
+    results are compared in the energy norm (oracle parity of the solves is
+    covered by the tests);
+  * "iteration_cost": the same workload at 8192^2, a fixed number of
+    iterations in each mode, time per iteration (at 8192^2 and contrast 1e8 a
+    solve to 1e-8 does not finish in a few minutes);
+  * "batch": 64 independent sinker problems (256^2 .. 2048^2, uneven mix),
+    one launch per (level, kernel) across all of them, both modes.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -43,6 +56,9 @@ def main():
     ap.add_argument("--variants", default="all", help="'all' or 'none'")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--solve-n", type=int, default=2048, help="refinement workload size (0: skip)")
+    ap.add_argument("--rate-n", type=int, default=8192, help="per-iteration cost size (0: skip)")
+    ap.add_argument("--batch", default="default", help="'default' (64-instance mix), 'small' or 'none'")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -90,25 +106,35 @@ def main():
         f"E = {e[3]:.3e}")
 
     # ---- dominant kernel: one RAS outer iteration per launch, timed live ----
+    # (a context that insists on the streaming kernel, so the timed kernel is known)
+    os.environ["STK_RAS_KERNEL"] = "stream"
+    kctx = api.Context(0)
+    del os.environ["STK_RAS_KERNEL"]
+    kernel_name = "k_ras_stream"
     bx, by = dp.fx, dp.fy
     ax, ay = dp.velocity()
     cx, cy = dp.velocity()
     shifts = api.ras_shifts(3, 64, 64, 64)
     nl = max(sweeps // k, 8)
+    try:
+        api.ras_outer(kctx, dt, dp.grid, ax, ay, dp.eta_c, dp.eta_n, bx, by, cx, cy, 0.7, 64, 64, k, k, *shifts[0])
+    except api.StkError:
+        kctx.close()
+        kctx, kernel_name = ctx, "k_ras"
     for t in range(2):
-        api.ras_outer(ctx, dt, dp.grid, ax, ay, dp.eta_c, dp.eta_n, bx, by, cx, cy, 0.7, 64, 64, k, k, *shifts[t])
+        api.ras_outer(kctx, dt, dp.grid, ax, ay, dp.eta_c, dp.eta_n, bx, by, cx, cy, 0.7, 64, 64, k, k, *shifts[t])
     torch.cuda.synchronize()
     ev0.record()
     for t in range(nl):
         src, dst = ((ax, ay), (cx, cy)) if t % 2 == 0 else ((cx, cy), (ax, ay))
-        api.ras_outer(ctx, dt, dp.grid, *src, dp.eta_c, dp.eta_n, bx, by, *dst, 0.7, 64, 64, k, k,
+        api.ras_outer(kctx, dt, dp.grid, *src, dp.eta_c, dp.eta_n, bx, by, *dst, 0.7, 64, 64, k, k,
                       *shifts[t % len(shifts)])
     ev1.record()
     torch.cuda.synchronize()
     launch_ms = ev0.elapsed_time(ev1) / nl
     alg_bytes = 8 * wbytes * cells  # read vx, vy, eta_c, eta_n, bx, by; write vx, vy
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
-    log(f"[bench] RAS kernel k={k}: {launch_ms:.3f} ms/launch, {achieved:.0f} GB/s effective "
+    log(f"[bench] {kernel_name} k={k}: {launch_ms:.3f} ms/launch, {achieved:.0f} GB/s effective "
         f"({achieved / HBM_PEAK_GBS:.1%} of HBM peak)")
 
     # ---- all variants, 100 sweeps each ----
@@ -158,6 +184,11 @@ def main():
                          f"= {it * k} of the step's {sweeps} sweeps, {el:.1f} s"}
         log(f"[bench] CPU oracle: {cpu_glups:.3f} GLUP/s on {cpu['cores']} threads ({el:.1f} s)")
 
+    del vx, vy, ax, ay, cx, cy
+    solve = run_solves(ctx, args.solve_n) if args.solve_n > 0 else None
+    rate = run_iteration_cost(ctx, args.rate_n) if args.rate_n > 0 else None
+    batch = run_batch(ctx, args.batch) if args.batch != "none" else None
+
     out = {
         "metric": "smoother GLUP/s + % HBM roofline (RAS-Jacobi)",
         "value": round(glups, 2),
@@ -176,14 +207,141 @@ def main():
                    "n": n, "sweeps": sweeps, "k": k, "tile": 64, "halo": k},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_ras (one RAS outer iteration per launch)",
+                     "kernel": f"{kernel_name} (one RAS outer iteration, k={k} sweeps, per launch)",
                      "launch_ms": round(launch_ms, 4), "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "variants": variants,
         "wall_ms_per_step": round(wall / args.steps * 1e3, 4),
+        "solve": solve,
+        "iteration_cost": rate,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
+    if kctx is not ctx:
+        kctx.close()
     ctx.close()
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    r = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return r, e0.elapsed_time(e1) * 1e-3
+
+
+def run_solves(ctx, n, tol=1e-8, max_iters=4000):
+    """FP64 vs FP32-refined solves of the refinement workload."""
+    import torch
+
+    from paper_2509_19061_amd import api, fields, inputs
+
+    t0 = time.time()
+    prob = inputs.lognormal_background_workload(n)
+    log(f"[bench] solve workload {n}^2 generated in {time.time() - t0:.1f}s")
+    dp = fields.DeviceProblem(prob, torch.float64)
+    m, setup_s = _timed(lambda: api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n))
+    info = m.info()
+    log(f"[bench] hierarchy: {info['levels']} levels, {info['coarse_unknowns']} coarsest unknowns, "
+        f"setup {setup_s:.3f}s")
+    res, sols = {}, {}
+    for mode in ("f64", "f32_refined"):
+        vx, vy = dp.velocity()
+        m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=tol, max_iters=1, allow_notconv=True)  # buffers, plan
+        vx, vy = dp.velocity()
+        rep, secs = _timed(lambda: m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=tol, max_iters=max_iters,
+                                            allow_notconv=True))
+        ev_check = float(api.energy_norm(ctx, torch.float64, dp.grid, vx, vy, None, dp.eta_c, dp.eta_n, dp.fx,
+                                         dp.fy)[4])
+        sols[mode] = (vx, vy)
+        res[mode] = {"seconds": round(secs, 4), "solves_per_s": round(1.0 / secs, 4), "converged": rep["converged"],
+                     "iterations": rep["iterations"],
+                     "ms_per_iteration": round(secs * 1e3 / max(1, rep["iterations"]), 3),
+                     "ev_report": rep["ev"], "ev_recomputed": ev_check}
+        log(f"[bench] solve {mode}: {secs:.3f}s, {rep['iterations']} iterations, "
+            f"E_v {rep['ev']:.3e} (recomputed {ev_check:.3e})")
+    # the FP32-refined result against the FP64 one in the relative energy norm
+    # ||d||_A^2 = -<d, M d>, with M d from the library's residual call (f = 0)
+    x64, x32 = sols["f64"], sols["f32_refined"]
+    d = (x32[0] - x64[0], x32[1] - x64[1])
+    zx, zy = torch.zeros_like(dp.fx), torch.zeros_like(dp.fy)
+    rx, ry = torch.empty_like(dp.fx), torch.empty_like(dp.fy)
+
+    def energy(v):
+        api.residual(ctx, torch.float64, dp.grid, v[0], v[1], None, dp.eta_c, dp.eta_n, zx, zy, rx, ry)
+        return float((v[0] * rx).sum() + (v[1] * ry).sum())  # r = -M v, so this is <v, -M v>
+
+    rel = (max(energy(d), 0.0) / energy(x64)) ** 0.5
+    del sols, d, x64, x32
+    m.close()
+    log(f"[bench] refined vs FP64: relative energy-norm difference {rel:.3e}")
+    return {"workload": f"{n}x{n} cells, 16 sinkers eta 1e6 over a smooth background with log10(eta) ~ U(-2, 4), "
+                        f"V(2,2)-preconditioned flexible CG to E_v <= {tol:g}",
+            "n": n, "tol": tol, "levels": info["levels"], "setup_s": round(setup_s, 4),
+            "f64": res["f64"], "f32_refined": res["f32_refined"],
+            "refined_speedup": round(res["f64"]["seconds"] / res["f32_refined"]["seconds"], 3),
+            "refined_vs_f64_energy_rel": rel}
+
+
+def run_iteration_cost(ctx, n, iters=30):
+    """Time per Krylov iteration with the FP64 and with the FP32 V-cycle."""
+    import torch
+
+    from paper_2509_19061_amd import api, fields, inputs
+
+    prob = inputs.lognormal_background_workload(n)
+    dp = fields.DeviceProblem(prob, torch.float64)
+    m = api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n)
+    out = {"workload": f"{n}x{n} cells, same family as the solve section", "n": n, "bytes": None}
+    for mode in ("f64", "f32_refined"):
+        vx, vy = dp.velocity()
+        m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=1e-30, max_iters=1, allow_notconv=True)  # buffers, plan
+        vx, vy = dp.velocity()
+        rep, secs = _timed(lambda: m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=1e-30, max_iters=iters,
+                                            allow_notconv=True))
+        out[mode] = {"seconds": round(secs, 4), "iterations": rep["iterations"],
+                     "ms_per_iteration": round(secs * 1e3 / max(1, rep["iterations"]), 3)}
+        log(f"[bench] {n}^2 {mode}: {rep['iterations']} iterations in {secs:.3f}s")
+        del vx, vy
+    out["bytes"] = m.info()["bytes"]
+    out["f32_speedup_per_iteration"] = round(out["f64"]["ms_per_iteration"] / out["f32_refined"]["ms_per_iteration"], 3)
+    m.close()
+    return out
+
+
+def run_batch(ctx, which, tol=1e-8, max_iters=3000):
+    """The 64-instance uneven mix solved in one batch per mode."""
+    import torch
+
+    from paper_2509_19061_amd import api, fields, inputs
+
+    sizes = ((256, 28), (512, 20), (1024, 12), (2048, 4)) if which == "default" else ((128, 6), (256, 4), (512, 2))
+    t0 = time.time()
+    probs = inputs.batch_mix(5, sizes)
+    dps = [fields.DeviceProblem(q, torch.float64) for q in probs]
+    mgs = [api.MG(ctx, d.grid, d.eta_c, d.eta_n) for d in dps]
+    cells = sum(q.nx * q.ny for q in probs)
+    log(f"[bench] batch of {len(probs)} instances ({cells / 1e6:.1f} M cells) ready in {time.time() - t0:.1f}s")
+    out = {"workload": f"{len(probs)} sinker problems " + ", ".join(f"{c} x {n}^2" for n, c in sizes)
+                       + f", contrast 10^U(2,6), E_v <= {tol:g}", "instances": len(probs), "cells": cells}
+    for mode in ("f64", "f32_refined"):
+        vs = [d.velocity() for d in dps]
+        reps, secs = _timed(lambda: api.mg_solve_batch(ctx, mgs, mode, [v[0] for v in vs], [v[1] for v in vs], None,
+                                                       [d.fx for d in dps], [d.fy for d in dps], tol=tol,
+                                                       max_iters=max_iters, allow_notconv=True))
+        its = [r["iterations"] for r in reps]
+        out[mode] = {"seconds": round(secs, 4), "solves_per_s": round(len(probs) / secs, 3),
+                     "all_converged": all(r["converged"] for r in reps), "max_iterations": max(its),
+                     "mean_iterations": round(sum(its) / len(its), 1), "max_ev": max(r["ev"] for r in reps)}
+        log(f"[bench] batch {mode}: {secs:.3f}s, {len(probs) / secs:.2f} solves/s, iterations max {max(its)}")
+        del vs
+    out["refined_speedup"] = round(out["f64"]["seconds"] / out["f32_refined"]["seconds"], 3)
+    for mm in mgs:
+        mm.close()
+    return out
 
 
 if __name__ == "__main__":

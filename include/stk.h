@@ -200,19 +200,21 @@ typedef struct {
     int nu1, nu2;      /* pre / post smoothing sweeps per level (default 2, 2)                 */
     double omega;      /* Jacobi damping (default 0.7)                                          */
     int coarsest;      /* stop coarsening at min(nx, ny) <= coarsest (default 8)                */
-    double inner_tol;  /* FP32_REFINED: energy-norm reduction of each inner FP32 solve (1e-3)   */
-    int inner_max;     /* FP32_REFINED: max inner iterations per refinement step (default 60)   */
 } stk_mg_opts;
 
+/* Both modes run the same FP64 outer iteration: flexible conjugate gradients
+ * with FP64 residual, operator, dot products and energy norms; each iteration
+ * refines the FP64 iterate by a preconditioned correction.  They differ in the
+ * precision of the preconditioner, one V-cycle per iteration: */
 typedef enum {
-    STK_SOLVE_F64 = 0,         /* flexible CG in FP64, preconditioned by one FP64 V-cycle per iteration */
-    STK_SOLVE_F32_REFINED = 1  /* FP64 iterative refinement: FP64 residual and update, each correction
-                                  solved by flexible CG in FP32 with FP32 V-cycles (coarsest grid FP64) */
+    STK_SOLVE_F64 = 0,         /* FP64 V-cycle                                                          */
+    STK_SOLVE_F32_REFINED = 1  /* FP32 V-cycle (smoothing, transfers, coarse stencils in FP32; the
+                                  coarsest solve accumulates in FP64), applied to the FP64 residual
+                                  rounded to FP32, its result widened back to FP64                      */
 } stk_solve_mode;
 
 typedef struct {
-    int iterations;        /* F64: Krylov iterations; F32_REFINED: refinement steps                 */
-    int inner_iterations;  /* F32_REFINED: total FP32 Krylov iterations (F64: = iterations)         */
+    int iterations;        /* Krylov iterations (= V-cycles applied) of this instance              */
     int converged;         /* final true E_v <= tol                                                 */
     double ev;             /* final E_v = sqrt(N_v / N_f) from a freshly computed FP64 residual     */
     double nf;             /* N_f = sum f^2 / diag(-M)                                              */
@@ -243,9 +245,11 @@ int stk_mg_vcycle(stk_mg* mg, stk_dtype dt, void* vx, void* vy, const void* bx, 
 
 /* Solve M v = f - G p to the velocity energy residual E_v = sqrt(N_v / N_f)
  * <= tol (Sec. 5.4), starting from (vx, vy) (device FP64, in/out).  p may be
- * NULL.  At most max_iters Krylov iterations (F64) or refinement steps
- * (F32_REFINED).  STK_ENOTCONV if the final E_v > tol (the iterate and the
- * report are still written).  Synchronises. */
+ * NULL.  At most max_iters Krylov iterations.  When the recurrence residual
+ * reaches tol the true FP64 residual is recomputed, and the iteration restarts
+ * from the current iterate if it is still above tol.  STK_ENOTCONV if the
+ * final E_v > tol (the iterate and the report are still written).
+ * Synchronises. */
 int stk_mg_solve(stk_mg* mg, stk_solve_mode mode, double* vx, double* vy, const double* p, const double* fx,
                  const double* fy, double tol, int max_iters, stk_report* rep);
 

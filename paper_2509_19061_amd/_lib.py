@@ -33,13 +33,12 @@ class SmoothOpts(C.Structure):
 
 
 class MgOpts(C.Structure):
-    _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("omega", C.c_double), ("coarsest", C.c_int),
-                ("inner_tol", C.c_double), ("inner_max", C.c_int)]
+    _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("omega", C.c_double), ("coarsest", C.c_int)]
 
 
 class Report(C.Structure):
-    _fields_ = [("iterations", C.c_int), ("inner_iterations", C.c_int), ("converged", C.c_int), ("ev", C.c_double),
-                ("nf", C.c_double), ("seconds", C.c_double)]
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("ev", C.c_double), ("nf", C.c_double),
+                ("seconds", C.c_double)]
 
 
 SOLVE_F64, SOLVE_F32_REFINED = 0, 1

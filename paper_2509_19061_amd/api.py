@@ -172,11 +172,10 @@ def ras_shifts(seed, n_outer, tile_x, tile_y):
 
 # ------------------------------------------------------------------ multigrid --
 
-def mg_opts(nu1=2, nu2=2, omega=0.7, coarsest=8, inner_tol=1e-3, inner_max=60):
+def mg_opts(nu1=2, nu2=2, omega=0.7, coarsest=8):
     o = MgOpts()
     L.lib.stk_mg_opts_default(C.byref(o))
     o.nu1, o.nu2, o.omega, o.coarsest = int(nu1), int(nu2), float(omega), int(coarsest)
-    o.inner_tol, o.inner_max = float(inner_tol), int(inner_max)
     return o
 
 
@@ -185,8 +184,7 @@ def _mode(mode):
 
 
 def _report(r):
-    return dict(iterations=r.iterations, inner_iterations=r.inner_iterations, converged=bool(r.converged),
-                ev=r.ev, nf=r.nf, seconds=r.seconds)
+    return dict(iterations=r.iterations, converged=bool(r.converged), ev=r.ev, nf=r.nf, seconds=r.seconds)
 
 
 def mg_footprint(grid, mode="f64", **opts):

@@ -5,9 +5,11 @@
 // The paper solves the velocity block with a matrix-free geometric multigrid
 // (Sec. 3.2, Sec. 5.2) and accelerates its fixed-point iteration with
 // Anderson acceleration (Sec. 3.3, Alg. 1).  Here the V-cycle is used as the
-// preconditioner of flexible conjugate gradients on the SPD system -M v = -b.
-// Coarse levels carry Galerkin operators P^T A P / 4 as stored 31-point
-// stencils (galerkin.hip); the finest level stays matrix-free.
+// preconditioner of flexible conjugate gradients on the SPD system -M v = -b,
+// always in FP64 (residual, operator, dot products, energy norms, coarsest
+// solve); the mixed-precision mode applies the V-cycle in FP32 between two
+// casts.  Coarse levels carry Galerkin operators P^T A P / 4 as stored
+// 31-point stencils (galerkin.hip); the finest level stays matrix-free.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -53,10 +55,12 @@ struct PlanT {  // one dtype, a fixed list of instances
     std::vector<int> ncj;
     Batch apply;                        // finest: v = P, b = 0, r = Q  ->  Q = A P
     Batch vec;                          // VecJob array
+    Batch xcast;                        // XCastJob array (FP32 plan only)
     FcgState* st = nullptr;
     double* part = nullptr;
     double* sums = nullptr;
     std::vector<void*> mem;
+    std::vector<std::vector<unsigned char>> stage;  // host sources of pending uploads
     void release() {
         for (void* p : mem) (void)hipFree(p);
         mem.clear();
@@ -71,7 +75,7 @@ struct stk_mg {
     int cn = 0;
     int* cmap = nullptr;
     double* cainv = nullptr;
-    Field2 ks[2][VS_N];   // finest Krylov slots; F, B64, X64, R64 are FP64 in both rows
+    Field2 ks[2][VS_N];   // finest-level slots: row 0 FP64 (all), row 1 FP32 (R, Z only)
     Field2 zero[2];       // zero right-hand side for the operator apply
     void* zero64 = nullptr;  // FP64 zeros (pressure of a p = 0 fold)
     bool have[2] = {false, false};
@@ -106,7 +110,11 @@ template <typename V>
 int upload(PlanT* P, const std::vector<V>& h, const void** out, hipStream_t s) {
     void* d = nullptr;
     STK_TRY(pdalloc(P, std::max<size_t>(1, h.size()) * sizeof(V), &d, s));
-    if (!h.empty()) STK_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice, s));
+    if (!h.empty()) {  // the host copy stays alive until the plan's final synchronisation
+        const auto* b = reinterpret_cast<const unsigned char*>(h.data());
+        P->stage.emplace_back(b, b + h.size() * sizeof(V));
+        STK_HIP(hipMemcpyAsync(d, P->stage.back().data(), P->stage.back().size(), hipMemcpyHostToDevice, s));
+    }
     *out = d;
     return STK_OK;
 }
@@ -285,22 +293,17 @@ int ensure_dtype(stk_mg* m, int t) {
             STK_TRY(dalloc(m, fb, &fs[q]->y));
         }
     }
-    const size_t fb0 = level_field_bytes(m->L[0], t), fb64 = level_field_bytes(m->L[0], 0);
-    for (int sl = VS_F; sl < VS_N; ++sl) {  // FP64 slots, shared by both dtypes
-        const int other = 1 - t;
-        if (!m->ks[other][sl].x) {
-            STK_TRY(dalloc(m, fb64, &m->ks[other][sl].x));
-            STK_TRY(dalloc(m, fb64, &m->ks[other][sl].y));
-        }
-        m->ks[t][sl] = m->ks[other][sl];
-    }
-    if (!m->zero64) STK_TRY(dalloc(m, fb64, &m->zero64));
-    for (int sl = 0; sl < VS_F; ++sl) {
+    const size_t fb0 = level_field_bytes(m->L[0], t);
+    for (int sl = 0; sl < VS_N; ++sl) {
+        if (t == 1 && sl != VS_R && sl != VS_Z) continue;
         STK_TRY(dalloc(m, fb0, &m->ks[t][sl].x));
         STK_TRY(dalloc(m, fb0, &m->ks[t][sl].y));
     }
-    STK_TRY(dalloc(m, fb0, &m->zero[t].x));
-    STK_TRY(dalloc(m, fb0, &m->zero[t].y));
+    if (t == 0) {
+        STK_TRY(dalloc(m, fb0, &m->zero64));
+        STK_TRY(dalloc(m, fb0, &m->zero[0].x));
+        STK_TRY(dalloc(m, fb0, &m->zero[0].y));
+    }
     m->L[0].v[t] = m->ks[t][VS_Z];
     m->L[0].b[t] = m->ks[t][VS_R];
     m->have[t] = true;
@@ -347,6 +350,7 @@ int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) {
     P->n = n;
     int maxl = 0;
     for (int q = 0; q < n; ++q) {
+        STK_TRY(ensure_dtype(mgs[q], 0));  // the FP64 Krylov slots exist in both modes
         STK_TRY(ensure_dtype(mgs[q], t));
         maxl = std::max(maxl, (int)mgs[q]->L.size());
         P->maxcn = std::max(P->maxcn, mgs[q]->cn);
@@ -390,6 +394,7 @@ int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) {
     // operator apply on the finest level: Q = 0 - M P
     std::vector<LevelJob<T>> aj;
     std::vector<VecJob> vj;
+    std::vector<XCastJob> xj;
     std::vector<int> pa{0};
     for (int q = 0; q < n; ++q) {
         stk_mg* m = mgs[q];
@@ -414,20 +419,29 @@ int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) {
             V.v[sl][0] = m->ks[t][sl].x;
             V.v[sl][1] = m->ks[t][sl].y;
         }
-        if (t == 0) {  // FP64 Krylov: the Krylov iterate/residual are the FP64 solution/residual
-            V.v[VS_X64][0] = V.v[VS_X][0];
-            V.v[VS_X64][1] = V.v[VS_X][1];
-            V.v[VS_R64][0] = V.v[VS_R][0];
-            V.v[VS_R64][1] = V.v[VS_R][1];
-        }
         vj.push_back(V);
+        XCastJob X{};
+        X.nx = V.nx;
+        X.ny = V.ny;
+        X.ld = V.ld;
+        for (int c = 0; c < 2; ++c) {
+            X.r64[c] = static_cast<const double*>(c ? m->ks[0][VS_R].y : m->ks[0][VS_R].x);
+            X.z64[c] = static_cast<double*>(c ? m->ks[0][VS_Z].y : m->ks[0][VS_Z].x);
+            X.r32[c] = static_cast<float*>(c ? m->ks[1][VS_R].y : m->ks[1][VS_R].x);
+            X.z32[c] = static_cast<const float*>(c ? m->ks[1][VS_Z].y : m->ks[1][VS_Z].x);
+        }
+        xj.push_back(X);
     }
-    const void *daj = nullptr, *dpa = nullptr, *dvj = nullptr;
+    const void *daj = nullptr, *dpa = nullptr, *dvj = nullptr, *dxj = nullptr;
     STK_TRY(upload(P, aj, &daj, s));
     STK_TRY(upload(P, pa, &dpa, s));
     STK_TRY(upload(P, vj, &dvj, s));
     P->apply = Batch{daj, (const int*)dpa, n, pa.back()};
     P->vec = Batch{dvj, (const int*)dpa, n, pa.back()};
+    if (t == 1) {  // casts between the FP64 Krylov slots and this plan's FP32 V-cycle slots
+        STK_TRY(upload(P, xj, &dxj, s));
+        P->xcast = Batch{dxj, (const int*)dpa, n, pa.back()};
+    }
     void *st = nullptr, *part = nullptr, *sums = nullptr;
     STK_TRY(pdalloc(P, sizeof(FcgState) * n, &st, s));
     STK_TRY(pdalloc(P, sizeof(double) * 2 * (size_t)pa.back(), &part, s));
@@ -436,6 +450,7 @@ int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) {
     P->part = static_cast<double*>(part);
     P->sums = static_cast<double*>(sums);
     STK_HIP(hipStreamSynchronize(s));
+    P->stage.clear();
     return STK_OK;
 }
 
@@ -482,13 +497,6 @@ int vcycle(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o) {
 int run_vcycle(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o, int t) {
     return t ? vcycle<float>(ctx, P, o) : vcycle<double>(ctx, P, o);
 }
-int vop(stk_ctx* ctx, const PlanT& P, int t, int op, bool sum) {
-    return t ? vec_op<float>(ctx, P.vec, op, P.st, P.part, sum ? P.sums : nullptr)
-             : vec_op<double>(ctx, P.vec, op, P.st, P.part, sum ? P.sums : nullptr);
-}
-int apply(stk_ctx* ctx, const PlanT& P, int t) {
-    return t ? mg_residual<float>(ctx, P.apply) : mg_residual<double>(ctx, P.apply);
-}
 
 int read_states(stk_ctx* ctx, const PlanT& P, std::vector<FcgState>& h) {
     h.resize(P.n);
@@ -502,15 +510,28 @@ int write_active(stk_ctx* ctx, const PlanT& P, std::vector<FcgState>& h, const s
     return STK_OK;
 }
 
-// Flexible CG on the Krylov slots of plan P (dtype t): X and R are set by the
+// One application of the preconditioner to every active instance:
+// Z = V-cycle(R) from zero, in FP64 (P32 == nullptr) or in FP32 between casts.
+int precondition(stk_ctx* ctx, const PlanT& P, const PlanT* P32, const stk_mg_opts& o) {
+    if (!P32) {
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_ZERO_Z, P.st, P.part, nullptr));
+        return vcycle<double>(ctx, P, o);
+    }
+    STK_TRY(prec_cast(ctx, P32->xcast, P.st, 0));
+    STK_TRY(vec_op<float>(ctx, P32->vec, OP_ZERO_Z, P.st, P.part, nullptr));
+    STK_TRY(vcycle<float>(ctx, *P32, o));
+    return prec_cast(ctx, P32->xcast, P.st, 1);
+}
+
+// Flexible CG in FP64 on the Krylov slots of plan P: X and R are set by the
 // caller and the per-instance stop thresholds are in the states; at most
 // `maxit` iterations.  its[q] = iterations during which instance q was active;
-// *loops = iterations run.
-int fcg(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o, int t, int maxit, std::vector<int>& its,
-        int* loops = nullptr) {
+// *loops = iterations run.  The V-cycle runs in FP32 when P32 is given.
+int fcg(stk_ctx* ctx, const PlanT& P, const PlanT* P32, const stk_mg_opts& o, int maxit, std::vector<int>& its,
+        int* loops) {
     std::vector<FcgState> h;
     its.assign(P.n, 0);
-    if (loops) *loops = 0;
+    *loops = 0;
     STK_TRY(read_states(ctx, P, h));
     std::vector<int> act(P.n);
     bool any = false;
@@ -519,18 +540,17 @@ int fcg(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o, int t, int maxit, st
         any = any || act[q];
     }
     if (!any) return STK_OK;
-    STK_TRY(vop(ctx, P, t, OP_ZERO_Z, false));
-    STK_TRY(run_vcycle(ctx, P, o, t));
-    STK_TRY(vop(ctx, P, t, OP_INIT_P, true));
+    STK_TRY(precondition(ctx, P, P32, o));
+    STK_TRY(vec_op<double>(ctx, P.vec, OP_INIT_P, P.st, P.part, P.sums));
     STK_TRY(fcg_scalars(ctx, P.st, P.sums, P.n, PH_INIT, 0.0));
     for (int it = 0; it < maxit; ++it) {
-        STK_TRY(apply(ctx, P, t));
-        STK_TRY(vop(ctx, P, t, OP_PQ, true));
+        STK_TRY(mg_residual<double>(ctx, P.apply));  // Q = 0 - M P = A P
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_PQ, P.st, P.part, P.sums));
         STK_TRY(fcg_scalars(ctx, P.st, P.sums, P.n, PH_ALPHA, 0.0));
-        STK_TRY(vop(ctx, P, t, OP_UPDATE, true));
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_UPDATE, P.st, P.part, P.sums));
         STK_TRY(fcg_scalars(ctx, P.st, P.sums, P.n, PH_NV, 0.0));
         STK_TRY(read_states(ctx, P, h));
-        if (loops) ++*loops;
+        ++*loops;
         any = false;
         for (int q = 0; q < P.n; ++q) {
             its[q] += act[q];
@@ -538,11 +558,10 @@ int fcg(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o, int t, int maxit, st
             any = any || act[q];
         }
         if (!any) break;
-        STK_TRY(vop(ctx, P, t, OP_ZERO_Z, false));
-        STK_TRY(run_vcycle(ctx, P, o, t));
-        STK_TRY(vop(ctx, P, t, OP_RZ_ZQ, true));
+        STK_TRY(precondition(ctx, P, P32, o));
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_RZ_ZQ, P.st, P.part, P.sums));
         STK_TRY(fcg_scalars(ctx, P.st, P.sums, P.n, PH_BETA, 0.0));
-        STK_TRY(vop(ctx, P, t, OP_XPBY, false));
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_XPBY, P.st, P.part, nullptr));
     }
     return STK_OK;
 }
@@ -568,8 +587,6 @@ void stk_mg_opts_default(stk_mg_opts* o) {
     o->nu2 = 2;
     o->omega = 0.7;
     o->coarsest = 8;
-    o->inner_tol = 1e-3;
-    o->inner_max = 60;
 }
 
 static int check_mg_opts(const stk_mg_opts& o) {
@@ -577,8 +594,6 @@ static int check_mg_opts(const stk_mg_opts& o) {
         return set_error(STK_EINVAL, "nu1, nu2 must be in [0, 64] with nu1 + nu2 >= 1");
     if (!(o.omega > 0.0 && o.omega < 2.0)) return set_error(STK_EINVAL, "omega must be in (0, 2)");
     if (o.coarsest < 2) return set_error(STK_EINVAL, "coarsest must be >= 2");
-    if (!(o.inner_tol > 0.0 && o.inner_tol < 1.0)) return set_error(STK_EINVAL, "inner_tol must be in (0, 1)");
-    if (o.inner_max < 1) return set_error(STK_EINVAL, "inner_max must be >= 1");
     return STK_OK;
 }
 
@@ -589,23 +604,18 @@ int stk_mg_footprint(const stk_grid* g, const stk_mg_opts* opts, int mode, size_
     stk_mg_opts_default(&o);
     if (opts) o = *opts;
     STK_TRY(check_mg_opts(o));
+    if (mode != STK_SOLVE_F64 && mode != STK_SOLVE_F32_REFINED) return set_error(STK_EINVAL, "unknown mode");
     size_t b = 0;
     int nx = g->nx, ny = g->ny, lvl = 0;
-    const bool f32 = mode == 1;
+    const bool f32 = mode == STK_SOLVE_F32_REFINED;
     while (true) {
-        const size_t cnt = (size_t)(ny + 1) * pad_ld(nx);
-        if (lvl == 0) {
-            b += cnt * 8 * 2;                   // eta FP64
-            if (f32) b += cnt * 4 * 2;          // eta FP32
-        } else {
-            b += cnt * 2 * NCOEF * (f32 ? 12 : 8);  // Galerkin stencil FP64 (+ FP32)
-        }
-        const int nf = (lvl == 0) ? 2 : 4;      // v, w, b, r (level 0: w, r)
-        b += cnt * (size_t)nf * 2 * (f32 ? 4 : 8);
-        if (lvl == 0) {
-            b += cnt * 2 * (f32 ? 4 : 8) * 6;   // Krylov X R Z P Q + zero
-            b += cnt * 2 * 8 * 4;               // F, B64, X64, R64
-        }
+        const size_t cnt = (size_t)(ny + 1) * (lvl == 0 ? (size_t)g->ld : (size_t)pad_ld(nx));
+        // fields of cnt words: finest = eta_c, eta_n, smoother partner w and residual r (2 components each),
+        // 7 two-component Krylov slots, 3 zero fields; FP32 extra: eta, w, r, R, Z.
+        // coarse = 2 * NCOEF stencil planes and v, w, b, r; FP32 extra: the same again.
+        const size_t w64 = lvl == 0 ? 2 + 4 + 2 * VS_N + 3 : 2 * NCOEF + 8;
+        const size_t w32 = lvl == 0 ? 2 + 4 + 4 : 2 * NCOEF + 8;
+        b += cnt * (w64 * 8 + (f32 ? w32 * 4 : 0));
         if (std::min(nx, ny) <= o.coarsest || (nx & 1) || (ny & 1)) break;
         nx /= 2;
         ny /= 2;
@@ -738,33 +748,31 @@ int stk_mg_solve_batch(stk_ctx* ctx, int n, stk_mg* const* mgs, stk_solve_mode m
     }
     STK_TRY(use_device(ctx));
     const auto t0 = std::chrono::steady_clock::now();
-    const int t = mode == STK_SOLVE_F32_REFINED ? 1 : 0;
-    PlanT* P = nullptr;
+    PlanT *P = nullptr, *P32 = nullptr;
     std::vector<stk_mg*> ms(mgs, mgs + n);
-    STK_TRY(make_plan(ctx, ms.data(), n, t, &P));
     auto cleanup = [&]() {
-        if (P) {
-            P->release();
-            delete P;
-        }
+        for (PlanT* q : {P, P32})
+            if (q) {
+                q->release();
+                delete q;
+            }
     };
     auto chk = [&](int rc) {
         if (rc != STK_OK) cleanup();
         return rc;
     };
-    // inputs: x0 -> X64, b = f - G p -> B64, f -> F (all FP64)
+    if (int rc = make_plan(ctx, ms.data(), n, 0, &P)) return chk(rc);
+    if (mode == STK_SOLVE_F32_REFINED)
+        if (int rc = make_plan(ctx, ms.data(), n, 1, &P32)) return chk(rc);
+    // inputs: x0 -> X, b = f - G p -> B, f -> F (FP64)
     for (int q = 0; q < n; ++q) {
         stk_mg* m = ms[q];
         const MgLevel& L = m->L[0];
         stk_grid g{L.nx, L.ny, L.ld, L.dx, L.dy};
-        const Field2& X = m->ks[0][VS_X64];
-        const Field2& B = m->ks[0][VS_B64];
+        const Field2& X = m->ks[0][VS_X];
+        const Field2& B = m->ks[0][VS_B];
         const Field2& F = m->ks[0][VS_F];
-        if (t == 0) {  // FP64 Krylov iterate is the solution itself
-            if (int rc = copy_vel_in(m, vx[q], vy[q], m->user_ld, m->ks[0][VS_X].x, m->ks[0][VS_X].y, L.ld, 8)) return chk(rc);
-        } else {
-            if (int rc = copy_vel_in(m, vx[q], vy[q], m->user_ld, X.x, X.y, L.ld, 8)) return chk(rc);
-        }
+        if (int rc = copy_vel_in(m, vx[q], vy[q], m->user_ld, X.x, X.y, L.ld, 8)) return chk(rc);
         if (int rc = copy_vel_in(m, fx[q], fy[q], m->user_ld, F.x, F.y, L.ld, 8)) return chk(rc);
         const void* pres = m->zero64;  // p = 0
         void* ptmp = nullptr;
@@ -786,86 +794,46 @@ int stk_mg_solve_batch(stk_ctx* ctx, int n, stk_mg* const* mgs, stk_solve_mode m
         }
         if (rcf) return chk(rcf);
     }
-    const PlanT& Pv = *P;
-    const PlanT& Po = *P;  // its vector jobs also carry the FP64 slots F, B64, X64, R64
     std::vector<FcgState> h(n);
     for (auto& s : h) {
         std::memset(&s, 0, sizeof s);
         s.active = 1;
     }
-    STK_HIP(hipMemcpyAsync(Po.st, h.data(), sizeof(FcgState) * n, hipMemcpyHostToDevice, ctx->stream));
-    if (int rc = t ? vec_op<float>(ctx, Po.vec, OP_FNORM, Po.st, Po.part, Po.sums)
-                   : vec_op<double>(ctx, Po.vec, OP_FNORM, Po.st, Po.part, Po.sums))
-        return chk(rc);
-    if (int rc = fcg_scalars(ctx, Po.st, Po.sums, n, PH_NF, tol * tol)) return chk(rc);
-    std::vector<int> outer_active(n, 1), its(n, 0), inner(n, 0);
-    int outer = 0;
-    if (t == 0) {
-        // FCG on the FP64 system; when an instance's recurrence residual reaches
-        // tol its true residual is recomputed and, if still above tol (rounding
-        // drift), CG restarts from the current iterate within the same budget.
-        int used = 0;
-        while (true) {
-            if (int rc = read_states(ctx, Po, h)) return chk(rc);
-            if (int rc = write_active(ctx, Po, h, outer_active)) return chk(rc);
-            if (int rc = vec_residual64_st(ctx, Po.vec, Po.st, Po.part, Po.sums)) return chk(rc);
-            if (int rc = fcg_scalars(ctx, Po.st, Po.sums, n, PH_NV, 0.0)) return chk(rc);
-            if (int rc = read_states(ctx, Po, h)) return chk(rc);
-            bool any = false;
-            for (int q = 0; q < n; ++q) {
-                outer_active[q] = outer_active[q] && h[q].active;
-                any = any || outer_active[q];
-            }
-            if (!any || used >= max_iters) break;
-            std::vector<int> per;
-            int loops = 0;
-            if (int rc = fcg(ctx, *P, ms[0]->o, 0, max_iters - used, per, &loops)) return chk(rc);
-            for (int q = 0; q < n; ++q) its[q] += per[q];
-            used += loops;
+    STK_HIP(hipMemcpyAsync(P->st, h.data(), sizeof(FcgState) * n, hipMemcpyHostToDevice, ctx->stream));
+    if (int rc = vec_op<double>(ctx, P->vec, OP_FNORM, P->st, P->part, P->sums)) return chk(rc);
+    if (int rc = fcg_scalars(ctx, P->st, P->sums, n, PH_NF, tol * tol)) return chk(rc);
+    // FCG; when an instance's recurrence residual reaches tol its true residual
+    // is recomputed and, if still above tol (rounding drift), CG restarts from
+    // the current iterate within the same iteration budget.
+    std::vector<int> running(n, 1), its(n, 0);
+    int used = 0;
+    while (true) {
+        if (int rc = read_states(ctx, *P, h)) return chk(rc);
+        if (int rc = write_active(ctx, *P, h, running)) return chk(rc);
+        if (int rc = vec_residual64_st(ctx, P->vec, P->st, P->part, P->sums)) return chk(rc);
+        if (int rc = fcg_scalars(ctx, P->st, P->sums, n, PH_NV, 0.0)) return chk(rc);
+        if (int rc = read_states(ctx, *P, h)) return chk(rc);
+        bool any = false;
+        for (int q = 0; q < n; ++q) {
+            running[q] = running[q] && h[q].active;
+            any = any || running[q];
         }
-    } else {
-        // refinement: outer FP64 residual, inner FP32 flexible CG
-        for (outer = 0; outer <= max_iters; ++outer) {
-            if (int rc = read_states(ctx, Po, h)) return chk(rc);
-            if (int rc = write_active(ctx, Po, h, outer_active)) return chk(rc);
-            if (int rc = fcg_scalars(ctx, Po.st, Po.sums, n, PH_THR, tol * tol)) return chk(rc);
-            if (int rc = vec_residual64_st(ctx, Po.vec, Po.st, Po.part, Po.sums)) return chk(rc);
-            if (int rc = fcg_scalars(ctx, Po.st, Po.sums, n, PH_NV, 0.0)) return chk(rc);
-            if (int rc = read_states(ctx, Po, h)) return chk(rc);
-            bool any = false;
-            for (int q = 0; q < n; ++q) {
-                if (outer_active[q]) {
-                    outer_active[q] = h[q].active;
-                    its[q] = outer;
-                }
-                any = any || outer_active[q];
-            }
-            if (!any || outer == max_iters) break;
-            // inner system: R = (float) R64, X = 0, relative threshold inner_tol^2 * nv0
-            if (int rc = vec_cast_st(ctx, Pv.vec, Pv.st, VS_R64, VS_R, 1)) return chk(rc);
-            if (int rc = vec_op<float>(ctx, Pv.vec, OP_ZERO_X, Pv.st, Pv.part, nullptr)) return chk(rc);
-            if (int rc = vec_op<float>(ctx, Pv.vec, OP_RNORM, Pv.st, Pv.part, Pv.sums)) return chk(rc);
-            const double itol = ms[0]->o.inner_tol;
-            if (int rc = fcg_scalars(ctx, Pv.st, Pv.sums, n, PH_NV0, itol * itol)) return chk(rc);
-            std::vector<int> per;
-            if (int rc = fcg(ctx, Pv, ms[0]->o, 1, ms[0]->o.inner_max, per)) return chk(rc);
-            for (int q = 0; q < n; ++q) inner[q] += per[q];
-            // X64 += X for the instances still refining
-            if (int rc = read_states(ctx, Po, h)) return chk(rc);
-            if (int rc = write_active(ctx, Po, h, outer_active)) return chk(rc);
-            if (int rc = vec_add_x64_st(ctx, Pv.vec, Pv.st)) return chk(rc);
-        }
+        if (!any || used >= max_iters) break;
+        std::vector<int> per;
+        int loops = 0;
+        if (int rc = fcg(ctx, *P, P32, ms[0]->o, max_iters - used, per, &loops)) return chk(rc);
+        for (int q = 0; q < n; ++q) its[q] += per[q];
+        used += loops;
     }
     // final true FP64 residual of every instance
     for (auto& s : h) s.active = 1;
-    STK_HIP(hipMemcpyAsync(Po.st, h.data(), sizeof(FcgState) * n, hipMemcpyHostToDevice, ctx->stream));
-    if (int rc = vec_residual64_st(ctx, Po.vec, Po.st, Po.part, Po.sums)) return chk(rc);
+    STK_HIP(hipMemcpyAsync(P->st, h.data(), sizeof(FcgState) * n, hipMemcpyHostToDevice, ctx->stream));
+    if (int rc = vec_residual64_st(ctx, P->vec, P->st, P->part, P->sums)) return chk(rc);
     std::vector<double> sums(2 * (size_t)n);
-    STK_HIP(hipMemcpyAsync(sums.data(), Po.sums, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, ctx->stream));
-    // results out
+    STK_HIP(hipMemcpyAsync(sums.data(), P->sums, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, ctx->stream));
     for (int q = 0; q < n; ++q) {
         stk_mg* m = ms[q];
-        const Field2& X = t ? m->ks[0][VS_X64] : m->ks[0][VS_X];
+        const Field2& X = m->ks[0][VS_X];
         if (int rc = copy_vel_in(m, X.x, X.y, m->L[0].ld, vx[q], vy[q], m->user_ld, 8)) return chk(rc);
     }
     STK_HIP(hipStreamSynchronize(ctx->stream));
@@ -875,7 +843,6 @@ int stk_mg_solve_batch(stk_ctx* ctx, int n, stk_mg* const* mgs, stk_solve_mode m
         const double evt = std::sqrt(sums[2 * q] / h[q].nf);
         if (reps) {
             reps[q].iterations = its[q];
-            reps[q].inner_iterations = t ? inner[q] : its[q];
             reps[q].ev = evt;
             reps[q].nf = h[q].nf;
             reps[q].seconds = secs;

@@ -42,11 +42,11 @@ struct CoarseJob {
     T *vx, *vy;
 };
 
-// Krylov vectors of one instance on its finest level.
-// X, R, Z, P, Q: Krylov iterate / residual / preconditioned residual /
-// direction / A p, in the Krylov dtype.  F, B64, X64, R64: FP64 force, folded
-// right-hand side, solution and true residual (refinement).
-enum { VS_X = 0, VS_R, VS_Z, VS_P, VS_Q, VS_F, VS_B64, VS_X64, VS_R64, VS_N };
+// Krylov vectors of one instance on its finest level (FP64): X, R, Z, P, Q =
+// iterate / residual b - M x / preconditioned residual / direction / A p;
+// F = force (for N_f), B = folded right-hand side f - G p.  The FP32 V-cycle
+// of the mixed-precision mode uses FP32 R and Z slots of its own.
+enum { VS_X = 0, VS_R, VS_Z, VS_P, VS_Q, VS_F, VS_B, VS_N };
 struct VecJob {
     int nx, ny;
     int64_t ld;
@@ -65,7 +65,6 @@ struct FcgState {
     double rz;      // rho . z
     double zq;      // z . q
     double nv;      // sum r^2 / d  (current residual, velocity energy)
-    double nv0;     // nv at the start of the current (inner) solve
     double nf;      // sum f^2 / d
     double thr;     // stop when nv <= thr
     int active;     // 1 while this instance iterates
@@ -110,26 +109,33 @@ enum VecOp {
     OP_UPDATE,      // x += alpha p; r += alpha q; acc0 += r^2/d
     OP_RZ_ZQ,       // acc0 += r.z ; acc1 += z.q  (rho = -r: gamma = -acc0)
     OP_XPBY,        // p = z + beta p
-    OP_RNORM,       // acc0 += r^2/d
     OP_FNORM,       // acc0 += f^2/d
     OP_INIT_P,      // p = z; acc0 += r.z
-    OP_ZERO_Z,      // z = 0
-    OP_ZERO_X       // x = 0
+    OP_ZERO_Z       // z = 0
 };
 // phases of fcg_scalars
-enum { PH_NF = 0, PH_NV, PH_NV0, PH_INIT, PH_ALPHA, PH_BETA, PH_THR };
-// Slot dtype T for the Krylov vectors (R, Z, P, Q, X); partial sums land in
+enum { PH_NF = 0, PH_NV, PH_INIT, PH_ALPHA, PH_BETA };
+// Slot dtype T for the slots touched (R, Z, P, Q, X); partial sums land in
 // `part` (2 per block), then per-instance sums in `sums` (2 per instance).
 template <typename T>
 int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* part, double* sums);
-// cast slot src -> dst (to_f32: FP64 -> float, else float -> FP64), active instances only
-int vec_cast_st(stk_ctx* ctx, const Batch& b, const FcgState* st, int src, int dst, int to_f32);
-int vec_add_x64_st(stk_ctx* ctx, const Batch& b, const FcgState* st);  // X64 += (double) X (float)
-// R64 = B64 - M X64 (FP64); sums[2i] = sum R64^2 / d
+// R = B - M X in FP64; sums[2i] = sum R^2 / d
 int vec_residual64_st(stk_ctx* ctx, const Batch& b, const FcgState* st, double* part, double* sums);
 // Per-instance scalar update from the reduced sums (one thread per instance);
-// `factor` scales the stop threshold (tol^2 for PH_NF, inner_tol^2 for PH_NV0).
+// `factor` scales the stop threshold (tol^2 for PH_NF).
 int fcg_scalars(stk_ctx* ctx, FcgState* st, const double* sums, int n, int phase, double factor);
+
+// Precision casts around the FP32 V-cycle preconditioner (active instances):
+// down: r32 = (float) r64; up: z64 = (double) z32.
+struct XCastJob {
+    int nx, ny;
+    int64_t ld;
+    const double* r64[2];
+    float* r32[2];
+    const float* z32[2];
+    double* z64[2];
+};
+int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st, int up);
 int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums);
 template <typename T> int mg_copy_wv(stk_ctx* ctx, const Batch& b);
 

@@ -364,9 +364,6 @@ __global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, con
                 case OP_XPBY:
                     P[k] = u ? T((double)Z[k] + be * (double)P[k]) : T(0);
                     break;
-                case OP_RNORM:
-                    if (u) a0 += (double)R[k] * (double)R[k] / (c == 0 ? dgx(J, i, j) : dgy(J, i, j));
-                    break;
                 case OP_FNORM: {
                     const double* F = static_cast<const double*>(J.v[VS_F][c]);
                     if (u) a0 += F[k] * F[k] / (c == 0 ? dgx(J, i, j) : dgy(J, i, j));
@@ -376,11 +373,8 @@ __global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, con
                     P[k] = u ? Z[k] : T(0);
                     if (u) a0 += (double)R[k] * (double)Z[k];
                     break;
-                case OP_ZERO_Z:
+                default:  // OP_ZERO_Z
                     Z[k] = T(0);
-                    break;
-                default:  // OP_ZERO_X
-                    X[k] = T(0);
                     break;
             }
         }
@@ -388,35 +382,22 @@ __global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, con
     block_sum2(a0, a1, part);
 }
 
-// slot src (FP64) -> slot dst (float), or src (float) -> dst (FP64)
-__global__ __launch_bounds__(NT) void k_vec_cast(const VecJob* __restrict__ jobs, const int* __restrict__ pre, int n,
-                                                 const FcgState* __restrict__ st, int src, int dst, int to_f32) {
+// r32 = (float) r64 (up = 0) or z64 = (double) z32 (up = 1), walls included
+__global__ __launch_bounds__(NT) void k_prec_cast(const XCastJob* __restrict__ jobs, const int* __restrict__ pre,
+                                                  int n, const FcgState* __restrict__ st, int up) {
     STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
     if (i > J.nx || j > J.ny || !st[inst].active) return;
     const int64_t k = (int64_t)j * J.ld + i;
     for (int c = 0; c < 2; ++c) {
         if (c == 0 ? j >= J.ny : i >= J.nx) continue;
-        if (to_f32)
-            static_cast<float*>(J.v[dst][c])[k] = (float)static_cast<const double*>(J.v[src][c])[k];
+        if (up)
+            J.z64[c][k] = (double)J.z32[c][k];
         else
-            static_cast<double*>(J.v[dst][c])[k] = (double)static_cast<const float*>(J.v[src][c])[k];
+            J.r32[c][k] = (float)J.r64[c][k];
     }
 }
 
-// X64 += (double) X  (X = the FP32 correction of the refinement step)
-__global__ __launch_bounds__(NT) void k_vec_add_x64(const VecJob* __restrict__ jobs, const int* __restrict__ pre,
-                                                    int n, const FcgState* __restrict__ st) {
-    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
-    if (i > J.nx || j > J.ny || !st[inst].active) return;
-    const int64_t k = (int64_t)j * J.ld + i;
-    for (int c = 0; c < 2; ++c) {
-        if (c == 0 ? j >= J.ny : i >= J.nx) continue;
-        double* x = static_cast<double*>(J.v[VS_X64][c]);
-        x[k] = x[k] + (double)static_cast<const float*>(J.v[VS_X][c])[k];
-    }
-}
-
-// R64 = B64 - M X64 in FP64 with sum R64^2 / d
+// R = B - M X in FP64 with sum R^2 / d
 __global__ __launch_bounds__(NT) void k_vec_res64(const VecJob* __restrict__ jobs, const int* __restrict__ pre, int n,
                                                   const FcgState* __restrict__ st, double* __restrict__ part) {
     STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
@@ -424,8 +405,8 @@ __global__ __launch_bounds__(NT) void k_vec_res64(const VecJob* __restrict__ job
     if (i <= J.nx && j <= J.ny && st[inst].active) {
         const int nx = J.nx, ny = J.ny;
         const int64_t ld = J.ld, k = (int64_t)j * ld + i;
-        const double* vx = static_cast<const double*>(J.v[VS_X64][0]);
-        const double* vy = static_cast<const double*>(J.v[VS_X64][1]);
+        const double* vx = static_cast<const double*>(J.v[VS_X][0]);
+        const double* vy = static_cast<const double*>(J.v[VS_X][1]);
         auto VX = [&](int a, int b) { return ldvx<double>(vx, ld, nx, ny, a, b); };
         auto VY = [&](int a, int b) { return ldvy<double>(vy, ld, nx, ny, a, b); };
         auto ENH = [&](int a, int b) { return (a >= 1 && a <= nx - 1 && b >= 1 && b <= ny - 1) ? J.en[(int64_t)b * ld + a] : 0.0; };
@@ -435,10 +416,10 @@ __global__ __launch_bounds__(NT) void k_vec_res64(const VecJob* __restrict__ job
                 const double m = mv_x<double>(VX(i, j), VX(i - 1, j), VX(i + 1, j), VX(i, j - 1), VX(i, j + 1), VY(i, j),
                                               VY(i - 1, j), VY(i, j + 1), VY(i - 1, j + 1), J.ec[k - 1], J.ec[k],
                                               ENH(i, j), ENH(i, j + 1), J.idx, J.idy);
-                r = static_cast<const double*>(J.v[VS_B64][0])[k] - m;
+                r = static_cast<const double*>(J.v[VS_B][0])[k] - m;
                 a0 += r * r / dgx(J, i, j);
             }
-            static_cast<double*>(J.v[VS_R64][0])[k] = r;
+            static_cast<double*>(J.v[VS_R][0])[k] = r;
         }
         if (i < nx) {
             double r = 0.0;
@@ -446,10 +427,10 @@ __global__ __launch_bounds__(NT) void k_vec_res64(const VecJob* __restrict__ job
                 const double m = mv_y<double>(VY(i, j), VY(i - 1, j), VY(i + 1, j), VY(i, j - 1), VY(i, j + 1), VX(i, j),
                                               VX(i + 1, j), VX(i, j - 1), VX(i + 1, j - 1), J.ec[k - ld], J.ec[k],
                                               ENH(i, j), ENH(i + 1, j), J.idx, J.idy);
-                r = static_cast<const double*>(J.v[VS_B64][1])[k] - m;
+                r = static_cast<const double*>(J.v[VS_B][1])[k] - m;
                 a0 += r * r / dgy(J, i, j);
             }
-            static_cast<double*>(J.v[VS_R64][1])[k] = r;
+            static_cast<double*>(J.v[VS_R][1])[k] = r;
         }
     }
     block_sum2(a0, 0.0, part);
@@ -491,12 +472,6 @@ __global__ void k_fcg_scalars(FcgState* __restrict__ st, const double* __restric
             s.nf = s0;
             s.thr = factor * s0;
             break;
-        case PH_NV0:  // start of an inner solve: relative threshold
-            s.nv = s0;
-            s.nv0 = s0;
-            s.thr = factor * s0;
-            s.active = s.active && s0 > s.thr;
-            break;
         case PH_NV:
             if (s.active) {
                 s.nv = s0;
@@ -511,9 +486,6 @@ __global__ void k_fcg_scalars(FcgState* __restrict__ st, const double* __restric
                 s.pq = s0;
                 s.alpha = (s0 != 0.0) ? s.gamma / s0 : 0.0;
             }
-            break;
-        case PH_THR:  // outer threshold from the stored N_f
-            s.thr = factor * s.nf;
             break;
         default: {  // PH_BETA: rho = -r, gamma' = rho.z, beta = -alpha (z.q) / gamma
             if (s.active) {
@@ -625,17 +597,10 @@ int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums) {
     return STK_OK;
 }
 
-int vec_cast_st(stk_ctx* ctx, const Batch& b, const FcgState* st, int src, int dst, int to_f32) {
+int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st, int up) {
     if (!b.n) return STK_OK;
-    hipLaunchKernelGGL(k_vec_cast, dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const VecJob*>(b.jobs), b.pre,
-                       b.n, st, src, dst, to_f32);
-    STK_LAUNCH_CHECK();
-    return STK_OK;
-}
-int vec_add_x64_st(stk_ctx* ctx, const Batch& b, const FcgState* st) {
-    if (!b.n) return STK_OK;
-    hipLaunchKernelGGL(k_vec_add_x64, dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const VecJob*>(b.jobs),
-                       b.pre, b.n, st);
+    hipLaunchKernelGGL(k_prec_cast, dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const XCastJob*>(b.jobs),
+                       b.pre, b.n, st, up);
     STK_LAUNCH_CHECK();
     return STK_OK;
 }

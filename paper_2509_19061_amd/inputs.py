@@ -41,9 +41,15 @@ class Problem:
 
 
 def _inside(x, y, sinkers):
-    m = np.zeros(np.broadcast(x, y).shape, dtype=bool)
+    """Mask (len(y), len(x)) of the points (x[i], y[j]) inside any circle,
+    evaluated on each circle's bounding box only."""
+    m = np.zeros((len(y), len(x)), dtype=bool)
     for (cx, cy, r) in sinkers:
-        m |= (x - cx) ** 2 + (y - cy) ** 2 <= r * r
+        i0, i1 = np.searchsorted(x, cx - r, "left"), np.searchsorted(x, cx + r, "right")
+        j0, j1 = np.searchsorted(y, cy - r, "left"), np.searchsorted(y, cy + r, "right")
+        if i0 >= i1 or j0 >= j1:
+            continue
+        m[j0:j1, i0:i1] |= (x[None, i0:i1] - cx) ** 2 + (y[j0:j1, None] - cy) ** 2 <= r * r
     return m
 
 
@@ -72,14 +78,12 @@ def sinker_problem(nx: int, ny: int, sinkers, eta_in: float, eta_out,
     dx, dy = 1.0 / nx, 1.0 / ny
     xc = (np.arange(nx) + 0.5) * dx
     yc = (np.arange(ny) + 0.5) * dy
-    X, Y = np.meshgrid(xc, yc)
-    ins = _inside(X, Y, sinkers)
+    ins = _inside(xc, yc, sinkers)
     bg = np.broadcast_to(np.asarray(eta_out, dtype=np.float64), (ny, nx))
     eta_c = np.where(ins, eta_in, bg).astype(np.float64)
     eta_n = nodal_harmonic(eta_c)
     # density sampled at the vy points ((i+1/2)dx, j dy)
-    Xv, Yv = np.meshgrid(xc, np.arange(ny + 1) * dy)
-    rho = np.where(_inside(Xv, Yv, sinkers), rho_in, rho_out)
+    rho = np.where(_inside(xc, np.arange(ny + 1) * dy, sinkers), rho_in, rho_out)
     fy = (rho * g).astype(np.float64)
     fx = np.zeros((ny, nx + 1))
     return Problem(nx, ny, dx, dy, eta_c, eta_n, fx, fy, dict(meta or {}))
@@ -111,16 +115,39 @@ def smoother_workload(n: int = 4096, seed: int = 2) -> Problem:
     return random_sinkers(n, 8, seed)
 
 
+def smooth_log_uniform_field(n: int, seed: int, lo: float = -2.0, hi: float = 4.0, kmax: int = 8,
+                             modes: int = 64) -> np.ndarray:
+    """(n, n) cell field with log10 values spread uniformly over [lo, hi] and
+    spatially smooth: a Gaussian random field of unit variance (``modes`` plane
+    waves, integer wavenumbers |k| <= kmax, random phases; correlation length
+    ~ 1/kmax of the domain) mapped through the normal CDF to U(0, 1), then to
+    [lo, hi].  Written as one rank-2*modes product so that 8192^2 takes seconds."""
+    from scipy.special import ndtr
+    rng = np.random.default_rng(seed)
+    k = rng.integers(-kmax, kmax + 1, size=(modes, 2))
+    k[(k == 0).all(axis=1)] = (1, 0)
+    ph = rng.uniform(0.0, 2.0 * np.pi, modes)
+    x = (np.arange(n) + 0.5) / n
+    a = 2.0 * np.pi * np.outer(x, k[:, 0])            # (n, modes): x phase
+    b = 2.0 * np.pi * np.outer(x, k[:, 1]) + ph       # (n, modes): y phase
+    # cos(a + b) = cos b cos a - sin b sin a, summed over modes: rows y, columns x
+    U = np.concatenate([np.cos(b), -np.sin(b)], axis=1)
+    V = np.concatenate([np.cos(a), np.sin(a)], axis=1)
+    g = (U @ V.T) * np.sqrt(2.0 / modes)
+    return 10.0 ** (lo + (hi - lo) * ndtr(g))
+
+
 def lognormal_background_workload(n: int = 8192, seed: int = 4, count: int = 16) -> Problem:
-    """16 sinkers of eta 1e6 over an i.i.d. per-cell background
-    log10(eta) ~ U(-2, 4) (multigrid / refinement workload)."""
+    """16 sinkers of eta 1e6 over a smooth background whose log10(eta) is
+    uniform on [-2, 4] (``smooth_log_uniform_field``): the multigrid /
+    refinement workload, viscosity contrast up to 1e8."""
     rng = np.random.default_rng(seed)
     c = rng.uniform(0.1, 0.9, size=(count, 2))
     r = rng.uniform(0.02, 0.08, size=count)
-    bg = 10.0 ** rng.uniform(-2.0, 4.0, size=(n, n))
+    bg = smooth_log_uniform_field(n, seed)
     sinkers = [(float(c[k, 0]), float(c[k, 1]), float(r[k])) for k in range(count)]
     return sinker_problem(n, n, sinkers, 1e6, bg,
-                          meta=dict(workload="lognormal_background", n=n, count=count, seed=seed))
+                          meta=dict(workload="log_uniform_background", n=n, count=count, seed=seed))
 
 
 def instance_problem(n: int, rng: np.random.Generator) -> Problem:

@@ -136,17 +136,25 @@ def test_solve_recovers_known_discrete_solution(ctx, mode):
 
 @pytest.mark.parametrize("contrast", [1e2, 1e6])
 def test_refined_solve_reaches_tolerance_and_matches_fp64_oracle(ctx, contrast):
+    """The FP32 V-cycle inside the FP64 iteration reaches the same FP64 energy
+    residual as the FP64 mode.  Its iteration count stays within 2x of the FP64
+    mode's: FP32 rounding of stencil sums whose terms are ~contrast times the
+    result weakens the preconditioner at high contrast (96 -> 140 here at 1e6)."""
     p = sinkers(128, 96, 11, contrast)
     levels = OM.hierarchy(p, coarsest=8)
     ox, oy, hist = OM.pcg(levels, p.fx, p.fy, tol=1e-12, max_iters=2000)
     m, dp = gpu_mg(ctx, p)
-    vx, vy = dp.velocity()
-    rep = m.solve("f32_refined", vx, vy, None, dp.fx, dp.fy, tol=1e-8, max_iters=50)
-    assert rep["converged"] and rep["ev"] <= 1e-8 and rep["iterations"] >= 1
-    gx, gy = dp.get_vx(vx), dp.get_vy(vy)
+    runs = {}
+    for mode in ("f64", "f32_refined"):
+        vx, vy = dp.velocity()
+        rep = m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=1e-8, max_iters=500)
+        assert rep["converged"] and rep["ev"] <= 1e-8 and rep["iterations"] >= 1
+        runs[mode] = (dp.get_vx(vx), dp.get_vy(vy), rep)
+    gx, gy, rep = runs["f32_refined"]
     assert S.energy(p, gx, gy, p.fx, p.fy)[4] <= 1.01e-8
     err = max(normwise(gx, ox), normwise(gy, oy))
     assert err <= 1e-5, err
+    assert rep["iterations"] <= 2 * runs["f64"][2]["iterations"] + 5, (rep, runs["f64"][2])
 
 
 @pytest.mark.parametrize("mode", ["f64", "f32_refined"])
@@ -224,4 +232,14 @@ def test_mg_errors(ctx):
     with pytest.raises(api.StkError) as e:
         m.solve("f64", vx, vy, None, dq.fx, dq.fy, tol=1e-12, max_iters=2)
     assert e.value.code == api.ENOTCONV
-    assert api.mg_footprint(dq.grid, "f32_refined") > 0
+
+
+def test_footprint_covers_what_a_solve_holds(ctx):
+    from paper_2509_19061_amd import api
+    q = sinkers(192, 128, 32, 1e3)
+    m, dq = gpu_mg(ctx, q)
+    for mode in ("f64", "f32_refined"):
+        vx, vy = dq.velocity()
+        m.solve(mode, vx, vy, None, dq.fx, dq.fy, tol=1e-6, max_iters=200)
+        held, fp = m.info()["bytes"], api.mg_footprint(dq.grid, mode)
+        assert held <= fp <= 1.05 * held, (mode, held, fp)
