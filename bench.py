@@ -4,7 +4,7 @@
 Workload: 4096 x 4096 cells, 8 seeded sinkers (eta 1e6 inside, 1 outside,
 harmonic nodal eta, rho 1.1 / 1.0), FP64, v = 0 start, p = 0.
 Step: 100 sweeps of RAS-Jacobi (tile 64 x 64, halo = k = 4, shift stream
-seed 3) through stk_smooth, followed by the energy norm (Sec. 5.4).
+seed 3) through stk_smooth, followed by the energy norm (Sec. 6.4).
 Value: GLUP/s = cells x sweeps / step time (HIP events on the stream).
 
 Also reported: every smoother variant at 100 sweeps (Jacobi split, fused,
@@ -27,6 +27,11 @@ multigrid solves:
     one launch per (level, kernel) across all of them, both modes.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+For profiling, ``--kernel-only L`` runs just L launches of the RAS
+outer-iteration kernel on the 4096^2 workload, followed by two copies of a
+512 MiB buffer (the calibration kernel for the HBM byte counters), and prints
+one JSON line with their timings.
 """
 import argparse
 import json
@@ -38,6 +43,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch of the streaming RAS kernel (4096^2, FP64, T = 64,
+# k = h = 4) from rocprofv3 FETCH_SIZE / WRITE_SIZE, each scaled by what the
+# counter reads for a copy of known size (profiles/k_ras_stream_4096_f64_k4.md).
+# Valid only for the kernel sources it was measured on: reported as null once
+# their hash differs.
+RAS_TRAFFIC = {"sources_sha256_16": "7df1ad38a9f32f40", "bytes_per_launch": 1.502e9, "n": 4096, "k": 4, "dtype": "f64"}
+
+
+def ras_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ras_stream.hip", "stencil.hpp"):
+        with open(os.path.join(ROOT, "paper_2509_19061_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -59,6 +80,7 @@ def main():
     ap.add_argument("--solve-n", type=int, default=2048, help="refinement workload size (0: skip)")
     ap.add_argument("--rate-n", type=int, default=8192, help="per-iteration cost size (0: skip)")
     ap.add_argument("--batch", default="default", help="'default' (64-instance mix), 'small' or 'none'")
+    ap.add_argument("--kernel-only", type=int, default=0, help="profiling mode: L RAS launches + copy calibration")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -76,6 +98,9 @@ def main():
     wbytes = 8 if dt == torch.float64 else 4
     n, sweeps, k = args.n, args.sweeps, args.k
     cells = n * n
+
+    if args.kernel_only:
+        return kernel_only(args)
 
     t0 = time.time()
     prob = inputs.smoother_workload(n, 2)
@@ -185,6 +210,9 @@ def main():
         log(f"[bench] CPU oracle: {cpu_glups:.3f} GLUP/s on {cpu['cores']} threads ({el:.1f} s)")
 
     del vx, vy, ax, ay, cx, cy
+    t_ok = (kernel_name == "k_ras_stream" and RAS_TRAFFIC["sources_sha256_16"] == ras_sources_hash()
+            and (n, k, args.dtype) == (RAS_TRAFFIC["n"], RAS_TRAFFIC["k"], RAS_TRAFFIC["dtype"]))
+    traffic = RAS_TRAFFIC["bytes_per_launch"] if t_ok else None
     solve = run_solves(ctx, args.solve_n) if args.solve_n > 0 else None
     rate = run_iteration_cost(ctx, args.rate_n) if args.rate_n > 0 else None
     batch = run_batch(ctx, args.batch) if args.batch != "none" else None
@@ -206,7 +234,9 @@ def main():
                                f"nodal eta), tile 64x64, halo=k={k}, {sweeps} sweeps + energy norm per step",
                    "n": n, "sweeps": sweeps, "k": k, "tile": 64, "halo": k},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
+                     "traffic_over_algorithmic": round(traffic / alg_bytes, 3) if traffic else None,
                      "kernel": f"{kernel_name} (one RAS outer iteration, k={k} sweeps, per launch)",
                      "launch_ms": round(launch_ms, 4), "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
@@ -219,6 +249,41 @@ def main():
     print(json.dumps(out), flush=True)
     if kctx is not ctx:
         kctx.close()
+    ctx.close()
+
+
+def kernel_only(args):
+    """L launches of the RAS outer-iteration kernel, then the copy calibration."""
+    import torch
+
+    from paper_2509_19061_amd import api, fields, inputs
+
+    dt = torch.float64 if args.dtype == "f64" else torch.float32
+    n, k = args.n, args.k
+    prob = inputs.smoother_workload(n, 2)
+    os.environ["STK_RAS_KERNEL"] = "stream"
+    ctx = api.Context(0)
+    del os.environ["STK_RAS_KERNEL"]
+    dp = fields.DeviceProblem(prob, dt)
+    (ax, ay), (cx, cy) = dp.velocity(), dp.velocity()
+    shifts = api.ras_shifts(3, args.kernel_only, 64, 64)
+
+    def launches():
+        for t in range(args.kernel_only):
+            src, dst = ((ax, ay), (cx, cy)) if t % 2 == 0 else ((cx, cy), (ax, ay))
+            api.ras_outer(ctx, dt, dp.grid, *src, dp.eta_c, dp.eta_n, dp.fx, dp.fy, *dst, 0.7, 64, 64, k, k,
+                          *shifts[t])
+
+    _, secs = _timed(launches)
+    copy_bytes = 512 << 20
+    a = torch.ones(copy_bytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    _, csecs = _timed(lambda: (b.copy_(a), a.copy_(b)))
+    out = {"kernel": "k_ras_stream", "n": n, "k": k, "launches": args.kernel_only,
+           "ms_per_launch": round(secs * 1e3 / args.kernel_only, 4),
+           "alg_bytes_per_launch": 8 * (8 if dt == torch.float64 else 4) * n * n,
+           "copy_bytes_each_way": copy_bytes, "copy_ms_per_launch": round(csecs * 1e3 / 2, 4)}
+    print(json.dumps(out), flush=True)
     ctx.close()
 
 

@@ -10,7 +10,8 @@
  *   Sec. 3.2  inexact Uzawa with a matrix-free geometric multigrid velocity
  *             solve whose smoothing dominates the cost,
  *   Sec. 4    loop fusion, spatial blocking, RAS-type temporal blocking (Alg. 2),
- *   Sec. 5    the five smoothers and the energy residual norms (Sec. 5.4).
+ *   Sec. 5    the five smoothers,
+ *   Sec. 6.4  the energy residual norms.
  *
  * ---------------------------------------------------------------------------
  * Conventions shared by every call
@@ -162,14 +163,14 @@ int stk_ras_outer(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx,
 
 /* rx, ry <- r_v = b - M v on the unknowns (0 on walls); rp (nullable) <-
  * r_p = -D v per cell, (Dv) = (vx(i+1,j)-vx(i,j))/dx + (vy(i,j+1)-vy(i,j))/dy
- * (Sec. 5.4).  With fx = fy = 0 and p = NULL this is -M v.  Output arrays use
+ * (Sec. 6.4).  With fx = fy = 0 and p = NULL this is -M v.  Output arrays use
  * the same layout and dtype as the inputs and must not alias them.
  * Asynchronous. */
 int stk_residual(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* p,
                  const void* eta_c, const void* eta_n, const void* fx, const void* fy, void* rx, void* ry,
                  void* rp);
 
-/* Energy residual norms of Sec. 5.4, accumulated in FP64 for both dtypes:
+/* Energy residual norms of Sec. 6.4, accumulated in FP64 for both dtypes:
  *   out[0] N_v = sum over unknowns r_v^2 / diag(-M)
  *   out[1] N_p = sum over cells r_p^2 eta_c / (2/dx^2 + 2/dy^2)
  *   out[2] N_f = sum over unknowns f^2 / diag(-M)
@@ -186,7 +187,7 @@ int stk_energy_norm(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* v
 
 /* Geometric multigrid for the velocity block (Sec. 3.2: the velocity update
  * of the inexact Uzawa scheme is solved approximately with a matrix-free
- * geometric multigrid whose smoothing dominates the cost; Sec. 5.2 runs one
+ * geometric multigrid whose smoothing dominates the cost; Sec. 6.2 runs one
  * V-cycle per Uzawa cycle).  The paper gives no transfer operators; this
  * library coarsens by 2 in x and y while min(nx, ny) > coarsest and both are
  * even, prolongs bilinearly per component (linear across faces, 3/4-1/4 along
@@ -244,7 +245,7 @@ int stk_mg_footprint(const stk_grid* g, const stk_mg_opts* opts, int mode, size_
 int stk_mg_vcycle(stk_mg* mg, stk_dtype dt, void* vx, void* vy, const void* bx, const void* by);
 
 /* Solve M v = f - G p to the velocity energy residual E_v = sqrt(N_v / N_f)
- * <= tol (Sec. 5.4), starting from (vx, vy) (device FP64, in/out).  p may be
+ * <= tol (Sec. 6.4), starting from (vx, vy) (device FP64, in/out).  p may be
  * NULL.  At most max_iters Krylov iterations.  When the recurrence residual
  * reaches tol the true FP64 residual is recomputed, and the iteration restarts
  * from the current iterate if it is still above tol.  STK_ENOTCONV if the

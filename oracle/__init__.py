@@ -2,7 +2,7 @@
 
 A plain, slow, obviously-correct FP64 reference for the staggered-grid
 variable-viscosity Stokes velocity smoothers (paper Sec. 2.1, Sec. 3, Sec. 4,
-Alg. 2, Sec. 5.4).  Only the tests, the smoke check and the benchmark's CPU
+Alg. 2, Sec. 6.4).  Only the tests, the smoke check and the benchmark's CPU
 baseline may import it; the HIP library never does, and the two share no
 code.  See ``stokes_oracle.c`` for the discrete operator it defines.
 

@@ -1,7 +1,7 @@
 """FP64 geometric multigrid V-cycle and Krylov solve (test infrastructure).
 
 The paper solves the velocity block M v = f - G p with a matrix-free
-geometric multigrid whose smoothing dominates the cost (Sec. 3.2, Sec. 5.2);
+geometric multigrid whose smoothing dominates the cost (Sec. 3.2, Sec. 6.2);
 it does not print the transfer operators, the coarse operators or the
 coarsest-grid solver.  This oracle takes the following reading:
 
@@ -19,7 +19,7 @@ coarsest-grid solver.  This oracle takes the following reading:
     post-smooth;
   * solve: V-cycle-preconditioned flexible conjugate gradients on the SPD
     system -M v = -b, stopping on the velocity energy residual
-    E_v = sqrt(N_v/N_f) <= tol (Sec. 5.4).  The paper's own accelerator is
+    E_v = sqrt(N_v/N_f) <= tol (Sec. 6.4).  The paper's own accelerator is
     Anderson acceleration (Sec. 3.3 / Alg. 1), of the same Krylov family.
 
 Internally level l works on packed unknown vectors with A_l = -M_l (SPD).
@@ -96,7 +96,7 @@ def _masked_energy(rx, ry, dxg, dyg):
 def pcg(levels, fx, fy, p=None, tol=1e-8, max_iters=500, nu1=2, nu2=2, omega=0.7, x0=None):
     """Flexible conjugate gradients on A x = -b (A = -M SPD, b = f - G p),
     preconditioned by one V-cycle per iteration, in FP64.  Stops when the
-    velocity energy residual E_v = sqrt(N_v / N_f) of Sec. 5.4 is <= tol.
+    velocity energy residual E_v = sqrt(N_v / N_f) of Sec. 6.4 is <= tol.
     When the recurrence residual reaches tol, the true residual b - M x is
     recomputed; if it is still above tol (rounding drift at high viscosity
     contrast) CG restarts from x with it, within the same iteration budget.

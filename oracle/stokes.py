@@ -152,7 +152,7 @@ def ras_outer(g, bx, by, omega, tile_x, tile_y, halo, kt, sx_, sy_, vx, vy):
 
 
 def energy(g, vx, vy, fx, fy, p=None):
-    """(N_v, N_p, N_f, E, E_v) of Sec. 5.4 (see stokes_oracle.c)."""
+    """(N_v, N_p, N_f, E, E_v) of Sec. 6.4 (see stokes_oracle.c)."""
     sx, sy = _shapes(g)
     vx, vy, fx, fy = _f(vx, sx), _f(vy, sy), _f(fx, sx), _f(fy, sy)
     pp = None if p is None else _f(p, (g.ny, g.nx))

@@ -27,7 +27,7 @@
  * right-hand side for fixed p is b = f - G p with
  *   (Gp)_x(i,j) = -(p(i,j)-p(i-1,j))/dx,  (Gp)_y(i,j) = -(p(i,j)-p(i,j-1))/dy,
  *   (Dv)(i,j)   = (vx(i+1,j)-vx(i,j))/dx + (vy(i,j+1)-vy(i,j))/dy.
- * M is symmetric negative definite (Sec. 5.4); d = diag(-M) > 0.
+ * M is symmetric negative definite (Sec. 6.4); d = diag(-M) > 0.
  */
 #include <math.h>
 #include <omp.h>
@@ -348,7 +348,7 @@ void or_ras(int nx, int ny, double dx, double dy, const double* ec, const double
 
 /* ---------------------------------------------------------- energy norm -- */
 
-/* Energy-norm pieces of Sec. 5.4 for the velocity state (vx, vy) and pressure
+/* Energy-norm pieces of Sec. 6.4 for the velocity state (vx, vy) and pressure
  * p (NULL = 0):
  *   r_v = b - M v  with b = f - G p,  r_p = -D v,
  *   out[0] = N_v = sum over unknowns r_v^2 / d           (||r_v||^2 in diag(-M)^-1)
@@ -409,7 +409,7 @@ void or_energy(int nx, int ny, double dx, double dy, const double* ec, const dou
 
 /* ------------------------------------------------------------ multigrid -- */
 /* The paper uses a matrix-free geometric multigrid for the velocity block
- * (Sec. 3.2, Sec. 5.2) but does not give its transfer operators; the oracle
+ * (Sec. 3.2, Sec. 6.2) but does not give its transfer operators; the oracle
  * follows this reading: coarsening by 2 in both directions, coarse cell (I,J)
  * = fine cells {2I,2I+1} x {2J,2J+1}; bilinear prolongation per component
  * (linear between coarse faces normal to the face, weights 3/4, 1/4 between

@@ -1,10 +1,10 @@
 // Setup of the Galerkin coarse operators A_c = P^T A P / 4 (A = -M) as stored
 // 31-coefficient stencils, one level from the next finer one.
 //
-// The paper's multigrid (Sec. 3.2, Sec. 5.2) leaves the coarse operators
+// The paper's multigrid (Sec. 3.2, Sec. 6.2) leaves the coarse operators
 // unspecified.  Rediscretised coarse operators (averaged coarse viscosities)
 // lose convergence at the viscosity contrasts of the sinker workloads
-// (Sec. 5.1, contrast up to 1e8); the Galerkin product keeps the coarse
+// (Sec. 6.1, contrast up to 1e8); the Galerkin product keeps the coarse
 // correction an A-orthogonal projection at any contrast.
 //
 // One thread per coarse (I, J) builds the rows of vx(I, J) and vy(I, J):

@@ -3,7 +3,7 @@
 // and in FP32 with FP64 iterative refinement.
 //
 // The paper solves the velocity block with a matrix-free geometric multigrid
-// (Sec. 3.2, Sec. 5.2) and accelerates its fixed-point iteration with
+// (Sec. 3.2, Sec. 6.2) and accelerates its fixed-point iteration with
 // Anderson acceleration (Sec. 3.3, Alg. 1).  Here the V-cycle is used as the
 // preconditioner of flexible conjugate gradients on the SPD system -M v = -b,
 // always in FP64 (residual, operator, dot products, energy norms, coarsest

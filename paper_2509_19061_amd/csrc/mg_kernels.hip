@@ -1,7 +1,7 @@
 // Multigrid and Krylov kernels for gfx950, batched over independent
 // instances (one launch per (level, kernel) serves every instance).
 //
-// Geometric multigrid for the velocity block (paper Sec. 3.2, Sec. 5.2); the
+// Geometric multigrid for the velocity block (paper Sec. 3.2, Sec. 6.2); the
 // paper does not print the transfers, so these follow the stated reading:
 // coarsening by 2, bilinear prolongation per velocity component (linear
 // between coarse faces along the face normal, weights 3/4 and 1/4 between

@@ -1,4 +1,4 @@
-// Residual and energy-norm kernels (paper Sec. 5.4).
+// Residual and energy-norm kernels (paper Sec. 6.4).
 //
 // residual: r_v = b - M v on the velocity unknowns, r_p = -D v per cell.
 // energy:   per-workgroup FP64 partial sums of N_v = sum r_v^2/d,

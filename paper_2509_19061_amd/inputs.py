@@ -12,7 +12,7 @@ Grid convention (paper Sec. 2.1, staggered grid of Fig. 1; unit square, y up):
   * vy(i, j) at ((i+1/2)dx, j dy): array shape (ny+1, nx);
   * density rho lives with vy (Fig. 1 caption), so fy has the vy shape.
 
-Problem family: the sinker benchmark of Sec. 5.1 (stiff, dense circular
+Problem family: the sinker benchmark of Sec. 6.1 (stiff, dense circular
 inclusions in a weaker medium, gravity pointing down), made non-dimensional.
 Right-hand side: with y up and gravity (0, -|g|), the momentum balance
 div(sigma') - grad p + rho g = 0 gives f = -rho g, i.e. fx = 0, fy = +rho|g|.
@@ -90,7 +90,7 @@ def sinker_problem(nx: int, ny: int, sinkers, eta_in: float, eta_out,
 
 
 # --------------------------------------------------------------------------
-# The workloads (non-dimensional sinker family, Sec. 5.1 / Sec. 6.1 shapes)
+# The workloads (non-dimensional sinker family, Sec. 6.1 / Sec. 7.1 shapes)
 # --------------------------------------------------------------------------
 
 def centred_sinker(n: int = 64) -> Problem:

@@ -1,6 +1,6 @@
 """Pins of the oracle's multigrid pieces (no GPU).
 
-The paper gives no transfer or coarse operators (Sec. 3.2, Sec. 5.2); the
+The paper gives no transfer or coarse operators (Sec. 3.2, Sec. 6.2); the
 oracle's reading is pinned by: exactness of the bilinear prolongation on
 linear fields, R = P^T/4 as an adjoint pair, the sparse P / A agreeing with
 the C stencil and transfers, second-order consistency of the Galerkin coarse

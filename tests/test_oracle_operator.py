@@ -3,7 +3,7 @@
 The paper prints no worked numbers, so the oracle is pinned by what the
 mathematics fixes: a manufactured solution (continuum operator from sympy,
 second-order consistency), a closed-form discrete eigenmode, an independent
-assembly A = B^T W B from the energy form, symmetry/definiteness (Sec. 5.4:
+assembly A = B^T W B from the energy form, symmetry/definiteness (Sec. 6.4:
 M symmetric negative definite), G = D^T, and hydrostatic balance.
 """
 from types import SimpleNamespace
@@ -140,7 +140,7 @@ def test_stencil_equals_assembled_BtWB(nx, ny, dx, dy, seed):
 
 
 def test_symmetric_negative_definite():
-    """Sec. 5.4: M is symmetric negative definite under these BCs."""
+    """Sec. 6.4: M is symmetric negative definite under these BCs."""
     g = rand_grid(37, 29, 5, lo=-2, hi=4)
     u = rand_v(37, 29, 6)
     v = rand_v(37, 29, 7)
@@ -172,7 +172,7 @@ def test_gradient_is_divergence_transpose():
 
 def test_hydrostatic_pressure_balances_gravity():
     """Constant density rho, gravity -y, fy = rho |g|: the lithostatic
-    pressure p = -rho y (Sec. 5.2, integral of rho g) gives b = f - G p = 0."""
+    pressure p = -rho y (Sec. 6.2, integral of rho g) gives b = f - G p = 0."""
     nx, ny, rho = 10, 12, 1.3
     g = rand_grid(nx, ny, 12)
     yc = (np.arange(ny) + 0.5) / ny

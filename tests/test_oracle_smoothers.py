@@ -4,7 +4,7 @@ Jacobi and red-black Gauss-Seidel are checked against textbook dense-matrix
 iterations on the independently assembled A = B^T W B; RAS-type temporal
 blocking (Alg. 2, snapshot semantics) against Jacobi^k where the overlap makes
 them identical and against a dense per-tile subdomain formulation where it
-does not; the energy norm (Sec. 5.4) against its exact special cases.
+does not; the energy norm (Sec. 6.4) against its exact special cases.
 """
 from types import SimpleNamespace
 
@@ -120,7 +120,7 @@ def test_ras_rectangular_tiles_and_partial_last_outer():
 # ----------------------------------------------------------- energy norm --
 
 def test_energy_norm_of_zero_state_is_one():
-    """v = 0, p = 0: r_v = f, r_p = 0, so E = E_v = 1 exactly (Sec. 5.4)."""
+    """v = 0, p = 0: r_v = f, r_p = 0, so E = E_v = 1 exactly (Sec. 6.4)."""
     p = I.random_sinkers(48, 3, 1, eta_in=1e4)
     out = S.energy(p, *p.zeros_v(), p.fx, p.fy)
     assert out[1] == 0.0 and out[0] == out[2] and out[3] == 1.0 and out[4] == 1.0
@@ -171,7 +171,7 @@ def test_energy_pressure_part_zero_for_divergence_free_mode():
 
 def test_centred_sinker_mirror_symmetry():
     """The centred sinker is symmetric about x = 1/2: vx is odd, vy even
-    (Sec. 5.1: the inclusion sinks vertically with a symmetric flow)."""
+    (Sec. 6.1: the inclusion sinks vertically with a symmetric flow)."""
     p = I.centred_sinker(64)
     bx, by = S.rhs(p, p.fx, p.fy)
     vx, vy = p.zeros_v()
@@ -187,7 +187,7 @@ def test_centred_sinker_mirror_symmetry():
 
 
 def test_sinker_sinks_with_two_vortices():
-    """Solved flow: vy < 0 through the dense inclusion (gravity -y, Sec. 5.1),
+    """Solved flow: vy < 0 through the dense inclusion (gravity -y, Sec. 6.1),
     and vx changes sign across the inclusion (two counter-rotating cells)."""
     p = I.centred_sinker(32)
     levels = mg.hierarchy(p, coarsest=8)
