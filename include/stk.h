@@ -254,14 +254,46 @@ int stk_mg_vcycle(stk_mg* mg, stk_dtype dt, void* vx, void* vy, const void* bx, 
 int stk_mg_solve(stk_mg* mg, stk_solve_mode mode, double* vx, double* vy, const double* p, const double* fx,
                  const double* fy, double tol, int max_iters, stk_report* rep);
 
-/* The same for n independent instances (distinct handles on one context):
- * every level kernel is ONE launch across all instances (work-list of
- * (instance, block)); instances stop individually; one host synchronisation
- * per iteration reads all convergence flags.  Arrays of n pointers; p may be
- * NULL or hold NULL entries; reps may be NULL. */
+/* The same for n independent instances (distinct handles on one context,
+ * equal nu1, nu2, omega): every level kernel is ONE launch across all
+ * instances (work-list of (instance, block)); instances stop individually;
+ * one host synchronisation per iteration reads all convergence flags.  Arrays
+ * of n pointers; p may be NULL or hold NULL entries; reps may be NULL.  Each
+ * instance's arithmetic is independent of the others: its result is the same
+ * bit for bit alone and in any mix. */
 int stk_mg_solve_batch(stk_ctx* ctx, int n, stk_mg* const* mgs, stk_solve_mode mode, double* const* vx,
                        double* const* vy, const double* const* p, const double* const* fx, const double* const* fy,
                        double tol, int max_iters, stk_report* reps);
+
+/* ------------------------------------------------ continuous batching -- */
+
+/* A batch of in-flight solves that instances join and leave at any time
+ * (the engine of stk_mg_solve_batch and of a serving loop).  Each step
+ * advances every in-flight solve together, one launch per (level, kernel)
+ * across all of them, and hands back the solves that finished.  Results are
+ * those of stk_mg_solve, bit for bit, whatever else shares the batch.  A batch
+ * is used from one host thread; its handles must not be destroyed while they
+ * are in it. */
+typedef struct stk_batch stk_batch;
+
+int stk_batch_create(stk_ctx* ctx, stk_solve_mode mode, int max_slots, stk_batch** out);
+/* Abandons solves still in flight (their handles become free again). */
+int stk_batch_destroy(stk_batch* b);
+/* Admit a solve of M v = f - G p (arguments as for stk_mg_solve, device FP64,
+ * caller-owned; vx, vy are read now and written when the solve finishes, p,
+ * fx, fy are read now).  *slot receives its slot id.  STK_EINVAL if no slot is
+ * free, the handle is already in a batch, or its nu1, nu2, omega differ from
+ * the batch's.  Asynchronous except for pressure staging. */
+int stk_batch_add(stk_batch* b, stk_mg* mg, double* vx, double* vy, const double* p, const double* fx,
+                  const double* fy, double tol, int max_iters, int* slot);
+/* Advance every in-flight solve by up to `iters` Krylov iterations.  On
+ * return done[0..*ndone) are the slots whose solves finished during the step
+ * (converged, or out of iterations: see reps[k].converged; seconds = time
+ * since admission), their solutions already in the caller's arrays, and those
+ * slots are free again.  done and reps need room for max_slots entries. */
+int stk_batch_step(stk_batch* b, int iters, int* done, stk_report* reps, int* ndone);
+/* Number of solves in flight. */
+int stk_batch_count(const stk_batch* b, int* in_flight);
 
 #ifdef __cplusplus
 }

@@ -75,6 +75,11 @@ _SIGS = {
     "stk_mg_solve": ([_P, _I, _P, _P, _P, _P, _P, C.c_double, _I, C.POINTER(Report)], _I),
     "stk_mg_solve_batch": ([_P, _I, C.POINTER(_P), _I, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P),
                             C.POINTER(_P), C.c_double, _I, C.POINTER(Report)], _I),
+    "stk_batch_create": ([_P, _I, _I, C.POINTER(_P)], _I),
+    "stk_batch_destroy": ([_P], _I),
+    "stk_batch_add": ([_P, _P, _P, _P, _P, _P, _P, C.c_double, _I, C.POINTER(_I)], _I),
+    "stk_batch_step": ([_P, _I, C.POINTER(_I), C.POINTER(Report), C.POINTER(_I)], _I),
+    "stk_batch_count": ([_P, C.POINTER(_I)], _I),
 }
 
 

@@ -21,7 +21,7 @@ from ._lib import (EHIP, EINVAL, ENOMEM, ENONFINITE, ENOTCONV, EUNSUPPORTED, F32
 __all__ = ["Context", "Grid", "SmoothOpts", "StkError", "smooth", "ras_outer", "residual", "energy_norm", "ras_shifts",
            "smooth_opts", "F64", "F32", "JACOBI", "JACOBI_FUSED", "RAS_JACOBI", "RBGS", "VARIANTS", "OK", "EINVAL",
            "ENOMEM", "EHIP", "ENOTCONV", "ENONFINITE", "EUNSUPPORTED", "dtype_code", "torch_dtype", "MG", "mg_opts",
-           "mg_footprint", "mg_solve_batch", "SOLVE_F64", "SOLVE_F32_REFINED", "MODES"]
+           "mg_footprint", "mg_solve_batch", "SOLVE_F64", "SOLVE_F32_REFINED", "MODES", "Batch"]
 
 MODES = {"f64": SOLVE_F64, "f32_refined": SOLVE_F32_REFINED}
 
@@ -79,6 +79,7 @@ class Context:
         self.device = device
         self.handle = C.c_void_p()
         self._mgs = weakref.WeakSet()
+        self._batches = weakref.WeakSet()
         s = stream if stream is not None else torch.cuda.current_stream(device)
         sp = s.cuda_stream if hasattr(s, "cuda_stream") else s
         check(L.lib.stk_ctx_create(C.byref(self.handle), device, C.c_void_p(sp)))
@@ -97,6 +98,8 @@ class Context:
         return n.value
 
     def close(self):
+        for b in list(self._batches):
+            b.close()
         for m in list(self._mgs):
             m.close()
         if self.handle:
@@ -225,7 +228,7 @@ class MG:
 
     def close(self):
         if self.handle:
-            L.lib.stk_mg_destroy(self.handle)
+            check(L.lib.stk_mg_destroy(self.handle))  # EINVAL while the handle is in a batch
             self.handle = C.c_void_p()
 
     def __del__(self, _finalizing=sys.is_finalizing):
@@ -249,3 +252,60 @@ def mg_solve_batch(ctx, mgs, mode, vx, vy, p, fx, fy, tol=1e-8, max_iters=500, a
     if not (allow_notconv and rc == ENOTCONV):
         check(rc)
     return [_report(r) for r in reps]
+
+
+class Batch:
+    """stk_batch: continuous batching of solves (instances join and leave between steps).
+
+    ``add`` admits a solve and returns its slot; ``step`` advances every solve in
+    flight by up to ``iters`` Krylov iterations and returns ``[(slot, report)]``
+    for those that finished (their solutions are then in the arrays given to
+    ``add``).  The tensors of a solve are kept alive here until it finishes."""
+
+    def __init__(self, ctx, mode, max_slots):
+        if not ctx.handle:
+            raise ValueError("context is closed")
+        self.ctx = ctx
+        self.max_slots = int(max_slots)
+        self.handle = C.c_void_p()
+        check(L.lib.stk_batch_create(ctx.handle, _mode(mode), self.max_slots, C.byref(self.handle)))
+        self._keep = {}
+        self._done = (C.c_int * self.max_slots)()
+        self._reps = (Report * self.max_slots)()
+        ctx._batches.add(self)
+
+    def add(self, mg, vx, vy, p, fx, fy, tol=1e-8, max_iters=500):
+        slot = C.c_int()
+        check(L.lib.stk_batch_add(self.handle, mg.handle, _ptr(vx, F64), _ptr(vy, F64), _ptr(p, F64),
+                                  _ptr(fx, F64), _ptr(fy, F64), float(tol), int(max_iters), C.byref(slot)))
+        self._keep[slot.value] = (mg, vx, vy, p, fx, fy)
+        return slot.value
+
+    def step(self, iters=1):
+        nd = C.c_int()
+        check(L.lib.stk_batch_step(self.handle, int(iters), self._done, self._reps, C.byref(nd)))
+        out = []
+        for k in range(nd.value):
+            s = self._done[k]
+            self._keep.pop(s, None)
+            out.append((s, _report(self._reps[k])))
+        return out
+
+    def count(self):
+        n = C.c_int()
+        check(L.lib.stk_batch_count(self.handle, C.byref(n)))
+        return n.value
+
+    def close(self):
+        if self.handle:
+            L.lib.stk_batch_destroy(self.handle)
+            self.handle = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -17,77 +17,13 @@
 #include <vector>
 
 #include "coarse_stencil.hpp"
-#include "mg_internal.hpp"
-
-namespace stk {
-namespace {
-
-struct Field2 {
-    void* x = nullptr;
-    void* y = nullptr;
-};
-
-struct MgLevel {
-    int nx = 0, ny = 0;
-    int64_t ld = 0;
-    double dx = 0, dy = 0;
-    double* ec64 = nullptr;  // viscosities (finest level only)
-    double* en64 = nullptr;
-    float* ec32 = nullptr;
-    float* en32 = nullptr;
-    double* st64 = nullptr;  // Galerkin stencil, 2 * NCOEF planes (coarse levels only)
-    float* st32 = nullptr;
-    int64_t plane = 0;
-    Field2 v[2], w[2], b[2], r[2];  // [0] FP64, [1] FP32; level 0 binds v, b to the Krylov Z, R slots
-};
-
-int64_t pad_ld(int nx) { return ((int64_t)nx + 1 + 63) / 64 * 64; }
-
-}  // namespace
-}  // namespace stk
+#include "mg_host.hpp"
 
 using namespace stk;
 
-struct PlanT {  // one dtype, a fixed list of instances
-    int n = 0, depth = 0, maxcn = 0;
-    std::vector<Batch> fine, crs;       // per depth: fine-block and coarse-block batches of LevelJob
-    std::vector<const void*> cjobs;     // per depth: CoarseJob array of instances whose coarsest it is
-    std::vector<int> ncj;
-    Batch apply;                        // finest: v = P, b = 0, r = Q  ->  Q = A P
-    Batch vec;                          // VecJob array
-    Batch xcast;                        // XCastJob array (FP32 plan only)
-    FcgState* st = nullptr;
-    double* part = nullptr;
-    double* sums = nullptr;
-    std::vector<void*> mem;
-    std::vector<std::vector<unsigned char>> stage;  // host sources of pending uploads
-    void release() {
-        for (void* p : mem) (void)hipFree(p);
-        mem.clear();
-    }
-};
-
-struct stk_mg {
-    stk_ctx* ctx = nullptr;
-    stk_mg_opts o{};
-    std::vector<MgLevel> L;
-    int64_t user_ld = 0;
-    int cn = 0;
-    int* cmap = nullptr;
-    double* cainv = nullptr;
-    Field2 ks[2][VS_N];   // finest-level slots: row 0 FP64 (all), row 1 FP32 (R, Z only)
-    Field2 zero[2];       // zero right-hand side for the operator apply
-    void* zero64 = nullptr;  // FP64 zeros (pressure of a p = 0 fold)
-    bool have[2] = {false, false};
-    std::vector<void*> mem;
-    size_t bytes = 0;
-    PlanT* plan[2] = {nullptr, nullptr};  // single-instance plans
-};
-
 namespace stk {
-namespace {
 
-int dalloc(stk_mg* m, size_t bytes, void** out) {
+static int dalloc(stk_mg* m, size_t bytes, void** out) {
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) return set_error(STK_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
@@ -97,7 +33,7 @@ int dalloc(stk_mg* m, size_t bytes, void** out) {
     *out = p;
     return STK_OK;
 }
-int pdalloc(PlanT* P, size_t bytes, void** out, hipStream_t s) {
+static int pdalloc(PlanT* P, size_t bytes, void** out, hipStream_t s) {
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) return set_error(STK_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
@@ -107,7 +43,7 @@ int pdalloc(PlanT* P, size_t bytes, void** out, hipStream_t s) {
     return STK_OK;
 }
 template <typename V>
-int upload(PlanT* P, const std::vector<V>& h, const void** out, hipStream_t s) {
+static int upload(PlanT* P, const std::vector<V>& h, const void** out, hipStream_t s) {
     void* d = nullptr;
     STK_TRY(pdalloc(P, std::max<size_t>(1, h.size()) * sizeof(V), &d, s));
     if (!h.empty()) {  // the host copy stays alive until the plan's final synchronisation
@@ -119,8 +55,8 @@ int upload(PlanT* P, const std::vector<V>& h, const void** out, hipStream_t s) {
     return STK_OK;
 }
 
-size_t level_field_bytes(const MgLevel& l, int t) { return (size_t)(l.ny + 1) * l.ld * (t ? 4 : 8); }
-int blocks_of(int nx, int ny) { return ((nx + 1 + 63) / 64) * ((ny + 1 + 3) / 4); }
+static size_t level_field_bytes(const MgLevel& l, int t) { return (size_t)(l.ny + 1) * l.ld * (t ? 4 : 8); }
+static int blocks_of(int nx, int ny) { return ((nx + 1 + 63) / 64) * ((ny + 1 + 3) / 4); }
 
 // ---- host operator for the coarsest level (same discretisation as the device stencil)
 struct HostGrid {
@@ -131,7 +67,7 @@ struct HostGrid {
     double enh(int i, int j) const { return (i >= 1 && i <= nx - 1 && j >= 1 && j <= ny - 1) ? en[(int64_t)j * ld + i] : 0.0; }
 };
 // (-M v) at every unknown, v given as vx, vy on the level layout
-void host_apply_neg(const HostGrid& g, const std::vector<double>& vx, const std::vector<double>& vy,
+static void host_apply_neg(const HostGrid& g, const std::vector<double>& vx, const std::vector<double>& vy,
                     std::vector<double>& ax, std::vector<double>& ay) {
     auto VX = [&](int i, int j) { return (i >= 1 && i <= g.nx - 1 && j >= 0 && j < g.ny) ? vx[(int64_t)j * g.ld + i] : 0.0; };
     auto VY = [&](int i, int j) { return (j >= 1 && j <= g.ny - 1 && i >= 0 && i < g.nx) ? vy[(int64_t)j * g.ld + i] : 0.0; };
@@ -159,7 +95,7 @@ void host_apply_neg(const HostGrid& g, const std::vector<double>& vx, const std:
 // Assemble A = -M on the coarsest level, invert it (Cholesky, A SPD) and
 // upload.  The coarsest level is the finest one (viscous stencil from the
 // viscosities) when the grid is too small to coarsen, else a Galerkin level.
-int build_coarse(stk_mg* m) {
+static int build_coarse(stk_mg* m) {
     MgLevel& l = m->L.back();
     const size_t cnt = (size_t)(l.ny + 1) * l.ld;
     const bool stored = l.st64 != nullptr;
@@ -256,7 +192,7 @@ int build_coarse(stk_mg* m) {
 }
 
 // FP32 copies of the viscosities and all per-dtype buffers
-__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, size_t n) {
+static __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, size_t n) {
     const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (q < n) b[q] = (float)a[q];
 }
@@ -311,7 +247,7 @@ int ensure_dtype(stk_mg* m, int t) {
 }
 
 template <typename T>
-LevelJob<T> level_job(const stk_mg* m, size_t l, int t) {
+static LevelJob<T> level_job(const stk_mg* m, size_t l, int t) {
     const MgLevel& L = m->L[l];
     LevelJob<T> J{};
     J.nx = L.nx;
@@ -345,7 +281,7 @@ LevelJob<T> level_job(const stk_mg* m, size_t l, int t) {
 }
 
 template <typename T>
-int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) {
+static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) {
     hipStream_t s = ctx->stream;
     P->n = n;
     int maxl = 0;
@@ -468,13 +404,13 @@ int make_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT** out) {
 
 // ---- the batched V-cycle on the level-0 binding (v = Z slot, b = R slot)
 template <typename T>
-int smooth_stage(stk_ctx* ctx, const Batch& F, const stk_mg_opts& o, int nu) {
+static int smooth_stage(stk_ctx* ctx, const Batch& F, const stk_mg_opts& o, int nu) {
     for (int q = 0; q < nu; ++q) STK_TRY(mg_jacobi<T>(ctx, F, o.omega, q & 1));
     if (nu & 1) STK_TRY(mg_copy_wv<T>(ctx, F));
     return STK_OK;
 }
 template <typename T>
-int vcycle(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o) {
+static int vcycle(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o) {
     STK_TRY(mg_coarse<T>(ctx, P.cjobs[0], P.ncj[0], P.maxcn));
     for (int d = 0; d < P.depth; ++d) {
         const Batch& F = P.fine[d];
@@ -504,66 +440,16 @@ int read_states(stk_ctx* ctx, const PlanT& P, std::vector<FcgState>& h) {
     STK_HIP(hipStreamSynchronize(ctx->stream));
     return STK_OK;
 }
-int write_active(stk_ctx* ctx, const PlanT& P, std::vector<FcgState>& h, const std::vector<int>& act) {
-    for (int q = 0; q < P.n; ++q) h[q].active = act[q];
+int write_states(stk_ctx* ctx, const PlanT& P, const std::vector<FcgState>& h) {
     STK_HIP(hipMemcpyAsync(P.st, h.data(), sizeof(FcgState) * P.n, hipMemcpyHostToDevice, ctx->stream));
     return STK_OK;
 }
 
-// One application of the preconditioner to every active instance:
-// Z = V-cycle(R) from zero, in FP64 (P32 == nullptr) or in FP32 between casts.
-int precondition(stk_ctx* ctx, const PlanT& P, const PlanT* P32, const stk_mg_opts& o) {
-    if (!P32) {
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_ZERO_Z, P.st, P.part, nullptr));
-        return vcycle<double>(ctx, P, o);
-    }
-    STK_TRY(prec_cast(ctx, P32->xcast, P.st, 0));
-    STK_TRY(vec_op<float>(ctx, P32->vec, OP_ZERO_Z, P.st, P.part, nullptr));
-    STK_TRY(vcycle<float>(ctx, *P32, o));
-    return prec_cast(ctx, P32->xcast, P.st, 1);
-}
-
-// Flexible CG in FP64 on the Krylov slots of plan P: X and R are set by the
-// caller and the per-instance stop thresholds are in the states; at most
-// `maxit` iterations.  its[q] = iterations during which instance q was active;
-// *loops = iterations run.  The V-cycle runs in FP32 when P32 is given.
-int fcg(stk_ctx* ctx, const PlanT& P, const PlanT* P32, const stk_mg_opts& o, int maxit, std::vector<int>& its,
-        int* loops) {
-    std::vector<FcgState> h;
-    its.assign(P.n, 0);
-    *loops = 0;
-    STK_TRY(read_states(ctx, P, h));
-    std::vector<int> act(P.n);
-    bool any = false;
-    for (int q = 0; q < P.n; ++q) {
-        act[q] = h[q].active;
-        any = any || act[q];
-    }
-    if (!any) return STK_OK;
-    STK_TRY(precondition(ctx, P, P32, o));
-    STK_TRY(vec_op<double>(ctx, P.vec, OP_INIT_P, P.st, P.part, P.sums));
-    STK_TRY(fcg_scalars(ctx, P.st, P.sums, P.n, PH_INIT, 0.0));
-    for (int it = 0; it < maxit; ++it) {
-        STK_TRY(mg_residual<double>(ctx, P.apply));  // Q = 0 - M P = A P
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_PQ, P.st, P.part, P.sums));
-        STK_TRY(fcg_scalars(ctx, P.st, P.sums, P.n, PH_ALPHA, 0.0));
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_UPDATE, P.st, P.part, P.sums));
-        STK_TRY(fcg_scalars(ctx, P.st, P.sums, P.n, PH_NV, 0.0));
-        STK_TRY(read_states(ctx, P, h));
-        ++*loops;
-        any = false;
-        for (int q = 0; q < P.n; ++q) {
-            its[q] += act[q];
-            act[q] = h[q].active;
-            any = any || act[q];
-        }
-        if (!any) break;
-        STK_TRY(precondition(ctx, P, P32, o));
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_RZ_ZQ, P.st, P.part, P.sums));
-        STK_TRY(fcg_scalars(ctx, P.st, P.sums, P.n, PH_BETA, 0.0));
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_XPBY, P.st, P.part, nullptr));
-    }
-    return STK_OK;
+void free_plan(PlanT*& P) {
+    if (!P) return;
+    P->release();
+    delete P;
+    P = nullptr;
 }
 
 int copy_vel_in(stk_mg* m, const void* sx, const void* sy, int64_t sld, void* dx, void* dy, int64_t dld, size_t es) {
@@ -575,7 +461,6 @@ int copy_vel_in(stk_mg* m, const void* sx, const void* sy, int64_t sld, void* dx
     return STK_OK;
 }
 
-}  // namespace
 }  // namespace stk
 
 // ============================================================== C ABI ====
@@ -696,6 +581,7 @@ int stk_mg_create(stk_ctx* ctx, stk_mg** out, const stk_grid* g, const double* e
 
 int stk_mg_destroy(stk_mg* m) {
     if (!m) return STK_OK;
+    if (m->busy) return set_error(STK_EINVAL, "mg handle is solving in a batch: destroy the batch first");
     (void)hipSetDevice(m->ctx->device);
     (void)hipStreamSynchronize(m->ctx->stream);
     for (int t = 0; t < 2; ++t)
@@ -732,133 +618,6 @@ int stk_mg_vcycle(stk_mg* m, stk_dtype dt, void* vx, void* vy, const void* bx, c
     STK_TRY(run_vcycle(ctx, *m->plan[t], m->o, t));
     STK_TRY(copy_vel_in(m, m->ks[t][VS_Z].x, m->ks[t][VS_Z].y, ld0, vx, vy, m->user_ld, es));
     return STK_OK;
-}
-
-int stk_mg_solve_batch(stk_ctx* ctx, int n, stk_mg* const* mgs, stk_solve_mode mode, double* const* vx,
-                       double* const* vy, const double* const* p, const double* const* fx, const double* const* fy,
-                       double tol, int max_iters, stk_report* reps) {
-    if (!ctx || n < 1 || !mgs || !vx || !vy || !fx || !fy) return set_error(STK_EINVAL, "bad batch arguments");
-    if (mode != STK_SOLVE_F64 && mode != STK_SOLVE_F32_REFINED) return set_error(STK_EINVAL, "unknown mode");
-    if (!(tol > 0.0) || max_iters < 0) return set_error(STK_EINVAL, "tol must be > 0 and max_iters >= 0");
-    for (int q = 0; q < n; ++q) {
-        if (!mgs[q] || mgs[q]->ctx != ctx) return set_error(STK_EINVAL, "instance %d: mg NULL or on another context", q);
-        if (!vx[q] || !vy[q] || !fx[q] || !fy[q]) return set_error(STK_EINVAL, "instance %d: NULL field", q);
-        for (int r = 0; r < q; ++r)
-            if (mgs[r] == mgs[q]) return set_error(STK_EINVAL, "instance %d repeats an mg handle", q);
-    }
-    STK_TRY(use_device(ctx));
-    const auto t0 = std::chrono::steady_clock::now();
-    PlanT *P = nullptr, *P32 = nullptr;
-    std::vector<stk_mg*> ms(mgs, mgs + n);
-    auto cleanup = [&]() {
-        for (PlanT* q : {P, P32})
-            if (q) {
-                q->release();
-                delete q;
-            }
-    };
-    auto chk = [&](int rc) {
-        if (rc != STK_OK) cleanup();
-        return rc;
-    };
-    if (int rc = make_plan(ctx, ms.data(), n, 0, &P)) return chk(rc);
-    if (mode == STK_SOLVE_F32_REFINED)
-        if (int rc = make_plan(ctx, ms.data(), n, 1, &P32)) return chk(rc);
-    // inputs: x0 -> X, b = f - G p -> B, f -> F (FP64)
-    for (int q = 0; q < n; ++q) {
-        stk_mg* m = ms[q];
-        const MgLevel& L = m->L[0];
-        stk_grid g{L.nx, L.ny, L.ld, L.dx, L.dy};
-        const Field2& X = m->ks[0][VS_X];
-        const Field2& B = m->ks[0][VS_B];
-        const Field2& F = m->ks[0][VS_F];
-        if (int rc = copy_vel_in(m, vx[q], vy[q], m->user_ld, X.x, X.y, L.ld, 8)) return chk(rc);
-        if (int rc = copy_vel_in(m, fx[q], fy[q], m->user_ld, F.x, F.y, L.ld, 8)) return chk(rc);
-        const void* pres = m->zero64;  // p = 0
-        void* ptmp = nullptr;
-        if (p && p[q]) {  // the caller's pressure, restrided to the mg layout
-            hipError_t e = hipMalloc(&ptmp, (size_t)L.ny * L.ld * 8);
-            if (e != hipSuccess) return chk(set_error(STK_ENOMEM, "pressure staging: %s", hipGetErrorString(e)));
-            e = hipMemcpy2DAsync(ptmp, L.ld * 8, p[q], m->user_ld * 8, (size_t)L.nx * 8, L.ny, hipMemcpyDeviceToDevice,
-                                 ctx->stream);
-            if (e != hipSuccess) {
-                (void)hipFree(ptmp);
-                return chk(hip_fail(e, "copy p"));
-            }
-            pres = ptmp;
-        }
-        const int rcf = launch_fold_rhs(ctx, STK_F64, &g, F.x, F.y, pres, B.x, B.y);
-        if (ptmp) {
-            (void)hipStreamSynchronize(ctx->stream);
-            (void)hipFree(ptmp);
-        }
-        if (rcf) return chk(rcf);
-    }
-    std::vector<FcgState> h(n);
-    for (auto& s : h) {
-        std::memset(&s, 0, sizeof s);
-        s.active = 1;
-    }
-    STK_HIP(hipMemcpyAsync(P->st, h.data(), sizeof(FcgState) * n, hipMemcpyHostToDevice, ctx->stream));
-    if (int rc = vec_op<double>(ctx, P->vec, OP_FNORM, P->st, P->part, P->sums)) return chk(rc);
-    if (int rc = fcg_scalars(ctx, P->st, P->sums, n, PH_NF, tol * tol)) return chk(rc);
-    // FCG; when an instance's recurrence residual reaches tol its true residual
-    // is recomputed and, if still above tol (rounding drift), CG restarts from
-    // the current iterate within the same iteration budget.
-    std::vector<int> running(n, 1), its(n, 0);
-    int used = 0;
-    while (true) {
-        if (int rc = read_states(ctx, *P, h)) return chk(rc);
-        if (int rc = write_active(ctx, *P, h, running)) return chk(rc);
-        if (int rc = vec_residual64_st(ctx, P->vec, P->st, P->part, P->sums)) return chk(rc);
-        if (int rc = fcg_scalars(ctx, P->st, P->sums, n, PH_NV, 0.0)) return chk(rc);
-        if (int rc = read_states(ctx, *P, h)) return chk(rc);
-        bool any = false;
-        for (int q = 0; q < n; ++q) {
-            running[q] = running[q] && h[q].active;
-            any = any || running[q];
-        }
-        if (!any || used >= max_iters) break;
-        std::vector<int> per;
-        int loops = 0;
-        if (int rc = fcg(ctx, *P, P32, ms[0]->o, max_iters - used, per, &loops)) return chk(rc);
-        for (int q = 0; q < n; ++q) its[q] += per[q];
-        used += loops;
-    }
-    // final true FP64 residual of every instance
-    for (auto& s : h) s.active = 1;
-    STK_HIP(hipMemcpyAsync(P->st, h.data(), sizeof(FcgState) * n, hipMemcpyHostToDevice, ctx->stream));
-    if (int rc = vec_residual64_st(ctx, P->vec, P->st, P->part, P->sums)) return chk(rc);
-    std::vector<double> sums(2 * (size_t)n);
-    STK_HIP(hipMemcpyAsync(sums.data(), P->sums, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, ctx->stream));
-    for (int q = 0; q < n; ++q) {
-        stk_mg* m = ms[q];
-        const Field2& X = m->ks[0][VS_X];
-        if (int rc = copy_vel_in(m, X.x, X.y, m->L[0].ld, vx[q], vy[q], m->user_ld, 8)) return chk(rc);
-    }
-    STK_HIP(hipStreamSynchronize(ctx->stream));
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    int rc_all = STK_OK;
-    for (int q = 0; q < n; ++q) {
-        const double evt = std::sqrt(sums[2 * q] / h[q].nf);
-        if (reps) {
-            reps[q].iterations = its[q];
-            reps[q].ev = evt;
-            reps[q].nf = h[q].nf;
-            reps[q].seconds = secs;
-            reps[q].converged = std::isfinite(evt) && evt <= tol;
-        }
-        if (!std::isfinite(evt)) rc_all = set_error(STK_ENONFINITE, "instance %d: residual not finite", q);
-        else if (evt > tol && rc_all == STK_OK) rc_all = set_error(STK_ENOTCONV, "instance %d: E_v = %.3e > tol", q, evt);
-    }
-    cleanup();
-    return rc_all;
-}
-
-int stk_mg_solve(stk_mg* m, stk_solve_mode mode, double* vx, double* vy, const double* p, const double* fx,
-                 const double* fy, double tol, int max_iters, stk_report* rep) {
-    if (!m) return set_error(STK_EINVAL, "mg is NULL");
-    return stk_mg_solve_batch(m->ctx, 1, &m, mode, &vx, &vy, p ? &p : nullptr, &fx, &fy, tol, max_iters, rep);
 }
 
 }  // extern "C"

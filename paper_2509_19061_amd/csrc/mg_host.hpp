@@ -1,0 +1,81 @@
+// Host-side types of the multigrid / Krylov layer shared by the hierarchy
+// code (mg.hip) and the solve and batch engine (solve.hip).
+#pragma once
+
+#include <vector>
+
+#include "mg_internal.hpp"
+
+namespace stk {
+
+struct Field2 {
+    void* x = nullptr;
+    void* y = nullptr;
+};
+
+struct MgLevel {
+    int nx = 0, ny = 0;
+    int64_t ld = 0;
+    double dx = 0, dy = 0;
+    double* ec64 = nullptr;  // viscosities (finest level only)
+    double* en64 = nullptr;
+    float* ec32 = nullptr;
+    float* en32 = nullptr;
+    double* st64 = nullptr;  // Galerkin stencil, 2 * NCOEF planes (coarse levels only)
+    float* st32 = nullptr;
+    int64_t plane = 0;
+    Field2 v[2], w[2], b[2], r[2];  // [0] FP64, [1] FP32; level 0 binds v, b to the Krylov Z, R slots
+};
+
+inline int64_t pad_ld(int nx) { return ((int64_t)nx + 1 + 63) / 64 * 64; }
+
+// Device job arrays of one dtype for a fixed, ordered list of instances.
+struct PlanT {
+    int n = 0, depth = 0, maxcn = 0;
+    std::vector<Batch> fine, crs;       // per depth: fine-block and coarse-block batches of LevelJob
+    std::vector<const void*> cjobs;     // per depth: CoarseJob array of instances whose coarsest it is
+    std::vector<int> ncj;
+    Batch apply;                        // finest: v = P, b = 0, r = Q  ->  Q = A P
+    Batch vec;                          // VecJob array
+    Batch xcast;                        // XCastJob array (FP32 plan only)
+    FcgState* st = nullptr;
+    double* part = nullptr;
+    double* sums = nullptr;
+    std::vector<void*> mem;
+    std::vector<std::vector<unsigned char>> stage;  // host sources of pending uploads
+    void release() {
+        for (void* p : mem) (void)hipFree(p);
+        mem.clear();
+    }
+};
+
+// Plans over mgs[0..n) for dtype t (0 FP64, 1 FP32); *out owns its memory.
+int make_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT** out);
+void free_plan(PlanT*& P);
+// One V-cycle on the level-0 binding (v = Z slot, b = R slot) of every instance of P.
+int run_vcycle(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o, int t);
+int read_states(stk_ctx* ctx, const PlanT& P, std::vector<FcgState>& h);
+int write_states(stk_ctx* ctx, const PlanT& P, const std::vector<FcgState>& h);
+// 2D copy of the used extents of a velocity pair between two row strides
+int copy_vel_in(stk_mg* m, const void* sx, const void* sy, int64_t sld, void* dx, void* dy, int64_t dld, size_t es);
+int ensure_dtype(stk_mg* m, int t);
+
+}  // namespace stk
+
+struct stk_mg {
+    stk_ctx* ctx = nullptr;
+    stk_mg_opts o{};
+    std::vector<stk::MgLevel> L;
+    int64_t user_ld = 0;
+    int cn = 0;
+    int* cmap = nullptr;
+    double* cainv = nullptr;
+    stk::Field2 ks[2][stk::VS_N];  // finest-level slots: row 0 FP64 (all), row 1 FP32 (R, Z only)
+    stk::Field2 zero[2];           // zero right-hand side for the operator apply
+    void* zero64 = nullptr;        // FP64 zeros (pressure of a p = 0 fold)
+    bool have[2] = {false, false};
+    std::vector<void*> mem;
+    size_t bytes = 0;
+    stk::PlanT* plan[2] = {nullptr, nullptr};  // single-instance plans of stk_mg_vcycle
+    bool busy = false;                          // in a batch
+};

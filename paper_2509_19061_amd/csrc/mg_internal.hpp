@@ -67,6 +67,7 @@ struct FcgState {
     double nv;      // sum r^2 / d  (current residual, velocity energy)
     double nf;      // sum f^2 / d
     double thr;     // stop when nv <= thr
+    double tol2;    // tol^2 of this instance (thr = tol2 * nf)
     int active;     // 1 while this instance iterates
     int pad;
 };
@@ -122,8 +123,8 @@ int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* par
 // R = B - M X in FP64; sums[2i] = sum R^2 / d
 int vec_residual64_st(stk_ctx* ctx, const Batch& b, const FcgState* st, double* part, double* sums);
 // Per-instance scalar update from the reduced sums (one thread per instance);
-// `factor` scales the stop threshold (tol^2 for PH_NF).
-int fcg_scalars(stk_ctx* ctx, FcgState* st, const double* sums, int n, int phase, double factor);
+// PH_NF sets N_f and the stop threshold tol2 * N_f.
+int fcg_scalars(stk_ctx* ctx, FcgState* st, const double* sums, int n, int phase);
 
 // Precision casts around the FP32 V-cycle preconditioner (active instances):
 // down: r32 = (float) r64; up: z64 = (double) z32.

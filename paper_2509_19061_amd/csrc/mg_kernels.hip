@@ -461,16 +461,17 @@ __global__ __launch_bounds__(256) void k_inst_sums(const int* __restrict__ pre, 
     }
 }
 
-__global__ void k_fcg_scalars(FcgState* __restrict__ st, const double* __restrict__ sums, int n, int phase,
-                              double factor) {
+__global__ void k_fcg_scalars(FcgState* __restrict__ st, const double* __restrict__ sums, int n, int phase) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     FcgState& s = st[q];
     const double s0 = sums[2 * q], s1 = sums[2 * q + 1];
     switch (phase) {
-        case PH_NF:  // N_f and the outer stop threshold
-            s.nf = s0;
-            s.thr = factor * s0;
+        case PH_NF:  // N_f and the stop threshold
+            if (s.active) {
+                s.nf = s0;
+                s.thr = s.tol2 * s0;
+            }
             break;
         case PH_NV:
             if (s.active) {
@@ -611,9 +612,9 @@ int vec_residual64_st(stk_ctx* ctx, const Batch& b, const FcgState* st, double* 
     STK_LAUNCH_CHECK();
     return inst_sums(ctx, b, part, sums);
 }
-int fcg_scalars(stk_ctx* ctx, FcgState* st, const double* sums, int n, int phase, double factor) {
+int fcg_scalars(stk_ctx* ctx, FcgState* st, const double* sums, int n, int phase) {
     if (!n) return STK_OK;
-    hipLaunchKernelGGL(k_fcg_scalars, dim3((n + 63) / 64), dim3(64), 0, ctx->stream, st, sums, n, phase, factor);
+    hipLaunchKernelGGL(k_fcg_scalars, dim3((n + 63) / 64), dim3(64), 0, ctx->stream, st, sums, n, phase);
     STK_LAUNCH_CHECK();
     return STK_OK;
 }

@@ -1,0 +1,177 @@
+"""Serving loop: solve requests arrive over time (Poisson), are admitted by
+their HBM footprint under a device budget, and are solved by continuous
+batching (``api.Batch``): requests that arrive while others are on the GPU
+join the batch at the next step as soon as a slot and memory are free, and
+every step advances all solves in flight with one launch per (level, kernel).
+
+Each request keeps its multigrid hierarchy on the device from admission to
+completion.  Latency = completion time - arrival time on the host clock.
+The loop itself (``Server``) is independent of the GPU: it talks to a backend
+with ``footprint / admit / step / release``, which the tests replace by a CPU
+fake to check admission and scheduling.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of the run
+    n: int                  # grid n x n cells
+    seed: int               # problem seed (instance_problem)
+    payload: object = None  # host problem (inputs.Problem), built before the run
+
+
+@dataclass
+class Done:
+    rid: int
+    n: int
+    arrival: float
+    admitted: float
+    finished: float
+    iterations: int
+    ev: float
+    converged: bool
+    inflight_at_admission: int
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+@dataclass
+class ServeResult:
+    done: list = field(default_factory=list)
+    rejected: list = field(default_factory=list)
+    makespan: float = 0.0
+    steps: int = 0
+    max_inflight: int = 0
+    peak_bytes: int = 0
+
+    def summary(self):
+        lat = np.array([d.latency for d in self.done]) if self.done else np.zeros(1)
+        joined = sum(1 for d in self.done if d.inflight_at_admission > 0)
+        return {"requests": len(self.done) + len(self.rejected), "completed": len(self.done),
+                "rejected": len(self.rejected),
+                "all_converged": all(d.converged for d in self.done),
+                "solves_per_s": round(len(self.done) / self.makespan, 4) if self.makespan > 0 else None,
+                "makespan_s": round(self.makespan, 4),
+                "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+                "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+                "latency_mean_s": round(float(lat.mean()), 4),
+                "admitted_while_busy": joined, "max_inflight": self.max_inflight,
+                "peak_bytes": self.peak_bytes, "steps": self.steps}
+
+
+def poisson_requests(count, rate, sizes, seed):
+    """``count`` requests with exponential inter-arrival times of mean 1/rate
+    (rate = inf: all at t = 0) and sizes drawn uniformly from ``sizes``."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        if np.isfinite(rate):
+            t += float(rng.exponential(1.0 / rate))
+        out.append(Request(i, t if np.isfinite(rate) else 0.0, int(rng.choice(sizes)), int(rng.integers(1 << 31))))
+    return out
+
+
+class Server:
+    """Admission (FIFO, by footprint under ``budget_bytes``, at most
+    ``max_slots`` in flight) + continuous batching over ``backend``."""
+
+    def __init__(self, backend, budget_bytes, max_slots=64, iters_per_step=4, clock=time.perf_counter,
+                 sleep=time.sleep):
+        self.b = backend
+        self.budget = int(budget_bytes)
+        self.max_slots = int(max_slots)
+        self.iters = int(iters_per_step)
+        self.clock = clock
+        self.sleep = sleep
+
+    def run(self, requests):
+        res = ServeResult()
+        queue = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        pending = collections.deque()
+        inflight = {}  # slot -> (request, handle, bytes, admitted)
+        used = 0
+        t0 = self.clock()
+        while queue or pending or inflight:
+            now = self.clock() - t0
+            while queue and queue[0].arrival <= now:
+                pending.append(queue.popleft())
+            while pending and len(inflight) < self.max_slots:
+                r = pending[0]
+                need = self.b.footprint(r)
+                if need > self.budget:  # can never fit
+                    res.rejected.append(pending.popleft().rid)
+                    continue
+                if used + need > self.budget:
+                    break
+                pending.popleft()
+                busy = len(inflight)
+                handle, slot = self.b.admit(r)
+                used += need
+                res.peak_bytes = max(res.peak_bytes, used)
+                inflight[slot] = (r, handle, need, self.clock() - t0, busy)
+            res.max_inflight = max(res.max_inflight, len(inflight))
+            if not inflight:
+                if queue:
+                    self.sleep(max(0.0, queue[0].arrival - (self.clock() - t0)))
+                continue
+            finished = self.b.step(self.iters)
+            res.steps += 1
+            now = self.clock() - t0
+            for slot, rep in finished:
+                r, handle, need, admitted, busy = inflight.pop(slot)
+                self.b.release(handle)
+                used -= need
+                res.done.append(Done(r.rid, r.n, r.arrival, admitted, now, rep["iterations"], rep["ev"],
+                                     rep["converged"], busy))
+        res.makespan = self.clock() - t0
+        return res
+
+
+class GpuBackend:
+    """Requests solved on the GPU: admission uploads the request's fields,
+    builds its hierarchy and adds it to one ``api.Batch``."""
+
+    def __init__(self, ctx, mode, max_slots, tol=1e-8, max_iters=3000, keep_results=False):
+        import torch
+
+        from . import api, fields
+        self.api, self.fields, self.torch = api, fields, torch
+        self.ctx, self.mode, self.tol, self.max_iters = ctx, mode, tol, max_iters
+        self.batch = api.Batch(ctx, mode, max_slots)
+        self.results = {} if keep_results else None  # rid -> (vx, vy) on the host
+
+    def footprint(self, r):
+        p = r.payload
+        ld = self.fields.pad_ld(p.nx)
+        g = self.api.Grid(p.nx, p.ny, ld, p.dx, p.dy)
+        return self.api.mg_footprint(g, self.mode) + 6 * (p.ny + 1) * ld * 8  # + eta_c, eta_n, fx, fy, vx, vy
+
+    def admit(self, r):
+        dp = self.fields.DeviceProblem(r.payload, self.torch.float64)
+        mg = self.api.MG(self.ctx, dp.grid, dp.eta_c, dp.eta_n)
+        vx, vy = dp.velocity()
+        slot = self.batch.add(mg, vx, vy, None, dp.fx, dp.fy, tol=self.tol, max_iters=self.max_iters)
+        return (r.rid, dp, mg, vx, vy), slot
+
+    def step(self, iters):
+        return self.batch.step(iters)
+
+    def release(self, handle):
+        rid, dp, mg, vx, vy = handle
+        if self.results is not None:
+            self.results[rid] = (dp.get_vx(vx), dp.get_vy(vy))
+        mg.close()
+
+    def close(self):
+        self.batch.close()
