@@ -24,7 +24,12 @@ multigrid solves:
     iterations in each mode, time per iteration (at 8192^2 and contrast 1e8 a
     solve to 1e-8 does not finish in a few minutes);
   * "batch": 64 independent sinker problems (256^2 .. 2048^2, uneven mix),
-    one launch per (level, kernel) across all of them, both modes.
+    one launch per (level, kernel) across all of them, both modes;
+  * "serve": requests with grids drawn from {128, ..., 4096}^2 (contrast
+    10^U(2,6)) admitted by HBM footprint under a 64 GB budget and solved by
+    continuous batching; per mode a saturation run (all requests at t = 0)
+    gives the peak solves/s, then Poisson arrivals at 0.8x that rate give
+    solves/s and p50 / p99 latency.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
@@ -81,6 +86,7 @@ def main():
     ap.add_argument("--rate-n", type=int, default=8192, help="per-iteration cost size (0: skip)")
     ap.add_argument("--batch", default="default", help="'default' (64-instance mix), 'small' or 'none'")
     ap.add_argument("--kernel-only", type=int, default=0, help="profiling mode: L RAS launches + copy calibration")
+    ap.add_argument("--serve", type=int, default=32, help="requests per serving run (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -216,6 +222,7 @@ def main():
     solve = run_solves(ctx, args.solve_n) if args.solve_n > 0 else None
     rate = run_iteration_cost(ctx, args.rate_n) if args.rate_n > 0 else None
     batch = run_batch(ctx, args.batch) if args.batch != "none" else None
+    served = run_serve(ctx, args.serve) if args.serve > 0 else None
 
     out = {
         "metric": "smoother GLUP/s + % HBM roofline (RAS-Jacobi)",
@@ -245,6 +252,7 @@ def main():
         "solve": solve,
         "iteration_cost": rate,
         "batch": batch,
+        "serve": served,
     }
     print(json.dumps(out), flush=True)
     if kctx is not ctx:
@@ -374,6 +382,47 @@ def run_iteration_cost(ctx, n, iters=30):
     out["bytes"] = m.info()["bytes"]
     out["f32_speedup_per_iteration"] = round(out["f64"]["ms_per_iteration"] / out["f32_refined"]["ms_per_iteration"], 3)
     m.close()
+    return out
+
+
+def run_serve(ctx, count, sizes=(128, 256, 512, 1024, 2048, 4096), budget=64 << 30, load=0.8, tol=1e-8,
+              max_iters=1000):
+    """Saturation and Poisson serving runs per mode (host problems built first).
+    Requests stop at E_v <= tol or after max_iters iterations: at 4096^2 and
+    contrast ~1e6, 1e-8 is at the FP64 rounding floor of E_v."""
+    import numpy as np
+
+    from paper_2509_19061_amd import inputs, serve
+
+    t0 = time.time()
+    base = serve.poisson_requests(count, float("inf"), list(sizes), seed=6)
+    payload = {r.rid: inputs.instance_problem(r.n, np.random.default_rng(r.seed)) for r in base}
+    log(f"[bench] serve: {count} requests built in {time.time() - t0:.1f}s, sizes "
+        + ", ".join(f"{n}:{sum(r.n == n for r in base)}" for n in sizes))
+    out = {"workload": f"{count} requests, n uniform over {list(sizes)}, sinkers U{{1..8}}, contrast 10^U(2,6), "
+                       f"E_v <= {tol:g} (at most {max_iters} iterations), HBM budget {budget >> 30} GiB, "
+                       f"continuous batching",
+           "requests": count, "budget_bytes": budget}
+    for mode in ("f64", "f32_refined"):
+        res = {}
+        for run in ("saturation", "poisson"):
+            if run == "saturation":
+                reqs = [serve.Request(r.rid, 0.0, r.n, r.seed, payload[r.rid]) for r in base]
+            else:
+                rate = load * res["saturation"]["solves_per_s"]
+                arr = serve.poisson_requests(count, rate, [0], seed=7)
+                reqs = [serve.Request(r.rid, a.arrival, r.n, r.seed, payload[r.rid]) for r, a in zip(base, arr)]
+            be = serve.GpuBackend(ctx, mode, 64, tol=tol, max_iters=max_iters)
+            summ = serve.Server(be, budget, max_slots=64, iters_per_step=4).run(reqs).summary()
+            be.close()
+            if run == "poisson":
+                summ["arrival_rate_per_s"] = round(rate, 4)
+            res[run] = summ
+            log(f"[bench] serve {mode} {run}: {summ['solves_per_s']} solves/s, p50 {summ['latency_p50_s']}s, "
+                f"p99 {summ['latency_p99_s']}s, admitted while busy {summ['admitted_while_busy']}, "
+                f"max in flight {summ['max_inflight']}, converged "
+                f"{sum(v['converged'] for v in summ['by_size'].values())}/{summ['completed']}")
+        out[mode] = res
     return out
 
 

@@ -78,7 +78,14 @@ struct Batch {       // a job array resident on the device plus its block prefix
     const int* pre = nullptr;
     int n = 0;       // instances
     int blocks = 0;  // total blocks
+    // reductions over the blocks (vector batches only): per-instance chunks of
+    // at most SUM_CHUNK block partials, chunk prefix cpre[0..n], partials of
+    // the chunks in part2 (2 per chunk)
+    const int* cpre = nullptr;
+    int chunks = 0;
+    double* part2 = nullptr;
 };
+constexpr int SUM_CHUNK = 4096;
 
 template <typename T> int mg_jacobi(stk_ctx* ctx, const Batch& b, double omega, int dir);
 template <typename T> int mg_residual(stk_ctx* ctx, const Batch& b);
@@ -137,6 +144,7 @@ struct XCastJob {
     double* z64[2];
 };
 int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st, int up);
+// per-instance sums of the block partials, in a fixed order: chunk sums, then chunks in order
 int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums);
 template <typename T> int mg_copy_wv(stk_ctx* ctx, const Batch& b);
 

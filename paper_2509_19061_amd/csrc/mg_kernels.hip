@@ -436,11 +436,16 @@ __global__ __launch_bounds__(NT) void k_vec_res64(const VecJob* __restrict__ job
     block_sum2(a0, 0.0, part);
 }
 
-// per-instance sums of the per-block partials, fixed order
-__global__ __launch_bounds__(256) void k_inst_sums(const int* __restrict__ pre, const double* __restrict__ part,
-                                                   double* __restrict__ sums) {
-    const int inst = blockIdx.x;
-    const int b0 = pre[inst], b1 = pre[inst + 1];
+// Per-instance sums of the per-block partials in a fixed order.  Stage 1:
+// chunk c (of instance inst) sums partials [pre[inst] + lc * SUM_CHUNK, ...)
+// with 256 threads; stage 2: one thread per instance adds its chunk sums in
+// order.  Both orders depend only on the instance's own block count.
+__global__ __launch_bounds__(256) void k_chunk_sums(const int* __restrict__ pre, const int* __restrict__ cpre, int n,
+                                                    const double* __restrict__ part, double* __restrict__ part2) {
+    const int c = blockIdx.x;
+    const int inst = find_inst(cpre, n, c);
+    const int b0 = pre[inst] + (c - cpre[inst]) * SUM_CHUNK;
+    const int b1 = min(pre[inst + 1], b0 + SUM_CHUNK);
     __shared__ double red[2][256 / 64];
     double s0 = 0.0, s1 = 0.0;
     for (int b = b0 + (int)threadIdx.x; b < b1; b += 256) {
@@ -457,8 +462,20 @@ __global__ __launch_bounds__(256) void k_inst_sums(const int* __restrict__ pre, 
     if (threadIdx.x < 2) {
         double s = 0.0;
         for (int q = 0; q < 256 / 64; ++q) s += red[threadIdx.x][q];
-        sums[2 * inst + threadIdx.x] = s;
+        part2[2 * c + threadIdx.x] = s;
     }
+}
+__global__ void k_inst_sums(const int* __restrict__ cpre, int n, const double* __restrict__ part2,
+                            double* __restrict__ sums) {
+    const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+    if (inst >= n) return;
+    double s0 = 0.0, s1 = 0.0;
+    for (int c = cpre[inst]; c < cpre[inst + 1]; ++c) {
+        s0 += part2[2 * c];
+        s1 += part2[2 * c + 1];
+    }
+    sums[2 * inst] = s0;
+    sums[2 * inst + 1] = s1;
 }
 
 __global__ void k_fcg_scalars(FcgState* __restrict__ st, const double* __restrict__ sums, int n, int phase) {
@@ -593,7 +610,10 @@ template int vec_op<double>(stk_ctx*, const Batch&, int, const FcgState*, double
 template int vec_op<float>(stk_ctx*, const Batch&, int, const FcgState*, double*, double*);
 
 int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums) {
-    hipLaunchKernelGGL(k_inst_sums, dim3(b.n), dim3(256), 0, ctx->stream, b.pre, part, sums);
+    if (!b.cpre || !b.part2) return set_error(STK_EINVAL, "internal: batch without reduction chunks");
+    hipLaunchKernelGGL(k_chunk_sums, dim3(b.chunks), dim3(256), 0, ctx->stream, b.pre, b.cpre, b.n, part, b.part2);
+    hipLaunchKernelGGL(k_inst_sums, dim3((b.n + 63) / 64), dim3(64), 0, ctx->stream, b.cpre, b.n,
+                       (const double*)b.part2, sums);
     STK_LAUNCH_CHECK();
     return STK_OK;
 }

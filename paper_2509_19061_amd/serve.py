@@ -66,7 +66,19 @@ class ServeResult:
                 "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
                 "latency_mean_s": round(float(lat.mean()), 4),
                 "admitted_while_busy": joined, "max_inflight": self.max_inflight,
-                "peak_bytes": self.peak_bytes, "steps": self.steps}
+                "peak_bytes": self.peak_bytes, "steps": self.steps, "by_size": self.by_size()}
+
+    def by_size(self):
+        out = {}
+        for n in sorted({d.n for d in self.done}):
+            ds = [d for d in self.done if d.n == n]
+            lat = np.array([d.latency for d in ds])
+            conv = [d for d in ds if d.converged]
+            out[str(n)] = {"completed": len(ds), "converged": len(conv),
+                           "mean_iterations": round(float(np.mean([d.iterations for d in ds])), 1),
+                           "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+                           "worst_ev": float(max(d.ev for d in ds))}
+        return out
 
 
 def poisson_requests(count, rate, sizes, seed):
