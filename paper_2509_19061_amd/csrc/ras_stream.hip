@@ -199,6 +199,8 @@ __device__ __forceinline__ void levels(const Grid<T>& g, T* __restrict__ ox, T* 
     const int i = G.ci0 + c;
     const bool ecol = c >= 1 && c <= W - 2;    // column inside E (else frozen ring)
     const bool ocol = i >= G.x0 && i < G.x1;  // owned column
+    const bool xcol = i >= 1 && i <= nx - 1;   // vx(i, .) is an unknown column
+    const bool ycol = i >= 0 && i <= nx - 1;   // vy(i, .) is an unknown column
     // waves that hold level < kt lanes store to LDS, waves that hold level kt lanes store to HBM
     const bool wave_lds = UNI ? s < kt : __builtin_amdgcn_readfirstlane(__ballot(lane_on && s < kt) != 0);
     const bool wave_out = UNI ? s == kt : __builtin_amdgcn_readfirstlane(__ballot(lane_on && s == kt) != 0);
@@ -248,7 +250,8 @@ __device__ __forceinline__ void levels(const Grid<T>& g, T* __restrict__ ox, T* 
             wy[2][2] = pr[WS + 1];
             const int sa1 = (sa + 1 == RC) ? 0 : sa + 1;
             const bool ain = a2 >= 0 && a2 < V;
-            const int fl = vtab[min(max(a2, 0), V - 1)];
+            const int fl_l = vtab[min(max(a2, 0), V - 1)];
+            const int fl = UNI ? __builtin_amdgcn_readfirstlane(fl_l) : fl_l;  // one row per level wave
             const int y = (fl & YMASK) - 1;
             const T* row = cfc + sa * (CF_N * WS);
             const T ecA = row[CF_EC * WS];
@@ -261,7 +264,7 @@ __device__ __forceinline__ void levels(const Grid<T>& g, T* __restrict__ ox, T* 
             const T ux = jac_step<T>(wx[1][1], row[CF_GX * WS], row[CF_BX * WS], mx);
             const T uy = jac_step<T>(wy[1][1], row[CF_GY * WS], row[CF_BY * WS], my);
             // frozen cells (ring rows/columns, walls) keep the snapshot value
-            const bool xu = is_vx_unknown(nx, ny, i, y), yu = is_vy_unknown(nx, ny, i, y);
+            const bool xu = xcol && y >= 0 && y < ny, yu = ycol && y >= 1 && y <= ny - 1;
             const T nvx = (upd && xu) ? ux : wx[1][1];
             const T nvy = (upd && yu) ? uy : wy[1][1];
             ec_prev = ecA;
