@@ -193,6 +193,24 @@ def main():
                               "effective_gbs": round(eff, 1), "frac_hbm": round(eff / HBM_PEAK_GBS, 4),
                               "words_per_lup": w}
             log(f"[bench] {name}: {t_ms:.2f} ms / {sweeps} sweeps, {g:.1f} GLUP/s, {eff:.0f} GB/s effective")
+        # residual (r_v = b - M v, r_p = -D v) and energy norm: algorithmic bytes per cell
+        # = vx, vy, eta_c, eta_n, fx, fy read (+ rx, ry, rp written for the residual)
+        rx, ry, rp = torch.empty_like(dp.fx), torch.empty_like(dp.fy), torch.empty_like(dp.eta_c)
+        for name, fn, words_c in (
+                ("residual", lambda: api.residual(ctx, dt, dp.grid, vx, vy, None, dp.eta_c, dp.eta_n, dp.fx, dp.fy,
+                                                  rx, ry, rp), 9),
+                ("energy_norm", lambda: api.energy_norm(ctx, dt, dp.grid, vx, vy, None, dp.eta_c, dp.eta_n, dp.fx,
+                                                        dp.fy), 6)):
+            fn()
+            reps = 10
+            _, secs = _timed(lambda: [fn() for _ in range(reps)])
+            t_ms = secs * 1e3 / reps
+            eff = words_c * wbytes * cells / (t_ms * 1e-3) / 1e9
+            variants[name] = {"ms": round(t_ms, 4), "gcells_per_s": round(cells / (t_ms * 1e-3) / 1e9, 2),
+                              "effective_gbs": round(eff, 1), "frac_hbm": round(eff / HBM_PEAK_GBS, 4),
+                              "words_per_cell": words_c}
+            log(f"[bench] {name}: {t_ms:.3f} ms, {eff:.0f} GB/s effective")
+        del rx, ry, rp
 
     # ---- CPU oracle on a bounded sample ----
     cpu = None

@@ -192,9 +192,9 @@ int stk_energy_norm(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* v
  * library coarsens by 2 in x and y while min(nx, ny) > coarsest and both are
  * even, prolongs bilinearly per component (linear across faces, 3/4-1/4 along
  * them, mirrored at the free-slip walls), restricts with R = P^T / 4, uses
- * Galerkin coarse operators M_c = R M P (stored as 31 coefficients per coarse
- * unknown, 62 * (ny_c+1) * ld_c words per coarse level; the finest level is
- * matrix-free), smooths with damped Jacobi (bit-identical to RAS with
+ * Galerkin coarse operators M_c = R M P (a row has 31 couplings; M_c is
+ * symmetric and each coupling is stored once, 32 * (ny_c+1) * ld_c words per
+ * coarse level; the finest level is matrix-free), smooths with damped Jacobi (bit-identical to RAS with
  * halo >= k - 1) and solves the coarsest level exactly in FP64 (dense inverse
  * of -M_c built at setup). */
 typedef struct {

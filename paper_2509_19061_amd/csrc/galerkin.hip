@@ -1,5 +1,6 @@
 // Setup of the Galerkin coarse operators A_c = P^T A P / 4 (A = -M) as stored
-// 31-coefficient stencils, one level from the next finer one.
+// stencils (each coupling stored once, coarse_stencil.hpp), one level from the
+// next finer one.
 //
 // The paper's multigrid (Sec. 3.2, Sec. 6.2) leaves the coarse operators
 // unspecified.  Rediscretised coarse operators (averaged coarse viscosities)
@@ -12,7 +13,9 @@
 // walking the fine support f of P's column q, the fine row of f (the
 // viscous stencil on the finest level, the stored stencil below it) and the
 // coarse support of P's row f'.  The accumulation order is fixed, so the
-// result is deterministic.  Setup only.
+// result is deterministic.  Of the full row only the couplings this row
+// stores are written; the coarse operator is exactly symmetric because each
+// coupling is computed once.  Setup only.
 #include "coarse_stencil.hpp"
 #include "mg_internal.hpp"
 
@@ -108,12 +111,11 @@ __global__ __launch_bounds__(GBX * GBY) void k_galerkin(GalerkinArgs g) {
                     if (STOKES) {
                         ne = stokes_row(g, a, fi, fj, cb, cdx, cdy, cv);
                     } else {
-                        const double* row = g.fst + (int64_t)a * NCOEF * g.fplane + (int64_t)fj * g.ld + fi;
                         for (int s = 0; s < NCOEF; ++s) {
                             cb[s] = slot_comp(a, s);
                             cdx[s] = slot_dx(a, s);
                             cdy[s] = slot_dy(a, s);
-                            cv[s] = row[s * g.fplane];
+                            cv[s] = stencil_coef<double>(g.fst, g.fplane, g.ld, nx, ny, a, s, fi, fj);
                         }
                         ne = NCOEF;
                     }
@@ -134,8 +136,11 @@ __global__ __launch_bounds__(GBX * GBY) void k_galerkin(GalerkinArgs g) {
                     }
                 }
         }
-        double* out = g.cst + (int64_t)a * NCOEF * g.cplane + (int64_t)J * g.cld + I;
-        for (int s = 0; s < NCOEF; ++s) out[s * g.cplane] = acc[s];
+        double* out = g.cst + (int64_t)J * g.cld + I;
+        for (int s = 0; s < NCOEF; ++s) {
+            const SlotSrc src = slot_src(a, s);
+            if (src.own) out[src.plane * g.cplane] = acc[s];
+        }
     }
 }
 

@@ -101,7 +101,7 @@ static int build_coarse(stk_mg* m) {
     const bool stored = l.st64 != nullptr;
     std::vector<double> ec, en, stc;
     if (stored) {
-        stc.resize(cnt * 2 * NCOEF);
+        stc.resize(cnt * NPLANES);
         STK_HIP(hipMemcpyAsync(stc.data(), l.st64, stc.size() * 8, hipMemcpyDeviceToHost, m->ctx->stream));
     } else {
         ec.resize(cnt);
@@ -121,14 +121,14 @@ static int build_coarse(stk_mg* m) {
                          l.nx, l.ny, n);
     std::vector<double> A((size_t)n * n);
     if (stored) {
-        // row (a, i, j) from its 31 stored coefficients; neighbour -> column via pos
+        // row (a, i, j) from its full stencil (gathered from the stored half); neighbour -> column via pos
         std::vector<int> pos(cnt * 2, -1);
         for (int q = 0; q < n; ++q) pos[(size_t)(map[q] >> 30) * cnt + (map[q] & 0x3fffffff)] = q;
         for (int r = 0; r < n; ++r) {
             const int a = map[r] >> 30, off = map[r] & 0x3fffffff;
             const int i = (int)(off % l.ld), j = (int)(off / l.ld);
             for (int s2 = 0; s2 < NCOEF; ++s2) {
-                const double v = stc[((size_t)a * NCOEF + s2) * cnt + off];
+                const double v = stencil_coef<double>(stc.data(), (int64_t)cnt, l.ld, l.nx, l.ny, a, s2, i, j);
                 const int b = slot_comp(a, s2), pi = i + slot_dx(a, s2), pj = j + slot_dy(a, s2);
                 if (pi < 0 || pj < 0 || pi > l.nx || pj > l.ny) continue;
                 const int c = pos[(size_t)b * cnt + (size_t)pj * l.ld + pi];
@@ -214,7 +214,7 @@ int ensure_dtype(stk_mg* m, int t) {
                                L.en32, cnt);
             STK_HIP(hipGetLastError());
         } else if (t == 1) {
-            const size_t cnt = (size_t)L.plane * 2 * NCOEF;
+            const size_t cnt = (size_t)L.plane * NPLANES;
             void* a = nullptr;
             STK_TRY(dalloc(m, cnt * 4, &a));
             L.st32 = static_cast<float*>(a);
@@ -508,9 +508,9 @@ int stk_mg_footprint(const stk_grid* g, const stk_mg_opts* opts, int mode, size_
         const size_t cnt = (size_t)(ny + 1) * (lvl == 0 ? (size_t)g->ld : (size_t)pad_ld(nx));
         // fields of cnt words: finest = eta_c, eta_n, smoother partner w and residual r (2 components each),
         // 7 two-component Krylov slots, 3 zero fields; FP32 extra: eta, w, r, R, Z.
-        // coarse = 2 * NCOEF stencil planes and v, w, b, r; FP32 extra: the same again.
-        const size_t w64 = lvl == 0 ? 2 + 4 + 2 * VS_N + 3 : 2 * NCOEF + 8;
-        const size_t w32 = lvl == 0 ? 2 + 4 + 4 : 2 * NCOEF + 8;
+        // coarse = NPLANES stencil planes and v, w, b, r; FP32 extra: the same again.
+        const size_t w64 = lvl == 0 ? 2 + 4 + 2 * VS_N + 3 : NPLANES + 8;
+        const size_t w32 = lvl == 0 ? 2 + 4 + 4 : NPLANES + 8;
         b += cnt * (w64 * 8 + (f32 ? w32 * 4 : 0));
         if (std::min(nx, ny) <= o.coarsest || (nx & 1) || (ny & 1)) break;
         nx /= 2;
@@ -574,7 +574,7 @@ int stk_mg_create(stk_ctx* ctx, stk_mg** out, const stk_grid* g, const double* e
             if (e1 != hipSuccess || e2 != hipSuccess) return fail(hip_fail(e1 != hipSuccess ? e1 : e2, "hipMemcpy2DAsync"));
         } else {
             void* a = nullptr;
-            int rc = dalloc(m, (size_t)L.plane * 2 * NCOEF * 8, &a);
+            int rc = dalloc(m, (size_t)L.plane * NPLANES * 8, &a);
             if (rc != STK_OK) return fail(rc);
             L.st64 = static_cast<double*>(a);
             const MgLevel& F = m->L[l - 1];

@@ -21,7 +21,7 @@ struct MgLevel {
     double* en64 = nullptr;
     float* ec32 = nullptr;
     float* en32 = nullptr;
-    double* st64 = nullptr;  // Galerkin stencil, 2 * NCOEF planes (coarse levels only)
+    double* st64 = nullptr;  // Galerkin stencil, NPLANES planes (coarse levels only)
     float* st32 = nullptr;
     int64_t plane = 0;
     Field2 v[2], w[2], b[2], r[2];  // [0] FP64, [1] FP32; level 0 binds v, b to the Krylov Z, R slots

@@ -335,3 +335,21 @@ def test_ras_large_k_falls_back_to_window_kernel(ctx):
     gx, gy = gpu_smooth(ctx, p, torch.float64, "ras", 20, vx0, vy0, **kw)
     ox, oy = S.smooth(p, vx0, vy0, p.fx, p.fy, None, 20, "ras", **kw)
     assert normwise(gx, ox) <= TOL64 and normwise(gy, oy) <= TOL64
+
+
+def test_8192_ras_equals_fused_jacobi_bitwise(ctx):
+    """Largest workload size (8192^2, the refinement workload): with h >= k - 1
+    an outer iteration is k Jacobi sweeps exactly, at any size, so the streaming
+    kernel must reproduce the fused kernel (oracle-checked at smaller sizes)
+    bit for bit; two outer iterations with different shifts."""
+    from paper_2509_19061_amd import api, fields
+    p = I.lognormal_background_workload(8192, 4, 16)
+    dp = fields.DeviceProblem(p, torch.float64)
+    shifts = I.random_shifts(2, 64, 64, 9)
+    vx, vy = dp.velocity(*I.random_velocity(p, 3, 1e-3))
+    wx, wy = vx.clone(), vy.clone()
+    api.smooth(ctx, torch.float64, dp.grid, vx, vy, None, dp.eta_c, dp.eta_n, dp.fx, dp.fy, 8, "ras",
+               tile_x=64, tile_y=64, k=4, halo=4, shifts=shifts)
+    api.smooth(ctx, torch.float64, dp.grid, wx, wy, None, dp.eta_c, dp.eta_n, dp.fx, dp.fy, 8, "jacobi_fused")
+    torch.cuda.synchronize()
+    assert torch.equal(vx, wx) and torch.equal(vy, wy)
