@@ -54,7 +54,7 @@ HBM_PEAK_GBS = 8000.0
 # counter reads for a copy of known size (profiles/k_ras_stream_4096_f64_k4.md).
 # Valid only for the kernel sources it was measured on: reported as null once
 # their hash differs.
-RAS_TRAFFIC = {"sources_sha256_16": "3a8df898edf1fa57", "bytes_per_launch": 1.503e9, "n": 4096, "k": 4, "dtype": "f64"}
+RAS_TRAFFIC = {"sources_sha256_16": "8ede888e4e835cb8", "bytes_per_launch": 1.504e9, "n": 4096, "k": 4, "dtype": "f64"}
 
 
 def ras_sources_hash():
@@ -91,8 +91,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the sharding design is "
-              "documented, not built). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (how it would shard is "
+              "documented, not implemented). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

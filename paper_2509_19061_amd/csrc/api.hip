@@ -97,6 +97,7 @@ int stk_ctx_create(stk_ctx** out, int device, void* hip_stream) {
     (void)hipDeviceGetAttribute(&b, hipDeviceAttributeSharedMemPerBlockOptin, device);
     c->lds_max = a > b ? a : b;
     (void)hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device);
+    (void)hipDeviceGetAttribute(&c->lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device);
     if (const char* rk = std::getenv("STK_RAS_KERNEL")) {
         if (!std::strcmp(rk, "window")) c->ras_kernel = 1;
         else if (!std::strcmp(rk, "stream")) c->ras_kernel = 2;

@@ -7,24 +7,39 @@
 // one-cell ring outside E frozen at the snapshot, owned cells written back.
 //
 // Execution: one workgroup streams up a column of NT tiles.  The rows of the
-// tiles' windows (ring row, E rows, ring row; tile after tile) form one
-// "virtual" row stream; ring rows never update, so the stencil of an E row
-// never reaches into another tile's rows and the stream need not drain
-// between tiles.  Sweep level s (1..kt) relaxes virtual row t - 1 - 2s at
-// step t, two rows behind level s - 1, so all levels advance together with
-// ONE barrier per step.  The waves of a workgroup have fixed roles:
+// tiles' windows (tile after tile) form one "virtual" row stream.  Sweep level
+// s (1..kt) relaxes virtual row t - 1 - 2s at step t, two rows behind level
+// s - 1, so all levels advance together with ONE barrier per step.
+//
+// Level kt is needed on the owned rows only, level kt - 1 one row further out,
+// and so on, so level 0 (the snapshot) is needed within min(kt, h + 1) rows of
+// the owned rows (h + 1 = the frozen ring).  Rows farther out are read by no
+// level and are left out of the stream.  Every row within kt - s of the owned
+// rows reads only rows of its own tile; level s relaxes the other rows too (so
+// that a step issues all its LDS reads at once), but their values are never
+// read.
+//
+// Frozen cells (ring rows and columns, walls, cells outside the grid) get
+// omega / diag = 0 from the feeders, so the update v - g (b - Mv) leaves them
+// unchanged without a select.  LDS is zeroed first and only finite values are
+// written to it, so the products with g = 0 are exact zeros.
+//
+// The waves of a workgroup have fixed roles:
 //   * level waves: wave w < kt owns window columns 0..63 of level w + 1, so
 //     its level, ring slots and row flags are wave-uniform (scalar); the
 //     columns past 64 of every level (window wider than 64) go to the
 //     remainder wave(s) after them;
 //   * feeder waves (the last NF): stream the snapshot, viscosities and
-//     right-hand side from HBM into LDS row rings through a P-row register
+//     right-hand side from HBM into LDS row rings through a PF-row register
 //     FIFO, and compute omega / diag(-M) once per cell of each row.
 // A level lane keeps a 3 x 3 window of level s-1 values in registers and reads
 // one new row per step from LDS; level kt writes the owned cells to HBM.
 // The update calls the same stencil functions as every other smoother, so
 // results are bit-identical to fused Jacobi wherever RAS equals Jacobi^kt.
 #include <algorithm>
+#include <cstdint>
+#include <mutex>
+#include <vector>
 
 #include "stencil.hpp"
 #include "stk_internal.hpp"
@@ -32,12 +47,21 @@
 namespace stk {
 namespace {
 
-constexpr int P = 6;     // FIFO depth in rows (also the unroll factor; multiple of 3)
-constexpr int NF = 3;    // feeder waves: 64 NF >= 2 Wm for Wm <= WS
-constexpr int RS0 = 8;   // level-0 ring rows
-constexpr int RS = 4;    // level >= 1 ring rows
-constexpr int YMASK = (1 << 27) - 1;
-constexpr int F_RING = 1 << 29, F_OWNED = 1 << 28, F_TOPWALL = 1 << 27;
+constexpr int U = 6;     // steps per unrolled group
+constexpr int PF = 6;    // feeder FIFO depth in rows
+// rows per level ring (levels 0..kt-1; level 0 = the snapshot): at step t row t - 2s
+// of level s - 1 is read while row t + 1 - 2s of it is written, and row t - 1 - 2s is
+// read at the next step, so three rows suffice
+constexpr int RING = 3;
+constexpr int NF = 3;    // feeder waves: 64 NF >= 2 Wm for Wm <= WS_WIDE
+// U: a multiple of 3 (the register window shifts by renaming), of RING (ring
+// slots are compile-time per unrolled step) and of PF (FIFO slots likewise)
+static_assert(U % 3 == 0 && U % RING == 0 && U % PF == 0, "unroll");
+// ring slot of row r (r may be negative)
+__device__ __forceinline__ int ring_slot(int r) { return ((r % RING) + RING) % RING; }
+// virtual row flags: y + 1, owned, frozen ring
+constexpr int YMASK = (1 << 20) - 1;
+constexpr int F_OWNED = 1 << 28, F_RING = 1 << 29;
 enum { CF_EC = 0, CF_EN, CF_BX, CF_BY, CF_GX, CF_GY, CF_N };
 
 struct RasArgs {
@@ -58,22 +82,31 @@ __device__ __forceinline__ void lds_barrier() {
 
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
-constexpr int WS = 96;  // LDS row stride (elements): window width bound, fixed so offsets fold
+// LDS row stride WS (elements): a compile-time bound on the window width, so
+// that row offsets fold into the instructions.  The narrow stride keeps an
+// FP64 workgroup with T = 64, h = k <= 5 within a third of the CU's LDS (three
+// resident workgroups); wider windows take the wide one.
+constexpr int WS_NARROW = 76, WS_WIDE = 96;
 
 // level lanes: 64 per level for columns 0..63, then Wm - 64 per level
 __host__ __device__ inline int level_lanes(int Wm, int kt) { return 64 * kt + kt * (Wm > 64 ? Wm - 64 : 0); }
 __host__ __device__ inline int level_waves(int Wm, int kt) { return (level_lanes(Wm, kt) + 63) / 64; }
 
-template <typename T>
-size_t stream_lds_bytes(const RasArgs& a, int nthr) {
-    const size_t n = (size_t)RS0 * 2 * WS + (size_t)(a.kt - 1) * RS * 2 * WS + (size_t)(2 * a.kt + 2) * CF_N * WS +
-                     (size_t)nthr;  // + one sink element per thread for disabled LDS stores
-    return align16((size_t)(a.Vmax + 1) * sizeof(int)) + n * sizeof(T);
+// LDS: row table | kt level rings | 2kt + 2 coefficient rows | sink for
+// disabled stores (one element per lane, shared by the waves, + WS for the
+// second component of a ring write)
+template <int WS>
+__host__ __device__ inline size_t stream_lds_elems(int kt) {
+    return (size_t)kt * RING * 2 * WS + (size_t)(2 * kt + 2) * CF_N * WS + 64 + WS;
+}
+template <typename T, int WS>
+size_t stream_lds_bytes(const RasArgs& a) {
+    return align16((size_t)(a.Vmax + 1) * sizeof(int)) + stream_lds_elems<WS>(a.kt) * sizeof(T);
 }
 
-// Bounds-checked output stores: a buffer resource over the used extent of an
-// output array; a lane with nothing to store passes an out-of-range offset and
-// the hardware drops its write (no branch).
+// Bounds-checked output stores: a buffer resource over one row of an output
+// array; a lane with nothing to store passes an out-of-range offset and the
+// hardware drops its write (no branch).
 constexpr unsigned OOB = 0xFFFFFFF0u;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(void* p, size_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)bytes, 0x00020000);
@@ -95,18 +128,34 @@ struct Geo {
     const int* vtab;
 };
 
+// Owned-row stores of level kt at grid row y: vx and vy of the owned columns
+// (lane_off), the right wall vx(nx, y) when the tile column ends at nx
+// (rw_off), and the top wall vy(., ny) after the last row.  Offsets are
+// lane-constant; the row is folded into the (scalar) buffer resources.
+template <typename T>
+__device__ __forceinline__ void store_row(T* __restrict__ ox, T* __restrict__ oy, const Geo& G, int y, T ux, T uy,
+                                          unsigned lane_off, unsigned rw_off) {
+    const __amdgpu_buffer_rsrc_t rox = out_rsrc(ox + (int64_t)y * G.ld, (size_t)(G.nx + 1) * sizeof(T));
+    const __amdgpu_buffer_rsrc_t roy = out_rsrc(oy + (int64_t)y * G.ld, (size_t)G.nx * sizeof(T));
+    store_out(ux, rox, lane_off);
+    store_out(uy, roy, lane_off);
+    if (G.x1 == G.nx) store_out(T(0), rox, rw_off);
+    if (y == G.ny - 1)
+        store_out(T(0), out_rsrc(oy + (int64_t)G.ny * G.ld, (size_t)G.nx * sizeof(T)), lane_off);
+}
+
 // ---------------------------------------------------------------- feeders --
 // Feeder lane fid (0 .. 64 NF - 1).  Task m = (field, window column): row t of
-// it goes to LDS at step t, row t + P is loaded at step t (unconditionally,
+// it goes to LDS at step t, row t + PF is loaded at step t (unconditionally,
 // from a row clamped into the array; the validity of the value is applied when
 // it leaves the FIFO, so no load sits under a branch that would wait for it).
 // Lanes past the last task repeat it (same value to the same place).  Then
-// omega / diag of row t - 2 for every window cell: the value of a cell that is
-// not relaxed (ring, wall) is never read, since its update is discarded.
-template <typename T, int MM>
+// omega / diag of row t - 2 for every window cell, 0 for a cell that is not
+// relaxed (ring row or column, wall, outside the grid).
+template <typename T, int WS, int MM>
 __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ vx, const T* __restrict__ vy,
-                                       const Geo& G, T* s0, T* cf, T* dummy, int fid) {
-    const int nx = G.nx, ny = G.ny, Wm = G.Wm, RC = G.RC, V = G.V, ci0 = G.ci0;
+                                       const Geo& G, T* rings, T* cf, T* sink, int fid) {
+    const int nx = G.nx, ny = G.ny, Wm = G.Wm, W = G.W, RC = G.RC, V = G.V, ci0 = G.ci0;
     const int64_t ld = G.ld;
     const int* vtab = G.vtab;
     const int nq = 6 * Wm;
@@ -128,91 +177,97 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
         ts0[m] = f < 2;
         tdst[m] = f < 2 ? f * WS + cq : (f - 2) * WS + cq;
     }
+    // omega / diag task of this lane: value v (0..Wm-1: vx, Wm..2Wm-1: vy)
+    const int v = fid;  // 64 NF >= 2 Wm: one value per lane
+    const bool bl = v < 2 * Wm;
+    const bool cy = v >= Wm;
+    const int cq = bl ? (cy ? v - Wm : v) : 1;
+    const int ii = ci0 + cq;
+    const bool gcol = bl && cq >= 1 && cq <= W - 2 && (cy ? ii <= nx - 1 : (ii >= 1 && ii <= nx - 1));
+    const int gylo = cy ? 1 : 0;
     auto row_off = [&](int y) -> int64_t { return (int64_t)min(max(y, 0), ny - 1) * ld; };
-    T fifo[P][MM];
-    int fy[P];  // the row each FIFO slot holds (uniform)
+    // omega / diag reads: e0 = eta_c left (vx) or below (vy), n1 = eta_n above (vx) or right (vy)
+    const int off_e0 = CF_EC * WS + cq - (cy ? 0 : 1), off_n1 = CF_EN * WS + cq + (cy ? 1 : 0);
+    const T ix = cy ? g.idy : g.idx, iy = cy ? g.idx : g.idy;
+    T fifo[PF][MM];
+    int ff[PF];  // flags of the row each FIFO slot holds (uniform; 0 past the last row)
 #pragma unroll
-    for (int u = 0; u < P; ++u) {
-        fy[u] = u < V ? (__builtin_amdgcn_readfirstlane(vtab[u]) & YMASK) - 1 : -1;
-        const int64_t yo = row_off(fy[u]);
+    for (int u = 0; u < PF; ++u) {
+        ff[u] = u < V ? __builtin_amdgcn_readfirstlane(vtab[u]) : 0;
+        const int64_t yo = row_off((ff[u] & YMASK) - 1);
 #pragma unroll
         for (int m = 0; m < MM; ++m) fifo[u][m] = tbase[m][yo];
     }
-    int rA = 0;  // t % RC
-    for (int t0 = 0; t0 < G.nsteps; t0 += P) {
+    int fn = PF < V ? vtab[PF] : 0;  // flags of row t + PF, read one step ahead
+    int f1 = 0, f2 = 0;              // flags of rows t - 1 and t - 2
+    int rA = 0;                      // t % RC
+    for (int t0 = 0; t0 < G.nsteps; t0 += U) {
 #pragma unroll
-        for (int u = 0; u < P; ++u) {
-            const int t = t0 + u;
-            {  // (A) row t: FIFO -> LDS rings; loads of row t + P
-                T* r0 = s0 + (t & (RS0 - 1)) * 2 * WS;
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u, q = u % PF;
+            // (B, reads) viscosities around row t - 2, written at steps t - 3 .. t - 1
+            const int sr = rA >= 2 ? rA - 2 : rA + RC - 2;
+            const int sm = sr >= 1 ? sr - 1 : RC - 1, sp = sr + 1 == RC ? 0 : sr + 1;
+            const T e0 = cf[(cy ? sm : sr) * CF_N * WS + off_e0];
+            const T e1 = cf[sr * CF_N * WS + CF_EC * WS + cq];
+            const T n0 = cf[sr * CF_N * WS + CF_EN * WS + cq];
+            const T n1 = cf[(cy ? sr : sp) * CF_N * WS + off_n1];
+            __builtin_amdgcn_sched_barrier(0);
+            const int ff_t = ff[q];  // flags of row t
+            {  // (A) row t: FIFO -> LDS rings; loads of row t + PF
+                T* r0 = rings + (u % RING) * 2 * WS;
                 T* rc = cf + rA * CF_N * WS;
-                const int y = fy[u];
+                const int y = (ff_t & YMASK) - 1;
 #pragma unroll
                 for (int m = 0; m < MM; ++m) {
                     const bool ok = tok[m] && y >= tylo[m] && y <= ny - 1;
-                    (ts0[m] ? r0 : rc)[tdst[m]] = ok ? fifo[u][m] : T(0);
+                    (ts0[m] ? r0 : rc)[tdst[m]] = ok ? fifo[q][m] : T(0);
                 }
-                const int yn = (t + P < V) ? (__builtin_amdgcn_readfirstlane(vtab[t + P]) & YMASK) - 1 : -1;
-                fy[u] = yn;
-                const int64_t yo = row_off(yn);
+                const int fnext = __builtin_amdgcn_readfirstlane(fn);
+                ff[q] = fnext;
+                const int64_t yo = row_off((fnext & YMASK) - 1);
 #pragma unroll
-                for (int m = 0; m < MM; ++m) fifo[u][m] = tbase[m][yo];
+                for (int m = 0; m < MM; ++m) fifo[q][m] = tbase[m][yo];
+                fn = t + PF + 1 < V ? vtab[t + PF + 1] : 0;
             }
-            {  // (B) omega / diag for the E cells of row t - 2 (values 0..Wm-1: vx, Wm..2Wm-1: vy;
-               //     diag_y is diag_x with the roles of x and y exchanged)
-                const int r = t - 2;
-                if (r >= 0 && r < V) {
-                    const int sr = rA >= 2 ? rA - 2 : rA + RC - 2;
-                    const int sm = sr >= 1 ? sr - 1 : RC - 1, sp = sr + 1 == RC ? 0 : sr + 1;
-                    const int v = fid;  // 64 NF >= 2 Wm: one value per lane
-                    const bool bl = v < 2 * Wm;
-                    const bool cy = v >= Wm;
-                    const int cq = bl ? (cy ? v - Wm : v) : 1;
-                    const T* row = cf + sr * CF_N * WS + cq;
-                    const T e0 = cy ? cf[sm * CF_N * WS + CF_EC * WS + cq] : row[CF_EC * WS - 1];
-                    const T e1 = row[CF_EC * WS];
-                    const T n0 = row[CF_EN * WS];
-                    const T n1 = cy ? row[CF_EN * WS + 1] : cf[sp * CF_N * WS + CF_EN * WS + cq];
-                    const T d = diag_x<T>(e0, e1, n0, n1, cy ? g.idy : g.idx, cy ? g.idx : g.idy);
-                    T* dst = bl ? cf + sr * CF_N * WS + (cy ? CF_GY : CF_GX) * WS + cq : dummy;
-                    *dst = g.omega / d;
-                }
+            {  // (B) omega / diag for row t - 2 (diag_y is diag_x with the roles of x and y exchanged);
+               //     0 for a cell that is not relaxed, and for no row (t < 2 or past the last row)
+                const int yr = (f2 & YMASK) - 1;
+                const bool upd = gcol && !(f2 & F_RING) && yr >= gylo && yr <= ny - 1;
+                const T d = diag_x<T>(e0, e1, n0, n1, ix, iy);
+                T* dst = bl ? cf + sr * CF_N * WS + (cy ? CF_GY : CF_GX) * WS + cq : sink;
+                *dst = (upd ? g.omega : T(0)) / (upd ? d : T(1));
             }
+            f2 = f1;
+            f1 = ff_t;
             rA = (rA + 1 == RC) ? 0 : rA + 1;
             lds_barrier();
         }
     }
 }
 
-// ------------------------------------------------------------------ levels --
-// Lanes of level s (1..kt, or > kt for an idle lane) at window column c.
-// UNI: the whole wave has one level (level waves), so the compiler keeps the
-// level-dependent quantities scalar.
-template <typename T, bool UNI>
-__device__ __forceinline__ void levels(const Grid<T>& g, T* __restrict__ ox, T* __restrict__ oy, const Geo& G,
-                                       const T* s0, T* s1, const T* cf, T* dummy, int s_in, int c) {
-    const int s = UNI ? __builtin_amdgcn_readfirstlane(s_in) : s_in;
-    const int nx = G.nx, ny = G.ny, kt = G.kt, RC = G.RC, V = G.V, W = G.W;
-    const int64_t ld = G.ld;
+// ------------------------------------------------------------- level wave --
+// Window columns c = 0..63 of level s (the same for the whole wave): level,
+// ring slots and row flags are scalar.
+template <typename T, int WS>
+__device__ __forceinline__ void level_wave(const Grid<T>& g, T* __restrict__ ox, T* __restrict__ oy, const Geo& G,
+                                           T* rings, const T* cf, int s_in, int c) {
+    const int s = __builtin_amdgcn_readfirstlane(s_in);
+    const int kt = G.kt, RC = G.RC, V = G.V;
     const int* vtab = G.vtab;
-    const bool lane_on = (s <= kt) && (c < W);
     const int i = G.ci0 + c;
-    const bool ecol = c >= 1 && c <= W - 2;    // column inside E (else frozen ring)
-    const bool ocol = i >= G.x0 && i < G.x1;  // owned column
-    const bool xcol = i >= 1 && i <= nx - 1;   // vx(i, .) is an unknown column
-    const bool ycol = i >= 0 && i <= nx - 1;   // vy(i, .) is an unknown column
-    // waves that hold level < kt lanes store to LDS, waves that hold level kt lanes store to HBM
-    const bool wave_lds = UNI ? s < kt : __builtin_amdgcn_readfirstlane(__ballot(lane_on && s < kt) != 0);
-    const bool wave_out = UNI ? s == kt : __builtin_amdgcn_readfirstlane(__ballot(lane_on && s == kt) != 0);
-    const int sl = min(s, kt);
-    const T* prevc = ((sl == 1) ? s0 : s1 + (sl - 2) * RS * 2 * WS) + c;
-    const int prs = (sl == 1) ? RS0 - 1 : RS - 1;
-    T* minec = s1 + (sl - 1) * RS * 2 * WS + c;  // level s ring (unused for s = kt)
+    // step t = t0 + u (t0 % RING == 0) reads level s-1 row t - 2s and writes level s row t - 1 - 2s
+    const T* pr[RING];
+    T* wr[RING];
+#pragma unroll
+    for (int k = 0; k < RING; ++k) {
+        pr[k] = rings + ((s - 1) * RING + ring_slot(k - 2 * s)) * 2 * WS + c;
+        wr[k] = rings + (min(s, kt - 1) * RING + ring_slot(k - 1 - 2 * s)) * 2 * WS + c;
+    }
     const T* cfc = cf + c;
-    int sa = RC - 1 - 2 * sl;  // ring slot of row t - 1 - 2s at t = 0
-    if (sa < 0) sa += RC;
-    const __amdgpu_buffer_rsrc_t rox = out_rsrc(ox, ((size_t)(ny - 1) * ld + nx + 1) * sizeof(T));
-    const __amdgpu_buffer_rsrc_t roy = out_rsrc(oy, ((size_t)ny * ld + nx) * sizeof(T));
+    int sa = RC - 1 - 2 * s;  // coefficient slot of row t - 1 - 2s at t = 0
+    const unsigned lane_off = (i >= G.x0 && i < G.x1) ? (unsigned)i * (unsigned)sizeof(T) : OOB;
+    const unsigned rw_off = i == G.nx ? (unsigned)i * (unsigned)sizeof(T) : OOB;
 
     // window of level s-1 values at columns c-1, c, c+1: rows a-1, a, a+1
     T wx[3][3], wy[3][3];
@@ -222,18 +277,10 @@ __device__ __forceinline__ void levels(const Grid<T>& g, T* __restrict__ ox, T* 
         for (int q = 0; q < 3; ++q) wx[r][q] = wy[r][q] = T(0);
     T ec_prev = T(0), en_prev = T(0);  // eta_c(c, a-1), eta_n-hat(c, a)
 
-    // Values of rows outside [0, V) (before the first and after the last virtual
-    // row) are never used by an updated row: rows 0 and V-1 are ring rows, which
-    // keep their snapshot value, and ring rows separate the tiles.  Only the
-    // HBM stores and the row flags need guarding.  Steps past V + 2kt are
-    // no-ops, so the loop runs whole groups of P steps without per-step guards.
-    for (int t0 = 0; t0 < G.nsteps; t0 += P) {
+    for (int t0 = 0; t0 < G.nsteps; t0 += U) {
 #pragma unroll
-        for (int u = 0; u < P; ++u) {
-            const int t = t0 + u;
-            const int a2 = t - 1 - 2 * sl;
-            // window rows 0, 1, 2 = a-1, a, a+1: shifted every step so that, unrolled,
-            // the shift is a register renaming
+        for (int u = 0; u < U; ++u) {
+            const int a2 = t0 + u - 1 - 2 * s;
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 wx[0][q] = wx[1][q];
@@ -241,51 +288,112 @@ __device__ __forceinline__ void levels(const Grid<T>& g, T* __restrict__ ox, T* 
                 wy[0][q] = wy[1][q];
                 wy[1][q] = wy[2][q];
             }
-            const T* pr = prevc + ((a2 + 1) & prs) * (2 * WS);
-            wx[2][0] = pr[-1];
-            wx[2][1] = pr[0];
-            wx[2][2] = pr[1];
-            wy[2][0] = pr[WS - 1];
-            wy[2][1] = pr[WS];
-            wy[2][2] = pr[WS + 1];
+            const T* p = pr[u % RING];
+            wx[2][0] = p[-1];
+            wx[2][1] = p[0];
+            wx[2][2] = p[1];
+            wy[2][0] = p[WS - 1];
+            wy[2][1] = p[WS];
+            wy[2][2] = p[WS + 1];
             const int sa1 = (sa + 1 == RC) ? 0 : sa + 1;
-            const bool ain = a2 >= 0 && a2 < V;
-            const int fl_l = vtab[min(max(a2, 0), V - 1)];
-            const int fl = UNI ? __builtin_amdgcn_readfirstlane(fl_l) : fl_l;  // one row per level wave
-            const int y = (fl & YMASK) - 1;
+            const int fl = __builtin_amdgcn_readfirstlane(vtab[min(max(a2, 0), V - 1)]);
             const T* row = cfc + sa * (CF_N * WS);
-            const T ecA = row[CF_EC * WS];
+            const T ecA = row[CF_EC * WS], ecL = row[CF_EC * WS - 1], enR = row[CF_EN * WS + 1];
+            const T gx = row[CF_GX * WS], bx = row[CF_BX * WS], gy = row[CF_GY * WS], by = row[CF_BY * WS];
             const T ent = cfc[sa1 * (CF_N * WS) + CF_EN * WS];
-            const bool upd = !(fl & F_RING) && ecol;
+            // every row is relaxed (a row outside the level's cone is never read), and all LDS
+            // reads of the step are issued together, ahead of the arithmetic
+            __builtin_amdgcn_sched_barrier(0);
             const T mx = mv_x<T>(wx[1][1], wx[1][0], wx[1][2], wx[0][1], wx[2][1], wy[1][1], wy[1][0], wy[2][1],
-                                 wy[2][0], row[CF_EC * WS - 1], ecA, en_prev, ent, g.idx, g.idy);
+                                 wy[2][0], ecL, ecA, en_prev, ent, g.idx, g.idy);
             const T my = mv_y<T>(wy[1][1], wy[1][0], wy[1][2], wy[0][1], wy[2][1], wx[1][1], wx[1][2], wx[0][1],
-                                 wx[0][2], ec_prev, ecA, en_prev, row[CF_EN * WS + 1], g.idx, g.idy);
-            const T ux = jac_step<T>(wx[1][1], row[CF_GX * WS], row[CF_BX * WS], mx);
-            const T uy = jac_step<T>(wy[1][1], row[CF_GY * WS], row[CF_BY * WS], my);
-            // frozen cells (ring rows/columns, walls) keep the snapshot value
-            const bool xu = xcol && y >= 0 && y < ny, yu = ycol && y >= 1 && y <= ny - 1;
-            const T nvx = (upd && xu) ? ux : wx[1][1];
-            const T nvy = (upd && yu) ? uy : wy[1][1];
+                                 wx[0][2], ec_prev, ecA, en_prev, enR, g.idx, g.idy);
+            const T ux = jac_step<T>(wx[1][1], gx, bx, mx);
+            const T uy = jac_step<T>(wy[1][1], gy, by, my);
+            if (s < kt) {
+                T* w = wr[u % RING];
+                w[0] = ux;
+                w[WS] = uy;
+            } else if (a2 >= 0 && a2 < V && (fl & F_OWNED)) {
+                store_row<T>(ox, oy, G, (fl & YMASK) - 1, ux, uy, lane_off, rw_off);
+            }
             ec_prev = ecA;
             en_prev = ent;
-            if (wave_lds) {  // levels < kt: into the level-s ring (other lanes into their sink)
-                const bool w = lane_on && s < kt;
-                T* wp = minec + (a2 & (RS - 1)) * (2 * WS);
-                (w ? wp : dummy)[0] = nvx;
-                (w ? wp + WS : dummy)[0] = nvy;
+            sa = sa1;
+            lds_barrier();
+        }
+    }
+}
+
+// --------------------------------------------------------- remainder wave --
+// Lanes of mixed levels: level s (1..kt) at window column c >= 64, or idle
+// (s > kt).  Every row is relaxed (results outside a level's cone are not
+// read).  Ring writes of level-kt and idle lanes go to the sink; the level-kt
+// lanes share one row per step, whose flags are read once for the stores.
+template <typename T, int WS>
+__device__ __forceinline__ void remainder_wave(const Grid<T>& g, T* __restrict__ ox, T* __restrict__ oy,
+                                               const Geo& G, T* rings, const T* cf, T* sink, int s, int c) {
+    const int kt = G.kt, RC = G.RC, V = G.V;
+    const int* vtab = G.vtab;
+    const int sl = min(s, kt);
+    const int i = G.ci0 + c;
+    const T* pr[RING];
+    T* wr[RING];
+#pragma unroll
+    for (int k = 0; k < RING; ++k) {
+        pr[k] = rings + ((sl - 1) * RING + ring_slot(k - 2 * sl)) * 2 * WS + c;
+        wr[k] = sl < kt ? rings + (sl * RING + ring_slot(k - 1 - 2 * sl)) * 2 * WS + c : sink;
+    }
+    const T* cfc = cf + c;
+    int sa = RC - 1 - 2 * sl;
+    const bool top = s == kt;
+    const unsigned lane_off = (top && i >= G.x0 && i < G.x1) ? (unsigned)i * (unsigned)sizeof(T) : OOB;
+    const unsigned rw_off = (top && i == G.nx) ? (unsigned)i * (unsigned)sizeof(T) : OOB;
+
+    T wx[3][3], wy[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) wx[r][q] = wy[r][q] = T(0);
+    T ec_prev = T(0), en_prev = T(0);
+
+    for (int t0 = 0; t0 < G.nsteps; t0 += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                wx[0][q] = wx[1][q];
+                wx[1][q] = wx[2][q];
+                wy[0][q] = wy[1][q];
+                wy[1][q] = wy[2][q];
             }
-            if (wave_out) {  // level kt: owned cells to HBM, walls as 0
-                const bool own = lane_on && s == kt && ain && (fl & F_OWNED);
-                const unsigned k = (unsigned)((int64_t)y * ld + i) * (unsigned)sizeof(T);
-                store_out(xu ? nvx : T(0), rox, own && ocol ? k : OOB);
-                store_out(yu ? nvy : T(0), roy, own && ocol ? k : OOB);
-                // right wall vx(nx, y) and top wall vy(i, ny) of the owning tiles
-                const bool rw = own && i == nx && G.x1 == nx;
-                store_out(T(0), rox, rw ? (unsigned)((int64_t)y * ld + nx) * (unsigned)sizeof(T) : OOB);
-                const bool tw = lane_on && s == kt && ain && (fl & F_TOPWALL) && ocol;
-                store_out(T(0), roy, tw ? (unsigned)((int64_t)ny * ld + i) * (unsigned)sizeof(T) : OOB);
-            }
+            const T* p = pr[u % RING];
+            wx[2][0] = p[-1];
+            wx[2][1] = p[0];
+            wx[2][2] = p[1];
+            wy[2][0] = p[WS - 1];
+            wy[2][1] = p[WS];
+            wy[2][2] = p[WS + 1];
+            const int sa1 = (sa + 1 == RC) ? 0 : sa + 1;
+            const T* row = cfc + sa * (CF_N * WS);
+            const T ecA = row[CF_EC * WS], ecL = row[CF_EC * WS - 1], enR = row[CF_EN * WS + 1];
+            const T gx = row[CF_GX * WS], bx = row[CF_BX * WS], gy = row[CF_GY * WS], by = row[CF_BY * WS];
+            const T ent = cfc[sa1 * (CF_N * WS) + CF_EN * WS];
+            const int ak = t0 + u - 1 - 2 * kt;  // the row of the level-kt lanes
+            const int flk = __builtin_amdgcn_readfirstlane(vtab[min(max(ak, 0), V - 1)]);
+            __builtin_amdgcn_sched_barrier(0);
+            const T mx = mv_x<T>(wx[1][1], wx[1][0], wx[1][2], wx[0][1], wx[2][1], wy[1][1], wy[1][0], wy[2][1],
+                                 wy[2][0], ecL, ecA, en_prev, ent, g.idx, g.idy);
+            const T my = mv_y<T>(wy[1][1], wy[1][0], wy[1][2], wy[0][1], wy[2][1], wx[1][1], wx[1][2], wx[0][1],
+                                 wx[0][2], ec_prev, ecA, en_prev, enR, g.idx, g.idy);
+            const T ux = jac_step<T>(wx[1][1], gx, bx, mx);
+            const T uy = jac_step<T>(wy[1][1], gy, by, my);
+            T* w = wr[u % RING];
+            w[0] = ux;
+            w[WS] = uy;
+            if (ak >= 0 && ak < V && (flk & F_OWNED)) store_row<T>(ox, oy, G, (flk & YMASK) - 1, ux, uy, lane_off, rw_off);
+            ec_prev = ecA;
+            en_prev = ent;
             sa = sa1;
             lds_barrier();
         }
@@ -293,13 +401,13 @@ __device__ __forceinline__ void levels(const Grid<T>& g, T* __restrict__ ox, T* 
 }
 
 // MM = HBM loads per feeder lane per row (6 fields x Wm / (64 NF)).
-template <typename T, int NTMAX, int MM>
+template <typename T, int NTMAX, int MM, int WS>
 __global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __restrict__ vx, const T* __restrict__ vy,
                                                       T* __restrict__ ox, T* __restrict__ oy, RasArgs a) {
     extern __shared__ unsigned char smem_raw[];
     const int nx = g.nx, ny = g.ny;
     const int kt = a.kt, Wm = a.Wm;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
 
     // ---- this workgroup's tile column and window columns
     const int x0 = max(0, a.sx + ((int)blockIdx.x - 1) * a.Tx), x1 = min(nx, a.sx + (int)blockIdx.x * a.Tx);
@@ -307,31 +415,39 @@ __global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __rest
     const int X0 = max(x0 - a.h, 0), X1 = min(x1 + a.h, nx);
 
     int* vtab = reinterpret_cast<int*>(smem_raw);
-    T* s0 = reinterpret_cast<T*>(smem_raw + align16((size_t)(a.Vmax + 1) * sizeof(int)));
-    T* s1 = s0 + RS0 * 2 * WS;
-    T* cf = s1 + (kt - 1) * RS * 2 * WS;
-    T* dummy = cf + (2 * kt + 2) * CF_N * WS + tid;  // this thread's sink for disabled LDS stores
+    T* rings = reinterpret_cast<T*>(smem_raw + align16((size_t)(a.Vmax + 1) * sizeof(int)));
+    T* cf = rings + kt * RING * 2 * WS;
+    T* sink = cf + (2 * kt + 2) * CF_N * WS + (tid & 63);  // this lane's sink for disabled LDS stores
 
-    // ---- virtual row table: y + 1 and flags, tile after tile
-    if (tid == 0) {
-        const int nty = (ny + a.Ty - 1) / a.Ty + 1;
-        const int tyb = blockIdx.y * a.NT, tye = min(nty, tyb + a.NT);
-        int v = 0;
-        for (int ty = tyb; ty < tye; ++ty) {
-            const int y0 = max(0, a.sy + (ty - 1) * a.Ty), y1 = min(ny, a.sy + ty * a.Ty);
-            if (y0 >= y1) continue;
-            const int Y0 = max(y0 - a.h, 0), Y1 = min(y1 + a.h, ny);
-            for (int y = Y0 - 1; y <= Y1; ++y) {
-                int f = y + 1;
-                if (y == Y0 - 1 || y == Y1) f |= F_RING;
-                if (y >= y0 && y < y1) f |= F_OWNED;
-                if (y == ny && y1 == ny) f |= F_TOPWALL;
-                vtab[v++] = f;
-            }
+    // ---- virtual row table: y + 1 and flags, tile after tile.
+    // Tile ty of this workgroup contributes the rows y of [Y0 - 1, Y1] within D of its owned rows.
+    const int D = min(kt, a.h + 1);
+    const int nty = (ny + a.Ty - 1) / a.Ty + 1;
+    const int tyb = blockIdx.y * a.NT;
+    int V = 0;
+    for (int q = 0; q < a.NT; ++q) {
+        const int ty = tyb + q;
+        if (ty >= nty) break;
+        const int y0 = max(0, a.sy + (ty - 1) * a.Ty), y1 = min(ny, a.sy + ty * a.Ty);
+        if (y0 >= y1) continue;
+        const int Y0 = max(y0 - a.h, 0), Y1 = min(y1 + a.h, ny);
+        const int lo = max(Y0 - 1, y0 - D), hi = min(Y1, y1 - 1 + D);
+        for (int v = V + tid; v <= V + hi - lo; v += nthr) {
+            const int y = lo + v - V;
+            int f = y + 1;
+            if (y == Y0 - 1 || y == Y1) f |= F_RING;
+            if (y >= y0 && y < y1) f |= F_OWNED;
+            vtab[v] = f;
         }
-        vtab[a.Vmax] = v;
+        V += hi - lo + 1;
+    }
+    // ---- LDS rings, coefficient rows and sinks start at 0 (finite everywhere)
+    {
+        const int n = (int)stream_lds_elems<WS>(kt);
+        for (int e = tid; e < n; e += nthr) rings[e] = T(0);
     }
     lds_barrier();
+    if (V == 0) return;
     Geo G;
     G.nx = nx;
     G.ny = ny;
@@ -339,9 +455,8 @@ __global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __rest
     G.kt = kt;
     G.Wm = Wm;
     G.RC = 2 * kt + 2;
-    G.V = vtab[a.Vmax];
-    if (G.V == 0) return;
-    G.nsteps = G.V + 2 * kt + 1;
+    G.V = V;
+    G.nsteps = V + 2 * kt + 1;
     G.x0 = x0;
     G.x1 = x1;
     G.W = X1 - X0 + 2;  // window column c <-> cell column i = X0 - 1 + c
@@ -351,88 +466,100 @@ __global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __rest
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int nlw = level_waves(Wm, kt);
     if (wave >= nlw) {
-        feeder<T, MM>(g, vx, vy, G, s0, cf, dummy, (wave - nlw) * 64 + lane);
+        feeder<T, WS, MM>(g, vx, vy, G, rings, cf, sink, (wave - nlw) * 64 + lane);
     } else if (wave < kt) {
-        levels<T, true>(g, ox, oy, G, s0, s1, cf, dummy, wave + 1, lane);
+        level_wave<T, WS>(g, ox, oy, G, rings, cf, wave + 1, lane);
     } else {  // remainder: columns 64.. of every level
         const int R = Wm - 64, j = (wave - kt) * 64 + lane;
         const int s = j / R + 1;
-        levels<T, false>(g, ox, oy, G, s0, s1, cf, dummy, s, s > kt ? 0 : 64 + j % R);
+        remainder_wave<T, WS>(g, ox, oy, G, rings, cf, sink, s, s > kt ? 64 : 64 + j % R);
     }
 }
 
-template <typename T, int NTMAX, int MM>
+template <typename T, int NTMAX, int MM, int WS>
 int launch_stream_t(stk_ctx* ctx, const Grid<T>& gg, const RasArgs& a, int nthr, size_t lds, dim3 grid, const T* vx,
                     const T* vy, T* ox, T* oy) {
     static size_t attr_set[64] = {};
     const int dev = ctx->device < 64 ? ctx->device : 63;
     if (lds > attr_set[dev]) {
-        STK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ras_stream<T, NTMAX, MM>),
+        STK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ras_stream<T, NTMAX, MM, WS>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set[dev] = lds;
     }
-    hipLaunchKernelGGL((k_ras_stream<T, NTMAX, MM>), grid, dim3(nthr), lds, ctx->stream, gg, vx, vy, ox, oy, a);
+    hipLaunchKernelGGL((k_ras_stream<T, NTMAX, MM, WS>), grid, dim3(nthr), lds, ctx->stream, gg, vx, vy, ox, oy, a);
     STK_HIP(hipGetLastError());
     return STK_OK;
 }
 
 // Resident workgroups per CU for the instance that serves `nthr` threads with
 // `mm` loads per feeder lane and `lds` bytes.
-template <typename T, int NTM, int MM>
+template <typename T, int NTM, int MM, int WS>
 int occ_one(int nthr, size_t lds) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_ras_stream<T, NTM, MM>),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_ras_stream<T, NTM, MM, WS>),
                                                      nthr, lds) != hipSuccess)
         return 0;
     return n;
 }
-template <typename T, int NTM>
+template <typename T, int NTM, int WS>
 int occ_mm(int mm, int nthr, size_t lds) {
     switch (mm) {
-        case 1: return occ_one<T, NTM, 1>(nthr, lds);
-        case 2: return occ_one<T, NTM, 2>(nthr, lds);
-        default: return occ_one<T, NTM, 3>(nthr, lds);
+        case 1: return occ_one<T, NTM, 1, WS>(nthr, lds);
+        case 2: return occ_one<T, NTM, 2, WS>(nthr, lds);
+        default: return occ_one<T, NTM, 3, WS>(nthr, lds);
     }
 }
-template <typename T>
-int stream_occupancy(int nthr, int mm, size_t lds) {
-    if (nthr <= 256) return occ_mm<T, 256>(mm, nthr, lds);
-    if (nthr <= 512) return occ_mm<T, 512>(mm, nthr, lds);
-    return occ_mm<T, 1024>(mm, nthr, lds);
+// Cached per (device, block size, loads per lane, LDS bytes): the query is
+// slow next to a launch, and every outer iteration asks for up to 8 of them.
+template <typename T, int WS>
+int stream_occupancy(int dev, int nthr, int mm, size_t lds) {
+    struct Entry {
+        int dev, nthr, mm;
+        size_t lds;
+        int n;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const Entry& e : cache)
+            if (e.dev == dev && e.nthr == nthr && e.mm == mm && e.lds == lds) return e.n;
+    }
+    int n;
+    if (nthr <= 256) n = occ_mm<T, 256, WS>(mm, nthr, lds);
+    else if (nthr <= 512) n = occ_mm<T, 512, WS>(mm, nthr, lds);
+    else n = occ_mm<T, 1024, WS>(mm, nthr, lds);
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache.size() < 1024) cache.push_back({dev, nthr, mm, lds, n});
+    return n;
 }
-template <typename T, int NTM>
+template <typename T, int NTM, int WS>
 int launch_mm(stk_ctx* ctx, int mm, const Grid<T>& gg, const RasArgs& a, int nthr, size_t lds, dim3 grid,
               const T* vx, const T* vy, T* ox, T* oy) {
     switch (mm) {
-        case 1: return launch_stream_t<T, NTM, 1>(ctx, gg, a, nthr, lds, grid, vx, vy, ox, oy);
-        case 2: return launch_stream_t<T, NTM, 2>(ctx, gg, a, nthr, lds, grid, vx, vy, ox, oy);
-        default: return launch_stream_t<T, NTM, 3>(ctx, gg, a, nthr, lds, grid, vx, vy, ox, oy);
+        case 1: return launch_stream_t<T, NTM, 1, WS>(ctx, gg, a, nthr, lds, grid, vx, vy, ox, oy);
+        case 2: return launch_stream_t<T, NTM, 2, WS>(ctx, gg, a, nthr, lds, grid, vx, vy, ox, oy);
+        default: return launch_stream_t<T, NTM, 3, WS>(ctx, gg, a, nthr, lds, grid, vx, vy, ox, oy);
     }
 }
 
-template <typename T>
-int try_stream(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, int Tx, int Ty, int h, int kt, int sx, int sy,
-               const void* vx, const void* vy, void* ox, void* oy, bool* done) {
-    *done = false;
-    if (kt < 1) return STK_OK;
-    RasArgs a{};
-    a.Tx = Tx;
-    a.Ty = Ty;
-    a.h = h;
-    a.kt = kt;
-    a.sx = sx;
-    a.sy = sy;
-    a.Wm = (int)std::min<int64_t>((int64_t)Tx + 2 * (int64_t)h, g->nx) + 2;
-    if (a.Wm > WS || kt > 16) return STK_OK;
-    // the output stores address whole arrays through 32-bit buffer offsets
-    if (((size_t)g->ny * g->ld + g->nx + 1) * sizeof(T) >= (size_t)OOB) return STK_OK;
+template <typename T, int WS>
+int try_stream_ws(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, RasArgs a, const void* vx, const void* vy,
+                  void* ox, void* oy, bool* done) {
+    const int kt = a.kt, Tx = a.Tx, Ty = a.Ty, h = a.h;
     const int nthr = 64 * (level_waves(a.Wm, kt) + NF);
     if (nthr > 1024) return STK_OK;
-    const int mm = (6 * a.Wm + 64 * NF - 1) / (64 * NF);  // <= 3 for Wm <= WS
+    const int mm = (6 * a.Wm + 64 * NF - 1) / (64 * NF);  // <= 3 for Wm <= WS_WIDE
     const int ntx = (g->nx + Tx - 1) / Tx + 1, nty = (g->ny + Ty - 1) / Ty + 1;
-    const int rows_per_tile = (int)std::min<int64_t>((int64_t)Ty + 2 * (int64_t)h, g->ny) + 2;
+    // rows of a tile in the stream: at most Ty + 2 min(kt, h + 1), and at most the window's
+    const int D = std::min(kt, h + 1);
+    const int rows_per_tile = (int)std::min<int64_t>(std::min<int64_t>((int64_t)Ty + 2 * (int64_t)h, g->ny) + 2,
+                                                     std::min<int64_t>(Ty, g->ny) + 2 * D);
     // Tiles per workgroup NT: a workgroup streams NT tiles (NT * rows + 2kt + 1 steps);
     // pick the NT that minimises (rounds of resident workgroups) x (steps per workgroup).
+    // Residency counts LDS in 2 KiB granules against the CU's LDS as well as the
+    // occupancy query: a workgroup just over a third of the LDS is resident only
+    // twice per CU, whatever the query says.
     int best_nt = 1;
     double best_cost = 1e300;
     size_t lds = 0;
@@ -440,9 +567,10 @@ int try_stream(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, int Tx, int T
         RasArgs t = a;
         t.NT = NT;
         t.Vmax = NT * rows_per_tile;
-        const size_t l = stream_lds_bytes<T>(t, nthr);
+        const size_t l = stream_lds_bytes<T, WS>(t);
         if (l > (size_t)ctx->lds_max) break;
-        const int per_cu = stream_occupancy<T>(nthr, mm, l);
+        int per_cu = stream_occupancy<T, WS>(ctx->device, nthr, mm, l);
+        if (ctx->lds_cu > 0) per_cu = std::min<int>(per_cu, ctx->lds_cu / (int)((l + 2047) & ~size_t(2047)));
         if (per_cu < 1) break;
         const int64_t nwg = (int64_t)ntx * ((nty + NT - 1) / NT);
         const int64_t slots = (int64_t)per_cu * std::max(ctx->num_cu, 1);
@@ -462,11 +590,31 @@ int try_stream(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, int Tx, int T
     auto* b0 = static_cast<T*>(ox);
     auto* b1 = static_cast<T*>(oy);
     int rc;
-    if (nthr <= 256) rc = launch_mm<T, 256>(ctx, mm, gg, a, nthr, lds, grid, a0, a1, b0, b1);
-    else if (nthr <= 512) rc = launch_mm<T, 512>(ctx, mm, gg, a, nthr, lds, grid, a0, a1, b0, b1);
-    else rc = launch_mm<T, 1024>(ctx, mm, gg, a, nthr, lds, grid, a0, a1, b0, b1);
+    if (nthr <= 256) rc = launch_mm<T, 256, WS>(ctx, mm, gg, a, nthr, lds, grid, a0, a1, b0, b1);
+    else if (nthr <= 512) rc = launch_mm<T, 512, WS>(ctx, mm, gg, a, nthr, lds, grid, a0, a1, b0, b1);
+    else rc = launch_mm<T, 1024, WS>(ctx, mm, gg, a, nthr, lds, grid, a0, a1, b0, b1);
     if (rc == STK_OK) *done = true;
     return rc;
+}
+
+template <typename T>
+int try_stream(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, int Tx, int Ty, int h, int kt, int sx, int sy,
+               const void* vx, const void* vy, void* ox, void* oy, bool* done) {
+    *done = false;
+    if (kt < 1) return STK_OK;
+    RasArgs a{};
+    a.Tx = Tx;
+    a.Ty = Ty;
+    a.h = h;
+    a.kt = kt;
+    a.sx = sx;
+    a.sy = sy;
+    a.Wm = (int)std::min<int64_t>((int64_t)Tx + 2 * (int64_t)h, g->nx) + 2;
+    // (the output stores address one row at a time through 32-bit buffer offsets)
+    if (a.Wm > WS_WIDE || kt > 16 || g->ny + 1 > YMASK || (int64_t)(g->nx + 1) * (int64_t)sizeof(T) >= INT32_MAX)
+        return STK_OK;
+    if (a.Wm <= WS_NARROW) return try_stream_ws<T, WS_NARROW>(ctx, g, gg, a, vx, vy, ox, oy, done);
+    return try_stream_ws<T, WS_WIDE>(ctx, g, gg, a, vx, vy, ox, oy, done);
 }
 
 }  // namespace

@@ -12,6 +12,7 @@ struct stk_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int lds_max = 0;  // bytes of LDS one workgroup may use on this device
+    int lds_cu = 0;   // bytes of LDS per CU
     int num_cu = 0;
     int ras_kernel = 0;  // 0 auto (streaming when it fits), 1 LDS window only, 2 streaming only
     // Scratch slots, grown on demand (device memory).
