@@ -25,9 +25,10 @@
 // written to it, so the products with g = 0 are exact zeros.
 //
 // The waves of a workgroup have fixed roles:
-//   * level waves: wave w < kt owns window columns 0..63 of level w + 1, so
-//     its level, ring slots and row flags are wave-uniform (scalar); the
-//     columns past 64 of every level (window wider than 64) go to the
+//   * level waves: wave w < kt relaxes window columns 0..62 of level w + 1
+//     (lane 63 carries column 63 as their neighbour), so its level, ring
+//     slots and row flags are wave-uniform (scalar) and neighbouring columns
+//     come from neighbouring lanes; columns 63.. of every level go to the
 //     remainder wave(s) after them;
 //   * feeder waves (the last NF): stream the snapshot, viscosities and
 //     right-hand side from HBM into LDS row rings through a PF-row register
@@ -88,8 +89,9 @@ __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(
 // resident workgroups); wider windows take the wide one.
 constexpr int WS_NARROW = 76, WS_WIDE = 96;
 
-// level lanes: 64 per level for columns 0..63, then Wm - 64 per level
-__host__ __device__ inline int level_lanes(int Wm, int kt) { return 64 * kt + kt * (Wm > 64 ? Wm - 64 : 0); }
+// level lanes: 64 per level for columns 0..63 (column 63 only as the right
+// neighbour of column 62), then Wm - 63 per level for columns 63..Wm-1
+__host__ __device__ inline int level_lanes(int Wm, int kt) { return 64 * kt + kt * (Wm > 63 ? Wm - 63 : 0); }
 __host__ __device__ inline int level_waves(int Wm, int kt) { return (level_lanes(Wm, kt) + 63) / 64; }
 
 // LDS: row table | kt level rings | 2kt + 2 coefficient rows | sink for
@@ -247,11 +249,31 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
 }
 
 // ------------------------------------------------------------- level wave --
-// Window columns c = 0..63 of level s (the same for the whole wave): level,
-// ring slots and row flags are scalar.
+// Neighbour exchange inside a wave whose lane is the window column: lane i
+// gets the value of lane i + 1 (DPP wave_shl:1) or of lane i - 1
+// (wave_shr:1); a lane whose source is outside the wave gets 0.
+constexpr int DPP_FROM_NEXT = 0x130, DPP_FROM_PREV = 0x138;
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
+}
+template <int CTRL>
+__device__ __forceinline__ float wave_shift(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+
+// Window columns c = 0..62 of level s (the same for the whole wave): level,
+// ring slots and row flags are scalar.  Of the new row and of the viscosities
+// each lane reads its own column; the neighbouring columns come from the
+// neighbouring lanes.  Lane 63 holds column 63 as the right neighbour of
+// column 62; its own result (which lacks column 64) goes to the sink, and the
+// remainder wave relaxes column 63.
 template <typename T, int WS>
 __device__ __forceinline__ void level_wave(const Grid<T>& g, T* __restrict__ ox, T* __restrict__ oy, const Geo& G,
-                                           T* rings, const T* cf, int s_in, int c) {
+                                           T* rings, const T* cf, T* sink, int s_in, int c) {
     const int s = __builtin_amdgcn_readfirstlane(s_in);
     const int kt = G.kt, RC = G.RC, V = G.V;
     const int* vtab = G.vtab;
@@ -262,12 +284,12 @@ __device__ __forceinline__ void level_wave(const Grid<T>& g, T* __restrict__ ox,
 #pragma unroll
     for (int k = 0; k < RING; ++k) {
         pr[k] = rings + ((s - 1) * RING + ring_slot(k - 2 * s)) * 2 * WS + c;
-        wr[k] = rings + (min(s, kt - 1) * RING + ring_slot(k - 1 - 2 * s)) * 2 * WS + c;
+        wr[k] = c < 63 ? rings + (min(s, kt - 1) * RING + ring_slot(k - 1 - 2 * s)) * 2 * WS + c : sink;
     }
     const T* cfc = cf + c;
     int sa = RC - 1 - 2 * s;  // coefficient slot of row t - 1 - 2s at t = 0
-    const unsigned lane_off = (i >= G.x0 && i < G.x1) ? (unsigned)i * (unsigned)sizeof(T) : OOB;
-    const unsigned rw_off = i == G.nx ? (unsigned)i * (unsigned)sizeof(T) : OOB;
+    const unsigned lane_off = (c < 63 && i >= G.x0 && i < G.x1) ? (unsigned)i * (unsigned)sizeof(T) : OOB;
+    const unsigned rw_off = (c < 63 && i == G.nx) ? (unsigned)i * (unsigned)sizeof(T) : OOB;
 
     // window of level s-1 values at columns c-1, c, c+1: rows a-1, a, a+1
     T wx[3][3], wy[3][3];
@@ -289,21 +311,26 @@ __device__ __forceinline__ void level_wave(const Grid<T>& g, T* __restrict__ ox,
                 wy[1][q] = wy[2][q];
             }
             const T* p = pr[u % RING];
-            wx[2][0] = p[-1];
-            wx[2][1] = p[0];
-            wx[2][2] = p[1];
-            wy[2][0] = p[WS - 1];
-            wy[2][1] = p[WS];
-            wy[2][2] = p[WS + 1];
             const int sa1 = (sa + 1 == RC) ? 0 : sa + 1;
             const int fl = __builtin_amdgcn_readfirstlane(vtab[min(max(a2, 0), V - 1)]);
             const T* row = cfc + sa * (CF_N * WS);
-            const T ecA = row[CF_EC * WS], ecL = row[CF_EC * WS - 1], enR = row[CF_EN * WS + 1];
+            const T xc = p[0], yc = p[WS];
+            const T ecA = row[CF_EC * WS];
             const T gx = row[CF_GX * WS], bx = row[CF_BX * WS], gy = row[CF_GY * WS], by = row[CF_BY * WS];
             const T ent = cfc[sa1 * (CF_N * WS) + CF_EN * WS];
             // every row is relaxed (a row outside the level's cone is never read), and all LDS
             // reads of the step are issued together, ahead of the arithmetic
             __builtin_amdgcn_sched_barrier(0);
+            // columns c - 1 and c + 1 from the neighbouring lanes (lane 0 is the frozen ring
+            // column and lane 63 is discarded: a 0 neighbour will do for both)
+            wx[2][1] = xc;
+            wy[2][1] = yc;
+            wx[2][0] = wave_shift<DPP_FROM_PREV>(xc);
+            wy[2][0] = wave_shift<DPP_FROM_PREV>(yc);
+            wx[2][2] = wave_shift<DPP_FROM_NEXT>(xc);
+            wy[2][2] = wave_shift<DPP_FROM_NEXT>(yc);
+            const T ecL = wave_shift<DPP_FROM_PREV>(ecA);
+            const T enR = wave_shift<DPP_FROM_NEXT>(en_prev);  // eta_n(c + 1, a)
             const T mx = mv_x<T>(wx[1][1], wx[1][0], wx[1][2], wx[0][1], wx[2][1], wy[1][1], wy[1][0], wy[2][1],
                                  wy[2][0], ecL, ecA, en_prev, ent, g.idx, g.idy);
             const T my = mv_y<T>(wy[1][1], wy[1][0], wy[1][2], wy[0][1], wy[2][1], wx[1][1], wx[1][2], wx[0][1],
@@ -326,7 +353,7 @@ __device__ __forceinline__ void level_wave(const Grid<T>& g, T* __restrict__ ox,
 }
 
 // --------------------------------------------------------- remainder wave --
-// Lanes of mixed levels: level s (1..kt) at window column c >= 64, or idle
+// Lanes of mixed levels: level s (1..kt) at window column c >= 63, or idle
 // (s > kt).  Every row is relaxed (results outside a level's cone are not
 // read).  Ring writes of level-kt and idle lanes go to the sink; the level-kt
 // lanes share one row per step, whose flags are read once for the stores.
@@ -468,11 +495,11 @@ __global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __rest
     if (wave >= nlw) {
         feeder<T, WS, MM>(g, vx, vy, G, rings, cf, sink, (wave - nlw) * 64 + lane);
     } else if (wave < kt) {
-        level_wave<T, WS>(g, ox, oy, G, rings, cf, wave + 1, lane);
-    } else {  // remainder: columns 64.. of every level
-        const int R = Wm - 64, j = (wave - kt) * 64 + lane;
+        level_wave<T, WS>(g, ox, oy, G, rings, cf, sink, wave + 1, lane);
+    } else {  // remainder: columns 63.. of every level
+        const int R = Wm - 63, j = (wave - kt) * 64 + lane;
         const int s = j / R + 1;
-        remainder_wave<T, WS>(g, ox, oy, G, rings, cf, sink, s, s > kt ? 64 : 64 + j % R);
+        remainder_wave<T, WS>(g, ox, oy, G, rings, cf, sink, s, s > kt ? 63 : 63 + j % R);
     }
 }
 
