@@ -70,7 +70,19 @@ struct RasArgs {
     int NT;    // tiles per workgroup along y
     int Wm;    // window width bound: min(Tx + 2h, nx) + 2
     int Vmax;  // virtual rows bound: NT * (min(Ty + 2h, ny) + 2)
+    int ntx;   // tile columns (the grid is ntx x tile-row groups, flattened)
+    int nwg;   // workgroups
 };
+
+// Workgroups are dealt to the XCDs round-robin (workgroup w to XCD w mod 8),
+// and each XCD has its own L2.  Renumber them so that each XCD takes one
+// contiguous run of tiles, row-major: tile columns side by side then sit on
+// one XCD at the same time and share the halo columns of their windows in L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_tile(int w, int nwg) {
+    const int q = nwg / NXCD, r = nwg % NXCD, x = w % NXCD;
+    return x * q + min(x, r) + w / NXCD;
+}
 
 // Workgroup barrier that orders LDS only.  __syncthreads() also waits for
 // every outstanding global access (vmcnt(0) on gfx9), which would drain the
@@ -312,7 +324,8 @@ __device__ __forceinline__ void level_wave(const Grid<T>& g, T* __restrict__ ox,
             }
             const T* p = pr[u % RING];
             const int sa1 = (sa + 1 == RC) ? 0 : sa + 1;
-            const int fl = __builtin_amdgcn_readfirstlane(vtab[min(max(a2, 0), V - 1)]);
+            // row flags: only level kt, which stores the owned rows, needs them
+            const int fl = s == kt ? __builtin_amdgcn_readfirstlane(vtab[min(max(a2, 0), V - 1)]) : 0;
             const T* row = cfc + sa * (CF_N * WS);
             const T xc = p[0], yc = p[WS];
             const T ecA = row[CF_EC * WS];
@@ -437,7 +450,9 @@ __global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __rest
     const int tid = threadIdx.x, nthr = blockDim.x;
 
     // ---- this workgroup's tile column and window columns
-    const int x0 = max(0, a.sx + ((int)blockIdx.x - 1) * a.Tx), x1 = min(nx, a.sx + (int)blockIdx.x * a.Tx);
+    const int tw = xcd_tile((int)blockIdx.x, a.nwg);
+    const int bx = tw % a.ntx, by = tw / a.ntx;
+    const int x0 = max(0, a.sx + (bx - 1) * a.Tx), x1 = min(nx, a.sx + bx * a.Tx);
     if (x0 >= x1) return;  // empty tile column: the whole workgroup leaves
     const int X0 = max(x0 - a.h, 0), X1 = min(x1 + a.h, nx);
 
@@ -450,7 +465,7 @@ __global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __rest
     // Tile ty of this workgroup contributes the rows y of [Y0 - 1, Y1] within D of its owned rows.
     const int D = min(kt, a.h + 1);
     const int nty = (ny + a.Ty - 1) / a.Ty + 1;
-    const int tyb = blockIdx.y * a.NT;
+    const int tyb = by * a.NT;
     int V = 0;
     for (int q = 0; q < a.NT; ++q) {
         const int ty = tyb + q;
@@ -611,7 +626,9 @@ int try_stream_ws(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, RasArgs a,
     if (best_cost >= 1e300) return STK_OK;
     a.NT = best_nt;
     a.Vmax = best_nt * rows_per_tile;
-    const dim3 grid((unsigned)ntx, (unsigned)((nty + best_nt - 1) / best_nt));
+    a.ntx = ntx;
+    a.nwg = ntx * ((nty + best_nt - 1) / best_nt);
+    const dim3 grid((unsigned)a.nwg);
     auto* a0 = static_cast<const T*>(vx);
     auto* a1 = static_cast<const T*>(vy);
     auto* b0 = static_cast<T*>(ox);
