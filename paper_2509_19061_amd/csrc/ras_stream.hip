@@ -44,6 +44,7 @@
 
 #include "stencil.hpp"
 #include "stk_internal.hpp"
+#include "wave.hpp"
 
 namespace stk {
 namespace {
@@ -74,15 +75,6 @@ struct RasArgs {
     int nwg;   // workgroups
 };
 
-// Workgroups are dealt to the XCDs round-robin (workgroup w to XCD w mod 8),
-// and each XCD has its own L2.  Renumber them so that each XCD takes one
-// contiguous run of tiles, row-major: tile columns side by side then sit on
-// one XCD at the same time and share the halo columns of their windows in L2.
-constexpr int NXCD = 8;
-__device__ __forceinline__ int xcd_tile(int w, int nwg) {
-    const int q = nwg / NXCD, r = nwg % NXCD, x = w % NXCD;
-    return x * q + min(x, r) + w / NXCD;
-}
 
 // Workgroup barrier that orders LDS only.  __syncthreads() also waits for
 // every outstanding global access (vmcnt(0) on gfx9), which would drain the
@@ -118,20 +110,6 @@ size_t stream_lds_bytes(const RasArgs& a) {
     return align16((size_t)(a.Vmax + 1) * sizeof(int)) + stream_lds_elems<WS>(a.kt) * sizeof(T);
 }
 
-// Bounds-checked output stores: a buffer resource over one row of an output
-// array; a lane with nothing to store passes an out-of-range offset and the
-// hardware drops its write (no branch).
-constexpr unsigned OOB = 0xFFFFFFF0u;
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(void* p, size_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)bytes, 0x00020000);
-}
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void store_out(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
-}
-__device__ __forceinline__ void store_out(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
-}
 
 // Per-workgroup geometry shared by the roles.
 struct Geo {
@@ -149,13 +127,13 @@ struct Geo {
 template <typename T>
 __device__ __forceinline__ void store_row(T* __restrict__ ox, T* __restrict__ oy, const Geo& G, int y, T ux, T uy,
                                           unsigned lane_off, unsigned rw_off) {
-    const __amdgpu_buffer_rsrc_t rox = out_rsrc(ox + (int64_t)y * G.ld, (size_t)(G.nx + 1) * sizeof(T));
-    const __amdgpu_buffer_rsrc_t roy = out_rsrc(oy + (int64_t)y * G.ld, (size_t)G.nx * sizeof(T));
-    store_out(ux, rox, lane_off);
-    store_out(uy, roy, lane_off);
-    if (G.x1 == G.nx) store_out(T(0), rox, rw_off);
+    const __amdgpu_buffer_rsrc_t rox = buf_rsrc(ox + (int64_t)y * G.ld, (size_t)(G.nx + 1) * sizeof(T));
+    const __amdgpu_buffer_rsrc_t roy = buf_rsrc(oy + (int64_t)y * G.ld, (size_t)G.nx * sizeof(T));
+    buf_store(ux, rox, lane_off);
+    buf_store(uy, roy, lane_off);
+    if (G.x1 == G.nx) buf_store(T(0), rox, rw_off);
     if (y == G.ny - 1)
-        store_out(T(0), out_rsrc(oy + (int64_t)G.ny * G.ld, (size_t)G.nx * sizeof(T)), lane_off);
+        buf_store(T(0), buf_rsrc(oy + (int64_t)G.ny * G.ld, (size_t)G.nx * sizeof(T)), lane_off);
 }
 
 // ---------------------------------------------------------------- feeders --
@@ -261,22 +239,6 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
 }
 
 // ------------------------------------------------------------- level wave --
-// Neighbour exchange inside a wave whose lane is the window column: lane i
-// gets the value of lane i + 1 (DPP wave_shl:1) or of lane i - 1
-// (wave_shr:1); a lane whose source is outside the wave gets 0.
-constexpr int DPP_FROM_NEXT = 0x130, DPP_FROM_PREV = 0x138;
-template <int CTRL>
-__device__ __forceinline__ double wave_shift(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
-}
-template <int CTRL>
-__device__ __forceinline__ float wave_shift(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
-}
-
 // Window columns c = 0..62 of level s (the same for the whole wave): level,
 // ring slots and row flags are scalar.  Of the new row and of the viscosities
 // each lane reads its own column; the neighbouring columns come from the
@@ -450,6 +412,8 @@ __global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __rest
     const int tid = threadIdx.x, nthr = blockDim.x;
 
     // ---- this workgroup's tile column and window columns
+    // tiles row-major, renumbered by XCD: tile columns side by side run on one
+    // XCD at the same time and share the halo columns of their windows in L2
     const int tw = xcd_tile((int)blockIdx.x, a.nwg);
     const int bx = tw % a.ntx, by = tw / a.ntx;
     const int x0 = max(0, a.sx + (bx - 1) * a.Tx), x1 = min(nx, a.sx + bx * a.Tx);

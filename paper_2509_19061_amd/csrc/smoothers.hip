@@ -46,18 +46,6 @@ __global__ __launch_bounds__(BX* BY) void k_fold_rhs(int nx, int ny, int64_t ld,
     if (i < nx) by[k] = is_vy_unknown(nx, ny, i, j) ? fy[k] + (p[k] - p[k - ld]) * idy : T(0);
 }
 
-// ---------------------------------------------------------- fused Jacobi --
-// One pass updates vx and vy of cell (i,j) (loop fusion, Sec. 4.1).
-template <typename T>
-__global__ __launch_bounds__(BX* BY) void k_jacobi_fused(Grid<T> g, const T* __restrict__ vx, const T* __restrict__ vy,
-                                                        T* __restrict__ ox, T* __restrict__ oy) {
-    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-    if (i > g.nx || j > g.ny) return;
-    const int64_t k = (int64_t)j * g.ld + i;
-    if (j < g.ny) ox[k] = is_vx_unknown(g.nx, g.ny, i, j) ? jac_vx_global(g, vx, vy, i, j) : T(0);
-    if (i < g.nx) oy[k] = is_vy_unknown(g.nx, g.ny, i, j) ? jac_vy_global(g, vx, vy, i, j) : T(0);
-}
-
 // ---------------------------------------------------------- split Jacobi --
 // Separate vx and vy passes, both from the old iterate (Sec. 5 (ii)).
 template <typename T>
@@ -277,17 +265,11 @@ int launch_fold_rhs(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* f
     return STK_OK;
 }
 
+// Fused Jacobi (one pass updates vx and vy of a cell, Sec. 4.1): the
+// row-streaming kernel (rowstream.hip).
 int launch_jacobi_fused(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega,
                         const void* vx, const void* vy, void* ox, void* oy) {
-    const dim3 grid = cell_grid(g), block(BX, BY);
-    if (dt == STK_F64)
-        hipLaunchKernelGGL(k_jacobi_fused<double>, grid, block, 0, ctx->stream, make_grid<double>(g, f, omega),
-                           (const double*)vx, (const double*)vy, (double*)ox, (double*)oy);
-    else
-        hipLaunchKernelGGL(k_jacobi_fused<float>, grid, block, 0, ctx->stream, make_grid<float>(g, f, omega),
-                           (const float*)vx, (const float*)vy, (float*)ox, (float*)oy);
-    STK_HIP(hipGetLastError());
-    return STK_OK;
+    return launch_jacobi_rows(ctx, dt, g, f, omega, vx, vy, ox, oy);
 }
 
 int launch_jacobi_split(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega,

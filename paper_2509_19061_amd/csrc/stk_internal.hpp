@@ -57,6 +57,8 @@ struct FieldPtrs {
 
 int launch_fold_rhs(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* fx, const void* fy, const void* p,
                     void* bx, void* by);
+int launch_jacobi_rows(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega,
+                       const void* vx, const void* vy, void* ox, void* oy);
 int launch_jacobi_fused(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega,
                         const void* vx, const void* vy, void* ox, void* oy);
 int launch_jacobi_split(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega,
