@@ -227,6 +227,32 @@ def test_tiny_grids_all_variants(ctx, nx, ny):
         assert np.abs(gy - oy).max() <= TOL64 * max(1e-300, np.abs(oy).max()) + 1e-300
 
 
+@pytest.mark.parametrize("nx,ny", [(61, 63), (62, 64), (123, 127), (124, 128), (186, 65)])
+def test_row_streaming_strip_and_segment_edges(ctx, nx, ny):
+    """The row-streaming kernels split the grid into strips of 62 columns and
+    segments of 64 rows (vx has nx + 1 columns, vy ny + 1 rows): exact
+    multiples and one either side, for the fused Jacobi sweep, the residual
+    with a pressure and the energy norm."""
+    from paper_2509_19061_amd import api, fields
+    p = ragged_problem(nx, ny, nx + ny, 1e4)
+    vx0, vy0 = I.random_velocity(p, nx, 1e-2)
+    gx, gy = gpu_smooth(ctx, p, torch.float64, "jacobi_fused", 2, vx0, vy0)
+    ox, oy = S.smooth(p, vx0, vy0, p.fx, p.fy, None, 2, "jacobi_fused")
+    assert normwise(gx, ox) <= TOL64 and normwise(gy, oy) <= TOL64
+    pr = I.random_pressure(p, ny)
+    dp = fields.DeviceProblem(p, torch.float64)
+    vx, vy = dp.velocity(vx0, vy0)
+    pt = dp.field(pr)
+    rx, ry, rp = dp.field(), dp.field(), dp.field()
+    api.residual(ctx, torch.float64, dp.grid, vx, vy, pt, dp.eta_c, dp.eta_n, dp.fx, dp.fy, rx, ry, rp)
+    torch.cuda.synchronize()
+    ax, ay, ap = S.residual(p, vx0, vy0, p.fx, p.fy, pr)
+    assert normwise(dp.get_vx(rx), ax) <= TOL64 and normwise(dp.get_vy(ry), ay) <= TOL64
+    assert normwise(dp.get_cell(rp), ap) <= TOL64
+    e = api.energy_norm(ctx, torch.float64, dp.grid, vx, vy, pt, dp.eta_c, dp.eta_n, dp.fx, dp.fy)
+    np.testing.assert_allclose(e, S.energy(p, vx0, vy0, p.fx, p.fy, pr), rtol=1e-11, atol=0)
+
+
 def test_walls_written_zero_and_garbage_walls_ignored(ctx):
     p = ragged_problem(70, 66, 21, 1e2)
     vx0, vy0 = I.random_velocity(p, 22, 1.0)
