@@ -60,7 +60,7 @@ RAS_TRAFFIC = {"sources_sha256_16": "7584d8c4ee28ff48", "bytes_per_launch": 1.14
 def ras_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("ras_stream.hip", "stencil.hpp"):
+    for f in ("ras_stream.hip", "stencil.hpp", "wave.hpp"):
         with open(os.path.join(ROOT, "paper_2509_19061_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -18,6 +18,7 @@
 
 #include "coarse_stencil.hpp"
 #include "mg_host.hpp"
+#include "rowstream.hpp"
 
 using namespace stk;
 
@@ -298,7 +299,7 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) 
     P->ncj.assign(maxl, 0);
     for (int d = 0; d < maxl; ++d) {
         std::vector<LevelJob<T>> jobs;
-        std::vector<int> pf{0}, pc{0};
+        std::vector<int> pf{0}, pc{0}, pr{0};
         std::vector<CoarseJob<T>> cj;
         for (int q = 0; q < n; ++q) {
             const stk_mg* m = mgs[q];
@@ -306,6 +307,7 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) 
             if (d < nl - 1) {
                 jobs.push_back(level_job<T>(m, d, t));
                 pf.push_back(pf.back() + blocks_of(m->L[d].nx, m->L[d].ny));
+                pr.push_back(pr.back() + rows::workgroups(m->L[d].nx, m->L[d].ny));
                 pc.push_back(pc.back() + blocks_of(m->L[d + 1].nx, m->L[d + 1].ny));
             } else if (d == nl - 1) {
                 const MgLevel& L = m->L[d];
@@ -321,6 +323,12 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) 
             STK_TRY(upload(P, pc, &dpc, s));
             P->fine[d] = Batch{dj, (const int*)dpf, (int)jobs.size(), pf.back()};
             P->crs[d] = Batch{dj, (const int*)dpc, (int)jobs.size(), pc.back()};
+            if (d == 0) {  // the finest level is matrix-free: row-streaming smoothing and residual
+                const void* dpr = nullptr;
+                STK_TRY(upload(P, pr, &dpr, s));
+                P->fine[d].rpre = (const int*)dpr;
+                P->fine[d].rblocks = pr.back();
+            }
         }
         if (!cj.empty()) {
             STK_TRY(upload(P, cj, &P->cjobs[d], s));
@@ -331,7 +339,7 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) 
     std::vector<LevelJob<T>> aj;
     std::vector<VecJob> vj;
     std::vector<XCastJob> xj;
-    std::vector<int> pa{0};
+    std::vector<int> pa{0}, pra{0};
     for (int q = 0; q < n; ++q) {
         stk_mg* m = mgs[q];
         LevelJob<T> J = level_job<T>(m, 0, t);
@@ -343,6 +351,7 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) 
         J.ry = (T*)m->ks[t][VS_Q].y;
         aj.push_back(J);
         pa.push_back(pa.back() + blocks_of(m->L[0].nx, m->L[0].ny));
+        pra.push_back(pra.back() + rows::workgroups(m->L[0].nx, m->L[0].ny));
         VecJob V{};
         V.nx = m->L[0].nx;
         V.ny = m->L[0].ny;
@@ -373,6 +382,12 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) 
     STK_TRY(upload(P, pa, &dpa, s));
     STK_TRY(upload(P, vj, &dvj, s));
     P->apply = Batch{daj, (const int*)dpa, n, pa.back()};
+    {
+        const void* dpra = nullptr;
+        STK_TRY(upload(P, pra, &dpra, s));
+        P->apply.rpre = (const int*)dpra;
+        P->apply.rblocks = pra.back();
+    }
     P->vec = Batch{dvj, (const int*)dpa, n, pa.back()};
     {  // reduction chunks of the vector batch
         std::vector<int> cp{0};

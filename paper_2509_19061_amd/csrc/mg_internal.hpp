@@ -84,6 +84,10 @@ struct Batch {       // a job array resident on the device plus its block prefix
     const int* cpre = nullptr;
     int chunks = 0;
     double* part2 = nullptr;
+    // finest (matrix-free) level: workgroup prefix of the row-streaming kernels
+    // (rowstream.hpp); when set, smoothing and residual use them
+    const int* rpre = nullptr;
+    int rblocks = 0;
 };
 constexpr int SUM_CHUNK = 4096;
 

@@ -14,6 +14,7 @@
 // instance's (nx+1) x (ny+1) index box.
 #include "coarse_stencil.hpp"
 #include "mg_internal.hpp"
+#include "rowstream.hpp"
 #include "stencil.hpp"
 
 namespace stk {
@@ -88,6 +89,65 @@ __global__ __launch_bounds__(NT) void k_mg_jacobi(const LevelJob<T>* __restrict_
     }
     if (j < J.ny) dx_[k] = is_vx_unknown(J.nx, J.ny, i, j) ? jac_vx_global(g, sx, sy, i, j) : T(0);
     if (i < J.nx) dy_[k] = is_vy_unknown(J.nx, J.ny, i, j) ? jac_vy_global(g, sx, sy, i, j) : T(0);
+}
+
+// Finest (matrix-free) level on the row-streaming engine (rowstream.hpp):
+// workgroup b (renumbered by XCD) belongs to the instance with
+// rpre[i] <= b < rpre[i+1], and its waves cover that instance's strips x
+// segments.  Same operands, same stencil functions: the same values as the
+// kernels above.
+template <typename T>
+__device__ __forceinline__ const LevelJob<T>& row_job(const LevelJob<T>* jobs, const int* rpre, int n, int& wv) {
+    const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int inst = find_inst(rpre, n, b);
+    wv = (b - rpre[inst]) * rows::WPB + rows::wave_in_group();
+    return jobs[inst];
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * rows::WPB) void k_mg_jacobi_rows(const LevelJob<T>* __restrict__ jobs,
+                                                                   const int* __restrict__ rpre, int n, T omega,
+                                                                   int dir) {
+    int wv;
+    const LevelJob<T>& J = row_job(jobs, rpre, n, wv);
+    const int nx = J.nx, ny = J.ny;
+    const rows::Place q = rows::place(wv, nx, ny);
+    if (q.y0 >= q.y1) return;  // the whole wave
+    const int i = q.i;
+    const T* sx = dir ? J.wx : J.vx;
+    const T* sy = dir ? J.wy : J.vy;
+    T* dx_ = dir ? J.vx : J.wx;
+    T* dy_ = dir ? J.vy : J.wy;
+    const rows::Loader<T> L = rows::make_loader<T>(sx, sy, J.ec, J.en, J.bx, J.by, nullptr, J.ld, nx, ny, i);
+    const bool xcol = i >= 1 && i <= nx - 1, ycol = i >= 0 && i <= nx - 1;
+    const unsigned col = (unsigned)i * (unsigned)sizeof(T);
+    const unsigned s_x = q.own ? col : OOB, s_y = (q.own && ycol) ? col : OOB;
+    rows::walk_rows<T>(L, q.y0, q.y1, [&](const rows::Row<T>& a, const rows::Row<T>& b, const rows::Row<T>& c, int j) {
+        T ux, uy;
+        rows::jacobi_row<T>(a, b, c, omega, J.idx, J.idy, ux, uy);
+        const bool xu = xcol && j <= ny - 1, yu = ycol && j >= 1 && j <= ny - 1;
+        rows::store_pair<T>(dx_, dy_, J.ld, nx, ny, j, xu ? ux : T(0), yu ? uy : T(0), s_x, s_y);
+    });
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * rows::WPB) void k_mg_residual_rows(const LevelJob<T>* __restrict__ jobs,
+                                                                     const int* __restrict__ rpre, int n) {
+    int wv;
+    const LevelJob<T>& J = row_job(jobs, rpre, n, wv);
+    const int nx = J.nx, ny = J.ny;
+    const rows::Place q = rows::place(wv, nx, ny);
+    if (q.y0 >= q.y1) return;  // the whole wave
+    const int i = q.i;
+    const rows::Loader<T> L = rows::make_loader<T>(J.vx, J.vy, J.ec, J.en, J.bx, J.by, nullptr, J.ld, nx, ny, i);
+    const bool xcol = i >= 1 && i <= nx - 1, ycol = i >= 0 && i <= nx - 1;
+    const unsigned col = (unsigned)i * (unsigned)sizeof(T);
+    const unsigned s_x = q.own ? col : OOB, s_y = (q.own && ycol) ? col : OOB;
+    rows::walk_rows<T>(L, q.y0, q.y1, [&](const rows::Row<T>& a, const rows::Row<T>& b, const rows::Row<T>& c, int j) {
+        const rows::Res<T> r = rows::residual_row<T, T>(a, b, c, false, J.idx, J.idy);
+        const bool xu = xcol && j <= ny - 1, yu = ycol && j >= 1 && j <= ny - 1;
+        rows::store_pair<T>(J.rx, J.ry, J.ld, nx, ny, j, xu ? r.rx : T(0), yu ? r.ry : T(0), s_x, s_y);
+    });
 }
 
 // ---------------------------------------------------------------- residual --
@@ -529,8 +589,12 @@ namespace stk {
 template <typename T>
 int mg_jacobi(stk_ctx* ctx, const Batch& b, double omega, int dir) {
     if (!b.n) return STK_OK;
-    hipLaunchKernelGGL(k_mg_jacobi<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
-                       static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n, T(omega), dir);
+    if (b.rpre)
+        hipLaunchKernelGGL(k_mg_jacobi_rows<T>, dim3(b.rblocks), dim3(64 * rows::WPB), 0, ctx->stream,
+                           static_cast<const LevelJob<T>*>(b.jobs), b.rpre, b.n, T(omega), dir);
+    else
+        hipLaunchKernelGGL(k_mg_jacobi<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
+                           static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n, T(omega), dir);
     STK_LAUNCH_CHECK();
     return STK_OK;
 }
@@ -545,8 +609,12 @@ int mg_copy_wv(stk_ctx* ctx, const Batch& b) {
 template <typename T>
 int mg_residual(stk_ctx* ctx, const Batch& b) {
     if (!b.n) return STK_OK;
-    hipLaunchKernelGGL(k_mg_residual<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
-                       static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n);
+    if (b.rpre)
+        hipLaunchKernelGGL(k_mg_residual_rows<T>, dim3(b.rblocks), dim3(64 * rows::WPB), 0, ctx->stream,
+                           static_cast<const LevelJob<T>*>(b.jobs), b.rpre, b.n);
+    else
+        hipLaunchKernelGGL(k_mg_residual<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
+                           static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n);
     STK_LAUNCH_CHECK();
     return STK_OK;
 }
