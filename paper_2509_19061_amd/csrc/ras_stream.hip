@@ -50,7 +50,7 @@ namespace stk {
 namespace {
 
 constexpr int U = 6;     // steps per unrolled group
-constexpr int PF = 6;    // feeder FIFO depth in rows
+constexpr int PF = 3;    // feeder FIFO depth in rows
 // rows per level ring (levels 0..kt-1; level 0 = the snapshot): at step t row t - 2s
 // of level s - 1 is read while row t + 1 - 2s of it is written, and row t - 1 - 2s is
 // read at the next step, so three rows suffice
