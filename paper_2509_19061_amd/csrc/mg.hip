@@ -382,11 +382,21 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) 
     STK_TRY(upload(P, pa, &dpa, s));
     STK_TRY(upload(P, vj, &dvj, s));
     P->apply = Batch{daj, (const int*)dpa, n, pa.back()};
-    {
+    {  // row-streaming prefix of the operator batch and its reduction chunks
         const void* dpra = nullptr;
         STK_TRY(upload(P, pra, &dpra, s));
         P->apply.rpre = (const int*)dpra;
         P->apply.rblocks = pra.back();
+        std::vector<int> cp{0};
+        for (int q = 0; q < n; ++q) cp.push_back(cp.back() + (pra[q + 1] - pra[q] + SUM_CHUNK - 1) / SUM_CHUNK);
+        const void* dcp = nullptr;
+        void* p2 = nullptr;
+        STK_TRY(upload(P, cp, &dcp, s));
+        STK_TRY(pdalloc(P, sizeof(double) * 2 * (size_t)std::max(1, cp.back()), &p2, s));
+        P->applyr = Batch{nullptr, (const int*)dpra, n, pra.back()};
+        P->applyr.cpre = static_cast<const int*>(dcp);
+        P->applyr.chunks = cp.back();
+        P->applyr.part2 = static_cast<double*>(p2);
     }
     P->vec = Batch{dvj, (const int*)dpa, n, pa.back()};
     {  // reduction chunks of the vector batch

@@ -35,7 +35,8 @@ struct PlanT {
     std::vector<Batch> fine, crs;       // per depth: fine-block and coarse-block batches of LevelJob
     std::vector<const void*> cjobs;     // per depth: CoarseJob array of instances whose coarsest it is
     std::vector<int> ncj;
-    Batch apply;                        // finest: v = P, b = 0, r = Q  ->  Q = A P
+    Batch apply;                        // finest: v = P, no right-hand side, r = Q  ->  Q = A P
+    Batch applyr;                       // reduction chunks over the row-streaming prefix of `apply`
     Batch vec;                          // VecJob array
     Batch xcast;                        // XCastJob array (FP32 plan only)
     FcgState* st = nullptr;

@@ -116,9 +116,9 @@ struct GalerkinArgs {
 };
 int mg_galerkin(stk_ctx* ctx, const GalerkinArgs& g);
 
+// (q = A p and p.q are one fused pass: fcg_apply_pq)
 enum VecOp {
-    OP_PQ = 0,      // acc0 += p.q
-    OP_UPDATE,      // x += alpha p; r += alpha q; acc0 += r^2/d
+    OP_UPDATE = 0,  // x += alpha p; r += alpha q; acc0 += r^2/d
     OP_RZ_ZQ,       // acc0 += r.z ; acc1 += z.q  (rho = -r: gamma = -acc0)
     OP_XPBY,        // p = z + beta p
     OP_FNORM,       // acc0 += f^2/d
@@ -150,6 +150,11 @@ struct XCastJob {
 int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st, int up);
 // per-instance sums of the block partials, in a fixed order: chunk sums, then chunks in order
 int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums);
+// FP64 FCG, finest level: Q = A P and per-instance P . Q into sums (apply:
+// the operator batch with its row-streaming prefix; red: the reduction chunks
+// over that prefix)
+int fcg_apply_pq(stk_ctx* ctx, const Batch& apply, const Batch& red, const FcgState* st, double* part,
+                 double* sums);
 template <typename T> int mg_copy_wv(stk_ctx* ctx, const Batch& b);
 
 }  // namespace stk

@@ -404,9 +404,6 @@ __global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, con
             T* P = static_cast<T*>(J.v[VS_P][c]);
             T* Q = static_cast<T*>(J.v[VS_Q][c]);
             switch (op) {
-                case OP_PQ:
-                    if (u) a0 += (double)P[k] * (double)Q[k];
-                    break;
                 case OP_UPDATE:
                     if (u) {
                         X[k] = T((double)X[k] + al * (double)P[k]);
@@ -415,14 +412,14 @@ __global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, con
                         a0 += (double)r * (double)r / (c == 0 ? dgx(J, i, j) : dgy(J, i, j));
                     }
                     break;
+                case OP_XPBY:
+                    P[k] = u ? T((double)Z[k] + be * (double)P[k]) : T(0);
+                    break;
                 case OP_RZ_ZQ:
                     if (u) {
                         a0 += (double)R[k] * (double)Z[k];
                         a1 += (double)Z[k] * (double)Q[k];
                     }
-                    break;
-                case OP_XPBY:
-                    P[k] = u ? T((double)Z[k] + be * (double)P[k]) : T(0);
                     break;
                 case OP_FNORM: {
                     const double* F = static_cast<const double*>(J.v[VS_F][c]);
@@ -440,6 +437,54 @@ __global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, con
         }
     }
     block_sum2(a0, a1, part);
+}
+
+// FCG operator apply on the finest level fused with its dot product: Q = A P
+// = -(M P) and the partial sums of P . Q, one per workgroup in part[2 b]
+// (workgroup b in the rpre numbering; part[2 b + 1] = 0), in one
+// row-streaming pass.  Jobs: v = P, no right-hand side, r = Q.  P is only
+// read (updating it here in place would race with the neighbouring waves'
+// halo reads).  Inactive instances are left as they are (zero partials).
+__global__ __launch_bounds__(64 * rows::WPB) void k_fcg_apply_rows(const LevelJob<double>* __restrict__ jobs,
+                                                                   const int* __restrict__ rpre, int n,
+                                                                   const FcgState* __restrict__ st,
+                                                                   double* __restrict__ part) {
+    const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int inst = find_inst(rpre, n, b);
+    const LevelJob<double>& J = jobs[inst];
+    const int wv = (b - rpre[inst]) * rows::WPB + rows::wave_in_group();
+    const int nx = J.nx, ny = J.ny;
+    const rows::Place q = rows::place(wv, nx, ny);
+    double pq = 0.0;
+    if (st[inst].active && q.y0 < q.y1) {
+        const int i = q.i;
+        const rows::Loader<double> L =
+            rows::make_loader<double>(J.vx, J.vy, J.ec, J.en, nullptr, nullptr, nullptr, J.ld, nx, ny, i);
+        const bool xcol = i >= 1 && i <= nx - 1, ycol = i >= 0 && i <= nx - 1;
+        const unsigned col = (unsigned)i * (unsigned)sizeof(double);
+        const unsigned s_x = q.own ? col : OOB, s_y = (q.own && ycol) ? col : OOB;
+        rows::walk_rows<double>(L, q.y0, q.y1,
+                                [&](const rows::Row<double>& a, const rows::Row<double>& c0, const rows::Row<double>& c,
+                                    int j) {
+                                    const rows::Res<double> r = rows::residual_row<double, double>(a, c0, c, false,
+                                                                                                  J.idx, J.idy);
+                                    const bool xu = xcol && j <= ny - 1, yu = ycol && j >= 1 && j <= ny - 1;
+                                    rows::store_pair<double>(J.rx, J.ry, J.ld, nx, ny, j, xu ? r.rx : 0.0,
+                                                             yu ? r.ry : 0.0, s_x, s_y);
+                                    if (q.own && xu) pq += c0.vx * r.rx;
+                                    if (q.own && yu) pq += c0.vy * r.ry;
+                                });
+    }
+    __shared__ double red[rows::WPB];
+    pq = wave_sum(pq);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < rows::WPB; ++w) s += red[w];
+        part[2 * b] = s;
+        part[2 * b + 1] = 0.0;
+    }
 }
 
 // r32 = (float) r64 (up = 0) or z64 = (double) z32 (up = 1), walls included
@@ -684,6 +729,16 @@ int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums) {
                        (const double*)b.part2, sums);
     STK_LAUNCH_CHECK();
     return STK_OK;
+}
+
+int fcg_apply_pq(stk_ctx* ctx, const Batch& apply, const Batch& red, const FcgState* st, double* part,
+                 double* sums) {
+    if (!apply.n) return STK_OK;
+    if (!apply.rpre) return set_error(STK_EINVAL, "internal: operator batch without row-streaming prefix");
+    hipLaunchKernelGGL(k_fcg_apply_rows, dim3(apply.rblocks), dim3(64 * rows::WPB), 0, ctx->stream,
+                       static_cast<const LevelJob<double>*>(apply.jobs), apply.rpre, apply.n, st, part);
+    STK_LAUNCH_CHECK();
+    return inst_sums(ctx, red, part, sums);
 }
 
 int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st, int up) {

@@ -61,8 +61,8 @@ struct Loader {
         q.vy = buf_load<T>(buf_rsrc(vy + o, wy), o_cell);
         q.ec = buf_load<T>(buf_rsrc(ec + o, wx), o_cell);
         q.en = buf_load<T>(buf_rsrc(en + o, wy), o_inner);
-        q.bx = buf_load<T>(buf_rsrc(bx + o, wx), o_inner);
-        q.by = buf_load<T>(buf_rsrc(by + o, wy), o_cell);
+        q.bx = bx ? buf_load<T>(buf_rsrc(bx + o, wx), o_inner) : T(0);  // no right-hand side: b = 0
+        q.by = by ? buf_load<T>(buf_rsrc(by + o, wy), o_cell) : T(0);
         q.p = p ? buf_load<T>(buf_rsrc(p + o, wx), o_cell) : T(0);
         return q;
     }
@@ -96,9 +96,10 @@ __device__ __forceinline__ Place place(int wv, int nx, int ny) {
 __device__ __forceinline__ int wave_in_group() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
 // Walks rows y0 .. y1-1 with the window (a, b, c) = rows (j-1, j, j+1),
-// loading row j+2 while row j is processed; body(a, b, c, j).
-template <typename T, typename F>
-__device__ __forceinline__ void walk_rows(const Loader<T>& L, int y0, int y1, F body) {
+// loading row j+2 while row j is processed; body(a, b, c, j).  L is any
+// loader with Row<T> load(int r).
+template <typename T, typename LD, typename F>
+__device__ __forceinline__ void walk_rows(const LD& L, int y0, int y1, F body) {
     Row<T> r0 = L.load(y0 - 1), r1 = L.load(y0), r2 = L.load(y0 + 1), r3;
     for (int j = y0; j < y1; j += 4) {  // four rows per trip: the window rotates by renaming
         r3 = L.load(j + 2);

@@ -197,8 +197,7 @@ int iterate_phase(stk_batch* b, int iters) {
     for (int q = 0; q < n; ++q) h[q] = b->slots[b->members[q]].fs;
     STK_TRY(write_states(ctx, P, h));
     for (int it = 0; it < iters; ++it) {
-        STK_TRY(mg_residual<double>(ctx, P.apply));  // Q = 0 - M P = A P
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_PQ, P.st, P.part, P.sums));
+        STK_TRY(fcg_apply_pq(ctx, P.apply, P.applyr, P.st, P.part, P.sums));  // Q = A P and P . Q
         STK_TRY(fcg_scalars(ctx, P.st, P.sums, n, PH_ALPHA));
         STK_TRY(vec_op<double>(ctx, P.vec, OP_UPDATE, P.st, P.part, P.sums));
         STK_TRY(fcg_scalars(ctx, P.st, P.sums, n, PH_NV));
