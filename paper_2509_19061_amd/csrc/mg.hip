@@ -20,6 +20,10 @@
 #include "mg_host.hpp"
 #include "rowstream.hpp"
 
+namespace {
+constexpr int RAS_TILE = 64;  // tile of the finest-level RAS smoothing (the paper's 64 x 64)
+}
+
 using namespace stk;
 
 namespace stk {
@@ -328,6 +332,28 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) 
                 STK_TRY(upload(P, pr, &dpr, s));
                 P->fine[d].rpre = (const int*)dpr;
                 P->fine[d].rblocks = pr.back();
+                // RAS smoothing v -> w -> v, and the level jobs with v and w exchanged
+                std::vector<RasJob<T>> vw, wv;
+                std::vector<LevelJob<T>> sw;
+                for (const LevelJob<T>& J : jobs) {
+                    const int ntx = (J.nx + RAS_TILE - 1) / RAS_TILE;
+                    vw.push_back(RasJob<T>{J.ec, J.en, J.bx, J.by, J.ld, J.nx, J.ny, J.idx, J.idy, J.vx, J.vy, J.wx,
+                                           J.wy, ntx});
+                    wv.push_back(RasJob<T>{J.ec, J.en, J.bx, J.by, J.ld, J.nx, J.ny, J.idx, J.idy, J.wx, J.wy, J.vx,
+                                           J.vy, ntx});
+                    LevelJob<T> X = J;
+                    std::swap(X.vx, X.wx);
+                    std::swap(X.vy, X.wy);
+                    sw.push_back(X);
+                    P->l0nx.push_back(J.nx);
+                    P->l0ny.push_back(J.ny);
+                }
+                STK_TRY(upload(P, vw, &P->ras_jobs[0], s));
+                STK_TRY(upload(P, wv, &P->ras_jobs[1], s));
+                const void* dsw = nullptr;
+                STK_TRY(upload(P, sw, &dsw, s));
+                P->fine0w = P->fine[d];
+                P->fine0w.jobs = dsw;
             }
         }
         if (!cj.empty()) {
@@ -439,6 +465,32 @@ int make_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT** out) {
 }
 
 // ---- the batched V-cycle on the level-0 binding (v = Z slot, b = R slot)
+// Launch shape of the finest-level RAS smoothing for k sweeps (cached per k).
+static const PlanT::RasK* ras_shape(stk_ctx* ctx, const PlanT& P, int kt, stk_dtype dt) {
+    for (const PlanT::RasK& r : P.ras_k)
+        if (r.kt == kt) return r.ok ? &r : nullptr;
+    PlanT::RasK r{kt, false, RasShape{}, nullptr};
+    std::vector<int> pre, ntx;
+    if (!P.l0nx.empty())
+        ras_batch_shape(ctx, dt, P.l0nx.data(), P.l0ny.data(), (int)P.l0nx.size(), RAS_TILE, kt, kt, &r.shape, &pre,
+                        &ntx, &r.ok);
+    if (r.ok) {
+        void* d = nullptr;
+        if (hipMalloc(&d, pre.size() * sizeof(int)) != hipSuccess) {
+            r.ok = false;
+        } else {
+            P.mem.push_back(d);
+            if (hipMemcpyAsync(d, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream) !=
+                    hipSuccess ||
+                hipStreamSynchronize(ctx->stream) != hipSuccess)
+                r.ok = false;
+            r.pre = static_cast<const int*>(d);
+        }
+    }
+    P.ras_k.push_back(r);
+    return r.ok ? &P.ras_k.back() : nullptr;
+}
+
 template <typename T>
 static int smooth_stage(stk_ctx* ctx, const Batch& F, const stk_mg_opts& o, int nu) {
     for (int q = 0; q < nu; ++q) STK_TRY(mg_jacobi<T>(ctx, F, o.omega, q & 1));
@@ -447,12 +499,28 @@ static int smooth_stage(stk_ctx* ctx, const Batch& F, const stk_mg_opts& o, int 
 }
 template <typename T>
 static int vcycle(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o) {
+    // Finest level: pre-smoothing v -> w and post-smoothing w -> v as one RAS
+    // outer iteration each (the iterate is in w in between), when the streaming
+    // kernel takes the instances; else Jacobi sweeps.
+    const stk_dtype dt = sizeof(T) == 8 ? STK_F64 : STK_F32;
+    const PlanT::RasK* pre_s = nullptr;
+    const PlanT::RasK* post_s = nullptr;
+    if (P.ras_jobs[0] && o.nu1 >= 1 && o.nu2 >= 1) {
+        pre_s = ras_shape(ctx, P, o.nu1, dt);
+        post_s = ras_shape(ctx, P, o.nu2, dt);
+    }
+    const bool ras0 = pre_s && post_s;
     STK_TRY(mg_coarse<T>(ctx, P.cjobs[0], P.ncj[0], P.maxcn));
     for (int d = 0; d < P.depth; ++d) {
         const Batch& F = P.fine[d];
         if (!F.n) break;
-        STK_TRY(smooth_stage<T>(ctx, F, o, o.nu1));
-        STK_TRY(mg_residual<T>(ctx, F));
+        if (d == 0 && ras0) {
+            STK_TRY(ras_batch_launch(ctx, dt, pre_s->shape, P.ras_jobs[0], pre_s->pre, P.fine0w.n, o.omega));
+            STK_TRY(mg_residual<T>(ctx, P.fine0w));
+        } else {
+            STK_TRY(smooth_stage<T>(ctx, F, o, o.nu1));
+            STK_TRY(mg_residual<T>(ctx, F));
+        }
         STK_TRY(mg_zero_coarse<T>(ctx, P.crs[d]));
         STK_TRY(mg_restrict<T>(ctx, P.crs[d]));
         if (d + 1 < (int)P.cjobs.size()) STK_TRY(mg_coarse<T>(ctx, P.cjobs[d + 1], P.ncj[d + 1], P.maxcn));
@@ -460,8 +528,13 @@ static int vcycle(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o) {
     for (int d = P.depth - 1; d >= 0; --d) {
         const Batch& F = P.fine[d];
         if (!F.n) continue;
-        STK_TRY(mg_prolong<T>(ctx, F));
-        STK_TRY(smooth_stage<T>(ctx, F, o, o.nu2));
+        if (d == 0 && ras0) {
+            STK_TRY(mg_prolong<T>(ctx, P.fine0w));
+            STK_TRY(ras_batch_launch(ctx, dt, post_s->shape, P.ras_jobs[1], post_s->pre, P.fine0w.n, o.omega));
+        } else {
+            STK_TRY(mg_prolong<T>(ctx, F));
+            STK_TRY(smooth_stage<T>(ctx, F, o, o.nu2));
+        }
     }
     return STK_OK;
 }

@@ -35,6 +35,21 @@ struct PlanT {
     std::vector<Batch> fine, crs;       // per depth: fine-block and coarse-block batches of LevelJob
     std::vector<const void*> cjobs;     // per depth: CoarseJob array of instances whose coarsest it is
     std::vector<int> ncj;
+    // finest level smoothed by batched RAS outer iterations (64 x 64 tiles, halo
+    // = k = the sweep count, so each is k Jacobi sweeps exactly): job arrays
+    // v -> w and w -> v, the finest-level jobs with v and w exchanged (residual
+    // and prolongation while the iterate is in w), the instances' sizes, and
+    // the launch shape per k (built on first use)
+    const void* ras_jobs[2] = {nullptr, nullptr};
+    Batch fine0w;
+    std::vector<int> l0nx, l0ny;
+    struct RasK {
+        int kt;
+        bool ok;
+        RasShape shape;
+        const int* pre;
+    };
+    mutable std::vector<RasK> ras_k;
     Batch apply;                        // finest: v = P, no right-hand side, r = Q  ->  Q = A P
     Batch applyr;                       // reduction chunks over the row-streaming prefix of `apply`
     Batch vec;                          // VecJob array
@@ -42,7 +57,7 @@ struct PlanT {
     FcgState* st = nullptr;
     double* part = nullptr;
     double* sums = nullptr;
-    std::vector<void*> mem;
+    mutable std::vector<void*> mem;
     std::vector<std::vector<unsigned char>> stage;  // host sources of pending uploads
     void release() {
         for (void* p : mem) (void)hipFree(p);

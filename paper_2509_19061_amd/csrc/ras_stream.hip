@@ -403,19 +403,17 @@ __device__ __forceinline__ void remainder_wave(const Grid<T>& g, T* __restrict__
 }
 
 // MM = HBM loads per feeder lane per row (6 fields x Wm / (64 NF)).
-template <typename T, int NTMAX, int MM, int WS>
-__global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __restrict__ vx, const T* __restrict__ vy,
-                                                      T* __restrict__ ox, T* __restrict__ oy, RasArgs a) {
+// One workgroup: tile column bx, tile rows by*NT .. by*NT + NT - 1.
+template <typename T, int MM, int WS>
+__device__ __forceinline__ void ras_workgroup(const Grid<T>& g, const T* __restrict__ vx, const T* __restrict__ vy,
+                                              T* __restrict__ ox, T* __restrict__ oy, const RasArgs& a, int bx,
+                                              int by) {
     extern __shared__ unsigned char smem_raw[];
     const int nx = g.nx, ny = g.ny;
     const int kt = a.kt, Wm = a.Wm;
     const int tid = threadIdx.x, nthr = blockDim.x;
 
     // ---- this workgroup's tile column and window columns
-    // tiles row-major, renumbered by XCD: tile columns side by side run on one
-    // XCD at the same time and share the halo columns of their windows in L2
-    const int tw = xcd_tile((int)blockIdx.x, a.nwg);
-    const int bx = tw % a.ntx, by = tw / a.ntx;
     const int x0 = max(0, a.sx + (bx - 1) * a.Tx), x1 = min(nx, a.sx + bx * a.Tx);
     if (x0 >= x1) return;  // empty tile column: the whole workgroup leaves
     const int X0 = max(x0 - a.h, 0), X1 = min(x1 + a.h, nx);
@@ -480,6 +478,35 @@ __global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __rest
         const int s = j / R + 1;
         remainder_wave<T, WS>(g, ox, oy, G, rings, cf, sink, s, s > kt ? 63 : 63 + j % R);
     }
+}
+
+template <typename T, int NTMAX, int MM, int WS>
+__global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __restrict__ vx, const T* __restrict__ vy,
+                                                      T* __restrict__ ox, T* __restrict__ oy, RasArgs a) {
+    // tiles row-major, renumbered by XCD: tile columns side by side run on one
+    // XCD at the same time and share the halo columns of their windows in L2
+    const int tw = xcd_tile((int)blockIdx.x, a.nwg);
+    ras_workgroup<T, MM, WS>(g, vx, vy, ox, oy, a, tw % a.ntx, tw / a.ntx);
+}
+
+// Batched: workgroup b (renumbered by XCD over the whole batch) belongs to
+// the instance with pre[i] <= b < pre[i+1]; the launch shape (tile, halo, k,
+// tiles per workgroup, window bound) is shared, the geometry is the
+// instance's, shifts are 0.
+template <typename T, int NTMAX, int MM, int WS>
+__global__ __launch_bounds__(NTMAX) void k_ras_batch(const RasJob<T>* __restrict__ jobs, const int* __restrict__ pre,
+                                                     int n, RasArgs a, T omega) {
+    const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const RasJob<T>& J = jobs[lo];
+    const Grid<T> g{J.ec, J.en, J.bx, J.by, J.ld, J.nx, J.ny, J.idx, J.idy, omega};
+    const int tw = b - pre[lo];
+    ras_workgroup<T, MM, WS>(g, J.vx, J.vy, J.ox, J.oy, a, tw % J.ntx, tw / J.ntx);
 }
 
 template <typename T, int NTMAX, int MM, int WS>
@@ -625,6 +652,116 @@ int try_stream(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, int Tx, int T
     return try_stream_ws<T, WS_WIDE>(ctx, g, gg, a, vx, vy, ox, oy, done);
 }
 
+// ------------------------------------------------------------------ batched --
+template <typename T, int NTMAX, int MM, int WS>
+int launch_batch_t(stk_ctx* ctx, const RasShape& sh, const void* jobs, const int* pre, int n, T omega) {
+    static size_t attr_set[64] = {};
+    const int dev = ctx->device < 64 ? ctx->device : 63;
+    if (sh.lds > attr_set[dev]) {
+        STK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ras_batch<T, NTMAX, MM, WS>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds));
+        attr_set[dev] = sh.lds;
+    }
+    RasArgs a{};
+    a.Tx = a.Ty = sh.tile;
+    a.h = sh.h;
+    a.kt = sh.kt;
+    a.sx = a.sy = sh.tile;  // cuts at multiples of the tile, the first tile at 0
+    a.NT = sh.NT;
+    a.Wm = sh.Wm;
+    a.Vmax = sh.Vmax;
+    hipLaunchKernelGGL((k_ras_batch<T, NTMAX, MM, WS>), dim3((unsigned)sh.nwg), dim3(sh.nthr), sh.lds, ctx->stream,
+                       static_cast<const RasJob<T>*>(jobs), pre, n, a, omega);
+    STK_HIP(hipGetLastError());
+    return STK_OK;
+}
+template <typename T, int NTM, int WS>
+int launch_batch_mm(stk_ctx* ctx, const RasShape& sh, const void* jobs, const int* pre, int n, T omega) {
+    switch (sh.mm) {
+        case 1: return launch_batch_t<T, NTM, 1, WS>(ctx, sh, jobs, pre, n, omega);
+        case 2: return launch_batch_t<T, NTM, 2, WS>(ctx, sh, jobs, pre, n, omega);
+        default: return launch_batch_t<T, NTM, 3, WS>(ctx, sh, jobs, pre, n, omega);
+    }
+}
+template <typename T, int WS>
+int launch_batch_ws(stk_ctx* ctx, const RasShape& sh, const void* jobs, const int* pre, int n, T omega) {
+    if (sh.nthr <= 256) return launch_batch_mm<T, 256, WS>(ctx, sh, jobs, pre, n, omega);
+    if (sh.nthr <= 512) return launch_batch_mm<T, 512, WS>(ctx, sh, jobs, pre, n, omega);
+    return launch_batch_mm<T, 1024, WS>(ctx, sh, jobs, pre, n, omega);
+}
+
+// Same model as try_stream_ws over the whole batch: the occupancy of the
+// single-grid instance (same body) and the LDS granule bound.
+template <typename T, int WS>
+void batch_shape_ws(stk_ctx* ctx, const int* nx, const int* ny, int n, int tile, int h, int kt, int Wm,
+                    RasShape* out, std::vector<int>* pre, std::vector<int>* ntxv, bool* ok) {
+    *ok = false;
+    const int nthr = 64 * (level_waves(Wm, kt) + NF);
+    if (nthr > 1024) return;
+    const int mm = (6 * Wm + 64 * NF - 1) / (64 * NF);
+    const int D = std::min(kt, h + 1);
+    int rows = 0;
+    for (int q = 0; q < n; ++q)
+        rows = std::max<int>(rows, (int)std::min<int64_t>(std::min<int64_t>((int64_t)tile + 2 * (int64_t)h, ny[q]) + 2,
+                                                          std::min<int64_t>(tile, ny[q]) + 2 * D));
+    double best_cost = 1e300;
+    for (int NT = 1; NT <= 8; ++NT) {
+        RasArgs t{};
+        t.kt = kt;
+        t.Vmax = NT * rows;
+        const size_t l = stream_lds_bytes<T, WS>(t);
+        if (l > (size_t)ctx->lds_max) break;
+        int per_cu = stream_occupancy<T, WS>(ctx->device, nthr, mm, l);
+        if (ctx->lds_cu > 0) per_cu = std::min<int>(per_cu, ctx->lds_cu / (int)((l + 2047) & ~size_t(2047)));
+        if (per_cu < 1) break;
+        int64_t nwg = 0;
+        for (int q = 0; q < n; ++q) {
+            const int ntx = (nx[q] + tile - 1) / tile, nty = (ny[q] + tile - 1) / tile;
+            nwg += (int64_t)ntx * ((nty + NT - 1) / NT);
+        }
+        const int64_t slots = (int64_t)per_cu * std::max(ctx->num_cu, 1);
+        const double cost = (double)((nwg + slots - 1) / slots) * (NT * rows + 2 * kt + 1);
+        if (cost < best_cost && nwg < INT32_MAX) {
+            best_cost = cost;
+            out->NT = NT;
+            out->Vmax = NT * rows;
+            out->lds = l;
+            out->nwg = (int)nwg;
+        }
+    }
+    if (best_cost >= 1e300) return;
+    out->tile = tile;
+    out->h = h;
+    out->kt = kt;
+    out->Wm = Wm;
+    out->nthr = nthr;
+    out->mm = mm;
+    out->ws = WS;
+    pre->assign(1, 0);
+    ntxv->clear();
+    for (int q = 0; q < n; ++q) {
+        const int ntx = (nx[q] + tile - 1) / tile, nty = (ny[q] + tile - 1) / tile;
+        ntxv->push_back(ntx);
+        pre->push_back(pre->back() + ntx * ((nty + out->NT - 1) / out->NT));
+    }
+    *ok = true;
+}
+
+template <typename T>
+void batch_shape(stk_ctx* ctx, const int* nx, const int* ny, int n, int tile, int h, int kt, RasShape* out,
+                 std::vector<int>* pre, std::vector<int>* ntx, bool* ok) {
+    *ok = false;
+    if (n < 1 || kt < 1 || kt > 16 || tile < 1) return;
+    int Wm = 0;
+    for (int q = 0; q < n; ++q) {
+        if (ny[q] + 1 > YMASK || (int64_t)(nx[q] + 1) * (int64_t)sizeof(T) >= INT32_MAX) return;
+        Wm = std::max<int>(Wm, (int)std::min<int64_t>((int64_t)tile + 2 * (int64_t)h, nx[q]) + 2);
+    }
+    if (Wm > WS_WIDE) return;
+    if (Wm <= WS_NARROW) batch_shape_ws<T, WS_NARROW>(ctx, nx, ny, n, tile, h, kt, Wm, out, pre, ntx, ok);
+    else batch_shape_ws<T, WS_WIDE>(ctx, nx, ny, n, tile, h, kt, Wm, out, pre, ntx, ok);
+}
+
 }  // namespace
 
 int launch_ras_stream(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega, int tile_x,
@@ -640,6 +777,27 @@ int launch_ras_stream(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const Field
                    static_cast<const float*>(f.bx), static_cast<const float*>(f.by), g->ld, g->nx, g->ny,
                    float(1.0 / g->dx), float(1.0 / g->dy), float(omega)};
     return try_stream<float>(ctx, g, gg, tile_x, tile_y, halo, kt, sx, sy, vx, vy, ox, oy, done);
+}
+
+}  // namespace stk
+
+namespace stk {
+
+int ras_batch_shape(stk_ctx* ctx, stk_dtype dt, const int* nx, const int* ny, int n, int tile, int h, int kt,
+                    RasShape* out, std::vector<int>* pre, std::vector<int>* ntx, bool* ok) {
+    if (dt == STK_F64) batch_shape<double>(ctx, nx, ny, n, tile, h, kt, out, pre, ntx, ok);
+    else batch_shape<float>(ctx, nx, ny, n, tile, h, kt, out, pre, ntx, ok);
+    return STK_OK;
+}
+
+int ras_batch_launch(stk_ctx* ctx, stk_dtype dt, const RasShape& s, const void* jobs, const int* pre, int n,
+                     double omega) {
+    if (n < 1 || s.nwg < 1) return STK_OK;
+    if (dt == STK_F64)
+        return s.ws == WS_NARROW ? launch_batch_ws<double, WS_NARROW>(ctx, s, jobs, pre, n, omega)
+                                 : launch_batch_ws<double, WS_WIDE>(ctx, s, jobs, pre, n, omega);
+    return s.ws == WS_NARROW ? launch_batch_ws<float, WS_NARROW>(ctx, s, jobs, pre, n, float(omega))
+                             : launch_batch_ws<float, WS_WIDE>(ctx, s, jobs, pre, n, float(omega));
 }
 
 }  // namespace stk

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "stk.h"
 
@@ -73,6 +74,33 @@ int launch_ras(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f
 int launch_ras_stream(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega, int tile_x,
                       int tile_y, int halo, int kt, int sx, int sy, const void* vx, const void* vy, void* ox, void* oy,
                       bool* done);
+// One instance of a batched RAS outer iteration: its grid's fields, the
+// snapshot and the result (device pointers, common row stride ld).
+template <typename T>
+struct RasJob {
+    const T *ec, *en, *bx, *by;
+    int64_t ld;
+    int nx, ny;
+    T idx, idy;
+    const T *vx, *vy;
+    T *ox, *oy;
+    int ntx;  // tile columns
+};
+// Launch shape of a batched RAS outer iteration, shared by its instances.
+struct RasShape {
+    int tile, h, kt, NT, Wm, Vmax, nthr, mm, ws, nwg;
+    size_t lds;
+};
+// Shape for instances of nx[i] x ny[i] cells (square tiles cut at multiples
+// of the tile, halo h, kt sweeps): fills the workgroup prefix pre[0..n] and
+// each instance's tile columns; *ok = false when the streaming kernel cannot
+// take them (window or LDS too large).
+int ras_batch_shape(stk_ctx* ctx, stk_dtype dt, const int* nx, const int* ny, int n, int tile, int h, int kt,
+                    RasShape* out, std::vector<int>* pre, std::vector<int>* ntx, bool* ok);
+// One outer iteration of every instance of a RasJob array (device) with the
+// shape above; pre: the device copy of the prefix.
+int ras_batch_launch(stk_ctx* ctx, stk_dtype dt, const RasShape& s, const void* jobs, const int* pre, int n,
+                     double omega);
 int launch_copy_velocity(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, void* ox,
                          void* oy);
 int launch_residual(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* p,
