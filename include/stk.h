@@ -194,9 +194,11 @@ int stk_energy_norm(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* v
  * them, mirrored at the free-slip walls), restricts with R = P^T / 4, uses
  * Galerkin coarse operators M_c = R M P (a row has 31 couplings; M_c is
  * symmetric and each coupling is stored once, 32 * (ny_c+1) * ld_c words per
- * coarse level; the finest level is matrix-free), smooths with damped Jacobi (bit-identical to RAS with
- * halo >= k - 1) and solves the coarsest level exactly in FP64 (dense inverse
- * of -M_c built at setup). */
+ * coarse level; the finest level is matrix-free), smooths with damped Jacobi
+ * (on the finest level each smoothing stage is one RAS-Jacobi outer
+ * iteration with 64 x 64 tiles and halo = k = the sweep count, bit-identical
+ * to that many Jacobi sweeps) and solves the coarsest level exactly in FP64
+ * (dense inverse of -M_c built at setup). */
 typedef struct {
     int nu1, nu2;      /* pre / post smoothing sweeps per level (default 2, 2)                 */
     double omega;      /* Jacobi damping (default 0.7)                                          */
