@@ -2,6 +2,7 @@
 // code (mg.hip) and the solve and batch engine (solve.hip).
 #pragma once
 
+#include <deque>
 #include <vector>
 
 #include "mg_internal.hpp"
@@ -49,7 +50,7 @@ struct PlanT {
         RasShape shape;
         const int* pre;
     };
-    mutable std::vector<RasK> ras_k;
+    mutable std::deque<RasK> ras_k;  // deque: entries keep their address as more are added
     Batch apply;                        // finest: v = P, no right-hand side, r = Q  ->  Q = A P
     Batch applyr;                       // reduction chunks over the row-streaming prefix of `apply`
     Batch vec;                          // VecJob array

@@ -111,6 +111,12 @@ size_t stream_lds_bytes(const RasArgs& a) {
 }
 
 
+// The scaled-stencil constants in scalar registers.
+template <typename T>
+__device__ __forceinline__ Scale<T> uniform_scale(const Scale<T>& s) {
+    return {wave_uniform(s.a), wave_uniform(s.n), wave_uniform(s.kap), wave_uniform(s.ry), wave_uniform(s.rx)};
+}
+
 // Per-workgroup geometry shared by the roles.
 struct Geo {
     int nx, ny;
@@ -137,37 +143,46 @@ __device__ __forceinline__ void store_row(T* __restrict__ ox, T* __restrict__ oy
 }
 
 // ---------------------------------------------------------------- feeders --
-// Feeder lane fid (0 .. 64 NF - 1).  Task m = (field, window column): row t of
-// it goes to LDS at step t, row t + PF is loaded at step t (unconditionally,
-// from a row clamped into the array; the validity of the value is applied when
-// it leaves the FIFO, so no load sits under a branch that would wait for it).
-// Lanes past the last task repeat it (same value to the same place).  Then
-// omega / diag of row t - 2 for every window cell, 0 for a cell that is not
-// relaxed (ring row or column, wall, outside the grid).
+// Feeder lane fid (0 .. 64 NF - 1).  Load slot 0 carries the snapshot (vx,
+// vy: 2 Wm tasks) into the level-0 ring; slots 1 .. MM-1 carry eta_c, eta_n,
+// bx, by (4 Wm tasks) into the coefficient rows, eta_c as A = 2 eta_c idx^2
+// and eta_n as N = eta_n idx idy (the scaled stencil coefficients).  Row t of
+// a task goes to LDS at step t, row t + PF is loaded at step t
+// (unconditionally, from a row clamped into the array; the validity of the
+// value is applied when it leaves the FIFO, so no load sits under a branch
+// that would wait for it).  Lanes past the last task of a slot repeat it
+// (same value to the same place).  Then omega / diag of row t - 2 for every
+// window cell, 0 for a cell that is not relaxed (ring row or column, wall,
+// outside the grid).
+__host__ __device__ inline int feeder_loads(int Wm) { return 1 + (4 * Wm + 64 * NF - 1) / (64 * NF); }
+
 template <typename T, int WS, int MM>
 __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ vx, const T* __restrict__ vy,
                                        const Geo& G, T* rings, T* cf, T* sink, int fid) {
-    const int nx = G.nx, ny = G.ny, Wm = G.Wm, W = G.W, RC = G.RC, V = G.V, ci0 = G.ci0;
+    const int nx = g.nx, ny = g.ny, Wm = G.Wm, W = G.W, RC = G.RC, V = G.V, ci0 = G.ci0;
     const int64_t ld = G.ld;
     const int* vtab = G.vtab;
-    const int nq = 6 * Wm;
+    const Scale<T> sc = uniform_scale(stencil_scale(g.idx, g.idy));
     const T* tbase[MM];
-    int tdst[MM];  // element offset of the task's column in its ring row
+    int tdst[MM];  // element offset of the task's column in its ring or coefficient row
     int tylo[MM];
-    bool tok[MM], ts0[MM];
+    bool tok[MM];
+    // slot 1 holds every eta_c and eta_n task (64 NF >= 2 Wm); its scale: 2 idx^2 for
+    // eta_c, idx idy for eta_n, 1 for the rest
+    const T tsc1 = fid < Wm ? sc.a : fid < 2 * Wm ? sc.n : T(1);
 #pragma unroll
     for (int m = 0; m < MM; ++m) {
-        const int q = min(fid + m * 64 * NF, nq - 1);
-        const int f = q / Wm, cq = q - f * Wm, ii = ci0 + cq;
+        const int q = m == 0 ? min(fid, 2 * Wm - 1) : min(fid + (m - 1) * 64 * NF, 4 * Wm - 1);
+        const int fl = q / Wm, cq = q - fl * Wm, ii = ci0 + cq;
         // field f: 0 vx, 1 vy, 2 eta_c, 3 eta_n (boundary nodes 0), 4 bx, 5 by
+        const int f = (m == 0 ? 0 : 2) + fl;
         const T* b = f == 0 ? vx : f == 1 ? vy : f == 2 ? g.ec : f == 3 ? g.en : f == 4 ? g.bx : g.by;
         const bool xface = (f == 0 || f == 4), yface = (f == 1 || f == 5);
         const bool colok = (xface || f == 3) ? (ii >= 1 && ii <= nx - 1) : (ii >= 0 && ii <= nx - 1);
         tok[m] = colok;
         tbase[m] = b + (colok ? ii : 0);
         tylo[m] = (yface || f == 3) ? 1 : 0;  // vy, by, eta_n-hat live on rows 1..ny-1
-        ts0[m] = f < 2;
-        tdst[m] = f < 2 ? f * WS + cq : (f - 2) * WS + cq;
+        tdst[m] = fl * WS + cq;
     }
     // omega / diag task of this lane: value v (0..Wm-1: vx, Wm..2Wm-1: vy)
     const int v = fid;  // 64 NF >= 2 Wm: one value per lane
@@ -178,9 +193,10 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
     const bool gcol = bl && cq >= 1 && cq <= W - 2 && (cy ? ii <= nx - 1 : (ii >= 1 && ii <= nx - 1));
     const int gylo = cy ? 1 : 0;
     auto row_off = [&](int y) -> int64_t { return (int64_t)min(max(y, 0), ny - 1) * ld; };
-    // omega / diag reads: e0 = eta_c left (vx) or below (vy), n1 = eta_n above (vx) or right (vy)
+    // diag reads: e0 = A left (vx) or below (vy), n1 = N above (vx) or right (vy); for vy
+    // the normal-stress coefficients are B = A kap and the shear terms carry rx
     const int off_e0 = CF_EC * WS + cq - (cy ? 0 : 1), off_n1 = CF_EN * WS + cq + (cy ? 1 : 0);
-    const T ix = cy ? g.idy : g.idx, iy = cy ? g.idx : g.idy;
+    const T kl = cy ? sc.kap : T(1), rr = cy ? sc.rx : sc.ry;
     T fifo[PF][MM];
     int ff[PF];  // flags of the row each FIFO slot holds (uniform; 0 past the last row)
 #pragma unroll
@@ -197,7 +213,7 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + u, q = u % PF;
-            // (B, reads) viscosities around row t - 2, written at steps t - 3 .. t - 1
+            // (B, reads) coefficients around row t - 2, written at steps t - 3 .. t - 1
             const int sr = rA >= 2 ? rA - 2 : rA + RC - 2;
             const int sm = sr >= 1 ? sr - 1 : RC - 1, sp = sr + 1 == RC ? 0 : sr + 1;
             const T e0 = cf[(cy ? sm : sr) * CF_N * WS + off_e0];
@@ -206,14 +222,16 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
             const T n1 = cf[(cy ? sr : sp) * CF_N * WS + off_n1];
             __builtin_amdgcn_sched_barrier(0);
             const int ff_t = ff[q];  // flags of row t
-            {  // (A) row t: FIFO -> LDS rings; loads of row t + PF
+            {  // (A) row t: FIFO -> LDS (slot 0 to the level-0 ring, the others to the
+               //     coefficient row); loads of row t + PF
                 T* r0 = rings + (u % RING) * 2 * WS;
                 T* rc = cf + rA * CF_N * WS;
                 const int y = (ff_t & YMASK) - 1;
 #pragma unroll
                 for (int m = 0; m < MM; ++m) {
                     const bool ok = tok[m] && y >= tylo[m] && y <= ny - 1;
-                    (ts0[m] ? r0 : rc)[tdst[m]] = ok ? fifo[q][m] : T(0);
+                    const T val = m == 1 ? fifo[q][m] * tsc1 : fifo[q][m];
+                    (m == 0 ? r0 : rc)[tdst[m]] = ok ? val : T(0);
                 }
                 const int fnext = __builtin_amdgcn_readfirstlane(fn);
                 ff[q] = fnext;
@@ -222,11 +240,11 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
                 for (int m = 0; m < MM; ++m) fifo[q][m] = tbase[m][yo];
                 fn = t + PF + 1 < V ? vtab[t + PF + 1] : 0;
             }
-            {  // (B) omega / diag for row t - 2 (diag_y is diag_x with the roles of x and y exchanged);
-               //     0 for a cell that is not relaxed, and for no row (t < 2 or past the last row)
+            {  // (B) omega / diag for row t - 2; 0 for a cell that is not relaxed, and for no
+               //     row (t < 2 or past the last row)
                 const int yr = (f2 & YMASK) - 1;
                 const bool upd = gcol && !(f2 & F_RING) && yr >= gylo && yr <= ny - 1;
-                const T d = diag_x<T>(e0, e1, n0, n1, ix, iy);
+                const T d = fmaT(n0 + n1, rr, e0 * kl + e1 * kl);
                 T* dst = bl ? cf + sr * CF_N * WS + (cy ? CF_GY : CF_GX) * WS + cq : sink;
                 *dst = (upd ? g.omega : T(0)) / (upd ? d : T(1));
             }
@@ -240,18 +258,19 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
 
 // ------------------------------------------------------------- level wave --
 // Window columns c = 0..62 of level s (the same for the whole wave): level,
-// ring slots and row flags are scalar.  Of the new row and of the viscosities
-// each lane reads its own column; the neighbouring columns come from the
-// neighbouring lanes.  Lane 63 holds column 63 as the right neighbour of
-// column 62; its own result (which lacks column 64) goes to the sink, and the
-// remainder wave relaxes column 63.
-template <typename T, int WS>
-__device__ __forceinline__ void level_wave(const Grid<T>& g, T* __restrict__ ox, T* __restrict__ oy, const Geo& G,
-                                           T* rings, const T* cf, T* sink, int s_in, int c) {
-    const int s = __builtin_amdgcn_readfirstlane(s_in);
+// ring slots and row flags are scalar.  Of the new row and of the
+// coefficients each lane reads its own column; the neighbouring columns come
+// from the neighbouring lanes.  Lane 63 holds column 63 as the right
+// neighbour of column 62; its own result (which lacks column 64) goes to the
+// sink, and the remainder wave relaxes column 63.  TOP: s == kt, the level
+// that stores the owned rows to HBM instead of writing a ring.
+template <typename T, int WS, bool TOP>
+__device__ __forceinline__ void level_loop(const Grid<T>& g, T* __restrict__ ox, T* __restrict__ oy, const Geo& G,
+                                           T* rings, const T* cf, T* sink, int s, int c) {
     const int kt = G.kt, RC = G.RC, V = G.V;
     const int* vtab = G.vtab;
     const int i = G.ci0 + c;
+    const Scale<T> sc = uniform_scale(stencil_scale(g.idx, g.idy));
     // step t = t0 + u (t0 % RING == 0) reads level s-1 row t - 2s and writes level s row t - 1 - 2s
     const T* pr[RING];
     T* wr[RING];
@@ -271,7 +290,7 @@ __device__ __forceinline__ void level_wave(const Grid<T>& g, T* __restrict__ ox,
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int q = 0; q < 3; ++q) wx[r][q] = wy[r][q] = T(0);
-    T ec_prev = T(0), en_prev = T(0);  // eta_c(c, a-1), eta_n-hat(c, a)
+    T b_prev = T(0), n_prev = T(0);  // B(c, a-1), N(c, a)
 
     for (int t0 = 0; t0 < G.nsteps; t0 += U) {
 #pragma unroll
@@ -286,13 +305,13 @@ __device__ __forceinline__ void level_wave(const Grid<T>& g, T* __restrict__ ox,
             }
             const T* p = pr[u % RING];
             const int sa1 = (sa + 1 == RC) ? 0 : sa + 1;
-            // row flags: only level kt, which stores the owned rows, needs them
-            const int fl = s == kt ? __builtin_amdgcn_readfirstlane(vtab[min(max(a2, 0), V - 1)]) : 0;
+            // row flags: only the level that stores the owned rows needs them
+            const int fl = TOP ? __builtin_amdgcn_readfirstlane(vtab[min(max(a2, 0), V - 1)]) : 0;
             const T* row = cfc + sa * (CF_N * WS);
             const T xc = p[0], yc = p[WS];
-            const T ecA = row[CF_EC * WS];
+            const T aA = row[CF_EC * WS];
             const T gx = row[CF_GX * WS], bx = row[CF_BX * WS], gy = row[CF_GY * WS], by = row[CF_BY * WS];
-            const T ent = cfc[sa1 * (CF_N * WS) + CF_EN * WS];
+            const T nt = cfc[sa1 * (CF_N * WS) + CF_EN * WS];
             // every row is relaxed (a row outside the level's cone is never read), and all LDS
             // reads of the step are issued together, ahead of the arithmetic
             __builtin_amdgcn_sched_barrier(0);
@@ -304,27 +323,35 @@ __device__ __forceinline__ void level_wave(const Grid<T>& g, T* __restrict__ ox,
             wy[2][0] = wave_shift<DPP_FROM_PREV>(yc);
             wx[2][2] = wave_shift<DPP_FROM_NEXT>(xc);
             wy[2][2] = wave_shift<DPP_FROM_NEXT>(yc);
-            const T ecL = wave_shift<DPP_FROM_PREV>(ecA);
-            const T enR = wave_shift<DPP_FROM_NEXT>(en_prev);  // eta_n(c + 1, a)
-            const T mx = mv_x<T>(wx[1][1], wx[1][0], wx[1][2], wx[0][1], wx[2][1], wy[1][1], wy[1][0], wy[2][1],
-                                 wy[2][0], ecL, ecA, en_prev, ent, g.idx, g.idy);
-            const T my = mv_y<T>(wy[1][1], wy[1][0], wy[1][2], wy[0][1], wy[2][1], wx[1][1], wx[1][2], wx[0][1],
-                                 wx[0][2], ec_prev, ecA, en_prev, enR, g.idx, g.idy);
+            const T aL = wave_shift<DPP_FROM_PREV>(aA);     // A(c - 1, a)
+            const T nR = wave_shift<DPP_FROM_NEXT>(n_prev);  // N(c + 1, a)
+            const T bA = coef_b(aA, sc);
+            const T mx = mvx_scaled<T>(wx[1][1], wx[1][0], wx[1][2], wx[0][1], wx[2][1], wy[1][1], wy[1][0], wy[2][1],
+                                       wy[2][0], aL, aA, n_prev, nt, sc.ry);
+            const T my = mvy_scaled<T>(wy[1][1], wy[1][0], wy[1][2], wy[0][1], wy[2][1], wx[1][1], wx[1][2], wx[0][1],
+                                       wx[0][2], b_prev, bA, n_prev, nR, sc.rx);
             const T ux = jac_step<T>(wx[1][1], gx, bx, mx);
             const T uy = jac_step<T>(wy[1][1], gy, by, my);
-            if (s < kt) {
+            if (!TOP) {
                 T* w = wr[u % RING];
                 w[0] = ux;
                 w[WS] = uy;
             } else if (a2 >= 0 && a2 < V && (fl & F_OWNED)) {
                 store_row<T>(ox, oy, G, (fl & YMASK) - 1, ux, uy, lane_off, rw_off);
             }
-            ec_prev = ecA;
-            en_prev = ent;
+            b_prev = bA;
+            n_prev = nt;
             sa = sa1;
             lds_barrier();
         }
     }
+}
+template <typename T, int WS>
+__device__ __forceinline__ void level_wave(const Grid<T>& g, T* __restrict__ ox, T* __restrict__ oy, const Geo& G,
+                                           T* rings, const T* cf, T* sink, int s_in, int c) {
+    const int s = __builtin_amdgcn_readfirstlane(s_in);
+    if (s == G.kt) level_loop<T, WS, true>(g, ox, oy, G, rings, cf, sink, s, c);
+    else level_loop<T, WS, false>(g, ox, oy, G, rings, cf, sink, s, c);
 }
 
 // --------------------------------------------------------- remainder wave --
@@ -347,6 +374,7 @@ __device__ __forceinline__ void remainder_wave(const Grid<T>& g, T* __restrict__
         wr[k] = sl < kt ? rings + (sl * RING + ring_slot(k - 1 - 2 * sl)) * 2 * WS + c : sink;
     }
     const T* cfc = cf + c;
+    const Scale<T> sc = uniform_scale(stencil_scale(g.idx, g.idy));
     int sa = RC - 1 - 2 * sl;
     const bool top = s == kt;
     const unsigned lane_off = (top && i >= G.x0 && i < G.x1) ? (unsigned)i * (unsigned)sizeof(T) : OOB;
@@ -357,7 +385,7 @@ __device__ __forceinline__ void remainder_wave(const Grid<T>& g, T* __restrict__
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int q = 0; q < 3; ++q) wx[r][q] = wy[r][q] = T(0);
-    T ec_prev = T(0), en_prev = T(0);
+    T b_prev = T(0), n_prev = T(0);  // B(c, a-1), N(c, a)
 
     for (int t0 = 0; t0 < G.nsteps; t0 += U) {
 #pragma unroll
@@ -378,31 +406,34 @@ __device__ __forceinline__ void remainder_wave(const Grid<T>& g, T* __restrict__
             wy[2][2] = p[WS + 1];
             const int sa1 = (sa + 1 == RC) ? 0 : sa + 1;
             const T* row = cfc + sa * (CF_N * WS);
-            const T ecA = row[CF_EC * WS], ecL = row[CF_EC * WS - 1], enR = row[CF_EN * WS + 1];
-            const T gx = row[CF_GX * WS], bx = row[CF_BX * WS], gy = row[CF_GY * WS], by = row[CF_BY * WS];
-            const T ent = cfc[sa1 * (CF_N * WS) + CF_EN * WS];
+            const T aA = row[CF_EC * WS], aL = row[CF_EC * WS - 1], nR = row[CF_EN * WS + 1];
+            const T nt = cfc[sa1 * (CF_N * WS) + CF_EN * WS];
             const int ak = t0 + u - 1 - 2 * kt;  // the row of the level-kt lanes
             const int flk = __builtin_amdgcn_readfirstlane(vtab[min(max(ak, 0), V - 1)]);
             __builtin_amdgcn_sched_barrier(0);
-            const T mx = mv_x<T>(wx[1][1], wx[1][0], wx[1][2], wx[0][1], wx[2][1], wy[1][1], wy[1][0], wy[2][1],
-                                 wy[2][0], ecL, ecA, en_prev, ent, g.idx, g.idy);
-            const T my = mv_y<T>(wy[1][1], wy[1][0], wy[1][2], wy[0][1], wy[2][1], wx[1][1], wx[1][2], wx[0][1],
-                                 wx[0][2], ec_prev, ecA, en_prev, enR, g.idx, g.idy);
+            const T bA = coef_b(aA, sc);
+            const T mx = mvx_scaled<T>(wx[1][1], wx[1][0], wx[1][2], wx[0][1], wx[2][1], wy[1][1], wy[1][0], wy[2][1],
+                                       wy[2][0], aL, aA, n_prev, nt, sc.ry);
+            const T my = mvy_scaled<T>(wy[1][1], wy[1][0], wy[1][2], wy[0][1], wy[2][1], wx[1][1], wx[1][2], wx[0][1],
+                                       wx[0][2], b_prev, bA, n_prev, nR, sc.rx);
+            // the update's factors are read after the operator values: fewer registers in flight
+            __builtin_amdgcn_sched_barrier(0);
+            const T gx = row[CF_GX * WS], bx = row[CF_BX * WS], gy = row[CF_GY * WS], by = row[CF_BY * WS];
             const T ux = jac_step<T>(wx[1][1], gx, bx, mx);
             const T uy = jac_step<T>(wy[1][1], gy, by, my);
             T* w = wr[u % RING];
             w[0] = ux;
             w[WS] = uy;
             if (ak >= 0 && ak < V && (flk & F_OWNED)) store_row<T>(ox, oy, G, (flk & YMASK) - 1, ux, uy, lane_off, rw_off);
-            ec_prev = ecA;
-            en_prev = ent;
+            b_prev = bA;
+            n_prev = nt;
             sa = sa1;
             lds_barrier();
         }
     }
 }
 
-// MM = HBM loads per feeder lane per row (6 fields x Wm / (64 NF)).
+// MM = HBM loads per feeder lane per row (feeder_loads).
 // One workgroup: tile column bx, tile rows by*NT .. by*NT + NT - 1.
 template <typename T, int MM, int WS>
 __device__ __forceinline__ void ras_workgroup(const Grid<T>& g, const T* __restrict__ vx, const T* __restrict__ vy,
@@ -480,8 +511,15 @@ __device__ __forceinline__ void ras_workgroup(const Grid<T>& g, const T* __restr
     }
 }
 
+// Waves per SIMD the register allocation must leave room for (at most 72
+// VGPRs each): an FP64 workgroup of up to 8 waves (k <= 4 with T = 64) is
+// resident three or four times per CU, 6 to 7 waves per SIMD, and the waves
+// of a workgroup do not always spread evenly over the SIMDs.  Other sizes are
+// bound by LDS or by their own wave count first.
+constexpr int ras_waves_per_simd(int nthr) { return nthr == 512 ? 7 : 1; }
+
 template <typename T, int NTMAX, int MM, int WS>
-__global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __restrict__ vx, const T* __restrict__ vy,
+__global__ __launch_bounds__(NTMAX, ras_waves_per_simd(NTMAX)) void k_ras_stream(Grid<T> g, const T* __restrict__ vx, const T* __restrict__ vy,
                                                       T* __restrict__ ox, T* __restrict__ oy, RasArgs a) {
     // tiles row-major, renumbered by XCD: tile columns side by side run on one
     // XCD at the same time and share the halo columns of their windows in L2
@@ -494,7 +532,7 @@ __global__ __launch_bounds__(NTMAX) void k_ras_stream(Grid<T> g, const T* __rest
 // tiles per workgroup, window bound) is shared, the geometry is the
 // instance's, shifts are 0.
 template <typename T, int NTMAX, int MM, int WS>
-__global__ __launch_bounds__(NTMAX) void k_ras_batch(const RasJob<T>* __restrict__ jobs, const int* __restrict__ pre,
+__global__ __launch_bounds__(NTMAX, ras_waves_per_simd(NTMAX)) void k_ras_batch(const RasJob<T>* __restrict__ jobs, const int* __restrict__ pre,
                                                      int n, RasArgs a, T omega) {
     const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     int lo = 0, hi = n - 1;
@@ -537,7 +575,6 @@ int occ_one(int nthr, size_t lds) {
 template <typename T, int NTM, int WS>
 int occ_mm(int mm, int nthr, size_t lds) {
     switch (mm) {
-        case 1: return occ_one<T, NTM, 1, WS>(nthr, lds);
         case 2: return occ_one<T, NTM, 2, WS>(nthr, lds);
         default: return occ_one<T, NTM, 3, WS>(nthr, lds);
     }
@@ -570,7 +607,6 @@ template <typename T, int NTM, int WS>
 int launch_mm(stk_ctx* ctx, int mm, const Grid<T>& gg, const RasArgs& a, int nthr, size_t lds, dim3 grid,
               const T* vx, const T* vy, T* ox, T* oy) {
     switch (mm) {
-        case 1: return launch_stream_t<T, NTM, 1, WS>(ctx, gg, a, nthr, lds, grid, vx, vy, ox, oy);
         case 2: return launch_stream_t<T, NTM, 2, WS>(ctx, gg, a, nthr, lds, grid, vx, vy, ox, oy);
         default: return launch_stream_t<T, NTM, 3, WS>(ctx, gg, a, nthr, lds, grid, vx, vy, ox, oy);
     }
@@ -582,7 +618,7 @@ int try_stream_ws(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, RasArgs a,
     const int kt = a.kt, Tx = a.Tx, Ty = a.Ty, h = a.h;
     const int nthr = 64 * (level_waves(a.Wm, kt) + NF);
     if (nthr > 1024) return STK_OK;
-    const int mm = (6 * a.Wm + 64 * NF - 1) / (64 * NF);  // <= 3 for Wm <= WS_WIDE
+    const int mm = feeder_loads(a.Wm);  // 2 or 3 for Wm <= WS_WIDE
     const int ntx = (g->nx + Tx - 1) / Tx + 1, nty = (g->ny + Ty - 1) / Ty + 1;
     // rows of a tile in the stream: at most Ty + 2 min(kt, h + 1), and at most the window's
     const int D = std::min(kt, h + 1);
@@ -678,7 +714,6 @@ int launch_batch_t(stk_ctx* ctx, const RasShape& sh, const void* jobs, const int
 template <typename T, int NTM, int WS>
 int launch_batch_mm(stk_ctx* ctx, const RasShape& sh, const void* jobs, const int* pre, int n, T omega) {
     switch (sh.mm) {
-        case 1: return launch_batch_t<T, NTM, 1, WS>(ctx, sh, jobs, pre, n, omega);
         case 2: return launch_batch_t<T, NTM, 2, WS>(ctx, sh, jobs, pre, n, omega);
         default: return launch_batch_t<T, NTM, 3, WS>(ctx, sh, jobs, pre, n, omega);
     }
@@ -698,7 +733,7 @@ void batch_shape_ws(stk_ctx* ctx, const int* nx, const int* ny, int n, int tile,
     *ok = false;
     const int nthr = 64 * (level_waves(Wm, kt) + NF);
     if (nthr > 1024) return;
-    const int mm = (6 * Wm + 64 * NF - 1) / (64 * NF);
+    const int mm = feeder_loads(Wm);
     const int D = std::min(kt, h + 1);
     int rows = 0;
     for (int q = 0; q < n; ++q)

@@ -50,6 +50,19 @@ __device__ __forceinline__ float wave_shift(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
 
+// A value that is the same in every lane, moved to scalar registers (FP64
+// arithmetic leaves its results in vector registers even when they are
+// uniform; kernels that are short of vector registers keep them scalar).
+__device__ __forceinline__ double wave_uniform(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
+}
+__device__ __forceinline__ float wave_uniform(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
 // Workgroups are dealt to the XCDs round-robin (workgroup w to XCD w mod 8),
 // and each XCD has its own L2.  This renumbering gives each XCD one contiguous
 // run of the workgroup index space, so that workgroups with neighbouring
