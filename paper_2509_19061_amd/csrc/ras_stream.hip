@@ -180,8 +180,8 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
         const bool xface = (f == 0 || f == 4), yface = (f == 1 || f == 5);
         const bool colok = (xface || f == 3) ? (ii >= 1 && ii <= nx - 1) : (ii >= 0 && ii <= nx - 1);
         tok[m] = colok;
-        tbase[m] = b + (colok ? ii : 0);
         tylo[m] = (yface || f == 3) ? 1 : 0;  // vy, by, eta_n-hat live on rows 1..ny-1
+        tbase[m] = b + (colok ? ii : 0);
         tdst[m] = fl * WS + cq;
     }
     // omega / diag task of this lane: value v (0..Wm-1: vx, Wm..2Wm-1: vy)
@@ -246,7 +246,8 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
                 const bool upd = gcol && !(f2 & F_RING) && yr >= gylo && yr <= ny - 1;
                 const T d = fmaT(n0 + n1, rr, e0 * kl + e1 * kl);
                 T* dst = bl ? cf + sr * CF_N * WS + (cy ? CF_GY : CF_GX) * WS + cq : sink;
-                *dst = (upd ? g.omega : T(0)) / (upd ? d : T(1));
+                const T gf = jac_factor(g.omega, d);  // not finite where d is 0: not selected
+                *dst = upd ? gf : T(0);
             }
             f2 = f1;
             f1 = ff_t;

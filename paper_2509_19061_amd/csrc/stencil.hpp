@@ -50,8 +50,28 @@ __device__ __forceinline__ T ldenh(const Grid<T>& g, int i, int j) {
 __host__ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __host__ __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// The Jacobi factor g = omega / d (d = diag(-M) > 0): a reciprocal estimate
+// refined by Newton steps r <- r + r (1 - d r), then one residual correction
+// of the quotient q <- q + r (omega - d q) (Markstein's scheme).  No range
+// scaling: a diagonal of the viscous operator is far from the limits of the
+// format.  Every kernel takes its factor from here.
+__device__ __forceinline__ double jac_factor(double omega, double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fmaT(r, fmaT(-d, r, 1.0), r);
+    r = fmaT(r, fmaT(-d, r, 1.0), r);
+    const double q = omega * r;
+    return fmaT(fmaT(-d, q, omega), r, q);
+}
+__device__ __forceinline__ float jac_factor(float omega, float d) {
+    float r = __builtin_amdgcn_rcpf(d);
+    r = fmaT(r, fmaT(-d, r, 1.0f), r);
+    const float q = omega * r;
+    return fmaT(fmaT(-d, q, omega), r, q);
+}
+
 // The damped Jacobi step from the operator value m = (Mv) at the unknown and
-// g = omega / diag(-M): v' = v - g (b - m).  Every kernel ends in this call.
+// g = jac_factor(omega, diag(-M)): v' = v - g (b - m).  Every kernel ends in
+// this call.
 template <typename T>
 __device__ __forceinline__ T jac_step(T vc, T g, T b, T m) {
     return fmaT(-g, b - m, vc);
@@ -139,7 +159,7 @@ template <typename T>
 __device__ __forceinline__ T jac_vx(T vc, T vl, T vr, T vb, T vt, T ybc, T ybl, T ytc, T ytl, T ecl, T ecr, T enb,
                                     T ent, T b, T omega, T idx, T idy) {
     const T m = mv_x<T>(vc, vl, vr, vb, vt, ybc, ybl, ytc, ytl, ecl, ecr, enb, ent, idx, idy);
-    const T g = omega / diag_x<T>(ecl, ecr, enb, ent, idx, idy);
+    const T g = jac_factor(omega, diag_x<T>(ecl, ecr, enb, ent, idx, idy));
     return jac_step<T>(vc, g, b, m);
 }
 
@@ -150,7 +170,7 @@ template <typename T>
 __device__ __forceinline__ T jac_vy(T vc, T vl, T vr, T vb, T vt, T xlc, T xrc, T xlb, T xrb, T ecb, T ect, T enl,
                                     T enr, T b, T omega, T idx, T idy) {
     const T m = mv_y<T>(vc, vl, vr, vb, vt, xlc, xrc, xlb, xrb, ecb, ect, enl, enr, idx, idy);
-    const T g = omega / diag_y<T>(ecb, ect, enl, enr, idx, idy);
+    const T g = jac_factor(omega, diag_y<T>(ecb, ect, enl, enr, idx, idy));
     return jac_step<T>(vc, g, b, m);
 }
 
