@@ -94,8 +94,12 @@ __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(
 constexpr int WS_NARROW = 76, WS_WIDE = 96;
 
 // level lanes: 64 per level for columns 0..63 (column 63 only as the right
-// neighbour of column 62), then Wm - 63 per level for columns 63..Wm-1
-__host__ __device__ inline int level_lanes(int Wm, int kt) { return 64 * kt + kt * (Wm > 63 ? Wm - 63 : 0); }
+// neighbour of column 62), then a group per level for columns 63..Wm-1.
+// Remainder lanes come in groups of GS per level: 16 when the Wm - 63 columns
+// fit (a 16-lane group then reads one LDS row, free of bank conflicts with the
+// other levels' groups), else Wm - 63.
+__host__ __device__ inline int rem_group(int Wm) { return Wm - 63 <= 16 ? 16 : Wm - 63; }
+__host__ __device__ inline int level_lanes(int Wm, int kt) { return 64 * kt + kt * (Wm > 63 ? rem_group(Wm) : 0); }
 __host__ __device__ inline int level_waves(int Wm, int kt) { return (level_lanes(Wm, kt) + 63) / 64; }
 
 // LDS: row table | kt level rings | 2kt + 2 coefficient rows | sink for
@@ -357,12 +361,15 @@ __device__ __forceinline__ void level_wave(const Grid<T>& g, T* __restrict__ ox,
 
 // --------------------------------------------------------- remainder wave --
 // Lanes of mixed levels: level s (1..kt) at window column c >= 63, or idle
-// (s > kt).  Every row is relaxed (results outside a level's cone are not
-// read).  Ring writes of level-kt and idle lanes go to the sink; the level-kt
-// lanes share one row per step, whose flags are read once for the stores.
+// (s > kt, or a spare lane of a level's group, which repeats a column of its
+// group so that its LDS reads stay in the group's rows).  Every row is
+// relaxed (results outside a level's cone are not read).  Ring writes of
+// level-kt and idle lanes go to the sink; the level-kt lanes share one row
+// per step, whose flags are read once for the stores.
 template <typename T, int WS>
 __device__ __forceinline__ void remainder_wave(const Grid<T>& g, T* __restrict__ ox, T* __restrict__ oy,
-                                               const Geo& G, T* rings, const T* cf, T* sink, int s, int c) {
+                                               const Geo& G, T* rings, const T* cf, T* sink, int s, int c,
+                                               bool idle) {
     const int kt = G.kt, RC = G.RC, V = G.V;
     const int* vtab = G.vtab;
     const int sl = min(s, kt);
@@ -372,12 +379,12 @@ __device__ __forceinline__ void remainder_wave(const Grid<T>& g, T* __restrict__
 #pragma unroll
     for (int k = 0; k < RING; ++k) {
         pr[k] = rings + ((sl - 1) * RING + ring_slot(k - 2 * sl)) * 2 * WS + c;
-        wr[k] = sl < kt ? rings + (sl * RING + ring_slot(k - 1 - 2 * sl)) * 2 * WS + c : sink;
+        wr[k] = sl < kt && !idle ? rings + (sl * RING + ring_slot(k - 1 - 2 * sl)) * 2 * WS + c : sink;
     }
     const T* cfc = cf + c;
     const Scale<T> sc = uniform_scale(stencil_scale(g.idx, g.idy));
     int sa = RC - 1 - 2 * sl;
-    const bool top = s == kt;
+    const bool top = s == kt && !idle;
     const unsigned lane_off = (top && i >= G.x0 && i < G.x1) ? (unsigned)i * (unsigned)sizeof(T) : OOB;
     const unsigned rw_off = (top && i == G.nx) ? (unsigned)i * (unsigned)sizeof(T) : OOB;
 
@@ -506,9 +513,9 @@ __device__ __forceinline__ void ras_workgroup(const Grid<T>& g, const T* __restr
     } else if (wave < kt) {
         level_wave<T, WS>(g, ox, oy, G, rings, cf, sink, wave + 1, lane);
     } else {  // remainder: columns 63.. of every level
-        const int R = Wm - 63, j = (wave - kt) * 64 + lane;
-        const int s = j / R + 1;
-        remainder_wave<T, WS>(g, ox, oy, G, rings, cf, sink, s, s > kt ? 63 : 63 + j % R);
+        const int R = Wm - 63, GS = rem_group(Wm), j = (wave - kt) * 64 + lane;
+        const int s = j / GS + 1, q = j % GS;
+        remainder_wave<T, WS>(g, ox, oy, G, rings, cf, sink, s, s > kt ? 63 : 63 + min(q, R - 1), s > kt || q >= R);
     }
 }
 
