@@ -296,6 +296,17 @@ __device__ __forceinline__ void level_loop(const Grid<T>& g, T* __restrict__ ox,
 #pragma unroll
         for (int q = 0; q < 3; ++q) wx[r][q] = wy[r][q] = T(0);
     T b_prev = T(0), n_prev = T(0);  // B(c, a-1), N(c, a)
+    // A, bx, by of row a and N of row a + 1 are read one step ahead, before the barrier:
+    // they were written two or more steps earlier, and their reads then stay out of the
+    // burst of LDS reads that follows each barrier
+    T qa, qbx, qby, qnt;
+    {
+        const T* row = cfc + sa * (CF_N * WS);
+        qa = row[CF_EC * WS];
+        qbx = row[CF_BX * WS];
+        qby = row[CF_BY * WS];
+        qnt = cfc[(sa + 1 == RC ? 0 : sa + 1) * (CF_N * WS) + CF_EN * WS];
+    }
 
     for (int t0 = 0; t0 < G.nsteps; t0 += U) {
 #pragma unroll
@@ -314,10 +325,9 @@ __device__ __forceinline__ void level_loop(const Grid<T>& g, T* __restrict__ ox,
             const int fl = TOP ? __builtin_amdgcn_readfirstlane(vtab[min(max(a2, 0), V - 1)]) : 0;
             const T* row = cfc + sa * (CF_N * WS);
             const T xc = p[0], yc = p[WS];
-            const T aA = row[CF_EC * WS];
-            const T gx = row[CF_GX * WS], bx = row[CF_BX * WS], gy = row[CF_GY * WS], by = row[CF_BY * WS];
-            const T nt = cfc[sa1 * (CF_N * WS) + CF_EN * WS];
-            // every row is relaxed (a row outside the level's cone is never read), and all LDS
+            const T gx = row[CF_GX * WS], gy = row[CF_GY * WS];  // level 1's are written in the last step
+            const T aA = qa, bx = qbx, by = qby, nt = qnt;
+            // every row is relaxed (a row outside the level's cone is never read), and the LDS
             // reads of the step are issued together, ahead of the arithmetic
             __builtin_amdgcn_sched_barrier(0);
             // columns c - 1 and c + 1 from the neighbouring lanes (lane 0 is the frozen ring
@@ -347,6 +357,13 @@ __device__ __forceinline__ void level_loop(const Grid<T>& g, T* __restrict__ ox,
             b_prev = bA;
             n_prev = nt;
             sa = sa1;
+            {
+                const T* nrow = cfc + sa * (CF_N * WS);
+                qa = nrow[CF_EC * WS];
+                qbx = nrow[CF_BX * WS];
+                qby = nrow[CF_BY * WS];
+                qnt = cfc[(sa + 1 == RC ? 0 : sa + 1) * (CF_N * WS) + CF_EN * WS];
+            }
             lds_barrier();
         }
     }
