@@ -52,17 +52,21 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the streaming RAS kernel (4096^2, FP64, T = 64,
 # k = h = 4) from rocprofv3 FETCH_SIZE / WRITE_SIZE, each scaled by what the
 # counter reads for a copy of known size (profiles/k_ras_stream_4096_f64_k4.md).
-# Valid only for the kernel sources it was measured on: reported as null once
-# their hash differs.
-RAS_TRAFFIC = {"sources_sha256_16": "4914e344b066001e", "bytes_per_launch": 1.139e9, "n": 4096, "k": 4, "dtype": "f64"}
+# Valid only for the kernel code it was measured on: reported as null once the
+# hash of its sources (comments and blank space removed) differs.
+RAS_TRAFFIC = {"sources_sha256_16": "9e5f5d523d8e9785", "bytes_per_launch": 1.139e9, "n": 4096, "k": 4, "dtype": "f64"}
 
 
 def ras_sources_hash():
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("ras_stream.hip", "stencil.hpp", "wave.hpp"):
-        with open(os.path.join(ROOT, "paper_2509_19061_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2509_19061_amd", "csrc", f), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)  # block comments
+        src = re.sub(r"//[^\n]*", " ", src)                # line comments
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -16,8 +16,7 @@
 // the owned rows (h + 1 = the frozen ring).  Rows farther out are read by no
 // level and are left out of the stream.  Every row within kt - s of the owned
 // rows reads only rows of its own tile; level s relaxes the other rows too (so
-// that a step issues all its LDS reads at once), but their values are never
-// read.
+// that its LDS reads are unconditional), but their values are never read.
 //
 // Frozen cells (ring rows and columns, walls, cells outside the grid) get
 // omega / diag = 0 from the feeders, so the update v - g (b - Mv) leaves them
@@ -30,9 +29,10 @@
 //     slots and row flags are wave-uniform (scalar) and neighbouring columns
 //     come from neighbouring lanes; columns 63.. of every level go to the
 //     remainder wave(s) after them;
-//   * feeder waves (the last NF): stream the snapshot, viscosities and
-//     right-hand side from HBM into LDS row rings through a PF-row register
-//     FIFO, and compute omega / diag(-M) once per cell of each row.
+//   * feeder waves (the last NF): stream the snapshot, viscosities (stored as
+//     the scaled coefficients A and N of the stencil) and right-hand side from
+//     HBM into LDS row rings through a PF-row register FIFO, and compute
+//     omega / diag(-M) once per cell of each row.
 // A level lane keeps a 3 x 3 window of level s-1 values in registers and reads
 // one new row per step from LDS; level kt writes the owned cells to HBM.
 // The update calls the same stencil functions as every other smoother, so
