@@ -286,13 +286,15 @@ static LevelJob<T> level_job(const stk_mg* m, size_t l, int t) {
 }
 
 template <typename T>
-static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) {
+static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P, bool z32) {
     hipStream_t s = ctx->stream;
     P->n = n;
+    P->vec_z32 = t == 0 && z32;
     int maxl = 0;
     for (int q = 0; q < n; ++q) {
         STK_TRY(ensure_dtype(mgs[q], 0));  // the FP64 Krylov slots exist in both modes
         STK_TRY(ensure_dtype(mgs[q], t));
+        if (P->vec_z32) STK_TRY(ensure_dtype(mgs[q], 1));  // the FP32 Z slot
         maxl = std::max(maxl, (int)mgs[q]->L.size());
         P->maxcn = std::max(P->maxcn, mgs[q]->cn);
     }
@@ -387,8 +389,9 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) 
         V.ec = m->L[0].ec64;
         V.en = m->L[0].en64;
         for (int sl = 0; sl < VS_N; ++sl) {
-            V.v[sl][0] = m->ks[t][sl].x;
-            V.v[sl][1] = m->ks[t][sl].y;
+            const int ts = sl == VS_Z && P->vec_z32 ? 1 : t;
+            V.v[sl][0] = m->ks[ts][sl].x;
+            V.v[sl][1] = m->ks[ts][sl].y;
         }
         vj.push_back(V);
         XCastJob X{};
@@ -397,9 +400,8 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) 
         X.ld = V.ld;
         for (int c = 0; c < 2; ++c) {
             X.r64[c] = static_cast<const double*>(c ? m->ks[0][VS_R].y : m->ks[0][VS_R].x);
-            X.z64[c] = static_cast<double*>(c ? m->ks[0][VS_Z].y : m->ks[0][VS_Z].x);
             X.r32[c] = static_cast<float*>(c ? m->ks[1][VS_R].y : m->ks[1][VS_R].x);
-            X.z32[c] = static_cast<const float*>(c ? m->ks[1][VS_Z].y : m->ks[1][VS_Z].x);
+            X.z32[c] = static_cast<float*>(c ? m->ks[1][VS_Z].y : m->ks[1][VS_Z].x);
         }
         xj.push_back(X);
     }
@@ -452,9 +454,9 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P) 
     return STK_OK;
 }
 
-int make_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT** out) {
+int make_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT** out, bool z32) {
     auto* P = new PlanT();
-    const int rc = t ? build_plan<float>(ctx, mgs, n, t, P) : build_plan<double>(ctx, mgs, n, t, P);
+    const int rc = t ? build_plan<float>(ctx, mgs, n, t, P, false) : build_plan<double>(ctx, mgs, n, t, P, z32);
     if (rc != STK_OK) {
         P->release();
         delete P;

@@ -54,6 +54,7 @@ struct PlanT {
     Batch apply;                        // finest: v = P, no right-hand side, r = Q  ->  Q = A P
     Batch applyr;                       // reduction chunks over the row-streaming prefix of `apply`
     Batch vec;                          // VecJob array
+    bool vec_z32 = false;               // its Z slot is FP32 (mixed-precision solves)
     Batch xcast;                        // XCastJob array (FP32 plan only)
     FcgState* st = nullptr;
     double* part = nullptr;
@@ -67,7 +68,8 @@ struct PlanT {
 };
 
 // Plans over mgs[0..n) for dtype t (0 FP64, 1 FP32); *out owns its memory.
-int make_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT** out);
+// z32 (FP64 plans): the Krylov Z slot is the FP32 V-cycle's output vector.
+int make_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT** out, bool z32 = false);
 void free_plan(PlanT*& P);
 // One V-cycle on the level-0 binding (v = Z slot, b = R slot) of every instance of P.
 int run_vcycle(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o, int t);

@@ -130,24 +130,26 @@ enum { PH_NF = 0, PH_NV, PH_INIT, PH_ALPHA, PH_BETA };
 // Slot dtype T for the slots touched (R, Z, P, Q, X); partial sums land in
 // `part` (2 per block), then per-instance sums in `sums` (2 per instance).
 template <typename T>
-int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* part, double* sums);
+// z32: the batch's Z slot holds FP32 vectors (the FP32 V-cycle's output, read
+// in place by the FP64 Krylov operations).
+int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* part, double* sums, bool z32 = false);
 // R = B - M X in FP64; sums[2i] = sum R^2 / d
 int vec_residual64_st(stk_ctx* ctx, const Batch& b, const FcgState* st, double* part, double* sums);
 // Per-instance scalar update from the reduced sums (one thread per instance);
 // PH_NF sets N_f and the stop threshold tol2 * N_f.
 int fcg_scalars(stk_ctx* ctx, FcgState* st, const double* sums, int n, int phase);
 
-// Precision casts around the FP32 V-cycle preconditioner (active instances):
-// down: r32 = (float) r64; up: z64 = (double) z32.
+// Entry of the FP32 V-cycle preconditioner (active instances): r32 = (float)
+// r64 and z32 = 0 (its initial guess) in one pass.  Its output z32 is read in
+// place by the FP64 Krylov operations.
 struct XCastJob {
     int nx, ny;
     int64_t ld;
     const double* r64[2];
     float* r32[2];
-    const float* z32[2];
-    double* z64[2];
+    float* z32[2];
 };
-int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st, int up);
+int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st);
 // per-instance sums of the block partials, in a fixed order: chunk sums, then chunks in order
 int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums);
 // FP64 FCG, finest level: Q = A P and per-instance P . Q into sums (apply:

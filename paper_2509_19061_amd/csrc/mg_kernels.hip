@@ -386,7 +386,7 @@ __device__ __forceinline__ double dgy(const VecJob& J, int i, int j) {
     return diag_y<double>(J.ec[k - ld], J.ec[k], enl, enr, J.idx, J.idy);
 }
 
-template <typename T>
+template <typename T, typename ZT>
 __global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, const int* __restrict__ pre, int n,
                                             int op, const FcgState* __restrict__ st, double* __restrict__ part) {
     STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, con
             if (!inbox) continue;
             T* X = static_cast<T*>(J.v[VS_X][c]);
             T* R = static_cast<T*>(J.v[VS_R][c]);
-            T* Z = static_cast<T*>(J.v[VS_Z][c]);
+            ZT* Z = static_cast<ZT*>(J.v[VS_Z][c]);
             T* P = static_cast<T*>(J.v[VS_P][c]);
             T* Q = static_cast<T*>(J.v[VS_Q][c]);
             switch (op) {
@@ -427,11 +427,11 @@ __global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, con
                     break;
                 }
                 case OP_INIT_P:
-                    P[k] = u ? Z[k] : T(0);
+                    P[k] = u ? T(Z[k]) : T(0);
                     if (u) a0 += (double)R[k] * (double)Z[k];
                     break;
                 default:  // OP_ZERO_Z
-                    Z[k] = T(0);
+                    Z[k] = ZT(0);
                     break;
             }
         }
@@ -487,18 +487,16 @@ __global__ __launch_bounds__(64 * rows::WPB) void k_fcg_apply_rows(const LevelJo
     }
 }
 
-// r32 = (float) r64 (up = 0) or z64 = (double) z32 (up = 1), walls included
+// r32 = (float) r64 and z32 = 0, walls included
 __global__ __launch_bounds__(NT) void k_prec_cast(const XCastJob* __restrict__ jobs, const int* __restrict__ pre,
-                                                  int n, const FcgState* __restrict__ st, int up) {
+                                                  int n, const FcgState* __restrict__ st) {
     STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
     if (i > J.nx || j > J.ny || !st[inst].active) return;
     const int64_t k = (int64_t)j * J.ld + i;
     for (int c = 0; c < 2; ++c) {
         if (c == 0 ? j >= J.ny : i >= J.nx) continue;
-        if (up)
-            J.z64[c][k] = (double)J.z32[c][k];
-        else
-            J.r32[c][k] = (float)J.r64[c][k];
+        J.r32[c][k] = (float)J.r64[c][k];
+        J.z32[c][k] = 0.0f;
     }
 }
 
@@ -711,16 +709,19 @@ template int mg_coarse<double>(stk_ctx*, const void*, int, int);
 template int mg_coarse<float>(stk_ctx*, const void*, int, int);
 
 template <typename T>
-int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* part, double* sums) {
+int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* part, double* sums, bool z32) {
     if (!b.n) return STK_OK;
-    hipLaunchKernelGGL(k_vec<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const VecJob*>(b.jobs), b.pre,
-                       b.n, op, st, part);
+    if (z32)
+        hipLaunchKernelGGL((k_vec<T, float>), dim3(b.blocks), dim3(NT), 0, ctx->stream,
+                           static_cast<const VecJob*>(b.jobs), b.pre, b.n, op, st, part);
+    else
+        hipLaunchKernelGGL((k_vec<T, T>), dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const VecJob*>(b.jobs),
+                           b.pre, b.n, op, st, part);
     STK_LAUNCH_CHECK();
     if (sums) return inst_sums(ctx, b, part, sums);
     return STK_OK;
 }
-template int vec_op<double>(stk_ctx*, const Batch&, int, const FcgState*, double*, double*);
-template int vec_op<float>(stk_ctx*, const Batch&, int, const FcgState*, double*, double*);
+template int vec_op<double>(stk_ctx*, const Batch&, int, const FcgState*, double*, double*, bool);
 
 int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums) {
     if (!b.cpre || !b.part2) return set_error(STK_EINVAL, "internal: batch without reduction chunks");
@@ -741,10 +742,10 @@ int fcg_apply_pq(stk_ctx* ctx, const Batch& apply, const Batch& red, const FcgSt
     return inst_sums(ctx, red, part, sums);
 }
 
-int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st, int up) {
+int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st) {
     if (!b.n) return STK_OK;
     hipLaunchKernelGGL(k_prec_cast, dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const XCastJob*>(b.jobs),
-                       b.pre, b.n, st, up);
+                       b.pre, b.n, st);
     STK_LAUNCH_CHECK();
     return STK_OK;
 }

@@ -51,10 +51,9 @@ int precondition(stk_ctx* ctx, const PlanT& P, const PlanT* P32, const stk_mg_op
         STK_TRY(vec_op<double>(ctx, P.vec, OP_ZERO_Z, P.st, P.part, nullptr));
         return run_vcycle(ctx, P, o, 0);
     }
-    STK_TRY(prec_cast(ctx, P32->xcast, P.st, 0));
-    STK_TRY(vec_op<float>(ctx, P32->vec, OP_ZERO_Z, P.st, P.part, nullptr));
-    STK_TRY(run_vcycle(ctx, *P32, o, 1));
-    return prec_cast(ctx, P32->xcast, P.st, 1);
+    // r32 = (float) r and z32 = 0, the FP32 V-cycle, whose z32 the Krylov steps read in place
+    STK_TRY(prec_cast(ctx, P32->xcast, P.st));
+    return run_vcycle(ctx, *P32, o, 1);
 }
 
 }  // namespace
@@ -80,7 +79,7 @@ namespace {
 int plans_for(stk_batch* b, const std::vector<int>& ids, PlanT** P, PlanT** P32) {
     std::vector<stk_mg*> ms;
     for (int id : ids) ms.push_back(b->slots[id].m);
-    STK_TRY(make_plan(b->ctx, ms.data(), (int)ms.size(), 0, P));
+    STK_TRY(make_plan(b->ctx, ms.data(), (int)ms.size(), 0, P, b->mode == STK_SOLVE_F32_REFINED));
     if (b->mode == STK_SOLVE_F32_REFINED) {
         const int rc = make_plan(b->ctx, ms.data(), (int)ms.size(), 1, P32);
         if (rc != STK_OK) {
@@ -160,7 +159,7 @@ int start_phase(stk_batch* b, int* done, stk_report* reps, int* ndone) {
     if (restart) {  // Z = V(R), P = Z, gamma for the slots that go on
         if (int rc = write_states(ctx, *Q, h)) return fail(rc);
         if (int rc = precondition(ctx, *Q, Q32, o)) return fail(rc);
-        if (int rc = vec_op<double>(ctx, Q->vec, OP_INIT_P, Q->st, Q->part, Q->sums)) return fail(rc);
+        if (int rc = vec_op<double>(ctx, Q->vec, OP_INIT_P, Q->st, Q->part, Q->sums, Q->vec_z32)) return fail(rc);
         if (int rc = fcg_scalars(ctx, Q->st, Q->sums, n, PH_INIT)) return fail(rc);
         if (int rc = read_states(ctx, *Q, h)) return fail(rc);
         for (int q = 0; q < n; ++q) {
@@ -223,9 +222,9 @@ int iterate_phase(stk_batch* b, int iters) {
         if (stopped) STK_TRY(write_states(ctx, P, h));
         if (!any) break;
         STK_TRY(precondition(ctx, P, b->P32, o));
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_RZ_ZQ, P.st, P.part, P.sums));
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_RZ_ZQ, P.st, P.part, P.sums, P.vec_z32));
         STK_TRY(fcg_scalars(ctx, P.st, P.sums, n, PH_BETA));
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_XPBY, P.st, P.part, nullptr));
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_XPBY, P.st, P.part, nullptr, P.vec_z32));
     }
     STK_TRY(read_states(ctx, P, h));
     for (int q = 0; q < n; ++q) b->slots[b->members[q]].fs = h[q];
