@@ -213,7 +213,7 @@ typedef enum {
     STK_SOLVE_F64 = 0,         /* FP64 V-cycle                                                          */
     STK_SOLVE_F32_REFINED = 1  /* FP32 V-cycle (smoothing, transfers, coarse stencils in FP32; the
                                   coarsest solve accumulates in FP64), applied to the FP64 residual
-                                  rounded to FP32, its result widened back to FP64                      */
+                                  rounded to FP32; the FP64 Krylov steps read its FP32 result       */
 } stk_solve_mode;
 
 typedef struct {
