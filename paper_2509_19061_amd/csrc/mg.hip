@@ -349,6 +349,7 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P, 
                     sw.push_back(X);
                     P->l0nx.push_back(J.nx);
                     P->l0ny.push_back(J.ny);
+                    P->l0ld.push_back(J.ld);
                 }
                 STK_TRY(upload(P, vw, &P->ras_jobs[0], s));
                 STK_TRY(upload(P, wv, &P->ras_jobs[1], s));
@@ -474,8 +475,8 @@ static const PlanT::RasK* ras_shape(stk_ctx* ctx, const PlanT& P, int kt, stk_dt
     PlanT::RasK r{kt, false, RasShape{}, nullptr};
     std::vector<int> pre, ntx;
     if (!P.l0nx.empty())
-        ras_batch_shape(ctx, dt, P.l0nx.data(), P.l0ny.data(), (int)P.l0nx.size(), RAS_TILE, kt, kt, &r.shape, &pre,
-                        &ntx, &r.ok);
+        ras_batch_shape(ctx, dt, P.l0nx.data(), P.l0ny.data(), P.l0ld.data(), (int)P.l0nx.size(), RAS_TILE, kt, kt,
+                        &r.shape, &pre, &ntx, &r.ok);
     if (r.ok) {
         void* d = nullptr;
         if (hipMalloc(&d, pre.size() * sizeof(int)) != hipSuccess) {

@@ -44,6 +44,7 @@ struct PlanT {
     const void* ras_jobs[2] = {nullptr, nullptr};
     Batch fine0w;
     std::vector<int> l0nx, l0ny;
+    std::vector<int64_t> l0ld;
     struct RasK {
         int kt;
         bool ok;

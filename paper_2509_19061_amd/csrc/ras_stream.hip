@@ -64,6 +64,8 @@ __device__ __forceinline__ int ring_slot(int r) { return ((r % RING) + RING) % R
 // virtual row flags: y + 1, owned, frozen ring
 constexpr int YMASK = (1 << 20) - 1;
 constexpr int F_OWNED = 1 << 28, F_RING = 1 << 29;
+// Row element offsets y * ld are 32-bit in the stream (ny * ld < 2^31,
+// checked on the host): one scalar multiply per row.
 enum { CF_EC = 0, CF_EN, CF_BX, CF_BY, CF_GX, CF_GY, CF_N };
 
 struct RasArgs {
@@ -130,15 +132,16 @@ struct Geo {
     const int* vtab;
 };
 
-// Owned-row stores of level kt at grid row y: vx and vy of the owned columns
-// (lane_off), the right wall vx(nx, y) when the tile column ends at nx
-// (rw_off), and the top wall vy(., ny) after the last row.  Offsets are
-// lane-constant; the row is folded into the (scalar) buffer resources.
+// Owned-row stores of level kt at grid row y (element offset off): vx and vy
+// of the owned columns (lane_off), the right wall vx(nx, y) when the tile
+// column ends at nx (rw_off), and the top wall vy(., ny) after the last row.
+// Offsets are lane-constant; the row is folded into the (scalar) buffer
+// resources.
 template <typename T>
-__device__ __forceinline__ void store_row(T* __restrict__ ox, T* __restrict__ oy, const Geo& G, int y, T ux, T uy,
-                                          unsigned lane_off, unsigned rw_off) {
-    const __amdgpu_buffer_rsrc_t rox = buf_rsrc(ox + (int64_t)y * G.ld, (size_t)(G.nx + 1) * sizeof(T));
-    const __amdgpu_buffer_rsrc_t roy = buf_rsrc(oy + (int64_t)y * G.ld, (size_t)G.nx * sizeof(T));
+__device__ __forceinline__ void store_row(T* __restrict__ ox, T* __restrict__ oy, const Geo& G, int y, int off, T ux,
+                                          T uy, unsigned lane_off, unsigned rw_off) {
+    const __amdgpu_buffer_rsrc_t rox = buf_rsrc(ox + off, (size_t)(G.nx + 1) * sizeof(T));  // off = y * ld
+    const __amdgpu_buffer_rsrc_t roy = buf_rsrc(oy + off, (size_t)G.nx * sizeof(T));
     buf_store(ux, rox, lane_off);
     buf_store(uy, roy, lane_off);
     if (G.x1 == G.nx) buf_store(T(0), rox, rw_off);
@@ -164,8 +167,8 @@ template <typename T, int WS, int MM>
 __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ vx, const T* __restrict__ vy,
                                        const Geo& G, T* rings, T* cf, T* sink, int fid) {
     const int nx = g.nx, ny = g.ny, Wm = G.Wm, W = G.W, RC = G.RC, V = G.V, ci0 = G.ci0;
-    const int64_t ld = G.ld;
     const int* vtab = G.vtab;
+    const int ld32 = (int)G.ld;
     const Scale<T> sc = uniform_scale(stencil_scale(g.idx, g.idy));
     const T* tbase[MM];
     int tdst[MM];  // element offset of the task's column in its ring or coefficient row
@@ -196,7 +199,7 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
     const int ii = ci0 + cq;
     const bool gcol = bl && cq >= 1 && cq <= W - 2 && (cy ? ii <= nx - 1 : (ii >= 1 && ii <= nx - 1));
     const int gylo = cy ? 1 : 0;
-    auto row_off = [&](int y) -> int64_t { return (int64_t)min(max(y, 0), ny - 1) * ld; };
+    auto row_off = [&](int y) -> int { return min(max(y, 0), ny - 1) * ld32; };
     // diag reads: e0 = A left (vx) or below (vy), n1 = N above (vx) or right (vy); for vy
     // the normal-stress coefficients are B = A kap and the shear terms carry rx
     const int off_e0 = CF_EC * WS + cq - (cy ? 0 : 1), off_n1 = CF_EN * WS + cq + (cy ? 1 : 0);
@@ -206,7 +209,7 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
         ff[u] = u < V ? __builtin_amdgcn_readfirstlane(vtab[u]) : 0;
-        const int64_t yo = row_off((ff[u] & YMASK) - 1);
+        const int yo = row_off((ff[u] & YMASK) - 1);
 #pragma unroll
         for (int m = 0; m < MM; ++m) fifo[u][m] = tbase[m][yo];
     }
@@ -239,7 +242,7 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
                 }
                 const int fnext = __builtin_amdgcn_readfirstlane(fn);
                 ff[q] = fnext;
-                const int64_t yo = row_off((fnext & YMASK) - 1);
+                const int yo = row_off((fnext & YMASK) - 1);
 #pragma unroll
                 for (int m = 0; m < MM; ++m) fifo[q][m] = tbase[m][yo];
                 fn = t + PF + 1 < V ? vtab[t + PF + 1] : 0;
@@ -352,7 +355,8 @@ __device__ __forceinline__ void level_loop(const Grid<T>& g, T* __restrict__ ox,
                 w[0] = ux;
                 w[WS] = uy;
             } else if (a2 >= 0 && a2 < V && (fl & F_OWNED)) {
-                store_row<T>(ox, oy, G, (fl & YMASK) - 1, ux, uy, lane_off, rw_off);
+                const int y = (fl & YMASK) - 1;
+                store_row<T>(ox, oy, G, y, y * (int)G.ld, ux, uy, lane_off, rw_off);
             }
             b_prev = bA;
             n_prev = nt;
@@ -449,7 +453,10 @@ __device__ __forceinline__ void remainder_wave(const Grid<T>& g, T* __restrict__
             T* w = wr[u % RING];
             w[0] = ux;
             w[WS] = uy;
-            if (ak >= 0 && ak < V && (flk & F_OWNED)) store_row<T>(ox, oy, G, (flk & YMASK) - 1, ux, uy, lane_off, rw_off);
+            if (ak >= 0 && ak < V && (flk & F_OWNED)) {
+                const int y = (flk & YMASK) - 1;
+                store_row<T>(ox, oy, G, y, y * (int)G.ld, ux, uy, lane_off, rw_off);
+            }
             b_prev = bA;
             n_prev = nt;
             sa = sa1;
@@ -707,7 +714,8 @@ int try_stream(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, int Tx, int T
     a.sy = sy;
     a.Wm = (int)std::min<int64_t>((int64_t)Tx + 2 * (int64_t)h, g->nx) + 2;
     // (the output stores address one row at a time through 32-bit buffer offsets)
-    if (a.Wm > WS_WIDE || kt > 16 || g->ny + 1 > YMASK || (int64_t)(g->nx + 1) * (int64_t)sizeof(T) >= INT32_MAX)
+    if (a.Wm > WS_WIDE || kt > 16 || g->ny + 1 > YMASK || (int64_t)(g->nx + 1) * (int64_t)sizeof(T) >= INT32_MAX ||
+        (int64_t)g->ny * g->ld >= INT32_MAX)
         return STK_OK;
     if (a.Wm <= WS_NARROW) return try_stream_ws<T, WS_NARROW>(ctx, g, gg, a, vx, vy, ox, oy, done);
     return try_stream_ws<T, WS_WIDE>(ctx, g, gg, a, vx, vy, ox, oy, done);
@@ -808,13 +816,15 @@ void batch_shape_ws(stk_ctx* ctx, const int* nx, const int* ny, int n, int tile,
 }
 
 template <typename T>
-void batch_shape(stk_ctx* ctx, const int* nx, const int* ny, int n, int tile, int h, int kt, RasShape* out,
-                 std::vector<int>* pre, std::vector<int>* ntx, bool* ok) {
+void batch_shape(stk_ctx* ctx, const int* nx, const int* ny, const int64_t* ld, int n, int tile, int h, int kt,
+                 RasShape* out, std::vector<int>* pre, std::vector<int>* ntx, bool* ok) {
     *ok = false;
     if (n < 1 || kt < 1 || kt > 16 || tile < 1) return;
     int Wm = 0;
     for (int q = 0; q < n; ++q) {
-        if (ny[q] + 1 > YMASK || (int64_t)(nx[q] + 1) * (int64_t)sizeof(T) >= INT32_MAX) return;
+        if (ny[q] + 1 > YMASK || (int64_t)(nx[q] + 1) * (int64_t)sizeof(T) >= INT32_MAX ||
+            (int64_t)ny[q] * ld[q] >= INT32_MAX)
+            return;
         Wm = std::max<int>(Wm, (int)std::min<int64_t>((int64_t)tile + 2 * (int64_t)h, nx[q]) + 2);
     }
     if (Wm > WS_WIDE) return;
@@ -843,10 +853,10 @@ int launch_ras_stream(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const Field
 
 namespace stk {
 
-int ras_batch_shape(stk_ctx* ctx, stk_dtype dt, const int* nx, const int* ny, int n, int tile, int h, int kt,
-                    RasShape* out, std::vector<int>* pre, std::vector<int>* ntx, bool* ok) {
-    if (dt == STK_F64) batch_shape<double>(ctx, nx, ny, n, tile, h, kt, out, pre, ntx, ok);
-    else batch_shape<float>(ctx, nx, ny, n, tile, h, kt, out, pre, ntx, ok);
+int ras_batch_shape(stk_ctx* ctx, stk_dtype dt, const int* nx, const int* ny, const int64_t* ld, int n, int tile,
+                    int h, int kt, RasShape* out, std::vector<int>* pre, std::vector<int>* ntx, bool* ok) {
+    if (dt == STK_F64) batch_shape<double>(ctx, nx, ny, ld, n, tile, h, kt, out, pre, ntx, ok);
+    else batch_shape<float>(ctx, nx, ny, ld, n, tile, h, kt, out, pre, ntx, ok);
     return STK_OK;
 }
 

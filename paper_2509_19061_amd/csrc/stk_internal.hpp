@@ -95,8 +95,8 @@ struct RasShape {
 // of the tile, halo h, kt sweeps): fills the workgroup prefix pre[0..n] and
 // each instance's tile columns; *ok = false when the streaming kernel cannot
 // take them (window or LDS too large).
-int ras_batch_shape(stk_ctx* ctx, stk_dtype dt, const int* nx, const int* ny, int n, int tile, int h, int kt,
-                    RasShape* out, std::vector<int>* pre, std::vector<int>* ntx, bool* ok);
+int ras_batch_shape(stk_ctx* ctx, stk_dtype dt, const int* nx, const int* ny, const int64_t* ld, int n, int tile,
+                    int h, int kt, RasShape* out, std::vector<int>* pre, std::vector<int>* ntx, bool* ok);
 // One outer iteration of every instance of a RasJob array (device) with the
 // shape above; pre: the device copy of the prefix.
 int ras_batch_launch(stk_ctx* ctx, stk_dtype dt, const RasShape& s, const void* jobs, const int* pre, int n,
