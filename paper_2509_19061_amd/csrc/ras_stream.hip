@@ -215,14 +215,15 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
     }
     int fn = PF < V ? vtab[PF] : 0;  // flags of row t + PF, read one step ahead
     int f1 = 0, f2 = 0;              // flags of rows t - 1 and t - 2
-    int rA = 0;                      // t % RC
+    // coefficient-row slots of rows t, t - 1, t - 2, t - 3 (mod RC; RC >= 4): one
+    // modular increment per step, the others are the last three values
+    int rA = 0, r1 = RC - 1, r2 = RC - 2, r3 = RC - 3;
     for (int t0 = 0; t0 < G.nsteps; t0 += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + u, q = u % PF;
             // (B, reads) coefficients around row t - 2, written at steps t - 3 .. t - 1
-            const int sr = rA >= 2 ? rA - 2 : rA + RC - 2;
-            const int sm = sr >= 1 ? sr - 1 : RC - 1, sp = sr + 1 == RC ? 0 : sr + 1;
+            const int sr = r2, sm = r3, sp = r1;
             const T e0 = cf[(cy ? sm : sr) * CF_N * WS + off_e0];
             const T e1 = cf[sr * CF_N * WS + CF_EC * WS + cq];
             const T n0 = cf[sr * CF_N * WS + CF_EN * WS + cq];
@@ -258,6 +259,9 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
             }
             f2 = f1;
             f1 = ff_t;
+            r3 = r2;
+            r2 = r1;
+            r1 = rA;
             rA = (rA + 1 == RC) ? 0 : rA + 1;
             lds_barrier();
         }
@@ -533,6 +537,9 @@ __device__ __forceinline__ void ras_workgroup(const Grid<T>& g, const T* __restr
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int nlw = level_waves(Wm, kt);
     if (wave >= nlw) {
+        // the feeders set the pace of a step (every role waits for their rows at the
+        // barrier): they issue ahead of the other waves of their SIMD
+        __builtin_amdgcn_s_setprio(1);
         feeder<T, WS, MM>(g, vx, vy, G, rings, cf, sink, (wave - nlw) * 64 + lane);
     } else if (wave < kt) {
         level_wave<T, WS>(g, ox, oy, G, rings, cf, sink, wave + 1, lane);
