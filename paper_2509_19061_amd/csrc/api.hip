@@ -229,35 +229,40 @@ int stk_smooth(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, void* vx, void* vy
         return STK_OK;
     }
 
-    void *tx = nullptr, *ty = nullptr;
+    // Out-of-place steps: the first reads the caller's arrays, the last writes them, and the
+    // ones between alternate over two scratch pairs, so no copy is needed for n >= 2 steps
+    // (two buffers alone would end an odd count in scratch).
+    const bool ras = !(variant == STK_JACOBI_FUSED || variant == STK_JACOBI);
+    const int n = ras ? nouter : sweeps;
+    void *tx = nullptr, *ty = nullptr, *ux = nullptr, *uy = nullptr;
     STK_TRY(scratch(ctx, stk_ctx::S_VX, vbytes, &tx));
     STK_TRY(scratch(ctx, stk_ctx::S_VY, vbytes, &ty));
+    if (n >= 3) {
+        STK_TRY(scratch(ctx, stk_ctx::S_VX2, vbytes, &ux));
+        STK_TRY(scratch(ctx, stk_ctx::S_VY2, vbytes, &uy));
+    }
     const void *cx = vx, *cy = vy;  // current iterate
-    void *nx_ = tx, *ny_ = ty;      // next
-    auto swap = [&]() {
-        const void* a = cx;
-        const void* b = cy;
-        cx = nx_;
-        cy = ny_;
-        nx_ = const_cast<void*>(a);
-        ny_ = const_cast<void*>(b);
-    };
-    if (variant == STK_JACOBI_FUSED || variant == STK_JACOBI) {
-        for (int s = 0; s < sweeps; ++s) {
-            if (variant == STK_JACOBI_FUSED)
-                STK_TRY(launch_jacobi_fused(ctx, dt, g, f, omega, cx, cy, nx_, ny_));
-            else
-                STK_TRY(launch_jacobi_split(ctx, dt, g, f, omega, cx, cy, nx_, ny_));
-            swap();
+    for (int t = 0; t < n; ++t) {
+        void *dx = tx, *dy = ty;  // next
+        if (t == n - 1 && n >= 2) {
+            dx = vx;
+            dy = vy;
+        } else if (cx == tx) {
+            dx = ux;
+            dy = uy;
         }
-    } else {
-        for (int t = 0; t < nouter; ++t) {
+        if (variant == STK_JACOBI_FUSED) {
+            STK_TRY(launch_jacobi_fused(ctx, dt, g, f, omega, cx, cy, dx, dy));
+        } else if (variant == STK_JACOBI) {
+            STK_TRY(launch_jacobi_split(ctx, dt, g, f, omega, cx, cy, dx, dy));
+        } else {
             int kt = o.k;
             if (o.last_partial && t == nouter - 1 && sweeps % o.k) kt = sweeps % o.k;
             STK_TRY(launch_ras(ctx, dt, g, f, omega, o.tile_x, o.tile_y, h, kt, shifts[2 * t], shifts[2 * t + 1], cx,
-                               cy, nx_, ny_));
-            swap();
+                               cy, dx, dy));
         }
+        cx = dx;
+        cy = dy;
     }
     if (cx != vx) STK_TRY(launch_copy_velocity(ctx, dt, g, cx, cy, vx, vy));
     return STK_OK;

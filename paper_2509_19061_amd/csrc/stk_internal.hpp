@@ -17,7 +17,7 @@ struct stk_ctx {
     int num_cu = 0;
     int ras_kernel = 0;  // 0 auto (streaming when it fits), 1 LDS window only, 2 streaming only
     // Scratch slots, grown on demand (device memory).
-    enum { S_VX = 0, S_VY, S_BX, S_BY, S_PART, S_RED, S_NSLOT };
+    enum { S_VX = 0, S_VY, S_VX2, S_VY2, S_BX, S_BY, S_PART, S_RED, S_NSLOT };
     void* slot[S_NSLOT] = {};
     size_t slot_bytes[S_NSLOT] = {};
     double* host_red = nullptr;  // pinned host landing buffer for reductions
