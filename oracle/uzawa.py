@@ -1,0 +1,66 @@
+"""FP64 inexact Uzawa iteration for the full Stokes system (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline may use it; the HIP library never does.
+
+The paper eliminates the velocity from M v + G p = f, D v = 0 (Sec. 3.1),
+runs a Richardson iteration on the pressure Schur complement with the
+viscosity as its diagonal approximate inverse, and solves each velocity update
+only approximately with geometric multigrid (Sec. 3.2, inexact Uzawa).  Its
+configuration (Sec. 6.2, 6.3) runs one V-cycle per Uzawa cycle, a pressure
+relaxation omega_p = 0.6, starts from the lithostatic pressure and removes the
+pressure mean after every update.
+
+Readings taken here (the paper leaves them open):
+  * sign of the update.  With G p = -grad p (the fold b = f - G p of the
+    velocity block) the Schur complement D A^{-1} D^T of A = -M is positive,
+    and the convergent Richardson step is p <- p + omega_p eta_c r_p with the
+    continuity residual r_p = -D v of Sec. 6.4.  The paper's "+ alpha eta D v"
+    is the same step in a sign convention where D carries the minus;
+  * eta is the cell viscosity eta_c, where p lives;
+  * lithostatic pressure: integrated from the top wall downwards so that the
+    discrete vertical balance (p(i,j-1) - p(i,j))/dy = fy(i,j) holds on every
+    interior vy face, then shifted to zero mean (the constant is free);
+  * one Uzawa cycle: b = f - G p^k; v^{k+1} = `vcycles` V-cycles on M v = b
+    from v^k; p^{k+1} = p^k + omega_p eta_c r_p(v^{k+1}); p^{k+1} -= mean;
+    then the global energy residual E of Sec. 6.4 (with p^{k+1}) decides
+    whether to stop.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import mg
+from . import stokes as S
+
+
+def litho(g, fy):
+    """Lithostatic pressure (Sec. 6.2) balancing the vertical body force fy on
+    every interior vy face, zero mean."""
+    p = np.zeros((g.ny, g.nx))
+    for j in range(g.ny - 1, 0, -1):        # top row first, walking down
+        p[j - 1] = p[j] + np.asarray(fy)[j] * g.dy
+    return p - p.mean()
+
+
+def pressure_update(g, vx, vy, p, omega_p):
+    """p + omega_p eta_c r_p with r_p = -D v (Sec. 3.1), then the domain mean
+    removed (Sec. 6.2)."""
+    q = np.asarray(p, float) + omega_p * np.asarray(g.eta_c, float) * (-S.divergence(g, vx, vy))
+    return q - q.mean()
+
+
+def uzawa(levels, g, fx, fy, vx, vy, p, omega_p=0.6, vcycles=1, tol=1e-8, max_cycles=100,
+          nu1=2, nu2=2, omega=0.7):
+    """Inexact Uzawa cycles from (vx, vy, p) until E <= tol or max_cycles.
+    Returns (vx, vy, p, history of E): history[0] is E of the start, one entry
+    per cycle follows."""
+    vx, vy, p = np.array(vx, float), np.array(vy, float), np.array(p, float)
+    hist = [S.energy(g, vx, vy, fx, fy, p)[3]]
+    while hist[-1] > tol and len(hist) <= max_cycles:
+        bx, by = S.rhs(g, fx, fy, p)
+        for _ in range(vcycles):
+            vx, vy = mg.vcycle(levels, 0, vx, vy, bx, by, nu1, nu2, omega)
+        p = pressure_update(g, vx, vy, p, omega_p)
+        hist.append(S.energy(g, vx, vy, fx, fy, p)[3])
+    return vx, vy, p, hist
