@@ -297,6 +297,62 @@ int stk_batch_step(stk_batch* b, int iters, int* done, stk_report* reps, int* nd
 /* Number of solves in flight. */
 int stk_batch_count(const stk_batch* b, int* in_flight);
 
+/* --------------------------------------------------- inexact Uzawa -- */
+
+/* The full Stokes system M v + G p = f, D v = 0 (Sec. 3.1) by the inexact
+ * Uzawa iteration (Sec. 3.2): each cycle updates the velocity for the current
+ * pressure approximately with V-cycles, then takes a Richardson step on the
+ * pressure Schur complement with the cell viscosity as its approximate inverse,
+ *   p <- p + omega_p eta_c r_p,   r_p = -D v,
+ * and removes the pressure's domain mean (Sec. 6.2: the pressure is defined up
+ * to a constant).  With this library's G (b = f - G p, G p = -grad p) the
+ * Schur complement of -M is positive and this is the convergent sign; the
+ * paper prints the same step with the sign carried by its D.  All arrays are
+ * DEVICE FP64 in the grid's layout (p: ny rows of nx cells, stride ld). */
+typedef struct {
+    double omega_p;   /* pressure relaxation, > 0 (default 0.6, Sec. 6.3)                      */
+    int vcycles;      /* V-cycles of the velocity update per Uzawa cycle, >= 1 (default 1, Sec. 6.2) */
+    double tol;       /* stop when the global energy residual E (Sec. 6.4, with N_p) <= tol
+                         (default 1e-8)                                                           */
+    int max_cycles;   /* at most this many Uzawa cycles (default 1000)                            */
+} stk_uzawa_opts;
+
+typedef struct {
+    int cycles;       /* Uzawa cycles run                                                          */
+    int converged;    /* final E <= tol                                                            */
+    double e;         /* final E = sqrt((N_v + N_p) / N_f)                                         */
+    double ev;        /* final E_v = sqrt(N_v / N_f)                                               */
+    double seconds;   /* host wall time of the call                                                */
+} stk_uzawa_report;
+
+void stk_uzawa_opts_default(stk_uzawa_opts* o);
+
+/* Lithostatic pressure (Sec. 6.2's initial pressure): p balances the vertical
+ * body force on every interior vy face, (p(i,j-1) - p(i,j)) / dy = fy(i,j),
+ * integrated from the top row down, then shifted to zero mean.  fy has the vy
+ * layout (ny + 1 rows).  Asynchronous. */
+int stk_litho_pressure(stk_ctx* ctx, const stk_grid* g, const double* fy, double* p);
+
+/* One pressure update of the Uzawa cycle, in place on p:
+ * p <- p + omega_p eta_c r_p(v), then p <- p - mean(p).  omega_p > 0.
+ * The mean is reduced in a fixed order (bitwise reproducible).  Asynchronous. */
+int stk_uzawa_pressure(stk_ctx* ctx, const stk_grid* g, const double* vx, const double* vy, const double* eta_c,
+                       double omega_p, double* p);
+
+/* Uzawa cycles from (vx, vy, p), all in/out, until E <= tol or max_cycles:
+ *   b = f - G p;  `vcycles` FP64 V(nu1, nu2)-cycles of `mg` on M v = b from v;
+ *   stk_uzawa_pressure;  E from a fresh FP64 residual (both blocks).
+ * g must be the grid `mg` was created for (same nx, ny, ld) and eta_c, eta_n
+ * the viscosities it was built from.  hist (nullable, HOST, max_cycles + 1
+ * doubles) receives E of the start and after every cycle; rep (nullable) the
+ * summary.  opts NULL means the defaults.  STK_ENOTCONV if E > tol at the end
+ * (arrays, hist and rep are still written); the handle must not be in a
+ * batch.  Allocates the folded right-hand side for the call's duration.
+ * Synchronises once per cycle (the stopping test). */
+int stk_uzawa_solve(stk_mg* mg, const stk_grid* g, double* vx, double* vy, double* p, const double* eta_c,
+                    const double* eta_n, const double* fx, const double* fy, const stk_uzawa_opts* opts,
+                    double* hist, stk_uzawa_report* rep);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,6 +41,15 @@ class Report(C.Structure):
                 ("seconds", C.c_double)]
 
 
+class UzawaOpts(C.Structure):
+    _fields_ = [("omega_p", C.c_double), ("vcycles", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int)]
+
+
+class UzawaReport(C.Structure):
+    _fields_ = [("cycles", C.c_int), ("converged", C.c_int), ("e", C.c_double), ("ev", C.c_double),
+                ("seconds", C.c_double)]
+
+
 SOLVE_F64, SOLVE_F32_REFINED = 0, 1
 
 if not os.path.exists(LIB_PATH):
@@ -80,6 +89,11 @@ _SIGS = {
     "stk_batch_add": ([_P, _P, _P, _P, _P, _P, _P, C.c_double, _I, C.POINTER(_I)], _I),
     "stk_batch_step": ([_P, _I, C.POINTER(_I), C.POINTER(Report), C.POINTER(_I)], _I),
     "stk_batch_count": ([_P, C.POINTER(_I)], _I),
+    "stk_uzawa_opts_default": ([C.POINTER(UzawaOpts)], None),
+    "stk_litho_pressure": ([_P, _G, _P, _P], _I),
+    "stk_uzawa_pressure": ([_P, _G, _P, _P, _P, C.c_double, _P], _I),
+    "stk_uzawa_solve": ([_P, _G, _P, _P, _P, _P, _P, _P, _P, C.POINTER(UzawaOpts), C.POINTER(C.c_double),
+                         C.POINTER(UzawaReport)], _I),
 }
 
 

@@ -21,7 +21,8 @@ from ._lib import (EHIP, EINVAL, ENOMEM, ENONFINITE, ENOTCONV, EUNSUPPORTED, F32
 __all__ = ["Context", "Grid", "SmoothOpts", "StkError", "smooth", "ras_outer", "residual", "energy_norm", "ras_shifts",
            "smooth_opts", "F64", "F32", "JACOBI", "JACOBI_FUSED", "RAS_JACOBI", "RBGS", "VARIANTS", "OK", "EINVAL",
            "ENOMEM", "EHIP", "ENOTCONV", "ENONFINITE", "EUNSUPPORTED", "dtype_code", "torch_dtype", "MG", "mg_opts",
-           "mg_footprint", "mg_solve_batch", "SOLVE_F64", "SOLVE_F32_REFINED", "MODES", "Batch"]
+           "mg_footprint", "mg_solve_batch", "SOLVE_F64", "SOLVE_F32_REFINED", "MODES", "Batch", "uzawa_opts",
+           "litho_pressure", "uzawa_pressure", "uzawa_solve"]
 
 MODES = {"f64": SOLVE_F64, "f32_refined": SOLVE_F32_REFINED}
 
@@ -309,3 +310,35 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def uzawa_opts(omega_p=0.6, vcycles=1, tol=1e-8, max_cycles=1000):
+    o = L.UzawaOpts()
+    L.lib.stk_uzawa_opts_default(C.byref(o))
+    o.omega_p, o.vcycles, o.tol, o.max_cycles = float(omega_p), int(vcycles), float(tol), int(max_cycles)
+    return o
+
+
+def litho_pressure(ctx, grid, fy, p):
+    """p <- lithostatic pressure of the vertical body force fy (zero mean)."""
+    check(L.lib.stk_litho_pressure(ctx.handle, C.byref(grid), _ptr(fy, F64), _ptr(p, F64)))
+
+
+def uzawa_pressure(ctx, grid, vx, vy, eta_c, omega_p, p):
+    """p <- p + omega_p eta_c (-D v), then the mean removed (in place)."""
+    check(L.lib.stk_uzawa_pressure(ctx.handle, C.byref(grid), _ptr(vx, F64), _ptr(vy, F64), _ptr(eta_c, F64),
+                                   float(omega_p), _ptr(p, F64)))
+
+
+def uzawa_solve(mg, grid, vx, vy, p, eta_c, eta_n, fx, fy, allow_notconv=False, **opts):
+    """Inexact Uzawa cycles in place on (vx, vy, p); returns (report dict, E history)."""
+    o = uzawa_opts(**opts)
+    hist = (C.c_double * (o.max_cycles + 1))()
+    r = L.UzawaReport()
+    rc = L.lib.stk_uzawa_solve(mg.handle, C.byref(grid), _ptr(vx, F64), _ptr(vy, F64), _ptr(p, F64),
+                               _ptr(eta_c, F64), _ptr(eta_n, F64), _ptr(fx, F64), _ptr(fy, F64), C.byref(o), hist,
+                               C.byref(r))
+    if not (allow_notconv and rc == ENOTCONV):
+        check(rc)
+    rep = dict(cycles=r.cycles, converged=bool(r.converged), e=r.e, ev=r.ev, seconds=r.seconds)
+    return rep, np.array(hist[:r.cycles + 1])

@@ -1,0 +1,252 @@
+// Inexact Uzawa iteration for the full Stokes system (Sec. 3.1, 3.2, 6.2).
+//
+// The pressure Schur complement of M v + G p = f, D v = 0 is never formed:
+// a Richardson step on it, preconditioned by the cell viscosity, reads
+//   p <- p + omega_p eta_c r_p,   r_p = -D v,
+// with v the (approximate) velocity for the current pressure.  With the
+// library's fold b = f - G p, (G p) = -grad p, the Schur complement of -M is
+// positive and this sign is the convergent one.  The pressure is defined up
+// to a constant; its domain mean is removed after every update (Sec. 6.2).
+//
+// Kernels (all FP64, bound by HBM bandwidth):
+//   k_pressure_update  one pass over the cells: p <- p + omega_p eta_c r_p and
+//                      a per-workgroup partial sum of the new p (fixed order)
+//   k_litho            lithostatic pressure: one lane per column walks down
+//                      from the top row, p(j-1) = p(j) + fy(j) dy
+//   k_mean             one workgroup sums the partials in a fixed order
+//   k_sub_mean         p <- p - mean
+// The reductions never use atomics: results are bitwise reproducible.
+#include <chrono>
+#include <cmath>
+
+#include "mg_host.hpp"
+#include "stk_internal.hpp"
+
+namespace stk {
+namespace {
+
+constexpr int UX = 64;    // cells per workgroup row (one wave)
+constexpr int UY = 4;     // waves per workgroup
+constexpr int UROWS = 8;  // rows each lane walks
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Sum of one value per lane of a UX x UY workgroup, in a fixed order.
+__device__ __forceinline__ double group_sum(double v) {
+    __shared__ double red[UY];
+    v = wave_sum64(v);
+    if (threadIdx.x == 0) red[threadIdx.y] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+        for (int w = 0; w < UY; ++w) s += red[w];
+    return s;
+}
+
+__global__ __launch_bounds__(UX* UY) void k_pressure_update(int nx, int ny, int64_t ld, double idx, double idy,
+                                                            double omega_p, const double* __restrict__ vx,
+                                                            const double* __restrict__ vy,
+                                                            const double* __restrict__ ec, double* __restrict__ p,
+                                                            double* __restrict__ part) {
+    const int i = (int)blockIdx.x * UX + (int)threadIdx.x;
+    const int j0 = ((int)blockIdx.y * UY + (int)threadIdx.y) * UROWS;
+    double s = 0.0;
+    if (i < nx && j0 < ny) {
+        const int j1 = min(j0 + UROWS, ny);
+        double below = vy[(int64_t)j0 * ld + i];
+        for (int j = j0; j < j1; ++j) {
+            const int64_t c = (int64_t)j * ld + i;
+            const double above = vy[c + ld];
+            const double div = (vx[c + 1] - vx[c]) * idx + (above - below) * idy;
+            const double q = p[c] - omega_p * ec[c] * div;  // + omega_p eta_c r_p, r_p = -D v
+            p[c] = q;
+            s += q;
+            below = above;
+        }
+    }
+    s = group_sum(s);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(UX) void k_litho(int nx, int ny, int64_t ld, double dy, const double* __restrict__ fy,
+                                              double* __restrict__ p, double* __restrict__ part) {
+    const int i = (int)blockIdx.x * UX + (int)threadIdx.x;
+    double s = 0.0;
+    if (i < nx) {
+        double q = 0.0;  // top row; the constant is removed afterwards
+        p[(int64_t)(ny - 1) * ld + i] = q;
+        for (int j = ny - 1; j >= 1; --j) {
+            q = q + fy[(int64_t)j * ld + i] * dy;
+            p[(int64_t)(j - 1) * ld + i] = q;
+            s += q;
+        }
+    }
+    s = wave_sum64(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(1024) void k_mean(const double* __restrict__ part, int64_t n, double inv_cells,
+                                               double* __restrict__ mean) {
+    __shared__ double red[1024 / 64];
+    double s = 0.0;
+    for (int64_t q = threadIdx.x; q < n; q += 1024) s += part[q];
+    s = wave_sum64(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 1024 / 64; ++w) t += red[w];
+        *mean = t * inv_cells;
+    }
+}
+
+__global__ __launch_bounds__(UX* UY) void k_sub_mean(int nx, int ny, int64_t ld, const double* __restrict__ mean,
+                                                     double* __restrict__ p) {
+    const int i = (int)blockIdx.x * UX + (int)threadIdx.x;
+    const int j0 = ((int)blockIdx.y * UY + (int)threadIdx.y) * UROWS;
+    if (i >= nx || j0 >= ny) return;
+    const double m = *mean;
+    const int j1 = min(j0 + UROWS, ny);
+    for (int j = j0; j < j1; ++j) p[(int64_t)j * ld + i] -= m;
+}
+
+dim3 cell_grid_u(const stk_grid* g) {
+    return dim3((unsigned)((g->nx + UX - 1) / UX), (unsigned)((g->ny + UY * UROWS - 1) / (UY * UROWS)));
+}
+
+// mean of p over the cells from `nblk` partials in `part`, then p -= mean;
+// the mean lands in part[nblk].
+int remove_mean(stk_ctx* ctx, const stk_grid* g, double* part, int64_t nblk, double* p) {
+    hipLaunchKernelGGL(k_mean, dim3(1), dim3(1024), 0, ctx->stream, (const double*)part, nblk,
+                       1.0 / ((double)g->nx * (double)g->ny), part + nblk);
+    hipLaunchKernelGGL(k_sub_mean, cell_grid_u(g), dim3(UX, UY), 0, ctx->stream, g->nx, g->ny, g->ld,
+                       (const double*)(part + nblk), p);
+    STK_HIP(hipGetLastError());
+    return STK_OK;
+}
+
+int pressure_update(stk_ctx* ctx, const stk_grid* g, const double* vx, const double* vy, const double* eta_c,
+                    double omega_p, double* p) {
+    const dim3 grid = cell_grid_u(g);
+    const int64_t nblk = (int64_t)grid.x * grid.y;
+    void* part = nullptr;
+    STK_TRY(scratch(ctx, stk_ctx::S_PART, sizeof(double) * (size_t)(nblk + 1), &part));
+    hipLaunchKernelGGL(k_pressure_update, grid, dim3(UX, UY), 0, ctx->stream, g->nx, g->ny, g->ld, 1.0 / g->dx,
+                       1.0 / g->dy, omega_p, vx, vy, eta_c, p, (double*)part);
+    STK_HIP(hipGetLastError());
+    return remove_mean(ctx, g, (double*)part, nblk, p);
+}
+
+int check_omega_p(double w) {
+    if (!(w > 0.0) || !std::isfinite(w)) return set_error(STK_EINVAL, "omega_p must be finite and > 0 (got %g)", w);
+    return STK_OK;
+}
+
+}  // namespace
+}  // namespace stk
+
+using namespace stk;
+
+extern "C" {
+
+void stk_uzawa_opts_default(stk_uzawa_opts* o) {
+    if (!o) return;
+    o->omega_p = 0.6;
+    o->vcycles = 1;
+    o->tol = 1e-8;
+    o->max_cycles = 1000;
+}
+
+int stk_litho_pressure(stk_ctx* ctx, const stk_grid* g, const double* fy, double* p) {
+    if (!ctx) return set_error(STK_EINVAL, "ctx is NULL");
+    STK_TRY(check_grid(g));
+    if (!fy || !p) return set_error(STK_EINVAL, "fy, p must be non-NULL");
+    STK_TRY(use_device(ctx));
+    const int64_t nblk = (g->nx + UX - 1) / UX;
+    void* part = nullptr;
+    STK_TRY(scratch(ctx, stk_ctx::S_PART, sizeof(double) * (size_t)(nblk + 1), &part));
+    hipLaunchKernelGGL(k_litho, dim3((unsigned)nblk), dim3(UX), 0, ctx->stream, g->nx, g->ny, g->ld, g->dy, fy, p,
+                       (double*)part);
+    STK_HIP(hipGetLastError());
+    return remove_mean(ctx, g, (double*)part, nblk, p);
+}
+
+int stk_uzawa_pressure(stk_ctx* ctx, const stk_grid* g, const double* vx, const double* vy, const double* eta_c,
+                       double omega_p, double* p) {
+    if (!ctx) return set_error(STK_EINVAL, "ctx is NULL");
+    STK_TRY(check_grid(g));
+    STK_TRY(check_omega_p(omega_p));
+    if (!vx || !vy || !eta_c || !p) return set_error(STK_EINVAL, "vx, vy, eta_c, p must be non-NULL");
+    STK_TRY(use_device(ctx));
+    return pressure_update(ctx, g, vx, vy, eta_c, omega_p, p);
+}
+
+int stk_uzawa_solve(stk_mg* m, const stk_grid* g, double* vx, double* vy, double* p, const double* eta_c,
+                    const double* eta_n, const double* fx, const double* fy, const stk_uzawa_opts* opts,
+                    double* hist, stk_uzawa_report* rep) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!m) return set_error(STK_EINVAL, "mg is NULL");
+    STK_TRY(check_grid(g));
+    if (g->nx != m->L[0].nx || g->ny != m->L[0].ny || g->ld != m->user_ld)
+        return set_error(STK_EINVAL, "grid (%d x %d, ld %lld) is not the handle's (%d x %d, ld %lld)", g->nx, g->ny,
+                         (long long)g->ld, m->L[0].nx, m->L[0].ny, (long long)m->user_ld);
+    if (!vx || !vy || !p || !eta_c || !eta_n || !fx || !fy)
+        return set_error(STK_EINVAL, "vx, vy, p, eta_c, eta_n, fx, fy must be non-NULL");
+    if (m->busy) return set_error(STK_EINVAL, "the handle is in a batch");
+    stk_uzawa_opts o;
+    stk_uzawa_opts_default(&o);
+    if (opts) o = *opts;
+    STK_TRY(check_omega_p(o.omega_p));
+    if (o.vcycles < 1) return set_error(STK_EINVAL, "vcycles must be >= 1 (got %d)", o.vcycles);
+    if (o.max_cycles < 0) return set_error(STK_EINVAL, "max_cycles must be >= 0 (got %d)", o.max_cycles);
+    if (!(o.tol >= 0.0)) return set_error(STK_EINVAL, "tol must be >= 0");
+    stk_ctx* ctx = m->ctx;
+    STK_TRY(use_device(ctx));
+    // folded right-hand side b = f - G p of the current pressure
+    const size_t bxb = field_bytes(g, g->ny, STK_F64), byb = field_bytes(g, g->ny + 1, STK_F64);
+    void* bx = nullptr;
+    void* by = nullptr;
+    if (hipMalloc(&bx, bxb) != hipSuccess || hipMalloc(&by, byb) != hipSuccess) {
+        (void)hipGetLastError();
+        if (bx) (void)hipFree(bx);
+        return set_error(STK_ENOMEM, "cannot allocate the folded right-hand side (%zu bytes)", bxb + byb);
+    }
+    struct Free {
+        void* a;
+        void* b;
+        ~Free() {
+            (void)hipFree(a);
+            (void)hipFree(b);
+        }
+    } fr{bx, by};
+    double out[5];
+    int rc = stk_energy_norm(ctx, STK_F64, g, vx, vy, p, eta_c, eta_n, fx, fy, out);
+    if (rc != STK_OK) return rc;
+    if (hist) hist[0] = out[3];
+    int k = 0;
+    while (out[3] > o.tol && k < o.max_cycles) {
+        STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, bx, by));
+        for (int c = 0; c < o.vcycles; ++c) STK_TRY(stk_mg_vcycle(m, STK_F64, vx, vy, bx, by));
+        STK_TRY(pressure_update(ctx, g, vx, vy, eta_c, o.omega_p, p));
+        ++k;
+        rc = stk_energy_norm(ctx, STK_F64, g, vx, vy, p, eta_c, eta_n, fx, fy, out);
+        if (rc != STK_OK) return rc;
+        if (hist) hist[k] = out[3];
+    }
+    const bool conv = out[3] <= o.tol;
+    if (rep) {
+        rep->cycles = k;
+        rep->converged = conv ? 1 : 0;
+        rep->e = out[3];
+        rep->ev = out[4];
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!conv) return set_error(STK_ENOTCONV, "Uzawa: E = %g > tol = %g after %d cycles", out[3], o.tol, k);
+    return STK_OK;
+}
+
+}  // extern "C"
