@@ -29,7 +29,13 @@ multigrid solves:
     10^U(2,6)) admitted by HBM footprint under a 64 GB budget and solved by
     continuous batching; per mode a saturation run (all requests at t = 0)
     gives the peak solves/s, then Poisson arrivals at 0.8x that rate give
-    solves/s and p50 / p99 latency.
+    solves/s and p50 / p99 latency;
+  * "uzawa": the full Stokes system (velocity and pressure) by inexact Uzawa
+    cycles (one V(2,2)-cycle and one eta_c-preconditioned pressure step per
+    cycle, omega_p = 0.6) from the lithostatic pressure to the global energy
+    residual E <= 1e-8, on 8 sinkers of contrast 1e2 (plain Uzawa stalls at
+    the smoother workload's 1e6 without the paper's continuation), plus the
+    pressure step's own HBM rate.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
@@ -91,6 +97,7 @@ def main():
     ap.add_argument("--batch", default="default", help="'default' (64-instance mix), 'small' or 'none'")
     ap.add_argument("--kernel-only", type=int, default=0, help="profiling mode: L RAS launches + copy calibration")
     ap.add_argument("--serve", type=int, default=32, help="requests per serving run (0: skip)")
+    ap.add_argument("--uzawa-n", type=int, default=4096, help="Uzawa workload size (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -245,6 +252,7 @@ def main():
     rate = run_iteration_cost(ctx, args.rate_n) if args.rate_n > 0 else None
     batch = run_batch(ctx, args.batch) if args.batch != "none" else None
     served = run_serve(ctx, args.serve) if args.serve > 0 else None
+    uz = run_uzawa(ctx, args.uzawa_n) if args.uzawa_n > 0 else None
 
     out = {
         "metric": "smoother GLUP/s + % HBM roofline (RAS-Jacobi)",
@@ -275,6 +283,7 @@ def main():
         "iteration_cost": rate,
         "batch": batch,
         "serve": served,
+        "uzawa": uz,
     }
     print(json.dumps(out), flush=True)
     if kctx is not ctx:
@@ -379,6 +388,50 @@ def run_solves(ctx, n, tol=1e-8, max_iters=4000):
             "f64": res["f64"], "f32_refined": res["f32_refined"],
             "refined_speedup": round(res["f64"]["seconds"] / res["f32_refined"]["seconds"], 3),
             "refined_vs_f64_energy_rel": rel}
+
+
+def run_uzawa(ctx, n, tol=1e-8, max_cycles=1000, omega_p=0.6, reps=20):
+    """Inexact Uzawa solve of the full Stokes system, and the pressure step's rate."""
+    import torch
+
+    from paper_2509_19061_amd import api, fields, inputs
+
+    prob = inputs.random_sinkers(n, 8, 2, eta_in=1e2)
+    dp = fields.DeviceProblem(prob, torch.float64)
+    m = api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n)
+    vx, vy, p = dp.velocity() + (dp.field(),)
+    api.uzawa_solve(m, dp.grid, vx, vy, p, dp.eta_c, dp.eta_n, dp.fx, dp.fy, allow_notconv=True,
+                    max_cycles=1)  # buffers, plan
+    vx, vy, p = dp.velocity() + (dp.field(),)
+
+    def solve():
+        api.litho_pressure(ctx, dp.grid, dp.fy, p)
+        return api.uzawa_solve(m, dp.grid, vx, vy, p, dp.eta_c, dp.eta_n, dp.fx, dp.fy, allow_notconv=True,
+                               omega_p=omega_p, tol=tol, max_cycles=max_cycles)
+
+    (rep, hist), secs = _timed(solve)
+    e = api.energy_norm(ctx, torch.float64, dp.grid, vx, vy, p, dp.eta_c, dp.eta_n, dp.fx, dp.fy)
+    log(f"[bench] uzawa {n}^2: {rep['cycles']} cycles in {secs:.3f}s, E {rep['e']:.3e} (recomputed {e[3]:.3e}), "
+        f"E_v {e[4]:.3e}")
+
+    def pressure_steps():
+        for _ in range(reps):
+            api.uzawa_pressure(ctx, dp.grid, vx, vy, dp.eta_c, omega_p, p)
+
+    pressure_steps()
+    _, psecs = _timed(pressure_steps)
+    pms = psecs * 1e3 / reps
+    words = 7  # update: vx, vy, eta_c, p read, p written; mean removal: p read and written
+    gbs = n * n * words * 8 / (pms * 1e-3) / 1e9
+    log(f"[bench] uzawa pressure step {n}^2: {pms:.4f} ms, {gbs:.0f} GB/s effective")
+    m.close()
+    return {"workload": f"{n}x{n} cells, 8 sinkers (seed 2) eta 1e2 / 1, inexact Uzawa (one V(2,2)-cycle + pressure "
+                        f"step, omega_p {omega_p}) from the lithostatic pressure to E <= {tol:g}",
+            "n": n, "tol": tol, "seconds": round(secs, 4), "cycles": rep["cycles"], "converged": rep["converged"],
+            "ms_per_cycle": round(secs * 1e3 / max(1, rep["cycles"]), 3), "e_start": float(hist[0]),
+            "e_report": rep["e"], "e_recomputed": float(e[3]), "ev": float(e[4]),
+            "pressure_step": {"ms": round(pms, 4), "words_per_cell": words, "effective_gbs": round(gbs, 1),
+                              "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}}
 
 
 def run_iteration_cost(ctx, n, iters=30):

@@ -206,36 +206,62 @@ int stk_uzawa_solve(stk_mg* m, const stk_grid* g, double* vx, double* vy, double
     if (!(o.tol >= 0.0)) return set_error(STK_EINVAL, "tol must be >= 0");
     stk_ctx* ctx = m->ctx;
     STK_TRY(use_device(ctx));
-    // folded right-hand side b = f - G p of the current pressure
-    const size_t bxb = field_bytes(g, g->ny, STK_F64), byb = field_bytes(g, g->ny + 1, STK_F64);
+    stk_mg* self = m;
+    if (!m->plan[0]) STK_TRY(make_plan(ctx, &self, 1, 0, &m->plan[0]));
+    // When the caller's stride is the hierarchy's level-0 stride the cycles
+    // run in the hierarchy's own level-0 vectors (the V-cycle's iterate and
+    // right-hand side): the velocity is copied in and out once per call
+    // instead of staging v and b through stk_mg_vcycle every cycle.
+    const bool direct = g->ld == m->L[0].ld;
+    double* wx = vx;
+    double* wy = vy;
     void* bx = nullptr;
     void* by = nullptr;
-    if (hipMalloc(&bx, bxb) != hipSuccess || hipMalloc(&by, byb) != hipSuccess) {
-        (void)hipGetLastError();
-        if (bx) (void)hipFree(bx);
-        return set_error(STK_ENOMEM, "cannot allocate the folded right-hand side (%zu bytes)", bxb + byb);
-    }
     struct Free {
-        void* a;
-        void* b;
+        void* a = nullptr;
+        void* b = nullptr;
         ~Free() {
-            (void)hipFree(a);
-            (void)hipFree(b);
+            if (a) (void)hipFree(a);
+            if (b) (void)hipFree(b);
         }
-    } fr{bx, by};
+    } fr;
+    if (direct) {
+        wx = static_cast<double*>(m->ks[0][VS_Z].x);
+        wy = static_cast<double*>(m->ks[0][VS_Z].y);
+        bx = m->ks[0][VS_R].x;
+        by = m->ks[0][VS_R].y;
+        STK_TRY(copy_vel_in(m, vx, vy, g->ld, wx, wy, g->ld, sizeof(double)));
+    } else {
+        const size_t bxb = field_bytes(g, g->ny, STK_F64), byb = field_bytes(g, g->ny + 1, STK_F64);
+        if (hipMalloc(&fr.a, bxb) != hipSuccess || hipMalloc(&fr.b, byb) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(STK_ENOMEM, "cannot allocate the folded right-hand side (%zu bytes)", bxb + byb);
+        }
+        bx = fr.a;
+        by = fr.b;
+    }
     double out[5];
-    int rc = stk_energy_norm(ctx, STK_F64, g, vx, vy, p, eta_c, eta_n, fx, fy, out);
+    int rc = stk_energy_norm(ctx, STK_F64, g, wx, wy, p, eta_c, eta_n, fx, fy, out);
     if (rc != STK_OK) return rc;
     if (hist) hist[0] = out[3];
     int k = 0;
     while (out[3] > o.tol && k < o.max_cycles) {
-        STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, bx, by));
-        for (int c = 0; c < o.vcycles; ++c) STK_TRY(stk_mg_vcycle(m, STK_F64, vx, vy, bx, by));
-        STK_TRY(pressure_update(ctx, g, vx, vy, eta_c, o.omega_p, p));
+        STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, bx, by));  // b = f - G p
+        for (int c = 0; c < o.vcycles; ++c) {
+            if (direct)
+                STK_TRY(run_vcycle(ctx, *m->plan[0], m->o, 0));
+            else
+                STK_TRY(stk_mg_vcycle(m, STK_F64, wx, wy, bx, by));
+        }
+        STK_TRY(pressure_update(ctx, g, wx, wy, eta_c, o.omega_p, p));
         ++k;
-        rc = stk_energy_norm(ctx, STK_F64, g, vx, vy, p, eta_c, eta_n, fx, fy, out);
+        rc = stk_energy_norm(ctx, STK_F64, g, wx, wy, p, eta_c, eta_n, fx, fy, out);
         if (rc != STK_OK) return rc;
         if (hist) hist[k] = out[3];
+    }
+    if (direct) {
+        STK_TRY(copy_vel_in(m, wx, wy, g->ld, vx, vy, g->ld, sizeof(double)));
+        STK_HIP(hipStreamSynchronize(ctx->stream));
     }
     const bool conv = out[3] <= o.tol;
     if (rep) {

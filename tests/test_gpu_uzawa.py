@@ -35,9 +35,9 @@ def sinkers(nx, ny, seed, contrast):
     return I.sinker_problem(nx, ny, [(float(c[k, 0]), float(c[k, 1]), float(r[k])) for k in range(3)], contrast, 1.0)
 
 
-def dev(p):
+def dev(p, align=64):
     from paper_2509_19061_amd import fields
-    return fields.DeviceProblem(p, torch.float64)
+    return fields.DeviceProblem(p, torch.float64, align=align)
 
 
 @pytest.mark.parametrize("nx,ny", [(2, 2), (64, 64), (130, 70), (257, 300)])
@@ -79,11 +79,14 @@ def test_pressure_update_matches_oracle(ctx, nx, ny, omega_p):
     assert torch.equal(pt, pt2)
 
 
-@pytest.mark.parametrize("nx,ny,contrast,vcycles", [(64, 64, 1e2, 1), (96, 64, 1e3, 2), (128, 128, 1e4, 1)])
-def test_uzawa_cycles_match_oracle(ctx, nx, ny, contrast, vcycles):
+# align 128 at nx = 128 gives a row stride (256) other than the hierarchy's (192):
+# the cycles then stage v and b through the V-cycle entry point
+@pytest.mark.parametrize("nx,ny,contrast,vcycles,align", [(64, 64, 1e2, 1, 64), (96, 64, 1e3, 2, 64),
+                                                         (128, 128, 1e4, 1, 64), (128, 128, 1e4, 1, 128)])
+def test_uzawa_cycles_match_oracle(ctx, nx, ny, contrast, vcycles, align):
     from paper_2509_19061_amd import api
     p = sinkers(nx, ny, nx + ny + 1, contrast)
-    d = dev(p)
+    d = dev(p, align)
     m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
     p0 = U.litho(p, p.fy)
     vx, vy = d.velocity()
@@ -100,6 +103,28 @@ def test_uzawa_cycles_match_oracle(ctx, nx, ny, contrast, vcycles):
     np.testing.assert_allclose(hist, oh, rtol=1e-8)
     assert rep["e"] == hist[-1]
     m.close()
+
+
+def test_uzawa_strides_agree_bitwise(ctx):
+    """Cycles in the hierarchy's own level-0 vectors (caller stride = level-0
+    stride) and cycles staged through the V-cycle entry point (another
+    stride) do the same arithmetic."""
+    from paper_2509_19061_amd import api
+    p = sinkers(128, 96, 17, 1e3)
+    res = []
+    for align in (64, 128):
+        d = dev(p, align)
+        assert d.ld == (192 if align == 64 else 256)
+        m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
+        vx, vy = d.velocity()
+        pt = d.field()
+        api.litho_pressure(ctx, d.grid, d.fy, pt)
+        _, hist = api.uzawa_solve(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, allow_notconv=True, tol=0.0,
+                                  max_cycles=6)
+        res.append((d.get_vx(vx), d.get_vy(vy), d.get_cell(pt), hist))
+        m.close()
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
 
 
 def test_uzawa_constant_viscosity_two_cycles_exact(ctx):
