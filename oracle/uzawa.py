@@ -64,3 +64,39 @@ def uzawa(levels, g, fx, fy, vx, vy, p, omega_p=0.6, vcycles=1, tol=1e-8, max_cy
         p = pressure_update(g, vx, vy, p, omega_p)
         hist.append(S.energy(g, vx, vy, fx, fy, p)[3])
     return vx, vy, p, hist
+
+
+def rescaled(g, theta, eta_min=None):
+    """The problem with the computational viscosity of Sec. 6.2,
+    (1 - theta) eta_min + theta eta, applied to the cell and to the nodal
+    viscosities alike; eta_min = the smallest cell viscosity."""
+    from types import SimpleNamespace
+    em = float(np.min(g.eta_c)) if eta_min is None else eta_min
+    return SimpleNamespace(nx=g.nx, ny=g.ny, dx=g.dx, dy=g.dy,
+                           eta_c=(1.0 - theta) * em + theta * np.asarray(g.eta_c, float),
+                           eta_n=(1.0 - theta) * em + theta * np.asarray(g.eta_n, float))
+
+
+def uzawa_continuation(g, fx, fy, vx, vy, p, stages=4, stage_cycles=25, omega_p=0.6, vcycles=1, tol=1e-8,
+                       max_cycles=1000, coarsest=8, nu1=2, nu2=2, omega=0.7):
+    """Uzawa cycles under viscosity continuation (Sec. 6.2): theta = s/stages
+    for s = 0 .. stages; every stage with theta < 1 runs stage_cycles cycles
+    on the rescaled system (its own hierarchy, and its eta_c in the pressure
+    step); the last stage (theta = 1, the true system) runs until E <= tol.
+    max_cycles bounds all cycles together.  history[k] is E of the TRUE
+    system after k cycles."""
+    vx, vy, p = np.array(vx, float), np.array(vy, float), np.array(p, float)
+    hist = [S.energy(g, vx, vy, fx, fy, p)[3]]
+    for s in range(stages + 1):
+        theta = s / stages if stages > 0 else 1.0
+        gs = rescaled(g, theta)
+        levels = mg.hierarchy(gs, coarsest)
+        last, n = s == stages, 0
+        while len(hist) <= max_cycles and (hist[-1] > tol if last else n < stage_cycles):
+            bx, by = S.rhs(gs, fx, fy, p)
+            for _ in range(vcycles):
+                vx, vy = mg.vcycle(levels, 0, vx, vy, bx, by, nu1, nu2, omega)
+            p = pressure_update(gs, vx, vy, p, omega_p)
+            hist.append(S.energy(g, vx, vy, fx, fy, p)[3])
+            n += 1
+    return vx, vy, p, hist

@@ -116,3 +116,52 @@ def test_inexact_cycles_scale_with_viscosity():
     assert np.abs(a[2] - b[2] / c).max() <= 1e-10 * np.abs(a[2]).max()
     np.testing.assert_allclose(a[3], b[3], rtol=1e-9)
     assert a[3][-1] < a[3][0]
+
+
+def _with_eta(g, eta_c, eta_n):
+    return I.Problem(g.nx, g.ny, g.dx, g.dy, eta_c, eta_n, g.fx, g.fy)
+
+
+def test_continuation_first_stage_is_constant_viscosity():
+    """theta = 0: both viscosity fields become the constant min(eta_c), so with
+    exact velocity solves and omega_p = 2 the first stage reaches the
+    constant-viscosity saddle-point solution in two cycles."""
+    g = sinkers(16, 1e3)
+    em = float(g.eta_c.min())
+    const = _with_eta(g, np.full_like(g.eta_c, em), np.full_like(g.eta_n, em))
+    vref_x, vref_y, pref = kkt(const, g.fx, g.fy)
+    vx, vy, p, hist = U.uzawa_continuation(g, g.fx, g.fy, *g.zeros_v(), np.zeros((16, 16)), stages=2,
+                                           stage_cycles=2, omega_p=2.0, tol=0.0, max_cycles=2, coarsest=64)
+    assert len(hist) == 3
+    assert np.abs(p - pref).max() <= 1e-10 * np.abs(pref).max()
+    assert np.abs(vx - vref_x).max() <= 1e-10 * np.abs(vref_x).max()
+    assert np.abs(vy - vref_y).max() <= 1e-10 * np.abs(vref_y).max()
+
+
+def test_continuation_stage_solves_the_rescaled_system():
+    """After a long stage at theta = 1/2 the iterate is the saddle-point
+    solution with viscosities (eta_min + eta) / 2 (cells and nodes)."""
+    g = sinkers(16, 1e2)
+    em = float(g.eta_c.min())
+    half = _with_eta(g, 0.5 * (em + g.eta_c), 0.5 * (em + g.eta_n))
+    vref_x, vref_y, pref = kkt(half, g.fx, g.fy)
+    N = 600
+    vx, vy, p, hist = U.uzawa_continuation(g, g.fx, g.fy, *g.zeros_v(), np.zeros((16, 16)), stages=2,
+                                           stage_cycles=N, tol=0.0, max_cycles=2 * N, coarsest=64)
+    assert len(hist) == 2 * N + 1
+    assert np.abs(p - pref).max() <= 1e-8 * np.abs(pref).max()
+    assert np.abs(vy - vref_y).max() <= 1e-8 * np.abs(vref_y).max()
+
+
+def test_continuation_ends_at_the_true_solution():
+    g = sinkers(16, 1e3)
+    vref_x, vref_y, pref = kkt(g, g.fx, g.fy)
+    vx, vy, p, hist = U.uzawa_continuation(g, g.fx, g.fy, *g.zeros_v(), U.litho(g, g.fy), stages=4,
+                                           stage_cycles=25, tol=1e-11, max_cycles=5000, coarsest=64)
+    assert hist[-1] <= 1e-11 and len(hist) > 4 * 25 + 1
+    assert np.abs(p - pref).max() <= 1e-8 * np.abs(pref).max()
+    assert np.abs(vx - vref_x).max() <= 1e-8 * np.abs(vref_x).max()
+    # without stages it is the plain loop, cycle for cycle
+    a = U.uzawa_continuation(g, g.fx, g.fy, *g.zeros_v(), U.litho(g, g.fy), stages=0, tol=0.0, max_cycles=5)
+    b = U.uzawa(mg.hierarchy(g), g, g.fx, g.fy, *g.zeros_v(), U.litho(g, g.fy), tol=0.0, max_cycles=5)
+    assert np.array_equal(a[2], b[2]) and a[3] == b[3]
