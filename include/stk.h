@@ -314,7 +314,13 @@ typedef struct {
     int vcycles;      /* V-cycles of the velocity update per Uzawa cycle, >= 1 (default 1, Sec. 6.2) */
     double tol;       /* stop when the global energy residual E (Sec. 6.4, with N_p) <= tol
                          (default 1e-8)                                                           */
-    int max_cycles;   /* at most this many Uzawa cycles (default 1000)                            */
+    int max_cycles;   /* at most this many Uzawa cycles, continuation stages included (default 1000) */
+    int stages;       /* viscosity continuation (Sec. 6.2): stages s = 0 .. stages-1 run on
+                         (1 - theta) eta_min + theta eta with theta = s / stages (cell and nodal
+                         fields, eta_min = the smallest cell viscosity), each with a hierarchy of
+                         its own built for the call, before the true system (theta = 1, `mg`);
+                         0 (default) = none; the paper runs 4                                   */
+    int stage_cycles; /* Uzawa cycles per stage with theta < 1 (default 25, Sec. 6.2)             */
 } stk_uzawa_opts;
 
 typedef struct {
@@ -342,12 +348,17 @@ int stk_uzawa_pressure(stk_ctx* ctx, const stk_grid* g, const double* vx, const 
 /* Uzawa cycles from (vx, vy, p), all in/out, until E <= tol or max_cycles:
  *   b = f - G p;  `vcycles` FP64 V(nu1, nu2)-cycles of `mg` on M v = b from v;
  *   stk_uzawa_pressure;  E from a fresh FP64 residual (both blocks).
+ * With opts->stages > 0 the continuation stages come first (their cycles use
+ * the stage's hierarchy and its eta_c in the pressure step; E and the history
+ * always measure the true system, and only the last stage tests tol).
  * g must be the grid `mg` was created for (same nx, ny, ld) and eta_c, eta_n
  * the viscosities it was built from.  hist (nullable, HOST, max_cycles + 1
  * doubles) receives E of the start and after every cycle; rep (nullable) the
  * summary.  opts NULL means the defaults.  STK_ENOTCONV if E > tol at the end
  * (arrays, hist and rep are still written); the handle must not be in a
- * batch.  Allocates the folded right-hand side for the call's duration.
+ * batch.  Allocates for the call's duration: the folded right-hand side when
+ * g's stride is not the hierarchy's level-0 stride, and with continuation the
+ * stage viscosities and hierarchies (stk_mg_footprint(g, .., 0) bytes each).
  * Synchronises once per cycle (the stopping test). */
 int stk_uzawa_solve(stk_mg* mg, const stk_grid* g, double* vx, double* vy, double* p, const double* eta_c,
                     const double* eta_n, const double* fx, const double* fy, const stk_uzawa_opts* opts,

@@ -42,7 +42,8 @@ class Report(C.Structure):
 
 
 class UzawaOpts(C.Structure):
-    _fields_ = [("omega_p", C.c_double), ("vcycles", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int)]
+    _fields_ = [("omega_p", C.c_double), ("vcycles", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
+                ("stages", C.c_int), ("stage_cycles", C.c_int)]
 
 
 class UzawaReport(C.Structure):

@@ -15,6 +15,10 @@
 //                      from the top row, p(j-1) = p(j) + fy(j) dy
 //   k_mean             one workgroup sums the partials in a fixed order
 //   k_sub_mean         p <- p - mean
+//   k_min_partial, k_min_final, k_rescale
+//                      viscosity continuation (Sec. 6.2): eta_min over the
+//                      cells, then (1 - theta) eta_min + theta eta on the cell
+//                      and nodal fields of each stage's hierarchy
 // The reductions never use atomics: results are bitwise reproducible.
 #include <chrono>
 #include <cmath>
@@ -114,6 +118,61 @@ __global__ __launch_bounds__(UX* UY) void k_sub_mean(int nx, int ny, int64_t ld,
     for (int j = j0; j < j1; ++j) p[(int64_t)j * ld + i] -= m;
 }
 
+__device__ __forceinline__ double wave_min64(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
+    return v;
+}
+
+// Per-workgroup minimum of eta_c over the cells (same tiling as the pressure step).
+__global__ __launch_bounds__(UX* UY) void k_min_partial(int nx, int ny, int64_t ld, const double* __restrict__ ec,
+                                                        double* __restrict__ part) {
+    __shared__ double red[UY];
+    const int i = (int)blockIdx.x * UX + (int)threadIdx.x;
+    const int j0 = ((int)blockIdx.y * UY + (int)threadIdx.y) * UROWS;
+    double m = INFINITY;
+    if (i < nx && j0 < ny) {
+        const int j1 = min(j0 + UROWS, ny);
+        for (int j = j0; j < j1; ++j) m = fmin(m, ec[(int64_t)j * ld + i]);
+    }
+    m = wave_min64(m);
+    if (threadIdx.x == 0) red[threadIdx.y] = m;
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        for (int w = 1; w < UY; ++w) m = fmin(m, red[w]);
+        part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = m;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_min_final(const double* __restrict__ part, int64_t n,
+                                                    double* __restrict__ out) {
+    __shared__ double red[1024 / 64];
+    double m = INFINITY;
+    for (int64_t q = threadIdx.x; q < n; q += 1024) m = fmin(m, part[q]);
+    m = wave_min64(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 1024 / 64; ++w) m = fmin(m, red[w]);
+        *out = m;
+    }
+}
+
+// Computational viscosity of the continuation, (1 - theta) eta_min + theta eta,
+// on the cell and the nodal fields; every element of the (ny + 1) x ld arrays
+// is written (0 outside the fields).  Products and sum rounded separately.
+__global__ __launch_bounds__(256) void k_rescale(int nx, int ny, int64_t ld, double theta,
+                                                 const double* __restrict__ emin, const double* __restrict__ ec,
+                                                 const double* __restrict__ en, double* __restrict__ oc,
+                                                 double* __restrict__ on) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (int64_t)(ny + 1) * ld) return;
+    const int j = (int)(q / ld), i = (int)(q - (int64_t)j * ld);
+    const double a = __dmul_rn(1.0 - theta, *emin);
+    oc[q] = (j < ny && i < nx) ? __dadd_rn(a, __dmul_rn(theta, ec[q])) : 0.0;
+    on[q] = (i <= nx) ? __dadd_rn(a, __dmul_rn(theta, en[q])) : 0.0;
+}
+
 dim3 cell_grid_u(const stk_grid* g) {
     return dim3((unsigned)((g->nx + UX - 1) / UX), (unsigned)((g->ny + UY * UROWS - 1) / (UY * UROWS)));
 }
@@ -146,6 +205,76 @@ int check_omega_p(double w) {
     return STK_OK;
 }
 
+// Device buffer owned for the duration of a call.
+struct DevBuf {
+    void* p = nullptr;
+    int alloc(size_t bytes) {
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return set_error(STK_ENOMEM, "cannot allocate %zu bytes", bytes);
+        }
+        return STK_OK;
+    }
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// Uzawa cycles with hierarchy `mm` and pressure-step viscosity `ec_step`,
+// from the caller's (vx, vy, p); E (true system: eta_c, eta_n) after every
+// cycle lands in out / hist[k].  The last stage runs while E > tol, earlier
+// ones `stage_cycles` cycles; k counts all cycles against max_cycles.
+// When the caller's stride is the hierarchy's level-0 stride the cycles run
+// in the hierarchy's own level-0 vectors (the V-cycle's iterate and
+// right-hand side): the velocity is copied in and out once per stage instead
+// of staging v and b through stk_mg_vcycle every cycle.
+int uzawa_stage(stk_mg* mm, const stk_grid* g, double* vx, double* vy, double* p, const double* ec_step,
+                const double* eta_c, const double* eta_n, const double* fx, const double* fy,
+                const stk_uzawa_opts& o, bool last, int& k, double* out, double* hist) {
+    stk_ctx* ctx = mm->ctx;
+    stk_mg* self = mm;
+    if (!mm->plan[0]) STK_TRY(make_plan(ctx, &self, 1, 0, &mm->plan[0]));
+    const bool direct = g->ld == mm->L[0].ld;
+    double* wx = vx;
+    double* wy = vy;
+    void* bx = nullptr;
+    void* by = nullptr;
+    DevBuf fbx, fby;
+    if (direct) {
+        wx = static_cast<double*>(mm->ks[0][VS_Z].x);
+        wy = static_cast<double*>(mm->ks[0][VS_Z].y);
+        bx = mm->ks[0][VS_R].x;
+        by = mm->ks[0][VS_R].y;
+        STK_TRY(copy_vel_in(mm, vx, vy, g->ld, wx, wy, g->ld, sizeof(double)));
+    } else {
+        STK_TRY(fbx.alloc(field_bytes(g, g->ny, STK_F64)));
+        STK_TRY(fby.alloc(field_bytes(g, g->ny + 1, STK_F64)));
+        bx = fbx.p;
+        by = fby.p;
+    }
+    int n = 0;
+    while (k < o.max_cycles && (last ? out[3] > o.tol : n < o.stage_cycles)) {
+        STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, bx, by));  // b = f - G p
+        for (int c = 0; c < o.vcycles; ++c) {
+            if (direct)
+                STK_TRY(run_vcycle(ctx, *mm->plan[0], mm->o, 0));
+            else
+                STK_TRY(stk_mg_vcycle(mm, STK_F64, wx, wy, bx, by));
+        }
+        STK_TRY(pressure_update(ctx, g, wx, wy, ec_step, o.omega_p, p));
+        ++k;
+        ++n;
+        STK_TRY(stk_energy_norm(ctx, STK_F64, g, wx, wy, p, eta_c, eta_n, fx, fy, out));
+        if (hist) hist[k] = out[3];
+    }
+    if (direct) {
+        STK_TRY(copy_vel_in(mm, wx, wy, g->ld, vx, vy, g->ld, sizeof(double)));
+        STK_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    return STK_OK;
+}
+
 }  // namespace
 }  // namespace stk
 
@@ -159,6 +288,8 @@ void stk_uzawa_opts_default(stk_uzawa_opts* o) {
     o->vcycles = 1;
     o->tol = 1e-8;
     o->max_cycles = 1000;
+    o->stages = 0;
+    o->stage_cycles = 25;
 }
 
 int stk_litho_pressure(stk_ctx* ctx, const stk_grid* g, const double* fy, double* p) {
@@ -204,64 +335,50 @@ int stk_uzawa_solve(stk_mg* m, const stk_grid* g, double* vx, double* vy, double
     if (o.vcycles < 1) return set_error(STK_EINVAL, "vcycles must be >= 1 (got %d)", o.vcycles);
     if (o.max_cycles < 0) return set_error(STK_EINVAL, "max_cycles must be >= 0 (got %d)", o.max_cycles);
     if (!(o.tol >= 0.0)) return set_error(STK_EINVAL, "tol must be >= 0");
+    if (o.stages < 0 || o.stage_cycles < 0)
+        return set_error(STK_EINVAL, "stages and stage_cycles must be >= 0 (got %d, %d)", o.stages, o.stage_cycles);
     stk_ctx* ctx = m->ctx;
     STK_TRY(use_device(ctx));
-    stk_mg* self = m;
-    if (!m->plan[0]) STK_TRY(make_plan(ctx, &self, 1, 0, &m->plan[0]));
-    // When the caller's stride is the hierarchy's level-0 stride the cycles
-    // run in the hierarchy's own level-0 vectors (the V-cycle's iterate and
-    // right-hand side): the velocity is copied in and out once per call
-    // instead of staging v and b through stk_mg_vcycle every cycle.
-    const bool direct = g->ld == m->L[0].ld;
-    double* wx = vx;
-    double* wy = vy;
-    void* bx = nullptr;
-    void* by = nullptr;
-    struct Free {
-        void* a = nullptr;
-        void* b = nullptr;
-        ~Free() {
-            if (a) (void)hipFree(a);
-            if (b) (void)hipFree(b);
-        }
-    } fr;
-    if (direct) {
-        wx = static_cast<double*>(m->ks[0][VS_Z].x);
-        wy = static_cast<double*>(m->ks[0][VS_Z].y);
-        bx = m->ks[0][VS_R].x;
-        by = m->ks[0][VS_R].y;
-        STK_TRY(copy_vel_in(m, vx, vy, g->ld, wx, wy, g->ld, sizeof(double)));
-    } else {
-        const size_t bxb = field_bytes(g, g->ny, STK_F64), byb = field_bytes(g, g->ny + 1, STK_F64);
-        if (hipMalloc(&fr.a, bxb) != hipSuccess || hipMalloc(&fr.b, byb) != hipSuccess) {
-            (void)hipGetLastError();
-            return set_error(STK_ENOMEM, "cannot allocate the folded right-hand side (%zu bytes)", bxb + byb);
-        }
-        bx = fr.a;
-        by = fr.b;
-    }
     double out[5];
-    int rc = stk_energy_norm(ctx, STK_F64, g, wx, wy, p, eta_c, eta_n, fx, fy, out);
+    int rc = stk_energy_norm(ctx, STK_F64, g, vx, vy, p, eta_c, eta_n, fx, fy, out);
     if (rc != STK_OK) return rc;
     if (hist) hist[0] = out[3];
     int k = 0;
-    while (out[3] > o.tol && k < o.max_cycles) {
-        STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, bx, by));  // b = f - G p
-        for (int c = 0; c < o.vcycles; ++c) {
-            if (direct)
-                STK_TRY(run_vcycle(ctx, *m->plan[0], m->o, 0));
-            else
-                STK_TRY(stk_mg_vcycle(m, STK_F64, wx, wy, bx, by));
+    if (o.stages == 0) {
+        STK_TRY(uzawa_stage(m, g, vx, vy, p, eta_c, eta_c, eta_n, fx, fy, o, true, k, out, hist));
+    } else {
+        // continuation stages on the rescaled viscosities, each with its own hierarchy
+        const size_t fb = field_bytes(g, g->ny + 1, STK_F64);
+        DevBuf ecs, ens, tmp;
+        STK_TRY(ecs.alloc(fb));
+        STK_TRY(ens.alloc(fb));
+        STK_TRY(tmp.alloc(sizeof(double)));
+        const dim3 grid = cell_grid_u(g);
+        const int64_t nblk = (int64_t)grid.x * grid.y;
+        void* part = nullptr;
+        STK_TRY(scratch(ctx, stk_ctx::S_PART, sizeof(double) * (size_t)nblk, &part));
+        hipLaunchKernelGGL(k_min_partial, grid, dim3(UX, UY), 0, ctx->stream, g->nx, g->ny, g->ld, eta_c,
+                           (double*)part);
+        hipLaunchKernelGGL(k_min_final, dim3(1), dim3(1024), 0, ctx->stream, (const double*)part, nblk,
+                           (double*)tmp.p);
+        STK_HIP(hipGetLastError());
+        const int64_t cnt = (int64_t)(g->ny + 1) * g->ld;
+        for (int st = 0; st <= o.stages; ++st) {
+            if (st == o.stages) {  // theta = 1: the true system and the caller's hierarchy
+                STK_TRY(uzawa_stage(m, g, vx, vy, p, eta_c, eta_c, eta_n, fx, fy, o, true, k, out, hist));
+                break;
+            }
+            const double theta = (double)st / (double)o.stages;
+            hipLaunchKernelGGL(k_rescale, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, ctx->stream, g->nx,
+                               g->ny, g->ld, theta, (const double*)tmp.p, eta_c, eta_n, (double*)ecs.p,
+                               (double*)ens.p);
+            STK_HIP(hipGetLastError());
+            stk_mg* ms = nullptr;
+            STK_TRY(stk_mg_create(ctx, &ms, g, (const double*)ecs.p, (const double*)ens.p, &m->o));
+            rc = uzawa_stage(ms, g, vx, vy, p, (const double*)ecs.p, eta_c, eta_n, fx, fy, o, false, k, out, hist);
+            (void)stk_mg_destroy(ms);
+            if (rc != STK_OK) return rc;
         }
-        STK_TRY(pressure_update(ctx, g, wx, wy, eta_c, o.omega_p, p));
-        ++k;
-        rc = stk_energy_norm(ctx, STK_F64, g, wx, wy, p, eta_c, eta_n, fx, fy, out);
-        if (rc != STK_OK) return rc;
-        if (hist) hist[k] = out[3];
-    }
-    if (direct) {
-        STK_TRY(copy_vel_in(m, wx, wy, g->ld, vx, vy, g->ld, sizeof(double)));
-        STK_HIP(hipStreamSynchronize(ctx->stream));
     }
     const bool conv = out[3] <= o.tol;
     if (rep) {

@@ -192,3 +192,61 @@ def test_uzawa_argument_errors(ctx):
                                 max_cycles=2)
     assert rep["cycles"] == 2 and not rep["converged"] and len(hist) == 3
     m.close()
+
+
+@pytest.mark.parametrize("nx,contrast,align", [(64, 1e4, 64), (128, 1e3, 128)])
+def test_continuation_matches_oracle(ctx, nx, contrast, align):
+    """Four continuation stages of three cycles each, then four cycles of the
+    true system; the second case's stride (256 at nx = 128) stages v and b
+    through the V-cycle entry point."""
+    from paper_2509_19061_amd import api
+    p = sinkers(nx, nx, nx + 5, contrast)
+    d = dev(p, align)
+    m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
+    p0 = U.litho(p, p.fy)
+    vx, vy = d.velocity()
+    pt = d.field(p0)
+    rep, hist = api.uzawa_solve(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, allow_notconv=True, tol=0.0,
+                                max_cycles=16, stages=4, stage_cycles=3)
+    assert rep["cycles"] == 16
+    ox, oy, op, oh = U.uzawa_continuation(p, p.fx, p.fy, *p.zeros_v(), p0, stages=4, stage_cycles=3, tol=0.0,
+                                          max_cycles=16)
+    assert normwise(d.get_vx(vx), ox) <= 1e-9 and normwise(d.get_vy(vy), oy) <= 1e-9
+    assert normwise(d.get_cell(pt), op) <= 1e-9
+    np.testing.assert_allclose(hist, oh, rtol=1e-8)
+    m.close()
+
+
+def test_continuation_exact_solves_match_oracle(ctx):
+    """One-level hierarchies (exact velocity solves): stage 0 runs on the
+    constant viscosity min(eta_c), where omega_p = 2 reaches that system's
+    saddle point in two cycles; the oracle's pin of this case is the
+    assembled saddle-point solve."""
+    from paper_2509_19061_amd import api
+    p = sinkers(32, 32, 3, 1e3)
+    d = dev(p)
+    m = api.MG(ctx, d.grid, d.eta_c, d.eta_n, coarsest=64)
+    vx, vy = d.velocity()
+    pt = d.field()
+    rep, hist = api.uzawa_solve(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, allow_notconv=True, tol=0.0,
+                                omega_p=2.0, max_cycles=6, stages=2, stage_cycles=2)
+    ox, oy, op, oh = U.uzawa_continuation(p, p.fx, p.fy, *p.zeros_v(), np.zeros((32, 32)), stages=2,
+                                          stage_cycles=2, omega_p=2.0, tol=0.0, max_cycles=6, coarsest=64)
+    assert normwise(d.get_vx(vx), ox) <= 1e-9 and normwise(d.get_vy(vy), oy) <= 1e-9
+    assert normwise(d.get_cell(pt), op) <= 1e-9
+    np.testing.assert_allclose(hist, oh, rtol=1e-8)
+    m.close()
+
+
+def test_continuation_options_rejected(ctx):
+    from paper_2509_19061_amd import api
+    p = sinkers(64, 64, 1, 1e2)
+    d = dev(p)
+    m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
+    vx, vy = d.velocity()
+    pt = d.field()
+    for bad in (dict(stages=-1), dict(stages=2, stage_cycles=-3)):
+        with pytest.raises(api.StkError) as e:
+            api.uzawa_solve(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, **bad)
+        assert e.value.code == api.EINVAL
+    m.close()
