@@ -100,3 +100,67 @@ def uzawa_continuation(g, fx, fy, vx, vy, p, stages=4, stage_cycles=25, omega_p=
             hist.append(S.energy(g, vx, vy, fx, fy, p)[3])
             n += 1
     return vx, vy, p, hist
+
+
+def _cycle(levels, g, fx, fy, vx, vy, p, omega_p, vcycles, nu1, nu2, omega):
+    """F(x): one inexact Uzawa cycle from x = (vx, vy, p)."""
+    bx, by = S.rhs(g, fx, fy, p)
+    for _ in range(vcycles):
+        vx, vy = mg.vcycle(levels, 0, vx, vy, bx, by, nu1, nu2, omega)
+    return vx, vy, pressure_update(g, vx, vy, p, omega_p)
+
+
+def anderson_weights(R):
+    """alpha = argmin ||R alpha||_2 subject to sum(alpha) = 1 (Alg. 1), from the
+    stationarity conditions of the Lagrangian: [H 1; 1^T 0] [alpha; mu] =
+    [0; 1] with the Gram matrix H = R^T R (scaled by its largest diagonal
+    entry, which leaves alpha unchanged).  A singular system falls back to
+    alpha = (0, .., 0, 1), the plain step."""
+    H = R.T @ R
+    n = H.shape[0]
+    s = np.max(np.diag(H))
+    if not np.isfinite(s) or s <= 0.0:
+        return np.eye(n)[-1]
+    K = np.zeros((n + 1, n + 1))
+    K[:n, :n] = H / s
+    K[:n, n] = 1.0
+    K[n, :n] = 1.0
+    rhs = np.zeros(n + 1)
+    rhs[n] = 1.0
+    try:
+        a = np.linalg.solve(K, rhs)[:n]
+    except np.linalg.LinAlgError:
+        return np.eye(n)[-1]
+    return a if np.all(np.isfinite(a)) else np.eye(n)[-1]
+
+
+def anderson(levels, g, fx, fy, vx, vy, p, m=3, omega_p=0.6, vcycles=1, tol=1e-8, max_iters=200, nu1=2, nu2=2,
+             omega=0.7):
+    """Anderson acceleration of the inexact Uzawa fixed-point map F on
+    x = [v, p] (Sec. 3.3, Alg. 1): x_1 = F(x_0); then with m_k = min(m, k),
+    r_i = F(x_i) - x_i, the new iterate is the combination of the last m_k + 1
+    values F(x_i) whose weights (summing to 1) minimise the l2 norm of the
+    same combination of the r_i.  The norm runs over every velocity unknown
+    and pressure cell as one vector.  Stops when E of the new iterate <= tol.
+    Returns (vx, vy, p, history of E), one entry per F evaluation after the
+    start's."""
+    def flat(x):
+        return np.concatenate([np.ravel(x[0]), np.ravel(x[1]), np.ravel(x[2])])
+
+    x = (np.array(vx, float), np.array(vy, float), np.array(p, float))
+    hist = [S.energy(g, *x[:2], fx, fy, x[2])[3]]
+    Fs, rs = [], []
+    while hist[-1] > tol and len(hist) <= max_iters:
+        fxk = _cycle(levels, g, fx, fy, *x, omega_p, vcycles, nu1, nu2, omega)
+        Fs.append(fxk)
+        rs.append(flat(fxk) - flat(x))
+        k = len(Fs) - 1                      # the index of x_k
+        if k == 0:
+            x = fxk                          # x_1 = F(x_0)
+        else:
+            mk = min(m, k)
+            Fs, rs = Fs[-(mk + 1):], rs[-(mk + 1):]
+            a = anderson_weights(np.stack(rs, axis=1))
+            x = tuple(sum(a[i] * Fs[i][c] for i in range(mk + 1)) for c in range(3))
+        hist.append(S.energy(g, *x[:2], fx, fy, x[2])[3])
+    return x[0], x[1], x[2], hist

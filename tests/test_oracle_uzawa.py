@@ -165,3 +165,58 @@ def test_continuation_ends_at_the_true_solution():
     a = U.uzawa_continuation(g, g.fx, g.fy, *g.zeros_v(), U.litho(g, g.fy), stages=0, tol=0.0, max_cycles=5)
     b = U.uzawa(mg.hierarchy(g), g, g.fx, g.fy, *g.zeros_v(), U.litho(g, g.fy), tol=0.0, max_cycles=5)
     assert np.array_equal(a[2], b[2]) and a[3] == b[3]
+
+
+def test_anderson_depth_zero_is_the_plain_iteration():
+    g = sinkers(32, 1e2)
+    lv = mg.hierarchy(g)
+    p0 = U.litho(g, g.fy)
+    a = U.anderson(lv, g, g.fx, g.fy, *g.zeros_v(), p0, m=0, tol=0.0, max_iters=6)
+    b = U.uzawa(lv, g, g.fx, g.fy, *g.zeros_v(), p0, tol=0.0, max_cycles=6)
+    for u, w in zip(a[:3], b[:3]):
+        assert np.array_equal(u, w)
+    assert a[3] == b[3]
+
+
+@pytest.mark.parametrize("omega_p", [0.6, 1.3])
+def test_anderson_exact_at_third_iterate_for_constant_viscosity(omega_p):
+    """Exact velocity solves, constant viscosity: F is affine and its pressure
+    part contracts by c = 1 - omega_p/2 exactly, so r_2 = c r_1 and the
+    weights (-c, 1)/(1 - c) make x_3 the saddle-point solution."""
+    g = constant(12, 8, 3.0, 2)
+    lv = mg.hierarchy(g, coarsest=64)
+    vref_x, vref_y, pref = kkt(g, g.fx, g.fy)
+    rng = np.random.default_rng(4)
+    vx0, vy0 = rng.standard_normal((8, 13)), rng.standard_normal((9, 12))
+    vx0[:, 0] = vx0[:, -1] = 0.0
+    vy0[0] = vy0[-1] = 0.0
+    vx, vy, p, hist = U.anderson(lv, g, g.fx, g.fy, vx0, vy0, rng.standard_normal((8, 12)), m=2, omega_p=omega_p,
+                                 tol=0.0, max_iters=3)
+    assert len(hist) == 4 and hist[2] > 1e-3
+    assert np.abs(p - pref).max() <= 1e-10 * np.abs(pref).max()
+    assert np.abs(vy - vref_y).max() <= 1e-10 * np.abs(vref_y).max()
+
+
+def test_anderson_weights_minimise_under_the_constraint():
+    rng = np.random.default_rng(7)
+    R = rng.standard_normal((50, 4))
+    a = U.anderson_weights(R)
+    assert abs(a.sum() - 1.0) <= 1e-14
+    # any other admissible weights give a larger norm
+    for _ in range(20):
+        d = rng.standard_normal(4)
+        d -= d.mean()
+        assert np.linalg.norm(R @ (a + 1e-3 * d)) >= np.linalg.norm(R @ a)
+    # dependent columns: the plain step
+    assert np.array_equal(U.anderson_weights(np.zeros((5, 3))), [0.0, 0.0, 1.0])
+
+
+def test_anderson_converges_to_the_saddle_point_faster():
+    g = sinkers(32, 1e3)
+    lv = mg.hierarchy(g)
+    p0 = U.litho(g, g.fy)
+    a = U.anderson(lv, g, g.fx, g.fy, *g.zeros_v(), p0, m=5, tol=1e-9, max_iters=400)
+    b = U.uzawa(lv, g, g.fx, g.fy, *g.zeros_v(), p0, tol=1e-9, max_cycles=2000)
+    assert a[3][-1] <= 1e-9 and b[3][-1] <= 1e-9
+    assert len(a[3]) < len(b[3])
+    assert np.abs(a[2] - b[2]).max() <= 1e-6 * np.abs(b[2]).max()
