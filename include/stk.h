@@ -364,6 +364,26 @@ int stk_uzawa_solve(stk_mg* mg, const stk_grid* g, double* vx, double* vy, doubl
                     const double* eta_n, const double* fx, const double* fy, const stk_uzawa_opts* opts,
                     double* hist, stk_uzawa_report* rep);
 
+/* Anderson acceleration of the Uzawa cycles (Sec. 3.3, Alg. 1) on
+ * x = [v, p], from (vx, vy, p), all in/out.  F(x) is one Uzawa cycle as in
+ * stk_uzawa_solve (fold, opts->vcycles V-cycles of `mg`, pressure step).
+ * x_1 = F(x_0); then, with m_k = min(depth, k) and r_i = F(x_i) - x_i,
+ *   x_{k+1} = sum_t alpha_t F(x_{k-m_k+t}),
+ *   alpha = argmin || sum_t alpha_t r_{k-m_k+t} ||_2  with  sum_t alpha_t = 1,
+ * the l2 norm running over every velocity unknown and pressure cell.  The
+ * weights solve the bordered Gram system of that constrained least-squares
+ * problem on the host (a singular system takes the plain step alpha =
+ * (0, .., 0, 1)); depth 0 is the plain iteration.  Stops when E of x_{k+1}
+ * (Sec. 6.4) <= opts->tol or after opts->max_cycles evaluations of F.
+ * depth in [0, 8].  opts->stages must be 0 (STK_EUNSUPPORTED otherwise).
+ * hist (nullable, HOST, max_cycles + 1 doubles): E of x_0, x_1, ..;
+ * rep->cycles counts F evaluations.  Allocates 6 (depth + 1) + 2 planes of
+ * (ny + 1) * ld doubles for the call's duration.  Synchronises once per
+ * step.  STK_ENOTCONV as stk_uzawa_solve. */
+int stk_uzawa_anderson(stk_mg* mg, const stk_grid* g, double* vx, double* vy, double* p, const double* eta_c,
+                       const double* eta_n, const double* fx, const double* fy, int depth,
+                       const stk_uzawa_opts* opts, double* hist, stk_uzawa_report* rep);
+
 #ifdef __cplusplus
 }
 #endif

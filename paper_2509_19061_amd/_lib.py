@@ -95,6 +95,8 @@ _SIGS = {
     "stk_uzawa_pressure": ([_P, _G, _P, _P, _P, C.c_double, _P], _I),
     "stk_uzawa_solve": ([_P, _G, _P, _P, _P, _P, _P, _P, _P, C.POINTER(UzawaOpts), C.POINTER(C.c_double),
                          C.POINTER(UzawaReport)], _I),
+    "stk_uzawa_anderson": ([_P, _G, _P, _P, _P, _P, _P, _P, _P, _I, C.POINTER(UzawaOpts), C.POINTER(C.c_double),
+                            C.POINTER(UzawaReport)], _I),
 }
 
 

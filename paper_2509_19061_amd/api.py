@@ -22,7 +22,7 @@ __all__ = ["Context", "Grid", "SmoothOpts", "StkError", "smooth", "ras_outer", "
            "smooth_opts", "F64", "F32", "JACOBI", "JACOBI_FUSED", "RAS_JACOBI", "RBGS", "VARIANTS", "OK", "EINVAL",
            "ENOMEM", "EHIP", "ENOTCONV", "ENONFINITE", "EUNSUPPORTED", "dtype_code", "torch_dtype", "MG", "mg_opts",
            "mg_footprint", "mg_solve_batch", "SOLVE_F64", "SOLVE_F32_REFINED", "MODES", "Batch", "uzawa_opts",
-           "litho_pressure", "uzawa_pressure", "uzawa_solve"]
+           "litho_pressure", "uzawa_pressure", "uzawa_solve", "uzawa_anderson"]
 
 MODES = {"f64": SOLVE_F64, "f32_refined": SOLVE_F32_REFINED}
 
@@ -339,6 +339,20 @@ def uzawa_solve(mg, grid, vx, vy, p, eta_c, eta_n, fx, fy, allow_notconv=False, 
     rc = L.lib.stk_uzawa_solve(mg.handle, C.byref(grid), _ptr(vx, F64), _ptr(vy, F64), _ptr(p, F64),
                                _ptr(eta_c, F64), _ptr(eta_n, F64), _ptr(fx, F64), _ptr(fy, F64), C.byref(o), hist,
                                C.byref(r))
+    if not (allow_notconv and rc == ENOTCONV):
+        check(rc)
+    rep = dict(cycles=r.cycles, converged=bool(r.converged), e=r.e, ev=r.ev, seconds=r.seconds)
+    return rep, np.array(hist[:r.cycles + 1])
+
+
+def uzawa_anderson(mg, grid, vx, vy, p, eta_c, eta_n, fx, fy, depth=3, allow_notconv=False, **opts):
+    """Anderson-accelerated Uzawa steps in place on (vx, vy, p); returns (report dict, E history)."""
+    o = uzawa_opts(**opts)
+    hist = (C.c_double * (o.max_cycles + 1))()
+    r = L.UzawaReport()
+    rc = L.lib.stk_uzawa_anderson(mg.handle, C.byref(grid), _ptr(vx, F64), _ptr(vy, F64), _ptr(p, F64),
+                                  _ptr(eta_c, F64), _ptr(eta_n, F64), _ptr(fx, F64), _ptr(fy, F64), int(depth),
+                                  C.byref(o), hist, C.byref(r))
     if not (allow_notconv and rc == ENOTCONV):
         check(rc)
     rep = dict(cycles=r.cycles, converged=bool(r.converged), e=r.e, ev=r.ev, seconds=r.seconds)

@@ -250,3 +250,85 @@ def test_continuation_options_rejected(ctx):
             api.uzawa_solve(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, **bad)
         assert e.value.code == api.EINVAL
     m.close()
+
+
+def test_anderson_depth_zero_equals_plain_cycles_bitwise(ctx):
+    from paper_2509_19061_amd import api
+    p = sinkers(96, 64, 21, 1e3)
+    res = []
+    for depth in (None, 0):
+        d = dev(p)
+        m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
+        vx, vy = d.velocity()
+        pt = d.field()
+        api.litho_pressure(ctx, d.grid, d.fy, pt)
+        if depth is None:
+            _, hist = api.uzawa_solve(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, allow_notconv=True,
+                                      tol=0.0, max_cycles=5)
+        else:
+            _, hist = api.uzawa_anderson(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, depth=0,
+                                         allow_notconv=True, tol=0.0, max_cycles=5)
+        res.append((d.get_vx(vx), d.get_vy(vy), d.get_cell(pt), hist))
+        m.close()
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("nx,ny,contrast,depth", [(64, 64, 1e3, 3), (96, 80, 1e2, 5)])
+def test_anderson_matches_oracle(ctx, nx, ny, contrast, depth):
+    from paper_2509_19061_amd import api
+    p = sinkers(nx, ny, nx + 2 * ny, contrast)
+    d = dev(p)
+    m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
+    p0 = U.litho(p, p.fy)
+    vx, vy = d.velocity()
+    pt = d.field(p0)
+    steps = 10
+    rep, hist = api.uzawa_anderson(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, depth=depth,
+                                   allow_notconv=True, tol=0.0, max_cycles=steps)
+    assert rep["cycles"] == steps
+    levels = OM.hierarchy(p, coarsest=8)
+    ox, oy, op, oh = U.anderson(levels, p, p.fx, p.fy, *p.zeros_v(), p0, m=depth, tol=0.0, max_iters=steps)
+    assert normwise(d.get_vx(vx), ox) <= 1e-8 and normwise(d.get_vy(vy), oy) <= 1e-8
+    assert normwise(d.get_cell(pt), op) <= 1e-8
+    np.testing.assert_allclose(hist, oh, rtol=1e-7)
+    m.close()
+
+
+def test_anderson_exact_third_iterate_constant_viscosity(ctx):
+    """Exact velocity solves and constant viscosity: r_2 = c r_1 with
+    c = 1 - omega_p/2, so the third iterate is the saddle-point solution."""
+    from paper_2509_19061_amd import api
+    nx = ny = 32
+    p = I.sinker_problem(nx, ny, [], 3.0, 3.0)
+    rng = np.random.default_rng(8)
+    p.fx = rng.standard_normal(p.fx.shape)
+    p.fy = rng.standard_normal(p.fy.shape)
+    d = dev(p)
+    m = api.MG(ctx, d.grid, d.eta_c, d.eta_n, coarsest=64)
+    p0 = rng.standard_normal((ny, nx))
+    vx, vy = d.velocity()
+    pt = d.field(p0)
+    rep, hist = api.uzawa_anderson(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, depth=2, omega_p=0.6,
+                                   allow_notconv=True, tol=0.0, max_cycles=3)
+    assert len(hist) == 4 and hist[2] > 1e-3 * hist[0]
+    assert hist[3] <= 1e-10 * hist[0]
+    lv = OM.hierarchy(p, coarsest=64)
+    ox, oy, op, oh = U.anderson(lv, p, p.fx, p.fy, *p.zeros_v(), p0, m=2, omega_p=0.6, tol=0.0, max_iters=3)
+    assert normwise(d.get_cell(pt), op) <= 1e-9 and normwise(d.get_vy(vy), oy) <= 1e-9
+    m.close()
+
+
+def test_anderson_options_rejected(ctx):
+    from paper_2509_19061_amd import api
+    p = sinkers(64, 64, 1, 1e2)
+    d = dev(p)
+    m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
+    vx, vy = d.velocity()
+    pt = d.field()
+    for kw, code in ((dict(depth=9), api.EINVAL), (dict(depth=-1), api.EINVAL),
+                     (dict(depth=2, stages=4), api.EUNSUPPORTED), (dict(depth=2, vcycles=0), api.EINVAL)):
+        with pytest.raises(api.StkError) as e:
+            api.uzawa_anderson(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, **kw)
+        assert e.value.code == code
+    m.close()
