@@ -13,10 +13,10 @@
 // p: ny x nx).
 //
 // Kernels (FP64, bound by HBM bandwidth):
-//   k_aa_diff     r = F - x
-//   k_aa_dots     products of the new residual with up to AA_MAX residuals,
-//                 per-workgroup partials; k_aa_dots_final sums them in a fixed
-//                 order (one workgroup per product)
+//   k_aa_diff_dots  r = F - x, and the products of r with the window's
+//                 residuals (itself included), per-workgroup partials;
+//                 k_aa_dots_final sums them in a fixed order (one workgroup
+//                 per product)
 //   k_aa_combine  x = sum_t a_t F_t (products and sums rounded separately, in
 //                 the order t = 0, 1, ..)
 #include <algorithm>
@@ -46,43 +46,40 @@ __device__ __forceinline__ void masks(int64_t q, int64_t ld, int nx, int ny, boo
     mp = j < ny && i < nx;
 }
 
-__global__ __launch_bounds__(AT) void k_aa_diff(int nx, int ny, int64_t ld, const double* __restrict__ fx,
-                                                const double* __restrict__ fy, const double* __restrict__ fp,
-                                                const double* __restrict__ xx, const double* __restrict__ xy,
-                                                const double* __restrict__ xp, double* __restrict__ rx,
-                                                double* __restrict__ ry, double* __restrict__ rp) {
-    const int64_t q = (int64_t)blockIdx.x * AT + threadIdx.x;
-    if (q >= (int64_t)(ny + 1) * ld) return;
-    bool mx, my, mp;
-    masks(q, ld, nx, ny, mx, my, mp);
-    rx[q] = mx ? fx[q] - xx[q] : 0.0;
-    ry[q] = my ? fy[q] - xy[q] : 0.0;
-    rp[q] = mp ? fp[q] - xp[q] : 0.0;
-}
-
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_down(v, o, 64);
     return v;
 }
 
-// part[t * nblk + block] = sum over the block's elements of r . r_t
-// (the residual planes are 0 outside the used extents)
-__global__ __launch_bounds__(AT) void k_aa_dots(int64_t cnt, const double* __restrict__ rx,
-                                                const double* __restrict__ ry, const double* __restrict__ rp,
-                                                Planes o, double* __restrict__ part) {
+// r = F - x written to the new residual's planes (0 outside the used
+// extents), and part[t * nblk + block] = sum over the block's elements of
+// r . r_t for the window's older residuals t < n - 1 and r . r for t = n - 1
+// (the window's newest entry is r itself and is not read back).
+__global__ __launch_bounds__(AT) void k_aa_diff_dots(int nx, int ny, int64_t ld, const double* __restrict__ fx,
+                                                     const double* __restrict__ fy, const double* __restrict__ fp,
+                                                     const double* __restrict__ xx, const double* __restrict__ xy,
+                                                     const double* __restrict__ xp, double* __restrict__ rx,
+                                                     double* __restrict__ ry, double* __restrict__ rp, Planes o,
+                                                     double* __restrict__ part) {
     __shared__ double red[AA_MAX][AT / 64];
     const int64_t q = (int64_t)blockIdx.x * AT + threadIdx.x;
+    const int64_t cnt = (int64_t)(ny + 1) * ld;
     double a = 0.0, b = 0.0, c = 0.0;
     if (q < cnt) {
-        a = rx[q];
-        b = ry[q];
-        c = rp[q];
+        bool mx, my, mp;
+        masks(q, ld, nx, ny, mx, my, mp);
+        a = mx ? fx[q] - xx[q] : 0.0;
+        b = my ? fy[q] - xy[q] : 0.0;
+        c = mp ? fp[q] - xp[q] : 0.0;
+        rx[q] = a;
+        ry[q] = b;
+        rp[q] = c;
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int t = 0; t < o.n; ++t) {
         double s = 0.0;
-        if (q < cnt) s = a * o.v[t][0][q] + b * o.v[t][1][q] + c * o.v[t][2][q];
+        if (q < cnt) s = t == o.n - 1 ? a * a + b * b + c * c : a * o.v[t][0][q] + b * o.v[t][1][q] + c * o.v[t][2][q];
         s = wsum(s);
         if (lane == 0) red[t][w] = s;
     }
@@ -230,6 +227,13 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
     void* part = nullptr;
     STK_TRY(scratch(ctx, stk_ctx::S_PART, sizeof(double) * (size_t)nblk * AA_MAX, &part));
     const dim3 eg((unsigned)nblk), eb(AT);
+    stk_mg* self = m;
+    if (!m->plan[0]) STK_TRY(make_plan(ctx, &self, 1, 0, &m->plan[0]));
+    const bool direct = g->ld == m->L[0].ld;
+    double* zx = static_cast<double*>(m->ks[0][VS_Z].x);
+    double* zy = static_cast<double*>(m->ks[0][VS_Z].y);
+    double* rx0 = static_cast<double*>(m->ks[0][VS_R].x);
+    double* ry0 = static_cast<double*>(m->ks[0][VS_R].y);
     std::vector<double> H((size_t)W * W, 0.0);       // Gram matrix over ring slots
     double out[5];
     int rc = stk_energy_norm(ctx, STK_F64, g, vx, vy, p, eta_c, eta_n, fx, fy, out);
@@ -238,20 +242,25 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
     int k = 0;  // index of the current iterate x_k = (vx, vy, p)
     while (out[3] > o.tol && k < o.max_cycles) {
         const int sk = k % W;
-        // F(x_k): the used extents of x_k copied into slot sk, one Uzawa cycle there
+        // F(x_k) into slot sk: one Uzawa cycle from x_k.  When the caller's
+        // stride is the hierarchy's level-0 stride, the V-cycle runs in the
+        // hierarchy's own level-0 vectors (iterate loaded from x_k, right-hand
+        // side folded in place); otherwise x_k is copied into the slot and the
+        // V-cycle entry point stages it.
         const size_t rowb = (size_t)g->ld * sizeof(double);
-        STK_HIP(hipMemcpy2DAsync(F(sk, 0), rowb, vx, rowb, (size_t)(g->nx + 1) * sizeof(double), g->ny,
-                                 hipMemcpyDeviceToDevice, ctx->stream));
-        STK_HIP(hipMemcpy2DAsync(F(sk, 1), rowb, vy, rowb, (size_t)g->nx * sizeof(double), g->ny + 1,
-                                 hipMemcpyDeviceToDevice, ctx->stream));
         STK_HIP(hipMemcpy2DAsync(F(sk, 2), rowb, p, rowb, (size_t)g->nx * sizeof(double), g->ny,
                                  hipMemcpyDeviceToDevice, ctx->stream));
-        STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, F(sk, 2), bx, by));
-        for (int c = 0; c < o.vcycles; ++c) STK_TRY(stk_mg_vcycle(m, STK_F64, F(sk, 0), F(sk, 1), bx, by));
+        if (direct) {
+            STK_TRY(copy_vel_in(m, vx, vy, g->ld, zx, zy, g->ld, sizeof(double)));
+            STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, rx0, ry0));
+            for (int c = 0; c < o.vcycles; ++c) STK_TRY(run_vcycle(ctx, *m->plan[0], m->o, 0));
+            STK_TRY(copy_vel_in(m, zx, zy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
+        } else {
+            STK_TRY(copy_vel_in(m, vx, vy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
+            STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, bx, by));
+            for (int c = 0; c < o.vcycles; ++c) STK_TRY(stk_mg_vcycle(m, STK_F64, F(sk, 0), F(sk, 1), bx, by));
+        }
         STK_TRY(stk_uzawa_pressure(ctx, g, F(sk, 0), F(sk, 1), eta_c, o.omega_p, F(sk, 2)));
-        hipLaunchKernelGGL(k_aa_diff, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, F(sk, 0), F(sk, 1), F(sk, 2),
-                           vx, vy, p, R(sk, 0), R(sk, 1), R(sk, 2));
-        STK_HIP(hipGetLastError());
         // products of r_k with the window r_{k-mk} .. r_k (oldest first) into
         // the Gram matrix over ring slots
         const int mk = std::min(depth, k);
@@ -259,8 +268,8 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
         D.n = mk + 1;
         for (int t = 0; t <= mk; ++t)
             for (int c = 0; c < 3; ++c) D.v[t][c] = R((k - mk + t) % W, c);
-        hipLaunchKernelGGL(k_aa_dots, eg, eb, 0, ctx->stream, plane, R(sk, 0), R(sk, 1), R(sk, 2), D,
-                           (double*)part);
+        hipLaunchKernelGGL(k_aa_diff_dots, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, F(sk, 0), F(sk, 1),
+                           F(sk, 2), vx, vy, p, R(sk, 0), R(sk, 1), R(sk, 2), D, (double*)part);
         hipLaunchKernelGGL(k_aa_dots_final, dim3((unsigned)D.n), dim3(1024), 0, ctx->stream, (const double*)part,
                            nblk, (double*)dots.p);
         STK_HIP(hipGetLastError());

@@ -274,11 +274,13 @@ def test_anderson_depth_zero_equals_plain_cycles_bitwise(ctx):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("nx,ny,contrast,depth", [(64, 64, 1e3, 3), (96, 80, 1e2, 5)])
-def test_anderson_matches_oracle(ctx, nx, ny, contrast, depth):
+# align 128 at nx = 128: a stride other than the hierarchy's (the staged V-cycle path)
+@pytest.mark.parametrize("nx,ny,contrast,depth,align", [(64, 64, 1e3, 3, 64), (96, 80, 1e2, 5, 64),
+                                                       (128, 128, 1e3, 3, 128)])
+def test_anderson_matches_oracle(ctx, nx, ny, contrast, depth, align):
     from paper_2509_19061_amd import api
     p = sinkers(nx, ny, nx + 2 * ny, contrast)
-    d = dev(p)
+    d = dev(p, align)
     m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
     p0 = U.litho(p, p.fy)
     vx, vy = d.velocity()
