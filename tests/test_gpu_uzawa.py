@@ -334,3 +334,38 @@ def test_anderson_options_rejected(ctx):
             api.uzawa_anderson(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, **kw)
         assert e.value.code == code
     m.close()
+
+
+def test_pressure_step_and_litho_full_size():
+    """4096^2 (the benchmark's size): the pressure step checked on 2000 sampled
+    cells, the lithostatic start by hydrostatic balance on every interior
+    face."""
+    from paper_2509_19061_amd import api
+    c = api.Context(0)
+    p = I.smoother_workload(4096)
+    d = dev(p)
+    rng = np.random.default_rng(31)
+    vx0, vy0 = I.random_velocity(p, 32, 1e-3)
+    p0 = rng.standard_normal((4096, 4096))
+    vx, vy = d.velocity(vx0, vy0)
+    pt = d.field(p0)
+    api.uzawa_pressure(c, d.grid, vx, vy, d.eta_c, 0.6, pt)
+    torch.cuda.synchronize()
+    got = d.get_cell(pt)
+    assert abs(got.mean()) <= 1e-12 * np.abs(got).max()
+    jj, ii = rng.integers(0, 4096, 2000), rng.integers(0, 4096, 2000)
+    div = (vx0[jj, ii + 1] - vx0[jj, ii]) * 4096 + (vy0[jj + 1, ii] - vy0[jj, ii]) * 4096
+    step = p0[jj, ii] - 0.6 * p.eta_c[jj, ii] * div        # before the mean is removed
+    shift = got[jj, ii] - step                             # = -mean, the same for every cell
+    assert np.abs(shift - shift.mean()).max() <= 1e-9 * np.abs(step).max()
+    full = p0 - 0.6 * p.eta_c * ((vx0[:, 1:] - vx0[:, :-1]) * 4096 + (vy0[1:] - vy0[:-1]) * 4096)
+    assert abs(shift.mean() + full.mean()) <= 1e-11 * np.abs(full).max()
+    # lithostatic pressure: with v = 0 the velocity residual b - M v = f - G p
+    # vanishes on every interior vy face
+    api.litho_pressure(c, d.grid, d.fy, pt)
+    zx, zy = d.velocity()
+    rx, ry = d.velocity()
+    api.residual(c, torch.float64, d.grid, zx, zy, pt, d.eta_c, d.eta_n, d.fx, d.fy, rx, ry)
+    torch.cuda.synchronize()
+    assert float(ry[1:4096, :4096].abs().max()) <= 1e-10 * float(d.fy.abs().max())
+    c.close()
