@@ -8,7 +8,9 @@ seed 3) through stk_smooth, followed by the energy norm (Sec. 6.4).
 Value: GLUP/s = cells x sweeps / step time (HIP events on the stream).
 
 Also reported: every smoother variant at 100 sweeps (Jacobi split, fused,
-RBGS, RAS k = 2, 4, 8), the dominant kernel's roofline (RAS outer-iteration
+RBGS, RAS k = 2, 4, 8 with halo k (= Jacobi^k) and with halo 0 (the paper's
+thin-overlap form), each with the energy residual reached after 100 sweeps
+from 0), the dominant kernel's roofline (RAS outer-iteration
 kernel timed per launch with HIP events; algorithmic bytes = one round trip
 of vx, vy, eta_c, eta_n, bx, by read and vx, vy written per launch), the CPU
 oracle timed on this host on a bounded sample of the same workload, and the
@@ -186,10 +188,14 @@ def main():
         words = {"jacobi": 12, "jacobi_fused": 8, "rbgs": 22}
         runs = [("jacobi", {}), ("jacobi_fused", {}), ("rbgs", {})]
         runs += [(f"ras_k{kk}", dict(tile_x=64, tile_y=64, k=kk, halo=kk, seed=3)) for kk in (2, 4, 8)]
+        # the paper's thin-overlap form (halo 0: tile boundaries frozen for k sweeps), a
+        # different smoother from Jacobi^k: convergence against k
+        runs += [(f"ras_h0_k{kk}", dict(tile_x=64, tile_y=64, k=kk, halo=0, seed=3)) for kk in (2, 4, 8)]
         for name, kw in runs:
             var = "ras" if name.startswith("ras") else name
             wx, wy = dp.velocity()
             api.smooth(ctx, dt, dp.grid, wx, wy, None, dp.eta_c, dp.eta_n, dp.fx, dp.fy, sweeps, var, **kw)
+            e_sweeps = float(api.energy_norm(ctx, dt, dp.grid, wx, wy, None, dp.eta_c, dp.eta_n, dp.fx, dp.fy)[3])
             torch.cuda.synchronize()
             reps = 3
             ev0.record()
@@ -203,8 +209,9 @@ def main():
             eff = g * w * wbytes
             variants[name] = {"ms_per_100_sweeps": round(t_ms, 3), "glups": round(g, 2),
                               "effective_gbs": round(eff, 1), "frac_hbm": round(eff / HBM_PEAK_GBS, 4),
-                              "words_per_lup": w}
-            log(f"[bench] {name}: {t_ms:.2f} ms / {sweeps} sweeps, {g:.1f} GLUP/s, {eff:.0f} GB/s effective")
+                              "words_per_lup": w, "e_after_sweeps": e_sweeps}
+            log(f"[bench] {name}: {t_ms:.2f} ms / {sweeps} sweeps, {g:.1f} GLUP/s, {eff:.0f} GB/s effective, "
+                f"E after {sweeps} sweeps from 0: {e_sweeps:.6e}")
         # residual (r_v = b - M v, r_p = -D v) and energy norm: algorithmic bytes per cell
         # = vx, vy, eta_c, eta_n, fx, fy read (+ rx, ry, rp written for the residual)
         rx, ry, rp = torch.empty_like(dp.fx), torch.empty_like(dp.fy), torch.empty_like(dp.eta_c)
