@@ -421,6 +421,25 @@ def run_uzawa(ctx, n, tol=1e-8, max_cycles=1000, omega_p=0.6, reps=20):
     e = api.energy_norm(ctx, torch.float64, dp.grid, vx, vy, p, dp.eta_c, dp.eta_n, dp.fx, dp.fy)
     log(f"[bench] uzawa {n}^2: {rep['cycles']} cycles in {secs:.3f}s, E {rep['e']:.3e} (recomputed {e[3]:.3e}), "
         f"E_v {e[4]:.3e}")
+    # the same solve with FP32 V-cycles on the FP64 residual
+    mvx, mvy, mp = dp.velocity() + (dp.field(),)
+    api.uzawa_solve(m, dp.grid, mvx, mvy, mp, dp.eta_c, dp.eta_n, dp.fx, dp.fy, allow_notconv=True, max_cycles=1,
+                    mode="f32_refined")  # FP32 buffers, plan
+    mvx, mvy, mp = dp.velocity() + (dp.field(),)
+
+    def msolve():
+        api.litho_pressure(ctx, dp.grid, dp.fy, mp)
+        return api.uzawa_solve(m, dp.grid, mvx, mvy, mp, dp.eta_c, dp.eta_n, dp.fx, dp.fy, allow_notconv=True,
+                               omega_p=omega_p, tol=tol, max_cycles=max_cycles, mode="f32_refined")
+
+    (mrep, _), msecs = _timed(msolve)
+    me = api.energy_norm(ctx, torch.float64, dp.grid, mvx, mvy, mp, dp.eta_c, dp.eta_n, dp.fx, dp.fy)
+    log(f"[bench] uzawa {n}^2 FP32 V-cycle: {mrep['cycles']} cycles in {msecs:.3f}s, E {mrep['e']:.3e} "
+        f"(recomputed {me[3]:.3e})")
+    mixed = {"seconds": round(msecs, 4), "cycles": mrep["cycles"], "converged": mrep["converged"],
+             "ms_per_cycle": round(msecs * 1e3 / max(1, mrep["cycles"]), 3), "e_report": mrep["e"],
+             "e_recomputed": float(me[3]), "speedup_vs_f64": round(secs / msecs, 3)}
+    del mvx, mvy, mp
 
     def pressure_steps():
         for _ in range(reps):
@@ -480,7 +499,7 @@ def run_uzawa(ctx, n, tol=1e-8, max_cycles=1000, omega_p=0.6, reps=20):
             "e_report": rep["e"], "e_recomputed": float(e[3]), "ev": float(e[4]),
             "pressure_step": {"ms": round(pms, 4), "words_per_cell": words, "effective_gbs": round(gbs, 1),
                               "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)},
-            "continuation": cont, "anderson": anderson}
+            "f32_refined": mixed, "continuation": cont, "anderson": anderson}
 
 
 def run_iteration_cost(ctx, n, iters=30):

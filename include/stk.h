@@ -321,6 +321,11 @@ typedef struct {
                          its own built for the call, before the true system (theta = 1, `mg`);
                          0 (default) = none; the paper runs 4                                   */
     int stage_cycles; /* Uzawa cycles per stage with theta < 1 (default 25, Sec. 6.2)             */
+    int mode;         /* velocity update precision (stk_solve_mode; default STK_SOLVE_F64): with
+                         STK_SOLVE_F32_REFINED each V-cycle runs in FP32 on the FP64 residual
+                         f - G p - M v rounded to FP32, from zero, and its result is added to
+                         the FP64 velocity (the V-cycle is consistent, so this is the FP64 cycle
+                         up to FP32 rounding); pressure step and norms stay FP64           */
 } stk_uzawa_opts;
 
 typedef struct {
@@ -356,9 +361,9 @@ int stk_uzawa_pressure(stk_ctx* ctx, const stk_grid* g, const double* vx, const 
  * doubles) receives E of the start and after every cycle; rep (nullable) the
  * summary.  opts NULL means the defaults.  STK_ENOTCONV if E > tol at the end
  * (arrays, hist and rep are still written); the handle must not be in a
- * batch.  Allocates for the call's duration: the folded right-hand side when
- * g's stride is not the hierarchy's level-0 stride, and with continuation the
- * stage viscosities and hierarchies (stk_mg_footprint(g, .., 0) bytes each).
+ * batch.  With continuation it allocates, for the call's duration, the stage
+ * viscosities and hierarchies (stk_mg_footprint(g, .., 0) bytes each); the
+ * FP32 V-cycle mode allocates an FP64 residual (two planes).
  * Synchronises once per cycle (the stopping test). */
 int stk_uzawa_solve(stk_mg* mg, const stk_grid* g, double* vx, double* vy, double* p, const double* eta_c,
                     const double* eta_n, const double* fx, const double* fy, const stk_uzawa_opts* opts,
@@ -375,9 +380,10 @@ int stk_uzawa_solve(stk_mg* mg, const stk_grid* g, double* vx, double* vy, doubl
  * problem on the host (a singular system takes the plain step alpha =
  * (0, .., 0, 1)); depth 0 is the plain iteration.  Stops when E of x_{k+1}
  * (Sec. 6.4) <= opts->tol or after opts->max_cycles evaluations of F.
- * depth in [0, 8].  opts->stages must be 0 (STK_EUNSUPPORTED otherwise).
+ * depth in [0, 8].  opts->stages must be 0 and opts->mode STK_SOLVE_F64
+ * (STK_EUNSUPPORTED otherwise).
  * hist (nullable, HOST, max_cycles + 1 doubles): E of x_0, x_1, ..;
- * rep->cycles counts F evaluations.  Allocates 6 (depth + 1) + 2 planes of
+ * rep->cycles counts F evaluations.  Allocates 6 (depth + 1) planes of
  * (ny + 1) * ld doubles for the call's duration.  Synchronises once per
  * step.  STK_ENOTCONV as stk_uzawa_solve. */
 int stk_uzawa_anderson(stk_mg* mg, const stk_grid* g, double* vx, double* vy, double* p, const double* eta_c,

@@ -43,7 +43,7 @@ class Report(C.Structure):
 
 class UzawaOpts(C.Structure):
     _fields_ = [("omega_p", C.c_double), ("vcycles", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
-                ("stages", C.c_int), ("stage_cycles", C.c_int)]
+                ("stages", C.c_int), ("stage_cycles", C.c_int), ("mode", C.c_int)]
 
 
 class UzawaReport(C.Structure):

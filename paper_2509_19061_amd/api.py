@@ -312,11 +312,11 @@ class Batch:
             pass
 
 
-def uzawa_opts(omega_p=0.6, vcycles=1, tol=1e-8, max_cycles=1000, stages=0, stage_cycles=25):
+def uzawa_opts(omega_p=0.6, vcycles=1, tol=1e-8, max_cycles=1000, stages=0, stage_cycles=25, mode="f64"):
     o = L.UzawaOpts()
     L.lib.stk_uzawa_opts_default(C.byref(o))
     o.omega_p, o.vcycles, o.tol, o.max_cycles = float(omega_p), int(vcycles), float(tol), int(max_cycles)
-    o.stages, o.stage_cycles = int(stages), int(stage_cycles)
+    o.stages, o.stage_cycles, o.mode = int(stages), int(stage_cycles), _mode(mode)
     return o
 
 

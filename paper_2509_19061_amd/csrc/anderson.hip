@@ -209,27 +209,24 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
     if (o.max_cycles < 0) return set_error(STK_EINVAL, "max_cycles must be >= 0 (got %d)", o.max_cycles);
     if (!(o.tol >= 0.0)) return set_error(STK_EINVAL, "tol must be >= 0");
     if (o.stages != 0) return set_error(STK_EUNSUPPORTED, "Anderson acceleration runs without continuation stages");
+    if (o.mode != STK_SOLVE_F64) return set_error(STK_EUNSUPPORTED, "Anderson acceleration runs FP64 V-cycles");
     stk_ctx* ctx = m->ctx;
     STK_TRY(use_device(ctx));
     const int W = depth + 1;                          // ring of W slots
     const int64_t plane = (int64_t)(g->ny + 1) * g->ld;
     const size_t pb = (size_t)plane * sizeof(double);
-    Dev ring, bbuf, dots;
+    Dev ring, dots;
     STK_TRY(ring.alloc(pb * 3 * 2 * (size_t)W));      // F and R vectors, 3 planes each
-    STK_TRY(bbuf.alloc(pb * 2));                      // folded right-hand side
     STK_TRY(dots.alloc(sizeof(double) * AA_MAX));
     double* base = static_cast<double*>(ring.p);
     auto F = [&](int s, int c) { return base + ((int64_t)(2 * s) * 3 + c) * plane; };
     auto R = [&](int s, int c) { return base + ((int64_t)(2 * s + 1) * 3 + c) * plane; };
-    double* bx = static_cast<double*>(bbuf.p);
-    double* by = bx + plane;
     const int64_t nblk = (plane + AT - 1) / AT;
     void* part = nullptr;
     STK_TRY(scratch(ctx, stk_ctx::S_PART, sizeof(double) * (size_t)nblk * AA_MAX, &part));
     const dim3 eg((unsigned)nblk), eb(AT);
     stk_mg* self = m;
     if (!m->plan[0]) STK_TRY(make_plan(ctx, &self, 1, 0, &m->plan[0]));
-    const bool direct = g->ld == m->L[0].ld;
     double* zx = static_cast<double*>(m->ks[0][VS_Z].x);
     double* zy = static_cast<double*>(m->ks[0][VS_Z].y);
     double* rx0 = static_cast<double*>(m->ks[0][VS_R].x);
@@ -242,24 +239,17 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
     int k = 0;  // index of the current iterate x_k = (vx, vy, p)
     while (out[3] > o.tol && k < o.max_cycles) {
         const int sk = k % W;
-        // F(x_k) into slot sk: one Uzawa cycle from x_k.  When the caller's
-        // stride is the hierarchy's level-0 stride, the V-cycle runs in the
-        // hierarchy's own level-0 vectors (iterate loaded from x_k, right-hand
-        // side folded in place); otherwise x_k is copied into the slot and the
-        // V-cycle entry point stages it.
+        // F(x_k) into slot sk: one Uzawa cycle from x_k.  The hierarchy's
+        // level 0 has the caller's row stride: the V-cycle runs in its own
+        // level-0 vectors (iterate loaded from x_k, right-hand side folded in
+        // place).
         const size_t rowb = (size_t)g->ld * sizeof(double);
         STK_HIP(hipMemcpy2DAsync(F(sk, 2), rowb, p, rowb, (size_t)g->nx * sizeof(double), g->ny,
                                  hipMemcpyDeviceToDevice, ctx->stream));
-        if (direct) {
-            STK_TRY(copy_vel_in(m, vx, vy, g->ld, zx, zy, g->ld, sizeof(double)));
-            STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, rx0, ry0));
-            for (int c = 0; c < o.vcycles; ++c) STK_TRY(run_vcycle(ctx, *m->plan[0], m->o, 0));
-            STK_TRY(copy_vel_in(m, zx, zy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
-        } else {
-            STK_TRY(copy_vel_in(m, vx, vy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
-            STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, bx, by));
-            for (int c = 0; c < o.vcycles; ++c) STK_TRY(stk_mg_vcycle(m, STK_F64, F(sk, 0), F(sk, 1), bx, by));
-        }
+        STK_TRY(copy_vel_in(m, vx, vy, g->ld, zx, zy, g->ld, sizeof(double)));
+        STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, rx0, ry0));
+        for (int c = 0; c < o.vcycles; ++c) STK_TRY(run_vcycle(ctx, *m->plan[0], m->o, 0));
+        STK_TRY(copy_vel_in(m, zx, zy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
         STK_TRY(stk_uzawa_pressure(ctx, g, F(sk, 0), F(sk, 1), eta_c, o.omega_p, F(sk, 2)));
         // products of r_k with the window r_{k-mk} .. r_k (oldest first) into
         // the Gram matrix over ring slots

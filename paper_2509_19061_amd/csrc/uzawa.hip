@@ -173,6 +173,36 @@ __global__ __launch_bounds__(256) void k_rescale(int nx, int ny, int64_t ld, dou
     on[q] = (i <= nx) ? __dadd_rn(a, __dmul_rn(theta, en[q])) : 0.0;
 }
 
+// Mixed precision: r32 = (float) r64 and z32 = 0 on the velocity extents
+// (vx: ny x (nx+1), vy: (ny+1) x nx), in the hierarchy's level-0 layout.
+__global__ __launch_bounds__(256) void k_cast_r(int nx, int ny, int64_t ld, const double* __restrict__ rx,
+                                                const double* __restrict__ ry, float* __restrict__ r32x,
+                                                float* __restrict__ r32y, float* __restrict__ z32x,
+                                                float* __restrict__ z32y) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (int64_t)(ny + 1) * ld) return;
+    const int j = (int)(q / ld), i = (int)(q - (int64_t)j * ld);
+    if (j < ny && i <= nx) {
+        r32x[q] = (float)rx[q];
+        z32x[q] = 0.0f;
+    }
+    if (i < nx) {
+        r32y[q] = (float)ry[q];
+        z32y[q] = 0.0f;
+    }
+}
+
+// v += (double) z32 on the velocity extents
+__global__ __launch_bounds__(256) void k_add_z(int nx, int ny, int64_t ld, const float* __restrict__ z32x,
+                                               const float* __restrict__ z32y, double* __restrict__ vx,
+                                               double* __restrict__ vy) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (int64_t)(ny + 1) * ld) return;
+    const int j = (int)(q / ld), i = (int)(q - (int64_t)j * ld);
+    if (j < ny && i <= nx) vx[q] += (double)z32x[q];
+    if (i < nx) vy[q] += (double)z32y[q];
+}
+
 dim3 cell_grid_u(const stk_grid* g) {
     return dim3((unsigned)((g->nx + UX - 1) / UX), (unsigned)((g->ny + UY * UROWS - 1) / (UY * UROWS)));
 }
@@ -221,57 +251,70 @@ struct DevBuf {
     }
 };
 
-// Uzawa cycles with hierarchy `mm` and pressure-step viscosity `ec_step`,
-// from the caller's (vx, vy, p); E (true system: eta_c, eta_n) after every
-// cycle lands in out / hist[k].  The last stage runs while E > tol, earlier
-// ones `stage_cycles` cycles; k counts all cycles against max_cycles.
-// When the caller's stride is the hierarchy's level-0 stride the cycles run
-// in the hierarchy's own level-0 vectors (the V-cycle's iterate and
+// Uzawa cycles with hierarchy `mm` and the stage's viscosities (ec_step,
+// en_step), from the caller's (vx, vy, p); E (true system: eta_c, eta_n)
+// after every cycle lands in out / hist[k].  The last stage runs while
+// E > tol, earlier ones `stage_cycles` cycles; k counts all cycles against
+// max_cycles.  The hierarchy's level 0 has the caller's row stride, so the
+// FP64 cycles run in its own level-0 vectors (the V-cycle's iterate and
 // right-hand side): the velocity is copied in and out once per stage instead
 // of staging v and b through stk_mg_vcycle every cycle.
 int uzawa_stage(stk_mg* mm, const stk_grid* g, double* vx, double* vy, double* p, const double* ec_step,
-                const double* eta_c, const double* eta_n, const double* fx, const double* fy,
+                const double* en_step, const double* eta_c, const double* eta_n, const double* fx, const double* fy,
                 const stk_uzawa_opts& o, bool last, int& k, double* out, double* hist) {
     stk_ctx* ctx = mm->ctx;
     stk_mg* self = mm;
     if (!mm->plan[0]) STK_TRY(make_plan(ctx, &self, 1, 0, &mm->plan[0]));
-    const bool direct = g->ld == mm->L[0].ld;
-    double* wx = vx;
-    double* wy = vy;
-    void* bx = nullptr;
-    void* by = nullptr;
-    DevBuf fbx, fby;
-    if (direct) {
-        wx = static_cast<double*>(mm->ks[0][VS_Z].x);
-        wy = static_cast<double*>(mm->ks[0][VS_Z].y);
-        bx = mm->ks[0][VS_R].x;
-        by = mm->ks[0][VS_R].y;
-        STK_TRY(copy_vel_in(mm, vx, vy, g->ld, wx, wy, g->ld, sizeof(double)));
-    } else {
-        STK_TRY(fbx.alloc(field_bytes(g, g->ny, STK_F64)));
-        STK_TRY(fby.alloc(field_bytes(g, g->ny + 1, STK_F64)));
-        bx = fbx.p;
-        by = fby.p;
+    if (o.mode == STK_SOLVE_F32_REFINED) {
+        // v += V32(0, (float)(f - G p - M v)) per V-cycle; the V-cycle is
+        // consistent, so in exact arithmetic this is the FP64 cycle
+        if (!mm->plan[1]) STK_TRY(make_plan(ctx, &self, 1, 1, &mm->plan[1]));
+        DevBuf r64x, r64y;
+        STK_TRY(r64x.alloc(field_bytes(g, g->ny, STK_F64)));
+        STK_TRY(r64y.alloc(field_bytes(g, g->ny + 1, STK_F64)));
+        float* r32x = static_cast<float*>(mm->ks[1][VS_R].x);
+        float* r32y = static_cast<float*>(mm->ks[1][VS_R].y);
+        float* z32x = static_cast<float*>(mm->ks[1][VS_Z].x);
+        float* z32y = static_cast<float*>(mm->ks[1][VS_Z].y);
+        const int64_t cnt = (int64_t)(g->ny + 1) * g->ld;
+        const dim3 eg((unsigned)((cnt + 255) / 256)), eb(256);
+        int n = 0;
+        while (k < o.max_cycles && (last ? out[3] > o.tol : n < o.stage_cycles)) {
+            for (int c = 0; c < o.vcycles; ++c) {
+                STK_TRY(stk_residual(ctx, STK_F64, g, vx, vy, p, ec_step, en_step, fx, fy, r64x.p, r64y.p, nullptr));
+                hipLaunchKernelGGL(k_cast_r, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, (const double*)r64x.p,
+                                   (const double*)r64y.p, r32x, r32y, z32x, z32y);
+                STK_HIP(hipGetLastError());
+                STK_TRY(run_vcycle(ctx, *mm->plan[1], mm->o, 1));
+                hipLaunchKernelGGL(k_add_z, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, (const float*)z32x,
+                                   (const float*)z32y, vx, vy);
+                STK_HIP(hipGetLastError());
+            }
+            STK_TRY(pressure_update(ctx, g, vx, vy, ec_step, o.omega_p, p));
+            ++k;
+            ++n;
+            STK_TRY(stk_energy_norm(ctx, STK_F64, g, vx, vy, p, eta_c, eta_n, fx, fy, out));
+            if (hist) hist[k] = out[3];
+        }
+        return STK_OK;
     }
+    double* wx = static_cast<double*>(mm->ks[0][VS_Z].x);
+    double* wy = static_cast<double*>(mm->ks[0][VS_Z].y);
+    double* bx = static_cast<double*>(mm->ks[0][VS_R].x);
+    double* by = static_cast<double*>(mm->ks[0][VS_R].y);
+    STK_TRY(copy_vel_in(mm, vx, vy, g->ld, wx, wy, g->ld, sizeof(double)));
     int n = 0;
     while (k < o.max_cycles && (last ? out[3] > o.tol : n < o.stage_cycles)) {
         STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, bx, by));  // b = f - G p
-        for (int c = 0; c < o.vcycles; ++c) {
-            if (direct)
-                STK_TRY(run_vcycle(ctx, *mm->plan[0], mm->o, 0));
-            else
-                STK_TRY(stk_mg_vcycle(mm, STK_F64, wx, wy, bx, by));
-        }
+        for (int c = 0; c < o.vcycles; ++c) STK_TRY(run_vcycle(ctx, *mm->plan[0], mm->o, 0));
         STK_TRY(pressure_update(ctx, g, wx, wy, ec_step, o.omega_p, p));
         ++k;
         ++n;
         STK_TRY(stk_energy_norm(ctx, STK_F64, g, wx, wy, p, eta_c, eta_n, fx, fy, out));
         if (hist) hist[k] = out[3];
     }
-    if (direct) {
-        STK_TRY(copy_vel_in(mm, wx, wy, g->ld, vx, vy, g->ld, sizeof(double)));
-        STK_HIP(hipStreamSynchronize(ctx->stream));
-    }
+    STK_TRY(copy_vel_in(mm, wx, wy, g->ld, vx, vy, g->ld, sizeof(double)));
+    STK_HIP(hipStreamSynchronize(ctx->stream));
     return STK_OK;
 }
 
@@ -290,6 +333,7 @@ void stk_uzawa_opts_default(stk_uzawa_opts* o) {
     o->max_cycles = 1000;
     o->stages = 0;
     o->stage_cycles = 25;
+    o->mode = STK_SOLVE_F64;
 }
 
 int stk_litho_pressure(stk_ctx* ctx, const stk_grid* g, const double* fy, double* p) {
@@ -337,6 +381,7 @@ int stk_uzawa_solve(stk_mg* m, const stk_grid* g, double* vx, double* vy, double
     if (!(o.tol >= 0.0)) return set_error(STK_EINVAL, "tol must be >= 0");
     if (o.stages < 0 || o.stage_cycles < 0)
         return set_error(STK_EINVAL, "stages and stage_cycles must be >= 0 (got %d, %d)", o.stages, o.stage_cycles);
+    if (o.mode != STK_SOLVE_F64 && o.mode != STK_SOLVE_F32_REFINED) return set_error(STK_EINVAL, "unknown mode %d", o.mode);
     stk_ctx* ctx = m->ctx;
     STK_TRY(use_device(ctx));
     double out[5];
@@ -345,7 +390,7 @@ int stk_uzawa_solve(stk_mg* m, const stk_grid* g, double* vx, double* vy, double
     if (hist) hist[0] = out[3];
     int k = 0;
     if (o.stages == 0) {
-        STK_TRY(uzawa_stage(m, g, vx, vy, p, eta_c, eta_c, eta_n, fx, fy, o, true, k, out, hist));
+        STK_TRY(uzawa_stage(m, g, vx, vy, p, eta_c, eta_n, eta_c, eta_n, fx, fy, o, true, k, out, hist));
     } else {
         // continuation stages on the rescaled viscosities, each with its own hierarchy
         const size_t fb = field_bytes(g, g->ny + 1, STK_F64);
@@ -365,7 +410,7 @@ int stk_uzawa_solve(stk_mg* m, const stk_grid* g, double* vx, double* vy, double
         const int64_t cnt = (int64_t)(g->ny + 1) * g->ld;
         for (int st = 0; st <= o.stages; ++st) {
             if (st == o.stages) {  // theta = 1: the true system and the caller's hierarchy
-                STK_TRY(uzawa_stage(m, g, vx, vy, p, eta_c, eta_c, eta_n, fx, fy, o, true, k, out, hist));
+                STK_TRY(uzawa_stage(m, g, vx, vy, p, eta_c, eta_n, eta_c, eta_n, fx, fy, o, true, k, out, hist));
                 break;
             }
             const double theta = (double)st / (double)o.stages;
@@ -375,7 +420,8 @@ int stk_uzawa_solve(stk_mg* m, const stk_grid* g, double* vx, double* vy, double
             STK_HIP(hipGetLastError());
             stk_mg* ms = nullptr;
             STK_TRY(stk_mg_create(ctx, &ms, g, (const double*)ecs.p, (const double*)ens.p, &m->o));
-            rc = uzawa_stage(ms, g, vx, vy, p, (const double*)ecs.p, eta_c, eta_n, fx, fy, o, false, k, out, hist);
+            rc = uzawa_stage(ms, g, vx, vy, p, (const double*)ecs.p, (const double*)ens.p, eta_c, eta_n, fx, fy, o,
+                             false, k, out, hist);
             (void)stk_mg_destroy(ms);
             if (rc != STK_OK) return rc;
         }

@@ -86,3 +86,10 @@ def test_host_side_argument_errors(L):
     assert not o.shifts
     assert L.lib.stk_ctx_destroy(None) == L.OK
     assert L.lib.stk_ctx_sync(None) == L.EINVAL
+
+
+def test_uzawa_option_defaults(L):
+    o = L.UzawaOpts()
+    L.lib.stk_uzawa_opts_default(C.byref(o))
+    assert (o.omega_p, o.vcycles, o.tol, o.max_cycles, o.stages, o.stage_cycles, o.mode) == \
+        (0.6, 1, 1e-8, 1000, 0, 25, L.SOLVE_F64)

@@ -79,8 +79,7 @@ def test_pressure_update_matches_oracle(ctx, nx, ny, omega_p):
     assert torch.equal(pt, pt2)
 
 
-# align 128 at nx = 128 gives a row stride (256) other than the hierarchy's (192):
-# the cycles then stage v and b through the V-cycle entry point
+# align 128 at nx = 128: a padded row stride (256 instead of 192)
 @pytest.mark.parametrize("nx,ny,contrast,vcycles,align", [(64, 64, 1e2, 1, 64), (96, 64, 1e3, 2, 64),
                                                          (128, 128, 1e4, 1, 64), (128, 128, 1e4, 1, 128)])
 def test_uzawa_cycles_match_oracle(ctx, nx, ny, contrast, vcycles, align):
@@ -106,9 +105,8 @@ def test_uzawa_cycles_match_oracle(ctx, nx, ny, contrast, vcycles, align):
 
 
 def test_uzawa_strides_agree_bitwise(ctx):
-    """Cycles in the hierarchy's own level-0 vectors (caller stride = level-0
-    stride) and cycles staged through the V-cycle entry point (another
-    stride) do the same arithmetic."""
+    """The result does not depend on the row stride (padding): 192 and 256
+    give the same bits."""
     from paper_2509_19061_amd import api
     p = sinkers(128, 96, 17, 1e3)
     res = []
@@ -197,8 +195,7 @@ def test_uzawa_argument_errors(ctx):
 @pytest.mark.parametrize("nx,contrast,align", [(64, 1e4, 64), (128, 1e3, 128)])
 def test_continuation_matches_oracle(ctx, nx, contrast, align):
     """Four continuation stages of three cycles each, then four cycles of the
-    true system; the second case's stride (256 at nx = 128) stages v and b
-    through the V-cycle entry point."""
+    true system; the second case has a padded stride (256 at nx = 128)."""
     from paper_2509_19061_amd import api
     p = sinkers(nx, nx, nx + 5, contrast)
     d = dev(p, align)
@@ -274,7 +271,7 @@ def test_anderson_depth_zero_equals_plain_cycles_bitwise(ctx):
         assert np.array_equal(a, b)
 
 
-# align 128 at nx = 128: a stride other than the hierarchy's (the staged V-cycle path)
+# align 128 at nx = 128: a padded row stride (256 instead of 192)
 @pytest.mark.parametrize("nx,ny,contrast,depth,align", [(64, 64, 1e3, 3, 64), (96, 80, 1e2, 5, 64),
                                                        (128, 128, 1e3, 3, 128)])
 def test_anderson_matches_oracle(ctx, nx, ny, contrast, depth, align):
@@ -369,3 +366,71 @@ def test_pressure_step_and_litho_full_size():
     torch.cuda.synchronize()
     assert float(ry[1:4096, :4096].abs().max()) <= 1e-10 * float(d.fy.abs().max())
     c.close()
+
+
+@pytest.mark.parametrize("stages", [0, 2])
+def test_uzawa_mixed_cycles_match_oracle(ctx, stages):
+    """FP32 V-cycles on the FP64 residual: the oracle's FP64 cycles to FP32
+    precision (the V-cycle is consistent: V(v, b) = v + V(0, b - M v))."""
+    from paper_2509_19061_amd import api
+    p = sinkers(64, 64, 41, 1e3)
+    d = dev(p)
+    m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
+    p0 = U.litho(p, p.fy)
+    vx, vy = d.velocity()
+    pt = d.field(p0)
+    rep, hist = api.uzawa_solve(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, allow_notconv=True, tol=0.0,
+                                max_cycles=6, stages=stages, stage_cycles=2, mode="f32_refined")
+    if stages:
+        ox, oy, op, oh = U.uzawa_continuation(p, p.fx, p.fy, *p.zeros_v(), p0, stages=stages, stage_cycles=2,
+                                              tol=0.0, max_cycles=6)
+    else:
+        ox, oy, op, oh = U.uzawa(OM.hierarchy(p), p, p.fx, p.fy, *p.zeros_v(), p0, tol=0.0, max_cycles=6)
+    assert normwise(d.get_vx(vx), ox) <= 1e-5 and normwise(d.get_vy(vy), oy) <= 1e-5
+    assert normwise(d.get_cell(pt), op) <= 1e-5
+    np.testing.assert_allclose(hist, oh, rtol=1e-4)
+    m.close()
+
+
+def test_uzawa_mixed_reaches_the_fp64_solution(ctx):
+    from paper_2509_19061_amd import api
+    p = sinkers(128, 128, 9, 1e2)
+    d = dev(p)
+    m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
+    out = {}
+    for mode in ("f64", "f32_refined"):
+        vx, vy = d.velocity()
+        pt = d.field()
+        api.litho_pressure(ctx, d.grid, d.fy, pt)
+        rep, hist = api.uzawa_solve(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, tol=1e-8, max_cycles=2000,
+                                    mode=mode)
+        assert rep["converged"]
+        out[mode] = (rep, d.get_vx(vx), d.get_vy(vy), d.get_cell(pt))
+    assert out["f32_refined"][0]["cycles"] <= 1.2 * out["f64"][0]["cycles"]
+    for a, b in zip(out["f32_refined"][1:], out["f64"][1:]):
+        assert normwise(a, b) <= 1e-6
+    m.close()
+
+
+def test_uzawa_mixed_strides_and_unsupported_forms(ctx):
+    """The FP32 V-cycle mode gives the same bits at strides 192 and 256;
+    Anderson acceleration rejects it."""
+    from paper_2509_19061_amd import api
+    p = sinkers(128, 128, 2, 1e2)
+    res = []
+    for align in (64, 128):
+        d = dev(p, align)
+        m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
+        vx, vy = d.velocity()
+        pt = d.field()
+        _, hist = api.uzawa_solve(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, allow_notconv=True, tol=0.0,
+                                  max_cycles=4, mode="f32_refined")
+        res.append((d.get_vx(vx), d.get_vy(vy), d.get_cell(pt), hist))
+        if align == 64:
+            m.close()
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+    with pytest.raises(api.StkError) as e:
+        api.uzawa_anderson(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, mode="f32_refined")
+    assert e.value.code == api.EUNSUPPORTED
+    m.close()
