@@ -209,7 +209,7 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
     if (o.max_cycles < 0) return set_error(STK_EINVAL, "max_cycles must be >= 0 (got %d)", o.max_cycles);
     if (!(o.tol >= 0.0)) return set_error(STK_EINVAL, "tol must be >= 0");
     if (o.stages != 0) return set_error(STK_EUNSUPPORTED, "Anderson acceleration runs without continuation stages");
-    if (o.mode != STK_SOLVE_F64) return set_error(STK_EUNSUPPORTED, "Anderson acceleration runs FP64 V-cycles");
+    if (o.mode != STK_SOLVE_F64 && o.mode != STK_SOLVE_F32_REFINED) return set_error(STK_EINVAL, "unknown mode %d", o.mode);
     stk_ctx* ctx = m->ctx;
     STK_TRY(use_device(ctx));
     const int W = depth + 1;                          // ring of W slots
@@ -246,10 +246,21 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
         const size_t rowb = (size_t)g->ld * sizeof(double);
         STK_HIP(hipMemcpy2DAsync(F(sk, 2), rowb, p, rowb, (size_t)g->nx * sizeof(double), g->ny,
                                  hipMemcpyDeviceToDevice, ctx->stream));
-        STK_TRY(copy_vel_in(m, vx, vy, g->ld, zx, zy, g->ld, sizeof(double)));
-        STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, rx0, ry0));
-        for (int c = 0; c < o.vcycles; ++c) STK_TRY(run_vcycle(ctx, *m->plan[0], m->o, 0));
-        STK_TRY(copy_vel_in(m, zx, zy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
+        if (o.mode == STK_SOLVE_F32_REFINED) {
+            // FP32 V-cycles on the FP64 residual (the slot's residual planes
+            // serve as scratch until the product pass rewrites them)
+            STK_TRY(copy_vel_in(m, vx, vy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
+            for (int c = 0; c < o.vcycles; ++c) {
+                STK_TRY(stk_residual(ctx, STK_F64, g, F(sk, 0), F(sk, 1), p, eta_c, eta_n, fx, fy, R(sk, 0),
+                                     R(sk, 1), nullptr));
+                STK_TRY(mixed_correction(m, g, R(sk, 0), R(sk, 1), F(sk, 0), F(sk, 1)));
+            }
+        } else {
+            STK_TRY(copy_vel_in(m, vx, vy, g->ld, zx, zy, g->ld, sizeof(double)));
+            STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, rx0, ry0));
+            for (int c = 0; c < o.vcycles; ++c) STK_TRY(run_vcycle(ctx, *m->plan[0], m->o, 0));
+            STK_TRY(copy_vel_in(m, zx, zy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
+        }
         STK_TRY(stk_uzawa_pressure(ctx, g, F(sk, 0), F(sk, 1), eta_c, o.omega_p, F(sk, 2)));
         // products of r_k with the window r_{k-mk} .. r_k (oldest first) into
         // the Gram matrix over ring slots

@@ -79,6 +79,9 @@ int write_states(stk_ctx* ctx, const PlanT& P, const std::vector<FcgState>& h);
 // 2D copy of the used extents of a velocity pair between two row strides
 int copy_vel_in(stk_mg* m, const void* sx, const void* sy, int64_t sld, void* dx, void* dy, int64_t dld, size_t es);
 int ensure_dtype(stk_mg* m, int t);
+// FP32 V-cycle correction of an FP64 velocity (uzawa.hip): v += V32(0, (float) r)
+// for the FP64 residual r = b - M v of the finest level, in the caller's layout.
+int mixed_correction(stk_mg* m, const stk_grid* g, const double* rx, const double* ry, double* vx, double* vy);
 
 }  // namespace stk
 

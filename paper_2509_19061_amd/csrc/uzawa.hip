@@ -268,27 +268,14 @@ int uzawa_stage(stk_mg* mm, const stk_grid* g, double* vx, double* vy, double* p
     if (o.mode == STK_SOLVE_F32_REFINED) {
         // v += V32(0, (float)(f - G p - M v)) per V-cycle; the V-cycle is
         // consistent, so in exact arithmetic this is the FP64 cycle
-        if (!mm->plan[1]) STK_TRY(make_plan(ctx, &self, 1, 1, &mm->plan[1]));
         DevBuf r64x, r64y;
         STK_TRY(r64x.alloc(field_bytes(g, g->ny, STK_F64)));
         STK_TRY(r64y.alloc(field_bytes(g, g->ny + 1, STK_F64)));
-        float* r32x = static_cast<float*>(mm->ks[1][VS_R].x);
-        float* r32y = static_cast<float*>(mm->ks[1][VS_R].y);
-        float* z32x = static_cast<float*>(mm->ks[1][VS_Z].x);
-        float* z32y = static_cast<float*>(mm->ks[1][VS_Z].y);
-        const int64_t cnt = (int64_t)(g->ny + 1) * g->ld;
-        const dim3 eg((unsigned)((cnt + 255) / 256)), eb(256);
         int n = 0;
         while (k < o.max_cycles && (last ? out[3] > o.tol : n < o.stage_cycles)) {
             for (int c = 0; c < o.vcycles; ++c) {
                 STK_TRY(stk_residual(ctx, STK_F64, g, vx, vy, p, ec_step, en_step, fx, fy, r64x.p, r64y.p, nullptr));
-                hipLaunchKernelGGL(k_cast_r, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, (const double*)r64x.p,
-                                   (const double*)r64y.p, r32x, r32y, z32x, z32y);
-                STK_HIP(hipGetLastError());
-                STK_TRY(run_vcycle(ctx, *mm->plan[1], mm->o, 1));
-                hipLaunchKernelGGL(k_add_z, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, (const float*)z32x,
-                                   (const float*)z32y, vx, vy);
-                STK_HIP(hipGetLastError());
+                STK_TRY(mixed_correction(mm, g, (const double*)r64x.p, (const double*)r64y.p, vx, vy));
             }
             STK_TRY(pressure_update(ctx, g, vx, vy, ec_step, o.omega_p, p));
             ++k;
@@ -319,6 +306,26 @@ int uzawa_stage(stk_mg* mm, const stk_grid* g, double* vx, double* vy, double* p
 }
 
 }  // namespace
+
+int mixed_correction(stk_mg* m, const stk_grid* g, const double* rx, const double* ry, double* vx, double* vy) {
+    stk_ctx* ctx = m->ctx;
+    stk_mg* self = m;
+    if (!m->plan[1]) STK_TRY(make_plan(ctx, &self, 1, 1, &m->plan[1]));
+    float* r32x = static_cast<float*>(m->ks[1][VS_R].x);
+    float* r32y = static_cast<float*>(m->ks[1][VS_R].y);
+    float* z32x = static_cast<float*>(m->ks[1][VS_Z].x);
+    float* z32y = static_cast<float*>(m->ks[1][VS_Z].y);
+    const int64_t cnt = (int64_t)(g->ny + 1) * g->ld;
+    const dim3 eg((unsigned)((cnt + 255) / 256)), eb(256);
+    hipLaunchKernelGGL(k_cast_r, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, rx, ry, r32x, r32y, z32x, z32y);
+    STK_HIP(hipGetLastError());
+    STK_TRY(run_vcycle(ctx, *m->plan[1], m->o, 1));
+    hipLaunchKernelGGL(k_add_z, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, (const float*)z32x, (const float*)z32y,
+                       vx, vy);
+    STK_HIP(hipGetLastError());
+    return STK_OK;
+}
+
 }  // namespace stk
 
 using namespace stk;
