@@ -220,3 +220,21 @@ def test_anderson_converges_to_the_saddle_point_faster():
     assert a[3][-1] <= 1e-9 and b[3][-1] <= 1e-9
     assert len(a[3]) < len(b[3])
     assert np.abs(a[2] - b[2]).max() <= 1e-6 * np.abs(b[2]).max()
+
+
+def test_vcycle_is_consistent_correction_form():
+    """V(v, b) = v + V(0, b - M v): the V-cycle is a consistent linear
+    iteration, so an update computed as a correction from zero on the
+    residual (the library's FP32 V-cycle mode) is the same cycle up to the
+    rounding of the correction."""
+    g = sinkers(64, 1e3)
+    lv = mg.hierarchy(g)
+    rng = np.random.default_rng(12)
+    vx, vy = I.random_velocity(g, 13, 1e-2)
+    p0 = rng.standard_normal((64, 64))
+    bx, by = S.rhs(g, g.fx, g.fy, p0)
+    ax, ay = mg.vcycle(lv, 0, vx, vy, bx, by)
+    mx, my = S.apply(g, vx, vy)
+    cx, cy = mg.vcycle(lv, 0, np.zeros_like(vx), np.zeros_like(vy), bx - mx, by - my)
+    assert np.abs(ax - (vx + cx)).max() <= 1e-11 * np.abs(ax).max()
+    assert np.abs(ay - (vy + cy)).max() <= 1e-11 * np.abs(ay).max()
