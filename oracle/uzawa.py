@@ -134,24 +134,16 @@ def anderson_weights(R):
     return a if np.all(np.isfinite(a)) else np.eye(n)[-1]
 
 
-def anderson(levels, g, fx, fy, vx, vy, p, m=3, omega_p=0.6, vcycles=1, tol=1e-8, max_iters=200, nu1=2, nu2=2,
-             omega=0.7):
-    """Anderson acceleration of the inexact Uzawa fixed-point map F on
-    x = [v, p] (Sec. 3.3, Alg. 1): x_1 = F(x_0); then with m_k = min(m, k),
-    r_i = F(x_i) - x_i, the new iterate is the combination of the last m_k + 1
-    values F(x_i) whose weights (summing to 1) minimise the l2 norm of the
-    same combination of the r_i.  The norm runs over every velocity unknown
-    and pressure cell as one vector.  Stops when E of the new iterate <= tol.
-    Returns (vx, vy, p, history of E), one entry per F evaluation after the
-    start's."""
-    def flat(x):
-        return np.concatenate([np.ravel(x[0]), np.ravel(x[1]), np.ravel(x[2])])
+def _anderson_steps(levels, gs, g, fx, fy, x, hist, m, omega_p, vcycles, nu1, nu2, omega, more):
+    """Anderson steps on the system gs (hierarchy `levels`) from x, while
+    more(n) holds (n = steps taken here); E of the true system g is appended
+    to hist after every step."""
+    def flat(y):
+        return np.concatenate([np.ravel(y[0]), np.ravel(y[1]), np.ravel(y[2])])
 
-    x = (np.array(vx, float), np.array(vy, float), np.array(p, float))
-    hist = [S.energy(g, *x[:2], fx, fy, x[2])[3]]
-    Fs, rs = [], []
-    while hist[-1] > tol and len(hist) <= max_iters:
-        fxk = _cycle(levels, g, fx, fy, *x, omega_p, vcycles, nu1, nu2, omega)
+    Fs, rs, n = [], [], 0
+    while more(n):
+        fxk = _cycle(levels, gs, fx, fy, *x, omega_p, vcycles, nu1, nu2, omega)
         Fs.append(fxk)
         rs.append(flat(fxk) - flat(x))
         k = len(Fs) - 1                      # the index of x_k
@@ -163,4 +155,40 @@ def anderson(levels, g, fx, fy, vx, vy, p, m=3, omega_p=0.6, vcycles=1, tol=1e-8
             a = anderson_weights(np.stack(rs, axis=1))
             x = tuple(sum(a[i] * Fs[i][c] for i in range(mk + 1)) for c in range(3))
         hist.append(S.energy(g, *x[:2], fx, fy, x[2])[3])
+        n += 1
+    return x
+
+
+def anderson(levels, g, fx, fy, vx, vy, p, m=3, omega_p=0.6, vcycles=1, tol=1e-8, max_iters=200, nu1=2, nu2=2,
+             omega=0.7):
+    """Anderson acceleration of the inexact Uzawa fixed-point map F on
+    x = [v, p] (Sec. 3.3, Alg. 1): x_1 = F(x_0); then with m_k = min(m, k),
+    r_i = F(x_i) - x_i, the new iterate is the combination of the last m_k + 1
+    values F(x_i) whose weights (summing to 1) minimise the l2 norm of the
+    same combination of the r_i.  The norm runs over every velocity unknown
+    and pressure cell as one vector.  Stops when E of the new iterate <= tol.
+    Returns (vx, vy, p, history of E), one entry per F evaluation after the
+    start's."""
+    x = (np.array(vx, float), np.array(vy, float), np.array(p, float))
+    hist = [S.energy(g, *x[:2], fx, fy, x[2])[3]]
+    x = _anderson_steps(levels, g, g, fx, fy, x, hist, m, omega_p, vcycles, nu1, nu2, omega,
+                        lambda n: hist[-1] > tol and len(hist) <= max_iters)
+    return x[0], x[1], x[2], hist
+
+
+def anderson_continuation(g, fx, fy, vx, vy, p, m=3, stages=4, stage_cycles=25, omega_p=0.6, vcycles=1, tol=1e-8,
+                          max_iters=1000, coarsest=8, nu1=2, nu2=2, omega=0.7):
+    """Anderson steps under the viscosity continuation of Sec. 6.2: each
+    stage theta = s/stages < 1 runs stage_cycles steps on the rescaled system
+    (its own hierarchy; the Anderson history restarts with the stage, whose
+    map differs), then the true system runs until E <= tol.  max_iters bounds
+    all steps together; history[k] is E of the TRUE system."""
+    x = (np.array(vx, float), np.array(vy, float), np.array(p, float))
+    hist = [S.energy(g, *x[:2], fx, fy, x[2])[3]]
+    for s in range(stages + 1):
+        theta = s / stages if stages > 0 else 1.0
+        gs = rescaled(g, theta)
+        last = s == stages
+        x = _anderson_steps(mg.hierarchy(gs, coarsest), gs, g, fx, fy, x, hist, m, omega_p, vcycles, nu1, nu2, omega,
+                            lambda n: len(hist) <= max_iters and (hist[-1] > tol if last else n < stage_cycles))
     return x[0], x[1], x[2], hist

@@ -238,3 +238,24 @@ def test_vcycle_is_consistent_correction_form():
     cx, cy = mg.vcycle(lv, 0, np.zeros_like(vx), np.zeros_like(vy), bx - mx, by - my)
     assert np.abs(ax - (vx + cx)).max() <= 1e-11 * np.abs(ax).max()
     assert np.abs(ay - (vy + cy)).max() <= 1e-11 * np.abs(ay).max()
+
+
+def test_anderson_continuation_first_stage_is_exact_at_third_step():
+    """theta = 0 with exact velocity solves: the stage system is the constant
+    viscosity min(eta_c), where Anderson's third iterate is that system's
+    saddle-point solution."""
+    g = sinkers(16, 1e3)
+    em = float(g.eta_c.min())
+    const = _with_eta(g, np.full_like(g.eta_c, em), np.full_like(g.eta_n, em))
+    vref_x, vref_y, pref = kkt(const, g.fx, g.fy)
+    rng = np.random.default_rng(6)
+    vx, vy, p, hist = U.anderson_continuation(g, g.fx, g.fy, *g.zeros_v(), rng.standard_normal((16, 16)), m=2,
+                                              stages=2, stage_cycles=3, tol=0.0, max_iters=3, coarsest=64)
+    assert len(hist) == 4
+    assert np.abs(p - pref).max() <= 1e-10 * np.abs(pref).max()
+    assert np.abs(vy - vref_y).max() <= 1e-10 * np.abs(vref_y).max()
+    # no stages: the plain Anderson steps
+    lv = mg.hierarchy(g)
+    a = U.anderson_continuation(g, g.fx, g.fy, *g.zeros_v(), U.litho(g, g.fy), m=3, stages=0, tol=0.0, max_iters=5)
+    b = U.anderson(lv, g, g.fx, g.fy, *g.zeros_v(), U.litho(g, g.fy), m=3, tol=0.0, max_iters=5)
+    assert np.array_equal(a[2], b[2]) and a[3] == b[3]
