@@ -380,8 +380,10 @@ int stk_uzawa_solve(stk_mg* mg, const stk_grid* g, double* vx, double* vy, doubl
  * problem on the host (a singular system takes the plain step alpha =
  * (0, .., 0, 1)); depth 0 is the plain iteration.  Stops when E of x_{k+1}
  * (Sec. 6.4) <= opts->tol or after opts->max_cycles evaluations of F.
- * depth in [0, 8].  opts->stages must be 0 (STK_EUNSUPPORTED otherwise);
- * opts->mode selects FP64 or FP32 V-cycles as in stk_uzawa_solve.
+ * depth in [0, 8].  opts->mode selects FP64 or FP32 V-cycles and
+ * opts->stages the viscosity continuation, as in stk_uzawa_solve: each stage
+ * runs its own Anderson steps (the history restarts with the stage, whose
+ * map F differs), and max_cycles bounds the steps of all stages together.
  * hist (nullable, HOST, max_cycles + 1 doubles): E of x_0, x_1, ..;
  * rep->cycles counts F evaluations.  Allocates 6 (depth + 1) planes of
  * (ny + 1) * ld doubles for the call's duration.  Synchronises once per

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <deque>
+#include <functional>
 #include <vector>
 
 #include "mg_internal.hpp"
@@ -82,6 +83,14 @@ int ensure_dtype(stk_mg* m, int t);
 // FP32 V-cycle correction of an FP64 velocity (uzawa.hip): v += V32(0, (float) r)
 // for the FP64 residual r = b - M v of the finest level, in the caller's layout.
 int mixed_correction(stk_mg* m, const stk_grid* g, const double* rx, const double* ry, double* vx, double* vy);
+// Viscosity continuation (uzawa.hip, Sec. 6.2): for theta = s / o.stages,
+// s < o.stages, calls stage(hierarchy of (1 - theta) eta_min + theta eta, its
+// cell and nodal viscosities, false), then stage(m, eta_c, eta_n, true) for
+// the true system; o.stages = 0 is the last call only.  A stage's hierarchy
+// is skipped when no cycle is left to run on it (k >= o.max_cycles or
+// o.stage_cycles = 0).
+int continuation(stk_mg* m, const stk_grid* g, const double* eta_c, const double* eta_n, const stk_uzawa_opts& o,
+                 const int& k, const std::function<int(stk_mg*, const double*, const double*, bool)>& stage);
 
 }  // namespace stk
 

@@ -22,6 +22,7 @@
 // The reductions never use atomics: results are bitwise reproducible.
 #include <chrono>
 #include <cmath>
+#include <functional>
 
 #include "mg_host.hpp"
 #include "stk_internal.hpp"
@@ -326,6 +327,38 @@ int mixed_correction(stk_mg* m, const stk_grid* g, const double* rx, const doubl
     return STK_OK;
 }
 
+int continuation(stk_mg* m, const stk_grid* g, const double* eta_c, const double* eta_n, const stk_uzawa_opts& o,
+                 const int& k, const std::function<int(stk_mg*, const double*, const double*, bool)>& stage) {
+    if (o.stages == 0) return stage(m, eta_c, eta_n, true);
+    stk_ctx* ctx = m->ctx;
+    const size_t fb = field_bytes(g, g->ny + 1, STK_F64);
+    DevBuf ecs, ens, tmp;
+    STK_TRY(ecs.alloc(fb));
+    STK_TRY(ens.alloc(fb));
+    STK_TRY(tmp.alloc(sizeof(double)));
+    const dim3 grid = cell_grid_u(g);
+    const int64_t nblk = (int64_t)grid.x * grid.y;
+    void* part = nullptr;
+    STK_TRY(scratch(ctx, stk_ctx::S_PART, sizeof(double) * (size_t)nblk, &part));
+    hipLaunchKernelGGL(k_min_partial, grid, dim3(UX, UY), 0, ctx->stream, g->nx, g->ny, g->ld, eta_c, (double*)part);
+    hipLaunchKernelGGL(k_min_final, dim3(1), dim3(1024), 0, ctx->stream, (const double*)part, nblk, (double*)tmp.p);
+    STK_HIP(hipGetLastError());
+    const int64_t cnt = (int64_t)(g->ny + 1) * g->ld;
+    for (int st = 0; st < o.stages; ++st) {
+        if (o.stage_cycles == 0 || k >= o.max_cycles) break;  // nothing would run on this stage's hierarchy
+        const double theta = (double)st / (double)o.stages;
+        hipLaunchKernelGGL(k_rescale, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, ctx->stream, g->nx, g->ny,
+                           g->ld, theta, (const double*)tmp.p, eta_c, eta_n, (double*)ecs.p, (double*)ens.p);
+        STK_HIP(hipGetLastError());
+        stk_mg* ms = nullptr;
+        STK_TRY(stk_mg_create(ctx, &ms, g, (const double*)ecs.p, (const double*)ens.p, &m->o));
+        const int rc = stage(ms, (const double*)ecs.p, (const double*)ens.p, false);
+        (void)stk_mg_destroy(ms);
+        if (rc != STK_OK) return rc;
+    }
+    return stage(m, eta_c, eta_n, true);  // theta = 1: the true system and the caller's hierarchy
+}
+
 }  // namespace stk
 
 using namespace stk;
@@ -396,43 +429,9 @@ int stk_uzawa_solve(stk_mg* m, const stk_grid* g, double* vx, double* vy, double
     if (rc != STK_OK) return rc;
     if (hist) hist[0] = out[3];
     int k = 0;
-    if (o.stages == 0) {
-        STK_TRY(uzawa_stage(m, g, vx, vy, p, eta_c, eta_n, eta_c, eta_n, fx, fy, o, true, k, out, hist));
-    } else {
-        // continuation stages on the rescaled viscosities, each with its own hierarchy
-        const size_t fb = field_bytes(g, g->ny + 1, STK_F64);
-        DevBuf ecs, ens, tmp;
-        STK_TRY(ecs.alloc(fb));
-        STK_TRY(ens.alloc(fb));
-        STK_TRY(tmp.alloc(sizeof(double)));
-        const dim3 grid = cell_grid_u(g);
-        const int64_t nblk = (int64_t)grid.x * grid.y;
-        void* part = nullptr;
-        STK_TRY(scratch(ctx, stk_ctx::S_PART, sizeof(double) * (size_t)nblk, &part));
-        hipLaunchKernelGGL(k_min_partial, grid, dim3(UX, UY), 0, ctx->stream, g->nx, g->ny, g->ld, eta_c,
-                           (double*)part);
-        hipLaunchKernelGGL(k_min_final, dim3(1), dim3(1024), 0, ctx->stream, (const double*)part, nblk,
-                           (double*)tmp.p);
-        STK_HIP(hipGetLastError());
-        const int64_t cnt = (int64_t)(g->ny + 1) * g->ld;
-        for (int st = 0; st <= o.stages; ++st) {
-            if (st == o.stages) {  // theta = 1: the true system and the caller's hierarchy
-                STK_TRY(uzawa_stage(m, g, vx, vy, p, eta_c, eta_n, eta_c, eta_n, fx, fy, o, true, k, out, hist));
-                break;
-            }
-            const double theta = (double)st / (double)o.stages;
-            hipLaunchKernelGGL(k_rescale, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, ctx->stream, g->nx,
-                               g->ny, g->ld, theta, (const double*)tmp.p, eta_c, eta_n, (double*)ecs.p,
-                               (double*)ens.p);
-            STK_HIP(hipGetLastError());
-            stk_mg* ms = nullptr;
-            STK_TRY(stk_mg_create(ctx, &ms, g, (const double*)ecs.p, (const double*)ens.p, &m->o));
-            rc = uzawa_stage(ms, g, vx, vy, p, (const double*)ecs.p, (const double*)ens.p, eta_c, eta_n, fx, fy, o,
-                             false, k, out, hist);
-            (void)stk_mg_destroy(ms);
-            if (rc != STK_OK) return rc;
-        }
-    }
+    STK_TRY(continuation(m, g, eta_c, eta_n, o, k, [&](stk_mg* mm, const double* ec, const double* en, bool last) {
+        return uzawa_stage(mm, g, vx, vy, p, ec, en, eta_c, eta_n, fx, fy, o, last, k, out, hist);
+    }));
     const bool conv = out[3] <= o.tol;
     if (rep) {
         rep->cycles = k;
