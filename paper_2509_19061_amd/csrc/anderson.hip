@@ -200,7 +200,8 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
     if (!vx || !vy || !p || !eta_c || !eta_n || !fx || !fy)
         return set_error(STK_EINVAL, "vx, vy, p, eta_c, eta_n, fx, fy must be non-NULL");
     if (m->busy) return set_error(STK_EINVAL, "the handle is in a batch");
-    if (depth < 0 || depth > AA_MAX - 1) return set_error(STK_EINVAL, "depth must be in [0, %d] (got %d)", AA_MAX - 1, depth);
+    if (depth < 0 || depth > AA_MAX - 1)
+        return set_error(STK_EINVAL, "depth must be in [0, %d] (got %d)", AA_MAX - 1, depth);
     stk_uzawa_opts o;
     stk_uzawa_opts_default(&o);
     if (opts) o = *opts;
@@ -210,7 +211,8 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
     if (!(o.tol >= 0.0)) return set_error(STK_EINVAL, "tol must be >= 0");
     if (o.stages < 0 || o.stage_cycles < 0)
         return set_error(STK_EINVAL, "stages and stage_cycles must be >= 0 (got %d, %d)", o.stages, o.stage_cycles);
-    if (o.mode != STK_SOLVE_F64 && o.mode != STK_SOLVE_F32_REFINED) return set_error(STK_EINVAL, "unknown mode %d", o.mode);
+    if (o.mode != STK_SOLVE_F64 && o.mode != STK_SOLVE_F32_REFINED)
+        return set_error(STK_EINVAL, "unknown mode %d", o.mode);
     stk_ctx* ctx = m->ctx;
     STK_TRY(use_device(ctx));
     const int W = depth + 1;                          // ring of W slots
@@ -235,80 +237,80 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
     // One stage: Anderson steps on the system of hierarchy mm (viscosities ec,
     // en); the window restarts with the stage, since F changes with it.
     auto stage = [&](stk_mg* mm, const double* ec, const double* en, bool last) -> int {
-    stk_mg* self = mm;
-    if (!mm->plan[0]) STK_TRY(make_plan(ctx, &self, 1, 0, &mm->plan[0]));
-    double* zx = static_cast<double*>(mm->ks[0][VS_Z].x);
-    double* zy = static_cast<double*>(mm->ks[0][VS_Z].y);
-    double* rx0 = static_cast<double*>(mm->ks[0][VS_R].x);
-    double* ry0 = static_cast<double*>(mm->ks[0][VS_R].y);
-    int kk = 0;  // index of the current iterate x_kk = (vx, vy, p) within the stage
-    while (k < o.max_cycles && (last ? out[3] > o.tol : kk < o.stage_cycles)) {
-        const int sk = kk % W;
-        // F(x_k) into slot sk: one Uzawa cycle from x_k.  The hierarchy's
-        // level 0 has the caller's row stride: the V-cycle runs in its own
-        // level-0 vectors (iterate loaded from x_k, right-hand side folded in
-        // place).
-        const size_t rowb = (size_t)g->ld * sizeof(double);
-        STK_HIP(hipMemcpy2DAsync(F(sk, 2), rowb, p, rowb, (size_t)g->nx * sizeof(double), g->ny,
-                                 hipMemcpyDeviceToDevice, ctx->stream));
-        if (o.mode == STK_SOLVE_F32_REFINED) {
-            // FP32 V-cycles on the FP64 residual (the slot's residual planes
-            // serve as scratch until the product pass rewrites them)
-            STK_TRY(copy_vel_in(mm, vx, vy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
-            for (int c = 0; c < o.vcycles; ++c) {
-                STK_TRY(stk_residual(ctx, STK_F64, g, F(sk, 0), F(sk, 1), p, ec, en, fx, fy, R(sk, 0),
-                                     R(sk, 1), nullptr));
-                STK_TRY(mixed_correction(mm, g, R(sk, 0), R(sk, 1), F(sk, 0), F(sk, 1)));
+        stk_mg* self = mm;
+        if (!mm->plan[0]) STK_TRY(make_plan(ctx, &self, 1, 0, &mm->plan[0]));
+        double* zx = static_cast<double*>(mm->ks[0][VS_Z].x);
+        double* zy = static_cast<double*>(mm->ks[0][VS_Z].y);
+        double* rx0 = static_cast<double*>(mm->ks[0][VS_R].x);
+        double* ry0 = static_cast<double*>(mm->ks[0][VS_R].y);
+        int kk = 0;  // index of the current iterate x_kk = (vx, vy, p) within the stage
+        while (k < o.max_cycles && (last ? out[3] > o.tol : kk < o.stage_cycles)) {
+            const int sk = kk % W;
+            // F(x_k) into slot sk: one Uzawa cycle from x_k.  The hierarchy's
+            // level 0 has the caller's row stride: the V-cycle runs in its own
+            // level-0 vectors (iterate loaded from x_k, right-hand side folded in
+            // place).
+            const size_t rowb = (size_t)g->ld * sizeof(double);
+            STK_HIP(hipMemcpy2DAsync(F(sk, 2), rowb, p, rowb, (size_t)g->nx * sizeof(double), g->ny,
+                                     hipMemcpyDeviceToDevice, ctx->stream));
+            if (o.mode == STK_SOLVE_F32_REFINED) {
+                // FP32 V-cycles on the FP64 residual (the slot's residual planes
+                // serve as scratch until the product pass rewrites them)
+                STK_TRY(copy_vel_in(mm, vx, vy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
+                for (int c = 0; c < o.vcycles; ++c) {
+                    STK_TRY(stk_residual(ctx, STK_F64, g, F(sk, 0), F(sk, 1), p, ec, en, fx, fy, R(sk, 0),
+                                         R(sk, 1), nullptr));
+                    STK_TRY(mixed_correction(mm, g, R(sk, 0), R(sk, 1), F(sk, 0), F(sk, 1)));
+                }
+            } else {
+                STK_TRY(copy_vel_in(mm, vx, vy, g->ld, zx, zy, g->ld, sizeof(double)));
+                STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, rx0, ry0));
+                for (int c = 0; c < o.vcycles; ++c) STK_TRY(run_vcycle(ctx, *mm->plan[0], mm->o, 0));
+                STK_TRY(copy_vel_in(mm, zx, zy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
             }
-        } else {
-            STK_TRY(copy_vel_in(mm, vx, vy, g->ld, zx, zy, g->ld, sizeof(double)));
-            STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, rx0, ry0));
-            for (int c = 0; c < o.vcycles; ++c) STK_TRY(run_vcycle(ctx, *mm->plan[0], mm->o, 0));
-            STK_TRY(copy_vel_in(mm, zx, zy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
+            STK_TRY(stk_uzawa_pressure(ctx, g, F(sk, 0), F(sk, 1), ec, o.omega_p, F(sk, 2)));
+            // products of r_k with the window r_{k-mk} .. r_k (oldest first) into
+            // the Gram matrix over ring slots
+            const int mk = std::min(depth, kk);
+            Planes D{};
+            D.n = mk + 1;
+            for (int t = 0; t <= mk; ++t)
+                for (int c = 0; c < 3; ++c) D.v[t][c] = R((kk - mk + t) % W, c);
+            hipLaunchKernelGGL(k_aa_diff_dots, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, F(sk, 0), F(sk, 1),
+                               F(sk, 2), vx, vy, p, R(sk, 0), R(sk, 1), R(sk, 2), D, (double*)part);
+            hipLaunchKernelGGL(k_aa_dots_final, dim3((unsigned)D.n), dim3(1024), 0, ctx->stream, (const double*)part,
+                               nblk, (double*)dots.p);
+            STK_HIP(hipGetLastError());
+            double d[AA_MAX];
+            STK_HIP(hipMemcpyAsync(d, dots.p, sizeof(double) * D.n, hipMemcpyDeviceToHost, ctx->stream));
+            STK_HIP(hipStreamSynchronize(ctx->stream));
+            for (int t = 0; t <= mk; ++t) {
+                const int st = (kk - mk + t) % W;
+                H[(size_t)sk * W + st] = H[(size_t)st * W + sk] = d[t];
+            }
+            // x_1 = F(x_0); later x_{k+1} = sum alpha_t F(x_{k-mk+t})
+            Planes P{};
+            P.n = mk + 1;
+            std::vector<double> al(1, 1.0);
+            if (kk > 0) {
+                std::vector<double> h((size_t)(mk + 1) * (mk + 1));
+                for (int a = 0; a <= mk; ++a)
+                    for (int b = 0; b <= mk; ++b)
+                        h[(size_t)a * (mk + 1) + b] = H[(size_t)((kk - mk + a) % W) * W + (kk - mk + b) % W];
+                al = aa_weights(h, mk + 1);
+            }
+            for (int t = 0; t <= mk; ++t) {
+                P.a[t] = al[t];
+                for (int c = 0; c < 3; ++c) P.v[t][c] = F((kk - mk + t) % W, c);
+            }
+            hipLaunchKernelGGL(k_aa_combine, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, P, vx, vy, p);
+            STK_HIP(hipGetLastError());
+            ++k;
+            ++kk;
+            STK_TRY(stk_energy_norm(ctx, STK_F64, g, vx, vy, p, eta_c, eta_n, fx, fy, out));
+            if (hist) hist[k] = out[3];
         }
-        STK_TRY(stk_uzawa_pressure(ctx, g, F(sk, 0), F(sk, 1), ec, o.omega_p, F(sk, 2)));
-        // products of r_k with the window r_{k-mk} .. r_k (oldest first) into
-        // the Gram matrix over ring slots
-        const int mk = std::min(depth, kk);
-        Planes D{};
-        D.n = mk + 1;
-        for (int t = 0; t <= mk; ++t)
-            for (int c = 0; c < 3; ++c) D.v[t][c] = R((kk - mk + t) % W, c);
-        hipLaunchKernelGGL(k_aa_diff_dots, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, F(sk, 0), F(sk, 1),
-                           F(sk, 2), vx, vy, p, R(sk, 0), R(sk, 1), R(sk, 2), D, (double*)part);
-        hipLaunchKernelGGL(k_aa_dots_final, dim3((unsigned)D.n), dim3(1024), 0, ctx->stream, (const double*)part,
-                           nblk, (double*)dots.p);
-        STK_HIP(hipGetLastError());
-        double d[AA_MAX];
-        STK_HIP(hipMemcpyAsync(d, dots.p, sizeof(double) * D.n, hipMemcpyDeviceToHost, ctx->stream));
-        STK_HIP(hipStreamSynchronize(ctx->stream));
-        for (int t = 0; t <= mk; ++t) {
-            const int st = (kk - mk + t) % W;
-            H[(size_t)sk * W + st] = H[(size_t)st * W + sk] = d[t];
-        }
-        // x_1 = F(x_0); later x_{k+1} = sum alpha_t F(x_{k-mk+t})
-        Planes P{};
-        P.n = mk + 1;
-        std::vector<double> al(1, 1.0);
-        if (kk > 0) {
-            std::vector<double> h((size_t)(mk + 1) * (mk + 1));
-            for (int a = 0; a <= mk; ++a)
-                for (int b = 0; b <= mk; ++b)
-                    h[(size_t)a * (mk + 1) + b] = H[(size_t)((kk - mk + a) % W) * W + (kk - mk + b) % W];
-            al = aa_weights(h, mk + 1);
-        }
-        for (int t = 0; t <= mk; ++t) {
-            P.a[t] = al[t];
-            for (int c = 0; c < 3; ++c) P.v[t][c] = F((kk - mk + t) % W, c);
-        }
-        hipLaunchKernelGGL(k_aa_combine, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, P, vx, vy, p);
-        STK_HIP(hipGetLastError());
-        ++k;
-        ++kk;
-        STK_TRY(stk_energy_norm(ctx, STK_F64, g, vx, vy, p, eta_c, eta_n, fx, fy, out));
-        if (hist) hist[k] = out[3];
-    }
-    return STK_OK;
+        return STK_OK;
     };
     STK_TRY(continuation(m, g, eta_c, eta_n, o, k, stage));
     const bool conv = out[3] <= o.tol;

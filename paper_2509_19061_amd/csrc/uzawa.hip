@@ -421,7 +421,8 @@ int stk_uzawa_solve(stk_mg* m, const stk_grid* g, double* vx, double* vy, double
     if (!(o.tol >= 0.0)) return set_error(STK_EINVAL, "tol must be >= 0");
     if (o.stages < 0 || o.stage_cycles < 0)
         return set_error(STK_EINVAL, "stages and stage_cycles must be >= 0 (got %d, %d)", o.stages, o.stage_cycles);
-    if (o.mode != STK_SOLVE_F64 && o.mode != STK_SOLVE_F32_REFINED) return set_error(STK_EINVAL, "unknown mode %d", o.mode);
+    if (o.mode != STK_SOLVE_F64 && o.mode != STK_SOLVE_F32_REFINED)
+        return set_error(STK_EINVAL, "unknown mode %d", o.mode);
     stk_ctx* ctx = m->ctx;
     STK_TRY(use_device(ctx));
     double out[5];
