@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0, help="profiling mode: L RAS launches + copy calibration")
     ap.add_argument("--serve", type=int, default=32, help="requests per serving run (0: skip)")
     ap.add_argument("--uzawa-n", type=int, default=4096, help="Uzawa workload size (0: skip)")
+    ap.add_argument("--uzawa-parts", default="all", choices=["all", "solve"],
+                    help="'solve': only the contrast-1e2 solves (FP64 and FP32 V-cycle) and the pressure step")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -260,7 +262,7 @@ def main():
     rate = run_iteration_cost(ctx, args.rate_n) if args.rate_n > 0 else None
     batch = run_batch(ctx, args.batch) if args.batch != "none" else None
     served = run_serve(ctx, args.serve) if args.serve > 0 else None
-    uz = run_uzawa(ctx, args.uzawa_n) if args.uzawa_n > 0 else None
+    uz = run_uzawa(ctx, args.uzawa_n, parts=args.uzawa_parts) if args.uzawa_n > 0 else None
 
     out = {
         "metric": "smoother GLUP/s + % HBM roofline (RAS-Jacobi)",
@@ -398,7 +400,7 @@ def run_solves(ctx, n, tol=1e-8, max_iters=4000):
             "refined_vs_f64_energy_rel": rel}
 
 
-def run_uzawa(ctx, n, tol=1e-8, max_cycles=1000, omega_p=0.6, reps=20):
+def run_uzawa(ctx, n, tol=1e-8, max_cycles=1000, omega_p=0.6, reps=20, parts="all"):
     """Inexact Uzawa solve of the full Stokes system, and the pressure step's rate."""
     import torch
 
@@ -453,6 +455,16 @@ def run_uzawa(ctx, n, tol=1e-8, max_cycles=1000, omega_p=0.6, reps=20):
     log(f"[bench] uzawa pressure step {n}^2: {pms:.4f} ms, {gbs:.0f} GB/s effective")
     m.close()
     del vx, vy, p, m, dp
+    out = {"workload": f"{n}x{n} cells, 8 sinkers (seed 2) eta 1e2 / 1, inexact Uzawa (one V(2,2)-cycle + pressure "
+                       f"step, omega_p {omega_p}) from the lithostatic pressure to E <= {tol:g}",
+           "n": n, "tol": tol, "seconds": round(secs, 4), "cycles": rep["cycles"], "converged": rep["converged"],
+           "ms_per_cycle": round(secs * 1e3 / max(1, rep["cycles"]), 3), "e_start": float(hist[0]),
+           "e_report": rep["e"], "e_recomputed": float(e[3]), "ev": float(e[4]),
+           "pressure_step": {"ms": round(pms, 4), "words_per_cell": words, "effective_gbs": round(gbs, 1),
+                             "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)},
+           "f32_refined": mixed}
+    if parts == "solve":
+        return out
 
     # the paper's schedule (Sec. 6.2): 1000 cycles, theta stepped 0, 1/4, .., 1 every 25
     # cycles, on the smoother workload (contrast 1e6)
@@ -523,14 +535,9 @@ def run_uzawa(ctx, n, tol=1e-8, max_cycles=1000, omega_p=0.6, reps=20):
             "ms_per_cycle": round(csecs * 1e3 / max(1, crep["cycles"]), 3), "e_start": float(chist[0]),
             "e_at": {str(c): float(chist[c]) for c in (100, 250, 500, 1000) if c < len(chist)},
             "e_final": crep["e"]}
-    return {"workload": f"{n}x{n} cells, 8 sinkers (seed 2) eta 1e2 / 1, inexact Uzawa (one V(2,2)-cycle + pressure "
-                        f"step, omega_p {omega_p}) from the lithostatic pressure to E <= {tol:g}",
-            "n": n, "tol": tol, "seconds": round(secs, 4), "cycles": rep["cycles"], "converged": rep["converged"],
-            "ms_per_cycle": round(secs * 1e3 / max(1, rep["cycles"]), 3), "e_start": float(hist[0]),
-            "e_report": rep["e"], "e_recomputed": float(e[3]), "ev": float(e[4]),
-            "pressure_step": {"ms": round(pms, 4), "words_per_cell": words, "effective_gbs": round(gbs, 1),
-                              "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)},
-            "f32_refined": mixed, "continuation": cont, "anderson": anderson}
+    out["continuation"] = cont
+    out["anderson"] = anderson
+    return out
 
 
 def run_iteration_cost(ctx, n, iters=30):
