@@ -379,3 +379,19 @@ def test_8192_ras_equals_fused_jacobi_bitwise(ctx):
     api.smooth(ctx, torch.float64, dp.grid, wx, wy, None, dp.eta_c, dp.eta_n, dp.fx, dp.fy, 8, "jacobi_fused")
     torch.cuda.synchronize()
     assert torch.equal(vx, wx) and torch.equal(vy, wy)
+
+
+@pytest.mark.parametrize("k", [2, 4, 8])
+def test_thin_overlap_ras_benchmark_configurations(ctx, k):
+    """The halo-0 RAS configurations the benchmark times (64 x 64 tiles,
+    k = 2, 4, 8, shift stream seed 3), with the kernel choice the benchmark
+    gets, against the oracle on a grid of several tiles with a ragged edge."""
+    p = ragged_problem(200, 136, 50 + k, 1e6)
+    vx0, vy0 = I.random_velocity(p, 60 + k, 1e-2)
+    sweeps = 3 * k
+    shifts = I.random_shifts(3, 64, 64, 3)
+    gx, gy = gpu_smooth(ctx, p, torch.float64, "ras", sweeps, vx0, vy0, tile_x=64, tile_y=64, k=k, halo=0,
+                        shifts=shifts)
+    ox, oy = S.smooth(p, vx0, vy0, p.fx, p.fy, None, sweeps, "ras", tile_x=64, tile_y=64, k=k, halo=0,
+                      shifts=shifts)
+    assert normwise(gx, ox) <= TOL64 and normwise(gy, oy) <= TOL64
