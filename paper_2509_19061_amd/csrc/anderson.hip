@@ -254,14 +254,10 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
             STK_HIP(hipMemcpy2DAsync(F(sk, 2), rowb, p, rowb, (size_t)g->nx * sizeof(double), g->ny,
                                      hipMemcpyDeviceToDevice, ctx->stream));
             if (o.mode == STK_SOLVE_F32_REFINED) {
-                // FP32 V-cycles on the FP64 residual (the slot's residual planes
-                // serve as scratch until the product pass rewrites them)
+                // FP32 V-cycles on the FP64 residual
                 STK_TRY(copy_vel_in(mm, vx, vy, g->ld, F(sk, 0), F(sk, 1), g->ld, sizeof(double)));
-                for (int c = 0; c < o.vcycles; ++c) {
-                    STK_TRY(stk_residual(ctx, STK_F64, g, F(sk, 0), F(sk, 1), p, ec, en, fx, fy, R(sk, 0),
-                                         R(sk, 1), nullptr));
-                    STK_TRY(mixed_correction(mm, g, R(sk, 0), R(sk, 1), F(sk, 0), F(sk, 1)));
-                }
+                for (int c = 0; c < o.vcycles; ++c)
+                    STK_TRY(mixed_correction(mm, g, F(sk, 0), F(sk, 1), p, ec, en, fx, fy));
             } else {
                 STK_TRY(copy_vel_in(mm, vx, vy, g->ld, zx, zy, g->ld, sizeof(double)));
                 STK_TRY(launch_fold_rhs(ctx, STK_F64, g, fx, fy, p, rx0, ry0));

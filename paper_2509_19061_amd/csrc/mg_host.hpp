@@ -81,8 +81,10 @@ int write_states(stk_ctx* ctx, const PlanT& P, const std::vector<FcgState>& h);
 int copy_vel_in(stk_mg* m, const void* sx, const void* sy, int64_t sld, void* dx, void* dy, int64_t dld, size_t es);
 int ensure_dtype(stk_mg* m, int t);
 // FP32 V-cycle correction of an FP64 velocity (uzawa.hip): v += V32(0, (float) r)
-// for the FP64 residual r = b - M v of the finest level, in the caller's layout.
-int mixed_correction(stk_mg* m, const stk_grid* g, const double* rx, const double* ry, double* vx, double* vy);
+// for the FP64 residual r = f - G p - M v of the finest level (viscosities ec,
+// en), in the caller's layout.
+int mixed_correction(stk_mg* m, const stk_grid* g, double* vx, double* vy, const double* p, const double* ec,
+                     const double* en, const double* fx, const double* fy);
 // Viscosity continuation (uzawa.hip, Sec. 6.2): for theta = s / o.stages,
 // s < o.stages, calls stage(hierarchy of (1 - theta) eta_min + theta eta, its
 // cell and nodal viscosities, false), then stage(m, eta_c, eta_n, true) for

@@ -45,6 +45,35 @@ __global__ __launch_bounds__(64 * WPB) void k_residual(int nx, int ny, int64_t l
     });
 }
 
+// The FP64 residual r = b - M v rounded to FP32 for an FP32 V-cycle from
+// zero: r32 <- (float) r, z32 <- 0 (FP32 arrays with the grid's row stride).
+// The same rows and values as k_residual<double> followed by a rounding pass.
+__global__ __launch_bounds__(64 * WPB) void k_residual_to32(int nx, int ny, int64_t ld, double idx, double idy,
+                                                            const double* __restrict__ vx,
+                                                            const double* __restrict__ vy,
+                                                            const double* __restrict__ p,
+                                                            const double* __restrict__ ec,
+                                                            const double* __restrict__ en,
+                                                            const double* __restrict__ fx,
+                                                            const double* __restrict__ fy, float* __restrict__ r32x,
+                                                            float* __restrict__ r32y, float* __restrict__ z32x,
+                                                            float* __restrict__ z32y) {
+    const int wv = xcd_tile((int)blockIdx.x, (int)gridDim.x) * WPB + wave_in_group();
+    const Place q = place(wv, nx, ny);
+    if (q.y0 >= q.y1) return;  // the whole wave
+    const int i = q.i;
+    const Loader<double> L = make_loader<double>(vx, vy, ec, en, fx, fy, p, ld, nx, ny, i);
+    const bool xcol = i >= 1 && i <= nx - 1, ycol = i >= 0 && i <= nx - 1;
+    const unsigned col = (unsigned)i * (unsigned)sizeof(float);
+    const unsigned s_x = q.own ? col : OOB, s_y = (q.own && ycol) ? col : OOB;
+    walk_rows<double>(L, q.y0, q.y1, [&](const Row<double>& a, const Row<double>& b, const Row<double>& c, int j) {
+        const Res<double> r = residual_row<double, double>(a, b, c, p != nullptr, idx, idy);
+        const bool ux = xcol && j <= ny - 1, uy = ycol && j >= 1 && j <= ny - 1;
+        store_pair<float>(r32x, r32y, ld, nx, ny, j, ux ? (float)r.rx : 0.0f, uy ? (float)r.ry : 0.0f, s_x, s_y);
+        store_pair<float>(z32x, z32y, ld, nx, ny, j, 0.0f, 0.0f, s_x, s_y);
+    });
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_down(v, o, 64);
@@ -126,6 +155,16 @@ int launch_residual(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* v
                            float(1.0 / g->dy), (const float*)vx, (const float*)vy, (const float*)p,
                            (const float*)eta_c, (const float*)eta_n, (const float*)fx, (const float*)fy, (float*)rx,
                            (float*)ry, (float*)rp);
+    STK_HIP(hipGetLastError());
+    return STK_OK;
+}
+
+int launch_residual_to32(stk_ctx* ctx, const stk_grid* g, const double* vx, const double* vy, const double* p,
+                         const double* eta_c, const double* eta_n, const double* fx, const double* fy, float* r32x,
+                         float* r32y, float* z32x, float* z32y) {
+    hipLaunchKernelGGL(k_residual_to32, dim3((unsigned)workgroups(g->nx, g->ny)), dim3(64 * WPB), 0, ctx->stream,
+                       g->nx, g->ny, g->ld, 1.0 / g->dx, 1.0 / g->dy, vx, vy, p, eta_c, eta_n, fx, fy, r32x, r32y,
+                       z32x, z32y);
     STK_HIP(hipGetLastError());
     return STK_OK;
 }

@@ -58,6 +58,11 @@ struct FieldPtrs {
 
 int launch_fold_rhs(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* fx, const void* fy, const void* p,
                     void* bx, void* by);
+// FP64 residual f - G p - M v rounded to FP32 into (r32x, r32y), and
+// (z32x, z32y) zeroed, on the velocity extents (FP32 arrays, stride g->ld).
+int launch_residual_to32(stk_ctx* ctx, const stk_grid* g, const double* vx, const double* vy, const double* p,
+                         const double* eta_c, const double* eta_n, const double* fx, const double* fy, float* r32x,
+                         float* r32y, float* z32x, float* z32y);
 int launch_jacobi_rows(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega,
                        const void* vx, const void* vy, void* ox, void* oy);
 int launch_jacobi_fused(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega,

@@ -174,25 +174,6 @@ __global__ __launch_bounds__(256) void k_rescale(int nx, int ny, int64_t ld, dou
     on[q] = (i <= nx) ? __dadd_rn(a, __dmul_rn(theta, en[q])) : 0.0;
 }
 
-// Mixed precision: r32 = (float) r64 and z32 = 0 on the velocity extents
-// (vx: ny x (nx+1), vy: (ny+1) x nx), in the hierarchy's level-0 layout.
-__global__ __launch_bounds__(256) void k_cast_r(int nx, int ny, int64_t ld, const double* __restrict__ rx,
-                                                const double* __restrict__ ry, float* __restrict__ r32x,
-                                                float* __restrict__ r32y, float* __restrict__ z32x,
-                                                float* __restrict__ z32y) {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= (int64_t)(ny + 1) * ld) return;
-    const int j = (int)(q / ld), i = (int)(q - (int64_t)j * ld);
-    if (j < ny && i <= nx) {
-        r32x[q] = (float)rx[q];
-        z32x[q] = 0.0f;
-    }
-    if (i < nx) {
-        r32y[q] = (float)ry[q];
-        z32y[q] = 0.0f;
-    }
-}
-
 // v += (double) z32 on the velocity extents
 __global__ __launch_bounds__(256) void k_add_z(int nx, int ny, int64_t ld, const float* __restrict__ z32x,
                                                const float* __restrict__ z32y, double* __restrict__ vx,
@@ -269,15 +250,10 @@ int uzawa_stage(stk_mg* mm, const stk_grid* g, double* vx, double* vy, double* p
     if (o.mode == STK_SOLVE_F32_REFINED) {
         // v += V32(0, (float)(f - G p - M v)) per V-cycle; the V-cycle is
         // consistent, so in exact arithmetic this is the FP64 cycle
-        DevBuf r64x, r64y;
-        STK_TRY(r64x.alloc(field_bytes(g, g->ny, STK_F64)));
-        STK_TRY(r64y.alloc(field_bytes(g, g->ny + 1, STK_F64)));
         int n = 0;
         while (k < o.max_cycles && (last ? out[3] > o.tol : n < o.stage_cycles)) {
-            for (int c = 0; c < o.vcycles; ++c) {
-                STK_TRY(stk_residual(ctx, STK_F64, g, vx, vy, p, ec_step, en_step, fx, fy, r64x.p, r64y.p, nullptr));
-                STK_TRY(mixed_correction(mm, g, (const double*)r64x.p, (const double*)r64y.p, vx, vy));
-            }
+            for (int c = 0; c < o.vcycles; ++c)
+                STK_TRY(mixed_correction(mm, g, vx, vy, p, ec_step, en_step, fx, fy));
             STK_TRY(pressure_update(ctx, g, vx, vy, ec_step, o.omega_p, p));
             ++k;
             ++n;
@@ -308,18 +284,18 @@ int uzawa_stage(stk_mg* mm, const stk_grid* g, double* vx, double* vy, double* p
 
 }  // namespace
 
-int mixed_correction(stk_mg* m, const stk_grid* g, const double* rx, const double* ry, double* vx, double* vy) {
+int mixed_correction(stk_mg* m, const stk_grid* g, double* vx, double* vy, const double* p, const double* ec,
+                     const double* en, const double* fx, const double* fy) {
     stk_ctx* ctx = m->ctx;
     stk_mg* self = m;
     if (!m->plan[1]) STK_TRY(make_plan(ctx, &self, 1, 1, &m->plan[1]));
-    float* r32x = static_cast<float*>(m->ks[1][VS_R].x);
-    float* r32y = static_cast<float*>(m->ks[1][VS_R].y);
     float* z32x = static_cast<float*>(m->ks[1][VS_Z].x);
     float* z32y = static_cast<float*>(m->ks[1][VS_Z].y);
     const int64_t cnt = (int64_t)(g->ny + 1) * g->ld;
     const dim3 eg((unsigned)((cnt + 255) / 256)), eb(256);
-    hipLaunchKernelGGL(k_cast_r, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, rx, ry, r32x, r32y, z32x, z32y);
-    STK_HIP(hipGetLastError());
+    // r32 = (float)(f - G p - M v) and z32 = 0 in one pass
+    STK_TRY(launch_residual_to32(ctx, g, vx, vy, p, ec, en, fx, fy, static_cast<float*>(m->ks[1][VS_R].x),
+                                 static_cast<float*>(m->ks[1][VS_R].y), z32x, z32y));
     STK_TRY(run_vcycle(ctx, *m->plan[1], m->o, 1));
     hipLaunchKernelGGL(k_add_z, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, (const float*)z32x, (const float*)z32y,
                        vx, vy);
