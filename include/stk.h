@@ -362,8 +362,10 @@ int stk_uzawa_pressure(stk_ctx* ctx, const stk_grid* g, const double* vx, const 
  * summary.  opts NULL means the defaults.  STK_ENOTCONV if E > tol at the end
  * (arrays, hist and rep are still written); the handle must not be in a
  * batch.  With continuation it allocates, for the call's duration, the stage
- * viscosities and hierarchies (stk_mg_footprint(g, .., 0) bytes each); the
- * FP32 V-cycle mode allocates an FP64 residual (two planes).
+ * viscosities and hierarchies (stk_mg_footprint(g, .., 0) bytes each).  With
+ * mode STK_SOLVE_F32_REFINED the V-cycles run in FP32 on the FP64 residual
+ * rounded to FP32 (in the handle's FP32 vectors, no further device memory)
+ * and their results are added to the FP64 velocity.
  * Synchronises once per cycle (the stopping test). */
 int stk_uzawa_solve(stk_mg* mg, const stk_grid* g, double* vx, double* vy, double* p, const double* eta_c,
                     const double* eta_n, const double* fx, const double* fy, const stk_uzawa_opts* opts,
@@ -386,7 +388,9 @@ int stk_uzawa_solve(stk_mg* mg, const stk_grid* g, double* vx, double* vy, doubl
  * map F differs), and max_cycles bounds the steps of all stages together.
  * hist (nullable, HOST, max_cycles + 1 doubles): E of x_0, x_1, ..;
  * rep->cycles counts F evaluations.  Allocates 6 (depth + 1) planes of
- * (ny + 1) * ld doubles for the call's duration.  Synchronises once per
+ * (ny + 1) * ld doubles and 9 doubles per 256 plane elements (the products'
+ * partial sums) for the call's duration.  The l2 norm and the combination
+ * take no wall value: walls are read as 0 and written as 0.  Synchronises once per
  * step.  STK_ENOTCONV as stk_uzawa_solve. */
 int stk_uzawa_anderson(stk_mg* mg, const stk_grid* g, double* vx, double* vy, double* p, const double* eta_c,
                        const double* eta_n, const double* fx, const double* fy, int depth,

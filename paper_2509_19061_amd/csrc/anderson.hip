@@ -39,11 +39,17 @@ struct Planes {
     int n;
 };
 
-__device__ __forceinline__ void masks(int64_t q, int64_t ld, int nx, int ny, bool& mx, bool& my, bool& mp) {
+// Used extents (ex, ey, ep) of the three planes at element q, and the
+// unknowns among them (ux, uy: the walls vx(0, .), vx(nx, .), vy(., 0),
+// vy(., ny) are not unknowns; every cell is a pressure unknown).
+__device__ __forceinline__ void masks(int64_t q, int64_t ld, int nx, int ny, bool& ex, bool& ey, bool& ep, bool& ux,
+                                      bool& uy) {
     const int j = (int)(q / ld), i = (int)(q - (int64_t)j * ld);
-    mx = j < ny && i <= nx;
-    my = j <= ny && i < nx;
-    mp = j < ny && i < nx;
+    ex = j < ny && i <= nx;
+    ey = j <= ny && i < nx;
+    ep = j < ny && i < nx;
+    ux = ex && i >= 1 && i <= nx - 1;
+    uy = ey && j >= 1 && j <= ny - 1;
 }
 
 __device__ __forceinline__ double wsum(double v) {
@@ -67,11 +73,11 @@ __global__ __launch_bounds__(AT) void k_aa_diff_dots(int nx, int ny, int64_t ld,
     const int64_t cnt = (int64_t)(ny + 1) * ld;
     double a = 0.0, b = 0.0, c = 0.0;
     if (q < cnt) {
-        bool mx, my, mp;
-        masks(q, ld, nx, ny, mx, my, mp);
-        a = mx ? fx[q] - xx[q] : 0.0;
-        b = my ? fy[q] - xy[q] : 0.0;
-        c = mp ? fp[q] - xp[q] : 0.0;
+        bool ex, ey, ep, ux, uy;
+        masks(q, ld, nx, ny, ex, ey, ep, ux, uy);
+        a = ux ? fx[q] - xx[q] : 0.0;  // wall values of F and x take no part
+        b = uy ? fy[q] - xy[q] : 0.0;
+        c = ep ? fp[q] - xp[q] : 0.0;
         rx[q] = a;
         ry[q] = b;
         rp[q] = c;
@@ -111,14 +117,15 @@ __global__ __launch_bounds__(AT) void k_aa_combine(int nx, int ny, int64_t ld, P
                                                    double* __restrict__ oy, double* __restrict__ op) {
     const int64_t q = (int64_t)blockIdx.x * AT + threadIdx.x;
     if (q >= (int64_t)(ny + 1) * ld) return;
-    bool mx, my, mp;
-    masks(q, ld, nx, ny, mx, my, mp);
-    const bool m3[3] = {mx, my, mp};
+    bool ex, ey, ep, ux, uy;
+    masks(q, ld, nx, ny, ex, ey, ep, ux, uy);
+    const bool e3[3] = {ex, ey, ep}, u3[3] = {ux, uy, ep};
     double* o3[3] = {ox, oy, op};
     for (int c = 0; c < 3; ++c) {
-        if (!m3[c]) continue;  // only the used extents are read and written
+        if (!e3[c]) continue;  // only the used extents are written: the unknowns, and 0 on the walls
         double s = 0.0;
-        for (int t = 0; t < f.n; ++t) s = __dadd_rn(s, __dmul_rn(f.a[t], f.v[t][c][q]));
+        if (u3[c])
+            for (int t = 0; t < f.n; ++t) s = __dadd_rn(s, __dmul_rn(f.a[t], f.v[t][c][q]));
         o3[c][q] = s;
     }
 }
@@ -225,8 +232,11 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
     auto F = [&](int s, int c) { return base + ((int64_t)(2 * s) * 3 + c) * plane; };
     auto R = [&](int s, int c) { return base + ((int64_t)(2 * s + 1) * 3 + c) * plane; };
     const int64_t nblk = (plane + AT - 1) / AT;
-    void* part = nullptr;
-    STK_TRY(scratch(ctx, stk_ctx::S_PART, sizeof(double) * (size_t)nblk * AA_MAX, &part));
+    // the products' per-workgroup partials have a buffer of their own: the Uzawa
+    // cycles and norms of every step use (and may regrow) the context's scratch
+    Dev parts;
+    STK_TRY(parts.alloc(sizeof(double) * (size_t)nblk * AA_MAX));
+    double* part = static_cast<double*>(parts.p);
     const dim3 eg((unsigned)nblk), eb(AT);
     std::vector<double> H((size_t)W * W, 0.0);       // Gram matrix over ring slots
     double out[5];
@@ -273,7 +283,7 @@ int stk_uzawa_anderson(stk_mg* m, const stk_grid* g, double* vx, double* vy, dou
             for (int t = 0; t <= mk; ++t)
                 for (int c = 0; c < 3; ++c) D.v[t][c] = R((kk - mk + t) % W, c);
             hipLaunchKernelGGL(k_aa_diff_dots, eg, eb, 0, ctx->stream, g->nx, g->ny, g->ld, F(sk, 0), F(sk, 1),
-                               F(sk, 2), vx, vy, p, R(sk, 0), R(sk, 1), R(sk, 2), D, (double*)part);
+                               F(sk, 2), vx, vy, p, R(sk, 0), R(sk, 1), R(sk, 2), D, part);
             hipLaunchKernelGGL(k_aa_dots_final, dim3((unsigned)D.n), dim3(1024), 0, ctx->stream, (const double*)part,
                                nblk, (double*)dots.p);
             STK_HIP(hipGetLastError());

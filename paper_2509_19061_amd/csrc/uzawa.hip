@@ -61,12 +61,15 @@ __global__ __launch_bounds__(UX* UY) void k_pressure_update(int nx, int ny, int6
     const int j0 = ((int)blockIdx.y * UY + (int)threadIdx.y) * UROWS;
     double s = 0.0;
     if (i < nx && j0 < ny) {
+        // the wall velocities vx(0, .), vx(nx, .), vy(., 0), vy(., ny) are read as 0
         const int j1 = min(j0 + UROWS, ny);
-        double below = vy[(int64_t)j0 * ld + i];
+        const bool lw = i == 0, rw = i + 1 == nx;
+        double below = j0 == 0 ? 0.0 : vy[(int64_t)j0 * ld + i];
         for (int j = j0; j < j1; ++j) {
             const int64_t c = (int64_t)j * ld + i;
-            const double above = vy[c + ld];
-            const double div = (vx[c + 1] - vx[c]) * idx + (above - below) * idy;
+            const double above = j + 1 == ny ? 0.0 : vy[c + ld];
+            const double xl = lw ? 0.0 : vx[c], xr = rw ? 0.0 : vx[c + 1];
+            const double div = (xr - xl) * idx + (above - below) * idy;
             const double q = p[c] - omega_p * ec[c] * div;  // + omega_p eta_c r_p, r_p = -D v
             p[c] = q;
             s += q;
@@ -174,15 +177,16 @@ __global__ __launch_bounds__(256) void k_rescale(int nx, int ny, int64_t ld, dou
     on[q] = (i <= nx) ? __dadd_rn(a, __dmul_rn(theta, en[q])) : 0.0;
 }
 
-// v += (double) z32 on the velocity extents
+// v += (double) z32 on the unknowns; the walls vx(0, .), vx(nx, .), vy(., 0),
+// vy(., ny) are written 0
 __global__ __launch_bounds__(256) void k_add_z(int nx, int ny, int64_t ld, const float* __restrict__ z32x,
                                                const float* __restrict__ z32y, double* __restrict__ vx,
                                                double* __restrict__ vy) {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= (int64_t)(ny + 1) * ld) return;
     const int j = (int)(q / ld), i = (int)(q - (int64_t)j * ld);
-    if (j < ny && i <= nx) vx[q] += (double)z32x[q];
-    if (i < nx) vy[q] += (double)z32y[q];
+    if (j < ny && i <= nx) vx[q] = (i == 0 || i == nx) ? 0.0 : vx[q] + (double)z32x[q];
+    if (i < nx) vy[q] = (j == 0 || j == ny) ? 0.0 : vy[q] + (double)z32y[q];
 }
 
 dim3 cell_grid_u(const stk_grid* g) {

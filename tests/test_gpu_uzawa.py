@@ -471,3 +471,91 @@ def test_anderson_continuation_matches_oracle(ctx):
     assert normwise(d.get_cell(pt), op) <= 1e-8
     np.testing.assert_allclose(hist, oh, rtol=1e-7)
     m.close()
+
+
+def test_anderson_mixed_continuation_matches_oracle(ctx):
+    """FP32 V-cycles, continuation stages and Anderson steps together (each
+    stage hierarchy builds its own FP32 plan) against the oracle's FP64
+    Anderson continuation, to the FP32 bar of the mixed tests (1e-4)."""
+    from paper_2509_19061_amd import api
+    p = sinkers(64, 64, 53, 1e3)
+    d = dev(p)
+    m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
+    p0 = U.litho(p, p.fy)
+    vx, vy = d.velocity()
+    pt = d.field(p0)
+    rep, hist = api.uzawa_anderson(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, depth=3, allow_notconv=True,
+                                   tol=0.0, max_cycles=8, stages=2, stage_cycles=2, mode="f32_refined")
+    assert rep["cycles"] == 8
+    ox, oy, op, oh = U.anderson_continuation(p, p.fx, p.fy, *p.zeros_v(), p0, m=3, stages=2, stage_cycles=2,
+                                             tol=0.0, max_iters=8)
+    assert normwise(d.get_vx(vx), ox) <= 1e-4 and normwise(d.get_vy(vy), oy) <= 1e-4
+    assert normwise(d.get_cell(pt), op) <= 1e-4
+    np.testing.assert_allclose(hist, oh, rtol=1e-3)
+    m.close()
+
+
+def _garbage_walls(vx, vy, nx, ny, value):
+    """Write +-value on the wall velocities vx(0, .), vx(nx, .), vy(., 0), vy(., ny)."""
+    vx[:ny, 0] = value
+    vx[:ny, nx] = -value
+    vy[0, :nx] = -value
+    vy[ny, :nx] = value
+
+
+def _walls_zero(vx, vy, nx, ny):
+    return (float(vx[:ny, 0].abs().max()) == 0.0 and float(vx[:ny, nx].abs().max()) == 0.0
+            and float(vy[0, :nx].abs().max()) == 0.0 and float(vy[ny, :nx].abs().max()) == 0.0)
+
+
+def test_pressure_step_ignores_wall_values(ctx):
+    """Walls are read as 0 whatever they hold: +-1e30 there gives the bits of
+    the zero-wall step."""
+    from paper_2509_19061_amd import api
+    nx, ny = 130, 97
+    p = sinkers(nx, ny, 5, 1e4)
+    vx0, vy0 = I.random_velocity(p, 3, 1e-2)
+    p0 = I.random_pressure(p, 4)
+    d = dev(p)
+    out = []
+    for wall in (0.0, 1e30):
+        tx, ty = d.velocity(vx0, vy0)
+        _garbage_walls(tx, ty, nx, ny, wall)
+        pt = d.field(p0)
+        api.uzawa_pressure(ctx, d.grid, tx, ty, d.eta_c, 0.6, pt)
+        torch.cuda.synchronize()
+        out.append(pt.clone())
+    assert torch.equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("call", ["solve_f64", "solve_f32", "anderson_f64", "anderson_f32"])
+def test_uzawa_cycles_ignore_wall_values(ctx, call):
+    """The Uzawa cycles (both precision modes) and the Anderson steps give the
+    same bits from a start whose walls hold +-1e30 as from zero walls, and
+    write 0 on the walls."""
+    from paper_2509_19061_amd import api
+    nx, ny = 64, 48
+    p = sinkers(nx, ny, 17, 1e3)
+    d = dev(p)
+    m = api.MG(ctx, d.grid, d.eta_c, d.eta_n)
+    vx0, vy0 = I.random_velocity(p, 21, 1e-3)
+    p0 = U.litho(p, p.fy)
+    mode = "f32_refined" if call.endswith("f32") else "f64"
+    res = []
+    for wall in (0.0, 1e30):
+        vx, vy = d.velocity(vx0, vy0)
+        _garbage_walls(vx, vy, nx, ny, wall)
+        pt = d.field(p0)
+        if call.startswith("solve"):
+            _, hist = api.uzawa_solve(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, allow_notconv=True,
+                                      tol=0.0, max_cycles=4, mode=mode)
+        else:
+            _, hist = api.uzawa_anderson(m, d.grid, vx, vy, pt, d.eta_c, d.eta_n, d.fx, d.fy, depth=3,
+                                         allow_notconv=True, tol=0.0, max_cycles=4, mode=mode)
+        torch.cuda.synchronize()
+        assert _walls_zero(vx, vy, nx, ny), (call, wall)
+        res.append((vx.clone(), vy.clone(), pt.clone(), hist))
+    for a, b in zip(res[0][:3], res[1][:3]):
+        assert torch.equal(a, b), call
+    assert np.array_equal(res[0][3][1:], res[1][3][1:])
+    m.close()
