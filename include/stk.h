@@ -183,6 +183,18 @@ int stk_energy_norm(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* v
                     const void* p, const void* eta_c, const void* eta_n, const void* fx, const void* fy,
                     double out[5]);
 
+/* ---------------------------------------------------------- measurement -- */
+
+/* A plain streaming pass with the traffic of one RAS outer iteration (Sec.
+ * 4.3: six planes read, two written), the practical HBM ceiling the smoother
+ * kernels are measured against and the calibration kernel of the HBM byte
+ * counters: o0 = a0 + a2 * a4 and o1 = a1 + a3 * a5 elementwise over all
+ * (ny + 1) * ld elements of each plane (DEVICE arrays of that many elements,
+ * dtype dt; outputs must not alias inputs).  Bytes moved: 8 (ny + 1) ld w.
+ * Asynchronous. */
+int stk_stream_probe(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* a0, const void* a1, const void* a2,
+                     const void* a3, const void* a4, const void* a5, void* o0, void* o1);
+
 /* ----------------------------------------------------------- multigrid -- */
 
 /* Geometric multigrid for the velocity block (Sec. 3.2: the velocity update

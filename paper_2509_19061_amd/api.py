@@ -19,7 +19,7 @@ from ._lib import (EHIP, EINVAL, ENOMEM, ENONFINITE, ENOTCONV, EUNSUPPORTED, F32
                    StkError, check)
 
 __all__ = ["Context", "Grid", "SmoothOpts", "StkError", "smooth", "ras_outer", "residual", "energy_norm", "ras_shifts",
-           "smooth_opts", "F64", "F32", "JACOBI", "JACOBI_FUSED", "RAS_JACOBI", "RBGS", "VARIANTS", "OK", "EINVAL",
+           "smooth_opts", "stream_probe", "F64", "F32", "JACOBI", "JACOBI_FUSED", "RAS_JACOBI", "RBGS", "VARIANTS", "OK", "EINVAL",
            "ENOMEM", "EHIP", "ENOTCONV", "ENONFINITE", "EUNSUPPORTED", "dtype_code", "torch_dtype", "MG", "mg_opts",
            "mg_footprint", "mg_solve_batch", "SOLVE_F64", "SOLVE_F32_REFINED", "MODES", "Batch", "uzawa_opts",
            "litho_pressure", "uzawa_pressure", "uzawa_solve", "uzawa_anderson"]
@@ -165,6 +165,12 @@ def energy_norm(ctx, dt, grid, vx, vy, p, eta_c, eta_n, fx, fy, allow_nonfinite=
     if not (allow_nonfinite and rc == ENONFINITE):
         check(rc)
     return np.array(out[:])
+
+
+def stream_probe(ctx, dt, grid, a, o):
+    """The six-read, two-write streaming pass (a: 6 tensors, o: 2) over whole planes."""
+    dt = dtype_code(dt)
+    check(L.lib.stk_stream_probe(ctx.handle, dt, C.byref(grid), *[_ptr(t, dt) for t in a], *[_ptr(t, dt) for t in o]))
 
 
 def ras_shifts(seed, n_outer, tile_x, tile_y):
