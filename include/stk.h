@@ -183,6 +183,25 @@ int stk_energy_norm(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* v
                     const void* p, const void* eta_c, const void* eta_n, const void* fx, const void* fy,
                     double out[5]);
 
+/* The energy norms of stk_energy_norm for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): `out` is a DEVICE array of 5 doubles that receives
+ * {N_v, N_p, N_f, E, E_v} (E and E_v computed on the device); the call
+ * enqueues the work and returns without waiting.  The per-wave partial sums
+ * live in a fixed 8 MiB array of the library on each GPU (held until the
+ * process ends), not in the context's scratch: nothing is allocated and the
+ * context's scratch is not touched.  N_v, N_p, N_f are bitwise those of
+ * stk_energy_norm.  Every call on one GPU shares that array, so calls that
+ * may overlap on one GPU (other streams, other host threads) race: order them
+ * on one stream.  Nothing needs to start at zero (every partial is written
+ * before it is read).  Grids needing more than 349525 partial triples
+ * (ceil((nx+1)/62) * ceil((ny+1)/64); about 37000 x 37000 cells) return
+ * STK_EUNSUPPORTED.  Non-finite results are not reported (there is no host
+ * result to check).  Other errors as stk_energy_norm. */
+int stk_energy_norm_noalloc(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy,
+                            const void* p, const void* eta_c, const void* eta_n, const void* fx, const void* fy,
+                            double* out);
+
 /* ---------------------------------------------------------- measurement -- */
 
 /* A plain streaming pass with the traffic of one RAS outer iteration (Sec.

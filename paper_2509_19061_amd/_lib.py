@@ -76,6 +76,7 @@ _SIGS = {
     "stk_ras_outer": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _P, C.c_double, _I, _I, _I, _I, _I, _I], _I),
     "stk_residual": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I),
     "stk_energy_norm": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_double)], _I),
+    "stk_energy_norm_noalloc": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _P], _I),
     "stk_stream_probe": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _P], _I),
     "stk_mg_opts_default": ([C.POINTER(MgOpts)], None),
     "stk_mg_create": ([_P, C.POINTER(_P), _G, _P, _P, C.POINTER(MgOpts)], _I),

@@ -19,7 +19,7 @@ from ._lib import (EHIP, EINVAL, ENOMEM, ENONFINITE, ENOTCONV, EUNSUPPORTED, F32
                    StkError, check)
 
 __all__ = ["Context", "Grid", "SmoothOpts", "StkError", "smooth", "ras_outer", "residual", "energy_norm", "ras_shifts",
-           "smooth_opts", "stream_probe", "F64", "F32", "JACOBI", "JACOBI_FUSED", "RAS_JACOBI", "RBGS", "VARIANTS", "OK", "EINVAL",
+           "smooth_opts", "energy_norm_noalloc", "stream_probe", "F64", "F32", "JACOBI", "JACOBI_FUSED", "RAS_JACOBI", "RBGS", "VARIANTS", "OK", "EINVAL",
            "ENOMEM", "EHIP", "ENOTCONV", "ENONFINITE", "EUNSUPPORTED", "dtype_code", "torch_dtype", "MG", "mg_opts",
            "mg_footprint", "mg_solve_batch", "SOLVE_F64", "SOLVE_F32_REFINED", "MODES", "Batch", "uzawa_opts",
            "litho_pressure", "uzawa_pressure", "uzawa_solve", "uzawa_anderson"]
@@ -165,6 +165,17 @@ def energy_norm(ctx, dt, grid, vx, vy, p, eta_c, eta_n, fx, fy, allow_nonfinite=
     if not (allow_nonfinite and rc == ENONFINITE):
         check(rc)
     return np.array(out[:])
+
+
+def energy_norm_noalloc(ctx, dt, grid, vx, vy, p, eta_c, eta_n, fx, fy, out):
+    """(N_v, N_p, N_f, E, E_v) into the device FP64 tensor ``out`` (>= 5
+    elements), enqueued without waiting; the library allocates nothing."""
+    dt = dtype_code(dt)
+    if not (isinstance(out, torch.Tensor) and out.dtype == torch.float64 and out.numel() >= 5):
+        raise ValueError("out must be a device float64 tensor of at least 5 elements")
+    check(L.lib.stk_energy_norm_noalloc(ctx.handle, dt, C.byref(grid), _ptr(vx, dt), _ptr(vy, dt), _ptr(p, dt),
+                                        _ptr(eta_c, dt), _ptr(eta_n, dt), _ptr(fx, dt), _ptr(fy, dt),
+                                        _ptr(out, F64)))
 
 
 def stream_probe(ctx, dt, grid, a, o):

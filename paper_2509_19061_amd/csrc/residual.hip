@@ -119,10 +119,12 @@ __global__ __launch_bounds__(64 * WPB) void k_energy(int nx, int ny, int64_t ld,
     }
 }
 
-// Fixed-order sum of n triples -> dst[0..2].
+// Fixed-order sum of n triples -> dst[0..2]; with `finish`, also
+// dst[3] = sqrt((dst[0] + dst[1]) / dst[2]) and dst[4] = sqrt(dst[0] / dst[2]).
 __global__ __launch_bounds__(1024) void k_reduce_triples(const double* __restrict__ part, int64_t n,
-                                                         double* __restrict__ dst) {
+                                                         double* __restrict__ dst, int finish) {
     __shared__ double red[3][1024 / 64];
+    __shared__ double tot[3];
     double s[3] = {0.0, 0.0, 0.0};
     for (int64_t q = threadIdx.x; q < n; q += 1024)
         for (int c = 0; c < 3; ++c) s[c] += part[3 * q + c];
@@ -136,6 +138,13 @@ __global__ __launch_bounds__(1024) void k_reduce_triples(const double* __restric
         double v = 0.0;
         for (int q = 0; q < 1024 / 64; ++q) v += red[threadIdx.x][q];
         dst[threadIdx.x] = v;
+        tot[threadIdx.x] = v;
+    }
+    if (!finish) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        dst[3] = sqrt((tot[0] + tot[1]) / tot[2]);
+        dst[4] = sqrt(tot[0] / tot[2]);
     }
 }
 
@@ -169,12 +178,20 @@ int launch_residual_to32(stk_ctx* ctx, const stk_grid* g, const double* vx, cons
     return STK_OK;
 }
 
+int64_t energy_partials(const stk_grid* g) { return (int64_t)strips(g->nx) * segments(g->ny); }
+
 int launch_energy(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* p,
                   const void* eta_c, const void* eta_n, const void* fx, const void* fy, double* dst) {
-    const int nwg = workgroups(g->nx, g->ny);
-    const int64_t waves = (int64_t)strips(g->nx) * segments(g->ny);  // one triple each (the rest leave at once)
     void* part = nullptr;
-    STK_TRY(scratch(ctx, stk_ctx::S_PART, sizeof(double) * 3 * (size_t)waves, &part));
+    STK_TRY(scratch(ctx, stk_ctx::S_PART, sizeof(double) * 3 * (size_t)energy_partials(g), &part));
+    return launch_energy_into(ctx, dt, g, vx, vy, p, eta_c, eta_n, fx, fy, static_cast<double*>(part), dst, false);
+}
+
+int launch_energy_into(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* p,
+                       const void* eta_c, const void* eta_n, const void* fx, const void* fy, double* part,
+                       double* dst, bool finish) {
+    const int nwg = workgroups(g->nx, g->ny);
+    const int64_t waves = energy_partials(g);  // one triple each (the rest leave at once)
     const double idx = 1.0 / g->dx, idy = 1.0 / g->dy, sp = 2.0 * idx * idx + 2.0 * idy * idy;
     const dim3 block(64 * WPB);
     if (dt == STK_F64)
@@ -187,7 +204,8 @@ int launch_energy(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx,
                            idy, sp, (const float*)vx, (const float*)vy, (const float*)p,
                            (const float*)eta_c, (const float*)eta_n, (const float*)fx, (const float*)fy,
                            (double*)part);
-    hipLaunchKernelGGL(k_reduce_triples, dim3(1), dim3(1024), 0, ctx->stream, (const double*)part, waves, dst);
+    hipLaunchKernelGGL(k_reduce_triples, dim3(1), dim3(1024), 0, ctx->stream, (const double*)part, waves, dst,
+                       finish ? 1 : 0);
     STK_HIP(hipGetLastError());
     return STK_OK;
 }

@@ -114,5 +114,13 @@ int launch_residual(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* v
 // Energy partial sums -> 3 doubles in device memory `dst` (N_v, N_p, N_f).
 int launch_energy(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* p,
                   const void* eta_c, const void* eta_n, const void* fx, const void* fy, double* dst);
+// Triples of partial sums the energy kernel writes for grid g.
+int64_t energy_partials(const stk_grid* g);
+// The energy norm with caller-provided partials (3 * energy_partials(g)
+// doubles); dst[0..2] = N_v, N_p, N_f and, with `finish`, dst[3] = E and
+// dst[4] = E_v, all in device memory.  Allocates nothing.
+int launch_energy_into(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* p,
+                       const void* eta_c, const void* eta_n, const void* fx, const void* fy, double* part,
+                       double* dst, bool finish);
 
 }  // namespace stk
