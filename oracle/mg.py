@@ -83,6 +83,103 @@ def coarse_solve(L, bx, by):
     return SP.unpack(L.nx, L.ny, sla.cho_solve(L.chol, -SP.pack(L.nx, L.ny, bx, by)))
 
 
+# ---------------------------------------------------------------------------
+# Smoother variants inside the V-cycle (Sec. 6.2, 6.3): RAS-type temporal
+# blocking (Alg. 2) on a level's assembled operator, the mixed smoother
+# (Jacobi on the finest level, RAS on the coarser ones), sweep counts growing
+# per level, and a truncated hierarchy whose coarsest level is relaxed.
+# ---------------------------------------------------------------------------
+
+def tile_intervals(n, T, s):
+    """Tiles along one axis: intervals between the cuts {s + mT} inside (0, n),
+    clipped to [0, n) (Alg. 2's shifted tiling; edge tiles may be partial)."""
+    cuts = [c for c in range(s % T, n, T) if c > 0]
+    edges = [0] + cuts + [n]
+    return [(edges[q], edges[q + 1]) for q in range(len(edges) - 1)]
+
+
+def _cell_unknowns(vx_id, vy_id, x0, x1, y0, y1):
+    """Packed unknowns associated with the cells [x0, x1) x [y0, y1): the
+    left-face vx(i, j) and the bottom-face vy(i, j) of each cell."""
+    e = np.concatenate([vx_id[y0:y1, x0:x1].ravel(), vy_id[y0:y1, x0:x1].ravel()])
+    return e[e >= 0]
+
+
+def ras_level(L, x, c, T, h, k, omega, shift=(0, 0)):
+    """One RAS outer iteration (Alg. 2 with snapshot semantics) for A_l x = c
+    on level L: every tile's owned cells grown by h (clipped) form the region
+    E; k damped-Jacobi sweeps update the unknowns of E while every unknown
+    outside E keeps its snapshot value; the unknowns of the owned cells are
+    written back.  Tiles are T x T cells, cut at the given shift."""
+    _, vx_id, vy_id = SP.numbering(L.nx, L.ny)
+    u = np.array(x, dtype=float)
+    out = u.copy()
+    for (x0, x1) in tile_intervals(L.nx, T, shift[0]):
+        for (y0, y1) in tile_intervals(L.ny, T, shift[1]):
+            E = _cell_unknowns(vx_id, vy_id, max(x0 - h, 0), min(x1 + h, L.nx), max(y0 - h, 0), min(y1 + h, L.ny))
+            own = _cell_unknowns(vx_id, vy_id, x0, x1, y0, y1)
+            AE = L.A[E]
+            z = u.copy()
+            for _ in range(k):
+                z[E] = z[E] + omega * (c[E] - AE @ z) / L.D[E]
+            out[own] = z[own]
+    return out
+
+
+def sweeps_per_level(nu, growth, l):
+    """nu * growth^l rounded to the nearest integer (halves up)."""
+    return int(np.floor(nu * growth ** l + 0.5))
+
+
+def _smooth_level(L, l, x, c, nu, omega, fine, coarse):
+    """nu sweeps of level l's smoother: Jacobi, or RAS outer iterations of
+    k_t = min(k, sweeps left) sweeps each (tile T, halo h, shift 0) when a RAS
+    setting is given for this level (`fine` for l = 0, `coarse` for l >= 1)."""
+    ras = fine if l == 0 else coarse
+    if not ras:
+        for _ in range(nu):
+            x = x + omega * (c - L.A @ x) / L.D
+        return x
+    left = nu
+    while left > 0:
+        kt = min(ras["k"], left)
+        x = ras_level(L, x, c, ras["T"], ras["h"], kt, omega)
+        left -= kt
+    return x
+
+
+def hierarchy_truncated(g, max_levels, coarsest=8):
+    """The Galerkin hierarchy of ``hierarchy`` cut after ``max_levels`` levels
+    (0: no cut)."""
+    levels = hierarchy(g, coarsest=coarsest)
+    if max_levels and len(levels) > max_levels:
+        levels = levels[:max_levels]
+        C = levels[-1]
+        del C.P
+        n = C.A.shape[0]
+        C.chol = sla.cho_factor(C.A.toarray()) if n <= 4096 else None
+    return levels
+
+
+def vcycle_general(levels, l, x, c, nu1=2, nu2=2, omega=0.7, growth=1.0, fine=None, coarse=None,
+                   relax_coarsest=False):
+    """One V-cycle for A_l x = c (packed unknowns) with the smoother variants:
+    level l takes nu1 * growth^l pre- and nu2 * growth^l post-sweeps of its
+    smoother (``_smooth_level``); the coarsest level is solved exactly, or,
+    with ``relax_coarsest``, relaxed by its pre- and post-sweeps from x."""
+    L = levels[l]
+    n1, n2 = sweeps_per_level(nu1, growth, l), sweeps_per_level(nu2, growth, l)
+    if l == len(levels) - 1:
+        if relax_coarsest:
+            return _smooth_level(L, l, x, c, n1 + n2, omega, fine, coarse)
+        return sla.cho_solve(L.chol, c)
+    x = _smooth_level(L, l, x, c, n1, omega, fine, coarse)
+    cc = 0.25 * (L.P.T @ (c - L.A @ x))
+    xc = vcycle_general(levels, l + 1, np.zeros(len(cc)), cc, nu1, nu2, omega, growth, fine, coarse, relax_coarsest)
+    x = x + L.P @ xc
+    return _smooth_level(L, l, x, c, n2, omega, fine, coarse)
+
+
 def _dot(a, b):
     return float(np.sum(a[0] * b[0]) + np.sum(a[1] * b[1]))
 
