@@ -96,10 +96,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solve-n", type=int, default=2048, help="refinement workload size (0: skip)")
-    ap.add_argument("--rate-n", type=int, default=8192, help="per-iteration cost size (0: skip)")
+    ap.add_argument("--config3-n", type=int, default=8192, help="refinement workload at full size (0: skip)")
+    ap.add_argument("--config3-cap", type=int, default=600, help="iteration cap of the smooth-background solves")
+    ap.add_argument("--config3-cap-iid", type=int, default=200, help="iteration cap of the i.i.d.-background solves")
+    ap.add_argument("--cpu-seconds-1t", type=float, default=10.0, help="CPU oracle sample at 1 thread (s)")
     ap.add_argument("--batch", default="default", help="'default' (64-instance mix), 'small' or 'none'")
     ap.add_argument("--kernel-only", type=int, default=0, help="profiling mode: L RAS launches + copy calibration")
-    ap.add_argument("--serve", type=int, default=32, help="requests per serving run (0: skip)")
+    ap.add_argument("--serve", type=int, default=16, help="requests per serving run (0: skip)")
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95", help="Poisson loads as fractions of saturation")
     ap.add_argument("--uzawa-n", type=int, default=4096, help="Uzawa workload size (0: skip)")
     ap.add_argument("--uzawa-parts", default="all", choices=["all", "solve"],
                     help="'solve': only the contrast-1e2 solves (FP64 and FP32 V-cycle) and the pressure step")
@@ -184,6 +188,28 @@ def main():
     log(f"[bench] {kernel_name} k={k}: {launch_ms:.3f} ms/launch, {achieved:.0f} GB/s effective "
         f"({achieved / HBM_PEAK_GBS:.1%} of HBM peak)")
 
+    # ---- practical HBM ceiling: a plain streaming pass with the same traffic pattern
+    # (6 planes read, 2 written) over the same arrays, timed the same way
+    probe_in = [dp.eta_c, dp.eta_n, dp.fx, dp.fy, ax, ay]
+    for _ in range(3):
+        api.stream_probe(kctx, dt, dp.grid, probe_in, [cx, cy])
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(20):
+        api.stream_probe(kctx, dt, dp.grid, probe_in, [cx, cy])
+    ev1.record()
+    torch.cuda.synchronize()
+    probe_ms = ev0.elapsed_time(ev1) / 20
+    probe_bytes = 8 * wbytes * (n + 1) * dp.ld
+    probe_gbs = probe_bytes / (probe_ms * 1e-3) / 1e9
+    ceiling = {"kernel": "k_stream6 (stk_stream_probe: 6 planes read, 2 written, one element per thread)",
+               "ms": round(probe_ms, 4), "bytes": probe_bytes, "gbs": round(probe_gbs, 1),
+               "frac_of_peak": round(probe_gbs / HBM_PEAK_GBS, 4),
+               "ras_alg_rate_over_ceiling": round(achieved / probe_gbs, 4)}
+    log(f"[bench] streaming ceiling: {probe_ms:.4f} ms, {probe_gbs:.0f} GB/s ({probe_gbs / HBM_PEAK_GBS:.1%} of peak); "
+        f"RAS at {achieved / probe_gbs:.1%} of it")
+    fp32 = run_fp32_leg(kctx, prob, sweeps) if args.dtype == "f64" and args.variants == "all" else None
+
     # ---- all variants, 100 sweeps each ----
     variants = {}
     if args.variants == "all":
@@ -253,15 +279,34 @@ def main():
                "sample": f"{it} RAS outer iterations (k={k}, T=64, h={k}, FP64) of the {n}x{n} workload "
                          f"= {it * k} of the step's {sweeps} sweeps, {el:.1f} s"}
         log(f"[bench] CPU oracle: {cpu_glups:.3f} GLUP/s on {cpu['cores']} threads ({el:.1f} s)")
+        # the same oracle on one thread (the sample is smaller: it runs ~nproc times slower)
+        if args.cpu_seconds_1t > 0:
+            nthreads = S.num_threads()
+            S.set_num_threads(1)
+            ox, oy = prob.zeros_v()
+            it1 = 0
+            c0 = time.perf_counter()
+            while True:
+                ox, oy = S.ras_outer(prob, bxo, byo, 0.7, 64, 64, k, k, osh[it1][0], osh[it1][1], ox, oy)
+                it1 += 1
+                el1 = time.perf_counter() - c0
+                if el1 >= args.cpu_seconds_1t or it1 >= len(osh):
+                    break
+            S.set_num_threads(nthreads)
+            cpu["one_thread"] = {"value": round(cells * k * it1 / el1 / 1e9, 5), "cores": 1,
+                                 "sample": f"{it1} RAS outer iterations (k={k}) of the {n}x{n} workload, {el1:.1f} s"}
+            log(f"[bench] CPU oracle, 1 thread: {cpu['one_thread']['value']} GLUP/s ({el1:.1f} s)")
 
     del vx, vy, ax, ay, cx, cy
     t_ok = (kernel_name == "k_ras_stream" and RAS_TRAFFIC["sources_sha256_16"] == ras_sources_hash()
             and (n, k, args.dtype) == (RAS_TRAFFIC["n"], RAS_TRAFFIC["k"], RAS_TRAFFIC["dtype"]))
     traffic = RAS_TRAFFIC["bytes_per_launch"] if t_ok else None
     solve = run_solves(ctx, args.solve_n) if args.solve_n > 0 else None
-    rate = run_iteration_cost(ctx, args.rate_n) if args.rate_n > 0 else None
+    config3 = (run_config3(ctx, args.config3_n, args.config3_cap, args.config3_cap_iid)
+               if args.config3_n > 0 else None)
     batch = run_batch(ctx, args.batch) if args.batch != "none" else None
-    served = run_serve(ctx, args.serve) if args.serve > 0 else None
+    loads = [float(x) for x in args.serve_loads.split(",") if x.strip()]
+    served = run_serve(ctx, args.serve, loads=loads) if args.serve > 0 else None
     uz = run_uzawa(ctx, args.uzawa_n, parts=args.uzawa_parts) if args.uzawa_n > 0 else None
 
     out = {
@@ -287,10 +332,12 @@ def main():
                      "kernel": f"{kernel_name} (one RAS outer iteration, k={k} sweeps, per launch)",
                      "launch_ms": round(launch_ms, 4), "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
+        "ceiling": ceiling,
         "variants": variants,
+        "fp32": fp32,
         "wall_ms_per_step": round(wall / args.steps * 1e3, 4),
         "solve": solve,
-        "iteration_cost": rate,
+        "config3": config3,
         "batch": batch,
         "serve": served,
         "uzawa": uz,
@@ -540,37 +587,136 @@ def run_uzawa(ctx, n, tol=1e-8, max_cycles=1000, omega_p=0.6, reps=20, parts="al
     return out
 
 
-def run_iteration_cost(ctx, n, iters=30):
-    """Time per Krylov iteration with the FP64 and with the FP32 V-cycle."""
+def run_fp32_leg(ctx, prob, sweeps, ks=(2, 4, 8)):
+    """The smoother workload in FP32 (fields rounded to FP32): RAS k = 2, 4, 8
+    and fused Jacobi at `sweeps` sweeps, and the RAS outer-iteration kernel's
+    own roofline at k = 4 (4-byte words)."""
+    import torch
+
+    from paper_2509_19061_amd import api, fields
+
+    dt = torch.float32
+    dp = fields.DeviceProblem(prob, dt)
+    n = prob.nx
+    cells = n * n
+    out = {"workload": "the smoother workload with every field rounded to FP32", "variants": {}}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    runs = [(f"ras_k{kk}", "ras", dict(tile_x=64, tile_y=64, k=kk, halo=kk, seed=3)) for kk in ks]
+    runs.append(("jacobi_fused", "jacobi_fused", {}))
+    for name, var, kw in runs:
+        vx, vy = dp.velocity()
+        api.smooth(ctx, dt, dp.grid, vx, vy, None, dp.eta_c, dp.eta_n, dp.fx, dp.fy, sweeps, var, **kw)
+        e_sw = float(api.energy_norm(ctx, dt, dp.grid, vx, vy, None, dp.eta_c, dp.eta_n, dp.fx, dp.fy)[3])
+        torch.cuda.synchronize()
+        reps = 3
+        e0.record()
+        for _ in range(reps):
+            api.smooth(ctx, dt, dp.grid, vx, vy, None, dp.eta_c, dp.eta_n, dp.fx, dp.fy, sweeps, var, **kw)
+        e1.record()
+        torch.cuda.synchronize()
+        t_ms = e0.elapsed_time(e1) / reps
+        g = cells * sweeps / (t_ms * 1e-3) / 1e9
+        w = 8.0 / kw["k"] if var == "ras" else 8
+        eff = g * w * 4
+        out["variants"][name] = {"ms_per_100_sweeps": round(t_ms, 3), "glups": round(g, 2),
+                                 "effective_gbs": round(eff, 1), "frac_hbm": round(eff / HBM_PEAK_GBS, 4),
+                                 "words_per_lup": w, "e_after_sweeps": e_sw}
+        log(f"[bench] fp32 {name}: {t_ms:.2f} ms / {sweeps} sweeps, {g:.1f} GLUP/s, {eff:.0f} GB/s effective")
+        del vx, vy
+    # the dominant kernel per launch, k = 4
+    (ax, ay), (cx, cy) = dp.velocity(), dp.velocity()
+    shifts = api.ras_shifts(3, 64, 64, 64)
+    for t in range(2):
+        api.ras_outer(ctx, dt, dp.grid, ax, ay, dp.eta_c, dp.eta_n, dp.fx, dp.fy, cx, cy, 0.7, 64, 64, 4, 4, *shifts[t])
+    torch.cuda.synchronize()
+    nl = 25
+    e0.record()
+    for t in range(nl):
+        src, dst = ((ax, ay), (cx, cy)) if t % 2 == 0 else ((cx, cy), (ax, ay))
+        api.ras_outer(ctx, dt, dp.grid, *src, dp.eta_c, dp.eta_n, dp.fx, dp.fy, *dst, 0.7, 64, 64, 4, 4,
+                      *shifts[t % len(shifts)])
+    e1.record()
+    torch.cuda.synchronize()
+    launch_ms = e0.elapsed_time(e1) / nl
+    alg = 8 * 4 * cells
+    ach = alg / (launch_ms * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": "k_ras_stream<float> (k=4, per launch)",
+                       "launch_ms": round(launch_ms, 4), "alg_bytes_per_launch": alg}
+    log(f"[bench] fp32 k_ras_stream k=4: {launch_ms:.4f} ms/launch, {ach:.0f} GB/s effective")
+    del ax, ay, cx, cy, dp
+    return out
+
+
+def run_config3(ctx, n, cap, cap_iid, tol=1e-8):
+    """The refinement workload at full size: FP64 and FP32-refined solves (FCG
+    preconditioned by one V(2,2)-cycle per iteration) of the smooth
+    log-uniform background to E_v <= tol within `cap` iterations, and of the
+    literal i.i.d. per-cell background within `cap_iid` iterations.  The
+    FP32-refined result is compared with the FP64 one in the relative energy
+    norm (no oracle solve fits at this size: the oracle's parity is tested at
+    small sizes)."""
     import torch
 
     from paper_2509_19061_amd import api, fields, inputs
 
-    prob = inputs.lognormal_background_workload(n)
-    dp = fields.DeviceProblem(prob, torch.float64)
-    m = api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n)
-    out = {"workload": f"{n}x{n} cells, same family as the solve section", "n": n, "bytes": None}
-    for mode in ("f64", "f32_refined"):
-        vx, vy = dp.velocity()
-        m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=1e-30, max_iters=1, allow_notconv=True)  # buffers, plan
-        vx, vy = dp.velocity()
-        rep, secs = _timed(lambda: m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=1e-30, max_iters=iters,
-                                            allow_notconv=True))
-        out[mode] = {"seconds": round(secs, 4), "iterations": rep["iterations"],
-                     "ms_per_iteration": round(secs * 1e3 / max(1, rep["iterations"]), 3)}
-        log(f"[bench] {n}^2 {mode}: {rep['iterations']} iterations in {secs:.3f}s")
-        del vx, vy
-    out["bytes"] = m.info()["bytes"]
-    out["f32_speedup_per_iteration"] = round(out["f64"]["ms_per_iteration"] / out["f32_refined"]["ms_per_iteration"], 3)
-    m.close()
+    out = {"n": n, "tol": tol}
+    for name, gen, maxit in (("smooth_background", inputs.lognormal_background_workload, cap),
+                             ("iid_background", inputs.iid_log_uniform_workload, cap_iid)):
+        t0 = time.time()
+        prob = gen(n)
+        dp = fields.DeviceProblem(prob, torch.float64)
+        del prob
+        m, setup_s = _timed(lambda: api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n))
+        log(f"[bench] config3 {name} {n}^2 ready in {time.time() - t0:.1f}s (hierarchy {setup_s:.2f}s)")
+        res, sols = {}, {}
+        for mode in ("f64", "f32_refined"):
+            vx, vy = dp.velocity()
+            m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=tol, max_iters=1, allow_notconv=True)  # buffers, plan
+            vx, vy = dp.velocity()
+            rep, secs = _timed(lambda: m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=tol, max_iters=maxit,
+                                                allow_notconv=True))
+            ev = float(api.energy_norm(ctx, torch.float64, dp.grid, vx, vy, None, dp.eta_c, dp.eta_n, dp.fx,
+                                       dp.fy)[4])
+            its = max(1, rep["iterations"])
+            res[mode] = {"converged": rep["converged"], "iterations": rep["iterations"], "seconds": round(secs, 3),
+                         "ms_per_iteration": round(secs * 1e3 / its, 3), "ev": ev,
+                         "rate_per_iteration": round(ev ** (1.0 / its), 5) if ev > 0 else None}
+            log(f"[bench] config3 {name} {mode}: {rep['iterations']} iterations in {secs:.2f}s, E_v {ev:.3e}")
+            sols[mode] = (vx, vy)
+        zx, zy = torch.zeros_like(dp.fx), torch.zeros_like(dp.fy)
+        rx, ry = torch.empty_like(dp.fx), torch.empty_like(dp.fy)
+
+        def energy(v):
+            api.residual(ctx, torch.float64, dp.grid, v[0], v[1], None, dp.eta_c, dp.eta_n, zx, zy, rx, ry)
+            return float((v[0] * rx).sum() + (v[1] * ry).sum())
+
+        x64, x32 = sols["f64"], sols["f32_refined"]
+        rel = (max(energy((x32[0] - x64[0], x32[1] - x64[1])), 0.0) / max(energy(x64), 1e-300)) ** 0.5
+        res["f32_vs_f64_energy_rel"] = rel
+        res["error_reference"] = "the FP64 GPU solve of the same run (no oracle solve at this size)"
+        if res["f64"]["converged"] and res["f32_refined"]["converged"]:
+            res["refined_speedup"] = round(res["f64"]["seconds"] / res["f32_refined"]["seconds"], 3)
+        res["refined_speedup_per_iteration"] = round(res["f64"]["ms_per_iteration"]
+                                                     / res["f32_refined"]["ms_per_iteration"], 3)
+        res["cap"] = maxit
+        res["setup_s"] = round(setup_s, 3)
+        out[name] = res
+        m.close()
+        del sols, x64, x32, zx, zy, rx, ry, dp, m
+        torch.cuda.empty_cache()
+    out["workload"] = (f"{n}x{n} cells, 16 sinkers eta 1e6 (seed 4); smooth_background: log10(eta) ~ U(-2, 4) as a "
+                       f"smooth random field; iid_background: log10(eta) ~ U(-2, 4) i.i.d. per cell (the literal "
+                       f"reading); FCG with one V(2,2)-cycle per iteration, FP64 and FP32 V-cycle")
     return out
 
 
-def run_serve(ctx, count, sizes=(128, 256, 512, 1024, 2048, 4096), budget=64 << 30, load=0.8, tol=1e-8,
-              max_iters=1000):
-    """Saturation and Poisson serving runs per mode (host problems built first).
-    Requests stop at E_v <= tol or after max_iters iterations: at 4096^2 and
-    contrast ~1e6, 1e-8 is at the FP64 rounding floor of E_v."""
+def run_serve(ctx, count, sizes=(128, 256, 512, 1024, 2048, 4096), budget=64 << 30, loads=(0.5, 0.8, 0.95),
+              tol=1e-8, max_iters=1000):
+    """Per mode: a saturation run (all requests at t = 0) gives the peak
+    solves/s, then Poisson arrivals at each fraction of that rate in `loads`
+    give solves/s and p50 / p99 latency.  Requests stop at E_v <= tol or after
+    max_iters iterations."""
     import numpy as np
 
     from paper_2509_19061_amd import inputs, serve
@@ -580,24 +726,26 @@ def run_serve(ctx, count, sizes=(128, 256, 512, 1024, 2048, 4096), budget=64 << 
     payload = {r.rid: inputs.instance_problem(r.n, np.random.default_rng(r.seed)) for r in base}
     log(f"[bench] serve: {count} requests built in {time.time() - t0:.1f}s, sizes "
         + ", ".join(f"{n}:{sum(r.n == n for r in base)}" for n in sizes))
-    out = {"workload": f"{count} requests, n uniform over {list(sizes)}, sinkers U{{1..8}}, contrast 10^U(2,6), "
-                       f"E_v <= {tol:g} (at most {max_iters} iterations), HBM budget {budget >> 30} GiB, "
-                       f"continuous batching",
-           "requests": count, "budget_bytes": budget}
+    out = {"workload": f"{count} requests per run, n uniform over {list(sizes)}, sinkers U{{1..8}}, contrast "
+                       f"10^U(2,6), E_v <= {tol:g} (at most {max_iters} iterations), HBM budget {budget >> 30} GiB, "
+                       f"continuous batching; Poisson loads {list(loads)} x saturation",
+           "requests": count, "budget_bytes": budget, "loads": list(loads)}
     for mode in ("f64", "f32_refined"):
         res = {}
-        for run in ("saturation", "poisson"):
-            if run == "saturation":
+        runs = ["saturation"] + [f"poisson_{ld:g}" for ld in loads]
+        for run, ld in zip(runs, [None] + list(loads)):
+            if ld is None:
                 reqs = [serve.Request(r.rid, 0.0, r.n, r.seed, payload[r.rid]) for r in base]
             else:
-                rate = load * res["saturation"]["solves_per_s"]
+                rate = ld * res["saturation"]["solves_per_s"]
                 arr = serve.poisson_requests(count, rate, [0], seed=7)
                 reqs = [serve.Request(r.rid, a.arrival, r.n, r.seed, payload[r.rid]) for r, a in zip(base, arr)]
             be = serve.GpuBackend(ctx, mode, 64, tol=tol, max_iters=max_iters)
             summ = serve.Server(be, budget, max_slots=64, iters_per_step=4).run(reqs).summary()
             be.close()
-            if run == "poisson":
+            if ld is not None:
                 summ["arrival_rate_per_s"] = round(rate, 4)
+                summ["load"] = ld
             res[run] = summ
             log(f"[bench] serve {mode} {run}: {summ['solves_per_s']} solves/s, p50 {summ['latency_p50_s']}s, "
                 f"p99 {summ['latency_p99_s']}s, admitted while busy {summ['admitted_while_busy']}, "
@@ -632,6 +780,24 @@ def run_batch(ctx, which, tol=1e-8, max_iters=3000):
                      "all_converged": all(r["converged"] for r in reps), "max_iterations": max(its),
                      "mean_iterations": round(sum(its) / len(its), 1), "max_ev": max(r["ev"] for r in reps)}
         log(f"[bench] batch {mode}: {secs:.3f}s, {len(probs) / secs:.2f} solves/s, iterations max {max(its)}")
+        # the same instances solved one after another with the single-instance call
+        seq = 0.0
+        same = True
+        for q, (d, mm) in enumerate(zip(dps, mgs)):
+            wx, wy = d.velocity()
+            mm.solve(mode, wx, wy, None, d.fx, d.fy, tol=tol, max_iters=1, allow_notconv=True)  # the handle's plan
+            wx.zero_()
+            wy.zero_()
+            rep, secs1 = _timed(lambda: mm.solve(mode, wx, wy, None, d.fx, d.fy, tol=tol, max_iters=max_iters,
+                                                 allow_notconv=True))
+            seq += secs1
+            same = same and torch.equal(wx, vs[q][0]) and torch.equal(wy, vs[q][1])
+            del wx, wy
+        out[mode]["sequential_seconds"] = round(seq, 4)
+        out[mode]["batch_speedup_vs_sequential"] = round(seq / secs, 3)
+        out[mode]["batch_equals_sequential_bitwise"] = bool(same)
+        log(f"[bench] batch {mode}: sequential single-instance solves {seq:.3f}s ({seq / secs:.2f}x the batch), "
+            f"identical results: {same}")
         del vs
     out["refined_speedup"] = round(out["f64"]["seconds"] / out["f32_refined"]["seconds"], 3)
     for mm in mgs:

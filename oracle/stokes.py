@@ -44,12 +44,19 @@ def lib():
             fn.restype = None
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = I
+        L.or_set_num_threads.argtypes = [I]
+        L.or_set_num_threads.restype = None
         _lib = L
     return _lib
 
 
 def num_threads():
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of the following oracle calls (OpenMP)."""
+    lib().or_set_num_threads(int(n))
 
 
 def _p(a):

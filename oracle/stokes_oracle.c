@@ -37,6 +37,8 @@
 
 /* Threads the OpenMP loops use (for reporting the CPU baseline's core count). */
 int or_num_threads(void) { return omp_get_max_threads(); }
+/* Threads for the following calls (the CPU baseline is timed at nproc and at 1). */
+void or_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 typedef struct {
     int nx, ny;

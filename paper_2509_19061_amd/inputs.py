@@ -150,6 +150,19 @@ def lognormal_background_workload(n: int = 8192, seed: int = 4, count: int = 16)
                           meta=dict(workload="log_uniform_background", n=n, count=count, seed=seed))
 
 
+def iid_log_uniform_workload(n: int = 8192, seed: int = 4, count: int = 16) -> Problem:
+    """The refinement workload with the literal background: log10(eta) drawn
+    i.i.d. per cell from U(-2, 4) (up to six decades between neighbouring
+    cells), the same 16 sinkers of eta 1e6."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.1, 0.9, size=(count, 2))
+    r = rng.uniform(0.02, 0.08, size=count)
+    bg = 10.0 ** np.random.default_rng(seed + 1).uniform(-2.0, 4.0, size=(n, n))
+    sinkers = [(float(c[k, 0]), float(c[k, 1]), float(r[k])) for k in range(count)]
+    return sinker_problem(n, n, sinkers, 1e6, bg,
+                          meta=dict(workload="iid_log_uniform_background", n=n, count=count, seed=seed))
+
+
 def instance_problem(n: int, rng: np.random.Generator) -> Problem:
     """One request/instance: sinker count U{1..8}, contrast 10^U(2,6)."""
     count = int(rng.integers(1, 9))

@@ -1,12 +1,20 @@
 """GPU multigrid V-cycle and Krylov solves vs the CPU oracle (oracle/mg.py).
 
 V-cycle: the GPU and oracle hierarchies are built independently from the same
-viscosities; they differ only in rounding, including the coarsest solve (GPU:
-dense inverse, oracle: Cholesky solve), whose error is amplified by the
-coarse condition number, hence the V-cycle tolerance TOL_V below.
+viscosities.  They differ only in rounding, and the coarse levels' Galerkin
+operators are sums of many products that the two sides form in different
+orders.  The V-cycle bar is therefore 1e-12 normwise or, where the coarse
+operators are ill conditioned (high viscosity contrast), 16 times the
+oracle's own change when every coupling of its coarse operators is moved by
+one unit in the last place (``ulp_sensitivity``; measured: 2e-15 at contrast
+1, 2e-14 at 1e2, 1.7e-12 at 1e4).  The coarsest solve's form does not matter
+at this level: the oracle's V-cycle with the library's dense inverse instead
+of its Cholesky solve moves by at most 5e-13 on these cases
+(``test_oracle_mg.py``).
 """
 import numpy as np
 import pytest
+import scipy.sparse as sp
 import torch
 
 from gpu_util import as_dtype, normwise
@@ -17,7 +25,28 @@ from paper_2509_19061_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-TOL_V = 1e-11
+TOL_V = 1e-12
+
+
+def ulp_sensitivity(p, vx0, vy0, rx, ry, trials=3, seed=0, **opts):
+    """Largest normwise change of the oracle V-cycle when every coupling of
+    every coarse operator is scaled by (1 + u eps), u ~ U(-1, 1), symmetric."""
+    ref = OM.vcycle(OM.hierarchy(p, coarsest=8), 0, vx0, vy0, rx, ry, **opts)
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for _ in range(trials):
+        lv = OM.hierarchy(p, coarsest=8)
+        for L in lv[1:]:
+            U = sp.triu(L.A, 1).tocoo()
+            Up = sp.coo_matrix((U.data * (1 + 2.2e-16 * rng.uniform(-1, 1, U.data.shape)), (U.row, U.col)),
+                               shape=L.A.shape)
+            D = L.A.diagonal() * (1 + 2.2e-16 * rng.uniform(-1, 1, L.A.shape[0]))
+            L.A = (Up + Up.T + sp.diags(D)).tocsr()
+            L.D = L.A.diagonal()
+        lv[-1].chol = OM.sla.cho_factor(lv[-1].A.toarray())
+        out = OM.vcycle(lv, 0, vx0, vy0, rx, ry, **opts)
+        worst = max(worst, normwise(out[0], ref[0]), normwise(out[1], ref[1]))
+    return worst
 
 
 @pytest.fixture(scope="module")
@@ -57,7 +86,8 @@ def test_vcycle_fp64_matches_oracle(ctx, nx, ny, contrast):
     m.vcycle(torch.float64, vx, vy, dp.field(rx), dp.field(ry))
     torch.cuda.synchronize()
     ox, oy = OM.vcycle(levels, 0, vx0, vy0, rx, ry)
-    assert normwise(dp.get_vx(vx), ox) <= TOL_V and normwise(dp.get_vy(vy), oy) <= TOL_V
+    tol = max(TOL_V, 16 * ulp_sensitivity(p, vx0, vy0, rx, ry))
+    assert normwise(dp.get_vx(vx), ox) <= tol and normwise(dp.get_vy(vy), oy) <= tol
 
 
 def test_vcycle_odd_nu_and_more_sweeps(ctx):
@@ -69,7 +99,8 @@ def test_vcycle_odd_nu_and_more_sweeps(ctx):
     m.vcycle(torch.float64, vx, vy, dp.field(rx), dp.field(ry))
     torch.cuda.synchronize()
     ox, oy = OM.vcycle(levels, 0, *p.zeros_v(), rx, ry, nu1=3, nu2=1, omega=0.6)
-    assert normwise(dp.get_vx(vx), ox) <= TOL_V and normwise(dp.get_vy(vy), oy) <= TOL_V
+    tol = max(TOL_V, 16 * ulp_sensitivity(p, *p.zeros_v(), rx, ry, nu1=3, nu2=1, omega=0.6))
+    assert normwise(dp.get_vx(vx), ox) <= tol and normwise(dp.get_vy(vy), oy) <= tol
 
 
 def test_vcycle_fp32_against_fp64_oracle(ctx):

@@ -321,6 +321,27 @@ def test_full_size_4096_ras_one_outer_iteration_vs_oracle(ctx, k):
     assert normwise(gx, ox) <= TOL64 and normwise(gy, oy) <= TOL64
 
 
+@pytest.mark.parametrize("k", [2, 4, 8])
+def test_full_size_4096_ras_fp32_one_outer_iteration_vs_oracle(ctx, k):
+    """The FP32 leg of the benchmark's workload (4096^2, 8 sinkers, eta 1e6/1,
+    T = 64, h = k): one outer iteration of k FP32 sweeps from an FP64 state
+    two Jacobi sweeps in, rounded to FP32 (the oracle takes the same rounded
+    inputs), against the FP64 oracle over the whole field, k * 1e-5."""
+    p = I.smoother_workload(4096, 2)
+    bx, by = S.rhs(p, p.fx, p.fy)
+    vx, vy = p.zeros_v()
+    for _ in range(2):
+        vx, vy = S.jacobi(p, bx, by, 0.7, vx, vy)
+    p32 = I.Problem(p.nx, p.ny, p.dx, p.dy, as_dtype(p.eta_c, torch.float32), as_dtype(p.eta_n, torch.float32),
+                    as_dtype(p.fx, torch.float32), as_dtype(p.fy, torch.float32))
+    vx, vy = as_dtype(vx, torch.float32), as_dtype(vy, torch.float32)
+    shifts = I.random_shifts(1, 64, 64, 3)
+    kw = dict(tile_x=64, tile_y=64, k=k, halo=k, shifts=shifts)
+    gx, gy = gpu_smooth(ctx, p32, torch.float32, "ras", k, vx, vy, **kw)
+    ox, oy = S.smooth(p32, vx, vy, p32.fx, p32.fy, None, k, "ras", **kw)
+    assert normwise(gx, ox) <= k * TOL32 and normwise(gy, oy) <= k * TOL32
+
+
 @pytest.mark.parametrize("kt,h", [(4, 4), (3, 1), (0, 2)])
 def test_ras_outer_entry_point_out_of_place(ctx, kt, h):
     from paper_2509_19061_amd import api, fields

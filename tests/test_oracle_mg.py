@@ -200,3 +200,40 @@ def test_vcycle_preconditioner_rate_is_mesh_independent_for_constant_viscosity()
         _, _, hist = mg.pcg(levels, np.zeros((n, n + 1)), np.ones((n + 1, n)), tol=1e-8, max_iters=200)
         its.append(len(hist))
     assert max(its) <= min(its) + 4, its
+
+
+def _mg_case(nx, ny, seed, contrast):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.15, 0.85, size=(3, 2))
+    r = rng.uniform(0.05, 0.12, size=3)
+    return I.sinker_problem(nx, ny, [(float(c[k, 0]), float(c[k, 1]), float(r[k])) for k in range(3)], contrast, 1.0)
+
+
+@pytest.mark.parametrize("nx,ny,contrast", [(64, 64, 1e2), (96, 64, 1e4), (50, 36, 1e3)])
+def test_coarse_solve_form_moves_the_vcycle_below_the_fp64_bar(nx, ny, contrast):
+    """The coarsest solve by the explicit inverse built from an unblocked
+    Cholesky factor (the library's form) instead of LAPACK's Cholesky solve
+    changes the oracle V-cycle by less than 1e-12 normwise: the form of the
+    coarse solve is not what separates the GPU V-cycle from the oracle's."""
+    import scipy.linalg as sla
+    p = _mg_case(nx, ny, nx + ny, contrast)
+    levels = mg.hierarchy(p, coarsest=8)
+    A = levels[-1].A.toarray()
+    n = A.shape[0]
+    L = np.zeros_like(A)
+    for j in range(n):
+        L[j, j] = np.sqrt(A[j, j] - L[j, :j] @ L[j, :j])
+        L[j + 1:, j] = (A[j + 1:, j] - L[j + 1:, :j] @ L[j, :j]) / L[j, j]
+    Li = sla.solve_triangular(L, np.eye(n), lower=True)
+    Ainv = Li.T @ Li
+    vx0, vy0 = I.random_velocity(p, 1, 1e-2)
+    rx, ry = I.random_velocity(p, 2, 1.0)
+    ref = mg.vcycle(levels, 0, vx0, vy0, rx, ry)
+    saved = mg.sla.cho_solve
+    try:
+        mg.sla.cho_solve = lambda _c, b: Ainv @ b
+        out = mg.vcycle(levels, 0, vx0, vy0, rx, ry)
+    finally:
+        mg.sla.cho_solve = saved
+    for a, b in zip(out, ref):
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
