@@ -234,6 +234,25 @@ typedef struct {
     int nu1, nu2;      /* pre / post smoothing sweeps per level (default 2, 2)                 */
     double omega;      /* Jacobi damping (default 0.7)                                          */
     int coarsest;      /* stop coarsening at min(nx, ny) <= coarsest (default 8)                */
+    /* Smoother variants of the paper's solver (Sec. 6.2, 6.3).  The defaults
+     * give the cycle described above. */
+    int fine_k;        /* finest level: RAS inner sweeps per outer iteration (64 x 64 tiles, shift
+                          0); a smoothing stage of nu sweeps is ceil(nu / fine_k) outer
+                          iterations, the last one partial; 0 (default) = nu (one outer iteration) */
+    int fine_halo;     /* finest-level RAS overlap in cells; -1 (default) = the outer iteration's
+                          sweep count, which makes it exactly that many Jacobi sweeps; 0 is the
+                          paper's thin overlap                                                   */
+    int coarse_smoother; /* 0 (default): damped Jacobi on the coarse (Galerkin) levels; 1: RAS on
+                          them, the paper's mixed smoother (Jacobi finest, RAS coarse)           */
+    int coarse_tile;   /* coarse RAS tile in cells (default 32, the paper's)                       */
+    int coarse_k;      /* coarse RAS inner sweeps per outer iteration (default 4, the paper's)     */
+    int coarse_halo;   /* coarse RAS overlap in cells (default 0, the paper's thin overlap)        */
+    double sweep_growth; /* level l takes floor(nu * sweep_growth^l + 1/2) pre- and post-sweeps
+                          (default 1; the paper grows them by 2.5 per level)                     */
+    int max_levels;    /* 0 (default): coarsen down to `coarsest` and solve there exactly; L >= 2:
+                          at most L levels, and when that stops the coarsening early the last
+                          level is relaxed by its pre- plus post-sweeps instead of solved (the
+                          paper runs four levels)                                                 */
 } stk_mg_opts;
 
 /* Both modes run the same FP64 outer iteration: flexible conjugate gradients
@@ -264,6 +283,13 @@ void stk_mg_opts_default(stk_mg_opts* o);
 int stk_mg_create(stk_ctx* ctx, stk_mg** out, const stk_grid* g, const double* eta_c, const double* eta_n,
                   const stk_mg_opts* opts);
 int stk_mg_destroy(stk_mg* mg);
+/* Move a hierarchy to another context on the same device, e.g. one built by
+ * a setup thread on its own stream and then solved in a batch on the serving
+ * stream: the device buffers that solves in `mode` need are created first
+ * (on the old context's stream), that stream is drained, and from then on
+ * the handle enqueues on `ctx`.  STK_EINVAL if the handle is in a batch or
+ * the devices differ.  Synchronises the old context's stream. */
+int stk_mg_bind(stk_mg* mg, stk_ctx* ctx, int mode);
 /* Levels, coarsest-grid unknowns and device bytes currently held. */
 int stk_mg_info(const stk_mg* mg, int* levels, int* coarse_unknowns, size_t* bytes);
 /* Device bytes a hierarchy for g needs when solving in `mode` (0 F64, 1 F32_REFINED),

@@ -78,6 +78,9 @@ def vcycle(levels, l, vx, vy, bx, by, nu1=2, nu2=2, omega=0.7):
     return SP.unpack(L.nx, L.ny, _vcycle_packed(levels, l, x, c, nu1, nu2, omega))
 
 
+_vcycle_natural = vcycle
+
+
 def coarse_solve(L, bx, by):
     """Exact solution of M v = b on the coarsest level."""
     return SP.unpack(L.nx, L.ny, sla.cho_solve(L.chol, -SP.pack(L.nx, L.ny, bx, by)))
@@ -190,7 +193,7 @@ def _masked_energy(rx, ry, dxg, dyg):
                  np.sum(np.where(my, ry * ry / np.where(my, dyg, 1.0), 0.0)))
 
 
-def pcg(levels, fx, fy, p=None, tol=1e-8, max_iters=500, nu1=2, nu2=2, omega=0.7, x0=None):
+def pcg(levels, fx, fy, p=None, tol=1e-8, max_iters=500, nu1=2, nu2=2, omega=0.7, x0=None, variants=None):
     """Flexible conjugate gradients on A x = -b (A = -M SPD, b = f - G p),
     preconditioned by one V-cycle per iteration, in FP64.  Stops when the
     velocity energy residual E_v = sqrt(N_v / N_f) of Sec. 6.4 is <= tol.
@@ -198,8 +201,18 @@ def pcg(levels, fx, fy, p=None, tol=1e-8, max_iters=500, nu1=2, nu2=2, omega=0.7
     recomputed; if it is still above tol (rounding drift at high viscosity
     contrast) CG restarts from x with it, within the same iteration budget.
     Returns (vx, vy, history): history[0] is the initial E_v and one entry
-    follows per iteration (the last one the true E_v)."""
+    follows per iteration (the last one the true E_v).  ``variants``: keyword
+    arguments of ``vcycle_general`` (smoother variants) for the preconditioner."""
     L = levels[0]
+
+    def vcycle(levels, l, vx, vy, bx, by, nu1, nu2, omega):
+        if variants is None:
+            return _vcycle_natural(levels, l, vx, vy, bx, by, nu1, nu2, omega)
+        Lv = levels[l]
+        x = SP.pack(Lv.nx, Lv.ny, vx, vy)
+        c = -SP.pack(Lv.nx, Lv.ny, bx, by)
+        return SP.unpack(Lv.nx, Lv.ny, vcycle_general(levels, l, x, c, nu1, nu2, omega, **variants))
+
     bx, by = S.rhs(L, fx, fy, p)
     dxg, dyg = S.diag(L)
     Nf = _masked_energy(fx, fy, dxg, dyg)

@@ -33,7 +33,10 @@ class SmoothOpts(C.Structure):
 
 
 class MgOpts(C.Structure):
-    _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("omega", C.c_double), ("coarsest", C.c_int)]
+    _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("omega", C.c_double), ("coarsest", C.c_int),
+                ("fine_k", C.c_int), ("fine_halo", C.c_int), ("coarse_smoother", C.c_int), ("coarse_tile", C.c_int),
+                ("coarse_k", C.c_int), ("coarse_halo", C.c_int), ("sweep_growth", C.c_double),
+                ("max_levels", C.c_int)]
 
 
 class Report(C.Structure):
@@ -81,6 +84,7 @@ _SIGS = {
     "stk_mg_opts_default": ([C.POINTER(MgOpts)], None),
     "stk_mg_create": ([_P, C.POINTER(_P), _G, _P, _P, C.POINTER(MgOpts)], _I),
     "stk_mg_destroy": ([_P], _I),
+    "stk_mg_bind": ([_P, _P, _I], _I),
     "stk_mg_info": ([_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(C.c_size_t)], _I),
     "stk_mg_footprint": ([_G, C.POINTER(MgOpts), _I, C.POINTER(C.c_size_t)], _I),
     "stk_mg_vcycle": ([_P, _I, _P, _P, _P, _P], _I),

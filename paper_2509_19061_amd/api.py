@@ -193,10 +193,16 @@ def ras_shifts(seed, n_outer, tile_x, tile_y):
 
 # ------------------------------------------------------------------ multigrid --
 
-def mg_opts(nu1=2, nu2=2, omega=0.7, coarsest=8):
+def mg_opts(nu1=2, nu2=2, omega=0.7, coarsest=8, fine_k=0, fine_halo=-1, coarse_smoother=0, coarse_tile=32,
+            coarse_k=4, coarse_halo=0, sweep_growth=1.0, max_levels=0):
+    """stk_mg_opts; coarse_smoother 'jacobi' / 'ras' (or 0 / 1)."""
     o = MgOpts()
     L.lib.stk_mg_opts_default(C.byref(o))
     o.nu1, o.nu2, o.omega, o.coarsest = int(nu1), int(nu2), float(omega), int(coarsest)
+    o.fine_k, o.fine_halo = int(fine_k), int(fine_halo)
+    o.coarse_smoother = {"jacobi": 0, "ras": 1}.get(coarse_smoother, coarse_smoother)
+    o.coarse_tile, o.coarse_k, o.coarse_halo = int(coarse_tile), int(coarse_k), int(coarse_halo)
+    o.sweep_growth, o.max_levels = float(sweep_growth), int(max_levels)
     return o
 
 
@@ -231,6 +237,14 @@ class MG:
         lv, cn, b = C.c_int(), C.c_int(), C.c_size_t()
         check(L.lib.stk_mg_info(self.handle, C.byref(lv), C.byref(cn), C.byref(b)))
         return dict(levels=lv.value, coarse_unknowns=cn.value, bytes=b.value)
+
+    def bind(self, ctx, mode="f64"):
+        """Move the handle to context ``ctx`` (same device), with the buffers of
+        ``mode`` built first on the old context's stream."""
+        check(L.lib.stk_mg_bind(self.handle, ctx.handle, _mode(mode)))
+        self.ctx._mgs.discard(self)
+        self.ctx = ctx
+        ctx._mgs.add(self)
 
     def vcycle(self, dt, vx, vy, bx, by):
         dt = dtype_code(dt)

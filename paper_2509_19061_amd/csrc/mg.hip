@@ -303,9 +303,14 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P, 
     P->crs.assign(maxl, Batch{});
     P->cjobs.assign(maxl, nullptr);
     P->ncj.assign(maxl, 0);
+    P->fine_t.assign(maxl, Batch{});
+    P->relax.assign(maxl, Batch{});
+    P->relax_t.assign(maxl, Batch{});
+    const stk_mg_opts& o0 = mgs[0]->o;
+    const bool cras = o0.coarse_smoother == 1;
     for (int d = 0; d < maxl; ++d) {
-        std::vector<LevelJob<T>> jobs;
-        std::vector<int> pf{0}, pc{0}, pr{0};
+        std::vector<LevelJob<T>> jobs, rj;
+        std::vector<int> pf{0}, pc{0}, pr{0}, pt{0}, rpf{0}, rpt{0};
         std::vector<CoarseJob<T>> cj;
         for (int q = 0; q < n; ++q) {
             const stk_mg* m = mgs[q];
@@ -315,11 +320,24 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P, 
                 pf.push_back(pf.back() + blocks_of(m->L[d].nx, m->L[d].ny));
                 pr.push_back(pr.back() + rows::workgroups(m->L[d].nx, m->L[d].ny));
                 pc.push_back(pc.back() + blocks_of(m->L[d + 1].nx, m->L[d + 1].ny));
+                pt.push_back(pt.back() + mg_ras_tiles(m->L[d].nx, m->L[d].ny, o0.coarse_tile));
+            } else if (d == nl - 1 && m->relaxed) {  // relaxed, not solved
+                rj.push_back(level_job<T>(m, d, t));
+                rpf.push_back(rpf.back() + blocks_of(m->L[d].nx, m->L[d].ny));
+                rpt.push_back(rpt.back() + mg_ras_tiles(m->L[d].nx, m->L[d].ny, o0.coarse_tile));
             } else if (d == nl - 1) {
                 const MgLevel& L = m->L[d];
                 cj.push_back(CoarseJob<T>{m->cn, m->cmap, m->cainv, (const T*)L.b[t].x, (const T*)L.b[t].y,
                                           (T*)L.v[t].x, (T*)L.v[t].y});
             }
+        }
+        if (!rj.empty()) {
+            const void *dj = nullptr, *dpf = nullptr, *dpt = nullptr;
+            STK_TRY(upload(P, rj, &dj, s));
+            STK_TRY(upload(P, rpf, &dpf, s));
+            STK_TRY(upload(P, rpt, &dpt, s));
+            P->relax[d] = Batch{dj, (const int*)dpf, (int)rj.size(), rpf.back()};
+            P->relax_t[d] = Batch{dj, (const int*)dpt, (int)rj.size(), rpt.back()};
         }
         if (!jobs.empty()) {
             const void* dj = nullptr;
@@ -329,6 +347,11 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P, 
             STK_TRY(upload(P, pc, &dpc, s));
             P->fine[d] = Batch{dj, (const int*)dpf, (int)jobs.size(), pf.back()};
             P->crs[d] = Batch{dj, (const int*)dpc, (int)jobs.size(), pc.back()};
+            if (d >= 1 && cras) {
+                const void* dpt = nullptr;
+                STK_TRY(upload(P, pt, &dpt, s));
+                P->fine_t[d] = Batch{dj, (const int*)dpt, (int)jobs.size(), pt.back()};
+            }
             if (d == 0) {  // the finest level is matrix-free: row-streaming smoothing and residual
                 const void* dpr = nullptr;
                 STK_TRY(upload(P, pr, &dpr, s));
@@ -469,13 +492,13 @@ int make_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT** out, bool 
 
 // ---- the batched V-cycle on the level-0 binding (v = Z slot, b = R slot)
 // Launch shape of the finest-level RAS smoothing for k sweeps (cached per k).
-static const PlanT::RasK* ras_shape(stk_ctx* ctx, const PlanT& P, int kt, stk_dtype dt) {
+static const PlanT::RasK* ras_shape(stk_ctx* ctx, const PlanT& P, int kt, int h, stk_dtype dt) {
     for (const PlanT::RasK& r : P.ras_k)
-        if (r.kt == kt) return r.ok ? &r : nullptr;
-    PlanT::RasK r{kt, false, RasShape{}, nullptr};
+        if (r.kt == kt && r.h == h) return r.ok ? &r : nullptr;
+    PlanT::RasK r{kt, h, false, RasShape{}, nullptr};
     std::vector<int> pre, ntx;
     if (!P.l0nx.empty())
-        ras_batch_shape(ctx, dt, P.l0nx.data(), P.l0ny.data(), P.l0ld.data(), (int)P.l0nx.size(), RAS_TILE, kt, kt,
+        ras_batch_shape(ctx, dt, P.l0nx.data(), P.l0ny.data(), P.l0ld.data(), (int)P.l0nx.size(), RAS_TILE, h, kt,
                         &r.shape, &pre, &ntx, &r.ok);
     if (r.ok) {
         void* d = nullptr;
@@ -500,43 +523,103 @@ static int smooth_stage(stk_ctx* ctx, const Batch& F, const stk_mg_opts& o, int 
     if (nu & 1) STK_TRY(mg_copy_wv<T>(ctx, F));
     return STK_OK;
 }
+
+// nu sweeps of a coarse level's smoother, v -> v: Jacobi, or (the mixed
+// smoother) RAS outer iterations of min(coarse_k, sweeps left) sweeps.
+template <typename T>
+static int coarse_stage(stk_ctx* ctx, const Batch& F, const Batch& Ft, const stk_mg_opts& o, int nu) {
+    if (o.coarse_smoother != 1) return smooth_stage<T>(ctx, F, o, nu);
+    int left = nu, q = 0;
+    for (; left > 0; ++q) {
+        const int kt = std::min(o.coarse_k, left);
+        STK_TRY(mg_ras<T>(ctx, Ft, o.coarse_tile, o.coarse_halo, kt, o.omega, q & 1));
+        left -= kt;
+    }
+    if (q & 1) STK_TRY(mg_copy_wv<T>(ctx, F));
+    return STK_OK;
+}
+
+// The finest level's smoothing stage of nu sweeps as RAS outer iterations of
+// min(k, sweeps left) sweeps each (k = fine_k, or nu), overlap fine_halo (or
+// the iteration's sweep count: Jacobi exactly).  from_w: the iterate starts
+// in w (post-smoothing) and must end in v; else starts in v and ends in w.
+// Returns false (nothing launched) when a launch shape does not fit.
+template <typename T>
+static int fine_ras_stage(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o, int nu, bool from_w, bool* done) {
+    const stk_dtype dt = sizeof(T) == 8 ? STK_F64 : STK_F32;
+    *done = false;
+    const int k = o.fine_k > 0 ? std::min(o.fine_k, nu) : nu;
+    std::vector<const PlanT::RasK*> sh;
+    for (int left = nu; left > 0; left -= std::min(k, left)) {
+        const int kt = std::min(k, left);
+        const PlanT::RasK* r = ras_shape(ctx, P, kt, o.fine_halo < 0 ? kt : o.fine_halo, dt);
+        if (!r) return STK_OK;
+        sh.push_back(r);
+    }
+    for (size_t q = 0; q < sh.size(); ++q) {
+        const int jb = (q & 1) ^ (from_w ? 1 : 0);  // 0: v -> w, 1: w -> v
+        STK_TRY(ras_batch_launch(ctx, dt, sh[q]->shape, P.ras_jobs[jb], sh[q]->pre, P.fine0w.n, o.omega));
+    }
+    // an even count ends where it started: move the iterate to its side
+    if (!(sh.size() & 1)) STK_TRY(mg_copy_wv<T>(ctx, from_w ? P.fine[0] : P.fine0w));
+    *done = true;
+    return STK_OK;
+}
+
 template <typename T>
 static int vcycle(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o) {
-    // Finest level: pre-smoothing v -> w and post-smoothing w -> v as one RAS
-    // outer iteration each (the iterate is in w in between), when the streaming
-    // kernel takes the instances; else Jacobi sweeps.
-    const stk_dtype dt = sizeof(T) == 8 ? STK_F64 : STK_F32;
-    const PlanT::RasK* pre_s = nullptr;
-    const PlanT::RasK* post_s = nullptr;
-    if (P.ras_jobs[0] && o.nu1 >= 1 && o.nu2 >= 1) {
-        pre_s = ras_shape(ctx, P, o.nu1, dt);
-        post_s = ras_shape(ctx, P, o.nu2, dt);
+    // Finest level: pre-smoothing v -> w and post-smoothing w -> v as RAS outer
+    // iterations (the iterate is in w in between), when the streaming kernel
+    // takes the instances; else Jacobi sweeps (exactly the same values when
+    // the overlap is the default).
+    const bool paper_fine = o.fine_halo >= 0 || o.fine_k > 0;  // a smoother other than Jacobi
+    bool ras0 = P.ras_jobs[0] && o.nu1 >= 1 && o.nu2 >= 1;
+    if (ras0) {  // both stages must fit, checked before anything is launched
+        const stk_dtype dt = sizeof(T) == 8 ? STK_F64 : STK_F32;
+        for (int nu : {o.nu1, o.nu2}) {
+            const int k = o.fine_k > 0 ? std::min(o.fine_k, nu) : nu;
+            for (int left = nu; left > 0 && ras0; left -= std::min(k, left)) {
+                const int kt = std::min(k, left);
+                ras0 = ras_shape(ctx, P, kt, o.fine_halo < 0 ? kt : o.fine_halo, dt) != nullptr;
+            }
+        }
     }
-    const bool ras0 = pre_s && post_s;
+    if (paper_fine && !ras0 && P.fine[0].n)
+        return set_error(STK_EUNSUPPORTED, "the finest-level RAS smoother does not fit these instances");
     STK_TRY(mg_coarse<T>(ctx, P.cjobs[0], P.ncj[0], P.maxcn));
     for (int d = 0; d < P.depth; ++d) {
         const Batch& F = P.fine[d];
         if (!F.n) break;
+        const int nu1 = level_sweeps(o.nu1, o.sweep_growth, d);
         if (d == 0 && ras0) {
-            STK_TRY(ras_batch_launch(ctx, dt, pre_s->shape, P.ras_jobs[0], pre_s->pre, P.fine0w.n, o.omega));
+            bool done = false;
+            STK_TRY(fine_ras_stage<T>(ctx, P, o, nu1, false, &done));
             STK_TRY(mg_residual<T>(ctx, P.fine0w));
         } else {
-            STK_TRY(smooth_stage<T>(ctx, F, o, o.nu1));
+            STK_TRY(d == 0 ? smooth_stage<T>(ctx, F, o, nu1) : coarse_stage<T>(ctx, F, P.fine_t[d], o, nu1));
             STK_TRY(mg_residual<T>(ctx, F));
         }
         STK_TRY(mg_zero_coarse<T>(ctx, P.crs[d]));
         STK_TRY(mg_restrict<T>(ctx, P.crs[d]));
-        if (d + 1 < (int)P.cjobs.size()) STK_TRY(mg_coarse<T>(ctx, P.cjobs[d + 1], P.ncj[d + 1], P.maxcn));
+        if (d + 1 < (int)P.cjobs.size()) {
+            STK_TRY(mg_coarse<T>(ctx, P.cjobs[d + 1], P.ncj[d + 1], P.maxcn));
+            if (P.relax[d + 1].n) {  // truncated hierarchies: the last level relaxed from 0
+                const int nr = level_sweeps(o.nu1, o.sweep_growth, d + 1) + level_sweeps(o.nu2, o.sweep_growth, d + 1);
+                STK_TRY(coarse_stage<T>(ctx, P.relax[d + 1], P.relax_t[d + 1], o, nr));
+            }
+        }
     }
     for (int d = P.depth - 1; d >= 0; --d) {
         const Batch& F = P.fine[d];
         if (!F.n) continue;
+        const int nu2 = level_sweeps(o.nu2, o.sweep_growth, d);
         if (d == 0 && ras0) {
             STK_TRY(mg_prolong<T>(ctx, P.fine0w));
-            STK_TRY(ras_batch_launch(ctx, dt, post_s->shape, P.ras_jobs[1], post_s->pre, P.fine0w.n, o.omega));
+            bool done = false;
+            STK_TRY(fine_ras_stage<T>(ctx, P, o, nu2, true, &done));
         } else {
             STK_TRY(mg_prolong<T>(ctx, F));
-            STK_TRY(smooth_stage<T>(ctx, F, o, o.nu2));
+            STK_TRY(d == 0 ? smooth_stage<T>(ctx, F, o, nu2) : coarse_stage<T>(ctx, F, P.fine_t[d], o, nu2));
         }
     }
     return STK_OK;
@@ -573,6 +656,17 @@ int copy_vel_in(stk_mg* m, const void* sx, const void* sy, int64_t sld, void* dx
     return STK_OK;
 }
 
+int level_sweeps(int nu, double growth, int l) {
+    const double v = std::floor((double)nu * std::pow(growth, (double)l) + 0.5);
+    return v > 1e5 ? 100000 : (int)v;
+}
+
+bool same_smoothing(const stk_mg_opts& a, const stk_mg_opts& b) {
+    return a.nu1 == b.nu1 && a.nu2 == b.nu2 && a.omega == b.omega && a.fine_k == b.fine_k &&
+           a.fine_halo == b.fine_halo && a.coarse_smoother == b.coarse_smoother && a.coarse_tile == b.coarse_tile &&
+           a.coarse_k == b.coarse_k && a.coarse_halo == b.coarse_halo && a.sweep_growth == b.sweep_growth;
+}
+
 }  // namespace stk
 
 // ============================================================== C ABI ====
@@ -584,6 +678,14 @@ void stk_mg_opts_default(stk_mg_opts* o) {
     o->nu2 = 2;
     o->omega = 0.7;
     o->coarsest = 8;
+    o->fine_k = 0;
+    o->fine_halo = -1;
+    o->coarse_smoother = 0;
+    o->coarse_tile = 32;
+    o->coarse_k = 4;
+    o->coarse_halo = 0;
+    o->sweep_growth = 1.0;
+    o->max_levels = 0;
 }
 
 static int check_mg_opts(const stk_mg_opts& o) {
@@ -591,6 +693,16 @@ static int check_mg_opts(const stk_mg_opts& o) {
         return set_error(STK_EINVAL, "nu1, nu2 must be in [0, 64] with nu1 + nu2 >= 1");
     if (!(o.omega > 0.0 && o.omega < 2.0)) return set_error(STK_EINVAL, "omega must be in (0, 2)");
     if (o.coarsest < 2) return set_error(STK_EINVAL, "coarsest must be >= 2");
+    if (o.fine_k < 0 || o.fine_k > 16) return set_error(STK_EINVAL, "fine_k must be in [0, 16]");
+    if ((o.fine_k > 0 || o.fine_halo >= 0) && std::max(o.nu1, o.nu2) > 16 && o.fine_k == 0)
+        return set_error(STK_EINVAL, "a finest-level RAS stage takes at most 16 sweeps per outer iteration");
+    if (o.fine_halo < -1 || o.fine_halo > 15) return set_error(STK_EINVAL, "fine_halo must be in [-1, 15]");
+    if (o.coarse_smoother != 0 && o.coarse_smoother != 1) return set_error(STK_EINVAL, "coarse_smoother must be 0 or 1");
+    if (o.coarse_tile < 1 || o.coarse_k < 1 || o.coarse_halo < 0)
+        return set_error(STK_EINVAL, "coarse_tile, coarse_k must be >= 1 and coarse_halo >= 0");
+    if (!(o.sweep_growth >= 1.0 && o.sweep_growth <= 16.0))
+        return set_error(STK_EINVAL, "sweep_growth must be in [1, 16]");
+    if (o.max_levels < 0 || o.max_levels == 1) return set_error(STK_EINVAL, "max_levels must be 0 or >= 2");
     return STK_OK;
 }
 
@@ -614,6 +726,10 @@ int stk_mg_footprint(const stk_grid* g, const stk_mg_opts* opts, int mode, size_
         const size_t w32 = lvl == 0 ? 2 + 4 + 4 : NPLANES + 8;
         b += cnt * (w64 * 8 + (f32 ? w32 * 4 : 0));
         if (std::min(nx, ny) <= o.coarsest || (nx & 1) || (ny & 1)) break;
+        if (o.max_levels > 0 && lvl + 1 == o.max_levels) {  // truncated: relaxed, no dense inverse
+            *bytes = b;
+            return STK_OK;
+        }
         nx /= 2;
         ny /= 2;
         ++lvl;
@@ -653,6 +769,10 @@ int stk_mg_create(stk_ctx* ctx, stk_mg** out, const stk_grid* g, const double* e
         L.dy = dy;
         m->L.push_back(L);
         if (std::min(nx, ny) <= o.coarsest || (nx & 1) || (ny & 1)) break;
+        if (o.max_levels > 0 && (int)m->L.size() == o.max_levels) {  // cut here: relax the last level
+            m->relaxed = true;
+            break;
+        }
         nx /= 2;
         ny /= 2;
         dx *= 2;
@@ -685,7 +805,10 @@ int stk_mg_create(stk_ctx* ctx, stk_mg** out, const stk_grid* g, const double* e
             if (rc != STK_OK) return fail(rc);
         }
     }
-    int rc = build_coarse(m);
+    if (o.coarse_smoother == 1 && mg_ras_lds_bytes(o.coarse_tile, o.coarse_halo, 8) > (size_t)ctx->lds_max)
+        return fail(set_error(STK_EUNSUPPORTED, "coarse RAS tile %d with overlap %d exceeds the LDS of a workgroup",
+                              o.coarse_tile, o.coarse_halo));
+    int rc = m->relaxed ? STK_OK : build_coarse(m);
     if (rc != STK_OK) return fail(rc);
     *out = m;
     return STK_OK;
@@ -703,6 +826,21 @@ int stk_mg_destroy(stk_mg* m) {
         }
     for (void* p : m->mem) (void)hipFree(p);
     delete m;
+    return STK_OK;
+}
+
+int stk_mg_bind(stk_mg* m, stk_ctx* ctx, int mode) {
+    if (!m || !ctx) return set_error(STK_EINVAL, "mg and ctx must be non-NULL");
+    if (m->busy) return set_error(STK_EINVAL, "mg handle is solving in a batch");
+    if (ctx->device != m->ctx->device)
+        return set_error(STK_EINVAL, "ctx is on device %d, the handle on device %d", ctx->device, m->ctx->device);
+    if (mode != STK_SOLVE_F64 && mode != STK_SOLVE_F32_REFINED) return set_error(STK_EINVAL, "unknown mode %d", mode);
+    STK_TRY(use_device(m->ctx));
+    // the buffers of `mode` are built on the old context's stream, which is drained
+    STK_TRY(ensure_dtype(m, 0));
+    if (mode == STK_SOLVE_F32_REFINED) STK_TRY(ensure_dtype(m, 1));
+    STK_HIP(hipStreamSynchronize(m->ctx->stream));
+    m->ctx = ctx;
     return STK_OK;
 }
 

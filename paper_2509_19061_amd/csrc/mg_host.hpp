@@ -44,10 +44,14 @@ struct PlanT {
     // the launch shape per k (built on first use)
     const void* ras_jobs[2] = {nullptr, nullptr};
     Batch fine0w;
+    // coarse levels: the same LevelJob arrays with a prefix over RAS tiles
+    // (coarse RAS smoothing); relaxed coarsest levels of truncated hierarchies
+    // (block and tile prefixes)
+    std::vector<Batch> fine_t, relax, relax_t;
     std::vector<int> l0nx, l0ny;
     std::vector<int64_t> l0ld;
     struct RasK {
-        int kt;
+        int kt, h;
         bool ok;
         RasShape shape;
         const int* pre;
@@ -101,6 +105,7 @@ struct stk_mg {
     stk_mg_opts o{};
     std::vector<stk::MgLevel> L;
     int64_t user_ld = 0;
+    bool relaxed = false;  // truncated by max_levels: the last level is relaxed, not solved
     int cn = 0;
     int* cmap = nullptr;
     double* cainv = nullptr;

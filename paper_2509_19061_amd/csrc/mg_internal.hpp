@@ -158,5 +158,15 @@ int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums);
 int fcg_apply_pq(stk_ctx* ctx, const Batch& apply, const Batch& red, const FcgState* st, double* part,
                  double* sums);
 template <typename T> int mg_copy_wv(stk_ctx* ctx, const Batch& b);
+// Coarse-level RAS outer iteration (mg_ras.hip): kt sweeps per tile of the
+// stored stencil, tiles `tile` cells cut at multiples of it, overlap h; b's
+// prefix counts tiles (mg_ras_tiles per instance); dir 0 v -> w, 1 w -> v.
+template <typename T> int mg_ras(stk_ctx* ctx, const Batch& b, int tile, int h, int kt, double omega, int dir);
+size_t mg_ras_lds_bytes(int tile, int h, size_t es);
+int mg_ras_tiles(int nx, int ny, int tile);
+// Sweeps of level l: floor(nu * growth^l + 1/2).
+int level_sweeps(int nu, double growth, int l);
+// Two handles smooth alike (may share a batch).
+bool same_smoothing(const stk_mg_opts& a, const stk_mg_opts& b);
 
 }  // namespace stk

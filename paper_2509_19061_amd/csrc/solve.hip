@@ -268,9 +268,9 @@ int stk_batch_add(stk_batch* b, stk_mg* m, double* vx, double* vy, const double*
     if (!vx || !vy || !fx || !fy) return set_error(STK_EINVAL, "vx, vy, fx, fy must be non-NULL");
     if (!(tol > 0.0) || max_iters < 0) return set_error(STK_EINVAL, "tol must be > 0 and max_iters >= 0");
     if (m->busy) return set_error(STK_EINVAL, "mg handle is already solving in a batch");
-    if (b->have_opts && (m->o.nu1 != b->o.nu1 || m->o.nu2 != b->o.nu2 || m->o.omega != b->o.omega))
-        return set_error(STK_EINVAL, "mg handle's nu1, nu2, omega differ from the batch's (%d, %d, %g)", b->o.nu1,
-                         b->o.nu2, b->o.omega);
+    if (b->have_opts && !same_smoothing(m->o, b->o))
+        return set_error(STK_EINVAL, "mg handle's smoothing options differ from the batch's (nu %d, %d, omega %g)",
+                         b->o.nu1, b->o.nu2, b->o.omega);
     int id = -1;
     for (int i = 0; i < (int)b->slots.size() && id < 0; ++i)
         if (b->slots[i].state == SL_FREE) id = i;
