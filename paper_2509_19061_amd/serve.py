@@ -1,14 +1,19 @@
 """Serving loop: solve requests arrive over time (Poisson), are admitted by
 their HBM footprint under a device budget, and are solved by continuous
 batching (``api.Batch``): requests that arrive while others are on the GPU
-join the batch at the next step as soon as a slot and memory are free, and
-every step advances all solves in flight with one launch per (level, kernel).
+join the batch as soon as a slot and memory are free, and every step
+advances all solves in flight with one launch per (level, kernel).
 
-Each request keeps its multigrid hierarchy on the device from admission to
-completion.  Latency = completion time - arrival time on the host clock.
-The loop itself (``Server``) is independent of the GPU: it talks to a backend
-with ``footprint / admit / step / release``, which the tests replace by a CPU
-fake to check admission and scheduling.
+Admission does not stall the solves in flight: an admitted request's fields
+are uploaded and its multigrid hierarchy is built by a setup thread on a
+stream of its own (``GpuBackend.prepare``), while the loop keeps stepping the
+batch; the request joins the batch at the first step after its setup is done.
+Each request keeps its hierarchy on the device from admission to completion.
+Latency = completion time - arrival time on the host clock.  The loop itself
+(``Server``) is independent of the GPU: it talks to a backend with
+``footprint / prepare / ready / join / step / release`` (or a synchronous
+``admit``), which the tests replace by CPU fakes to check admission and
+scheduling.
 """
 from __future__ import annotations
 
@@ -111,14 +116,17 @@ class Server:
         res = ServeResult()
         queue = collections.deque(sorted(requests, key=lambda r: r.arrival))
         pending = collections.deque()
-        inflight = {}  # slot -> (request, handle, bytes, admitted)
+        preparing = collections.deque()  # (request, token, bytes, in flight when admitted), FIFO
+        inflight = {}  # slot -> (request, handle, bytes, joined, in flight when admitted)
         used = 0
+        asynchronous = hasattr(self.b, "prepare")
         t0 = self.clock()
-        while queue or pending or inflight:
+        while queue or pending or preparing or inflight:
             now = self.clock() - t0
             while queue and queue[0].arrival <= now:
                 pending.append(queue.popleft())
-            while pending and len(inflight) < self.max_slots:
+            # admission: memory and a slot are reserved now; the setup runs beside the batch
+            while pending and len(inflight) + len(preparing) < self.max_slots:
                 r = pending[0]
                 need = self.b.footprint(r)
                 if need > self.budget:  # can never fit
@@ -127,14 +135,22 @@ class Server:
                 if used + need > self.budget:
                     break
                 pending.popleft()
-                busy = len(inflight)
-                handle, slot = self.b.admit(r)
+                busy = len(inflight) + len(preparing)
                 used += need
                 res.peak_bytes = max(res.peak_bytes, used)
+                if asynchronous:
+                    preparing.append((r, self.b.prepare(r), need, busy))
+                else:
+                    handle, slot = self.b.admit(r)
+                    inflight[slot] = (r, handle, need, self.clock() - t0, busy)
+            # requests whose setup is done join the batch (in admission order)
+            while preparing and (self.b.ready(preparing[0][1]) or not inflight):
+                r, token, need, busy = preparing.popleft()
+                handle, slot = self.b.join(token)  # waits for the setup if the batch is idle
                 inflight[slot] = (r, handle, need, self.clock() - t0, busy)
             res.max_inflight = max(res.max_inflight, len(inflight))
             if not inflight:
-                if queue:
+                if queue and not preparing:
                     self.sleep(max(0.0, queue[0].arrival - (self.clock() - t0)))
                 continue
             finished = self.b.step(self.iters)
@@ -151,10 +167,15 @@ class Server:
 
 
 class GpuBackend:
-    """Requests solved on the GPU: admission uploads the request's fields,
-    builds its hierarchy and adds it to one ``api.Batch``."""
+    """Requests solved on the GPU.  ``prepare`` hands the request to a setup
+    thread, which uploads its fields and builds its hierarchy on a setup
+    stream and context of its own, then moves the hierarchy to the serving
+    context (``MG.bind``, which drains the setup stream); ``join`` adds it to
+    the one ``api.Batch`` that the serving loop steps."""
 
     def __init__(self, ctx, mode, max_slots, tol=1e-8, max_iters=3000, keep_results=False):
+        from concurrent.futures import ThreadPoolExecutor
+
         import torch
 
         from . import api, fields
@@ -162,6 +183,10 @@ class GpuBackend:
         self.ctx, self.mode, self.tol, self.max_iters = ctx, mode, tol, max_iters
         self.batch = api.Batch(ctx, mode, max_slots)
         self.results = {} if keep_results else None  # rid -> (vx, vy) on the host
+        self.setup_stream = torch.cuda.Stream(device=ctx.device)  # default priority
+        self.setup_ctx = api.Context(ctx.device, stream=self.setup_stream)
+        self.serve_stream = torch.cuda.current_stream(ctx.device)
+        self.pool = ThreadPoolExecutor(max_workers=1)
 
     def footprint(self, r):
         p = r.payload
@@ -169,7 +194,31 @@ class GpuBackend:
         g = self.api.Grid(p.nx, p.ny, ld, p.dx, p.dy)
         return self.api.mg_footprint(g, self.mode) + 6 * (p.ny + 1) * ld * 8  # + eta_c, eta_n, fx, fy, vx, vy
 
+    def _setup(self, r):
+        torch = self.torch
+        with torch.cuda.stream(self.setup_stream):
+            dp = self.fields.DeviceProblem(r.payload, torch.float64)
+            vx, vy = dp.velocity()
+        mg = self.api.MG(self.setup_ctx, dp.grid, dp.eta_c, dp.eta_n)
+        mg.bind(self.ctx, self.mode)  # the setup stream is drained here
+        for t in (dp.eta_c, dp.eta_n, dp.fx, dp.fy, vx, vy):
+            t.record_stream(self.serve_stream)  # used by the serving stream from now on
+        return (r.rid, dp, mg, vx, vy)
+
+    def prepare(self, r):
+        return self.pool.submit(self._setup, r)
+
+    def ready(self, token):
+        return token.done()
+
+    def join(self, token):
+        handle = token.result()
+        rid, dp, mg, vx, vy = handle
+        slot = self.batch.add(mg, vx, vy, None, dp.fx, dp.fy, tol=self.tol, max_iters=self.max_iters)
+        return handle, slot
+
     def admit(self, r):
+        """Synchronous admission (setup on the serving stream)."""
         dp = self.fields.DeviceProblem(r.payload, self.torch.float64)
         mg = self.api.MG(self.ctx, dp.grid, dp.eta_c, dp.eta_n)
         vx, vy = dp.velocity()
@@ -186,4 +235,6 @@ class GpuBackend:
         mg.close()
 
     def close(self):
+        self.pool.shutdown(wait=True)
         self.batch.close()
+        self.setup_ctx.close()

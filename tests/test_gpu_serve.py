@@ -113,3 +113,34 @@ def test_batch_errors(ctx):
     b2.close()
     for h in (m, m2, m3):
         h.close()
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32_refined"])
+def test_hierarchy_built_on_a_setup_stream_and_bound_solves_the_same(ctx, mode):
+    """A hierarchy built on another context (its own stream, as the serving
+    loop's setup thread does) and moved with stk_mg_bind gives the bits of one
+    built on the solving context; a handle in a batch cannot be moved."""
+    from paper_2509_19061_amd import api, fields
+    p = problems()[1]
+    rx, ry, rrep = alone(ctx, p, mode)
+    s2 = torch.cuda.Stream()
+    ctx2 = api.Context(0, stream=s2)
+    with torch.cuda.stream(s2):
+        dp = fields.DeviceProblem(p, torch.float64)
+        vx, vy = dp.velocity()
+    m = api.MG(ctx2, dp.grid, dp.eta_c, dp.eta_n)
+    m.bind(ctx, mode)
+    torch.cuda.synchronize()
+    b = api.Batch(ctx, mode, 1)
+    b.add(m, vx, vy, None, dp.fx, dp.fy, tol=1e-8, max_iters=2000)
+    with pytest.raises(api.StkError) as e:
+        m.bind(ctx2, mode)
+    assert e.value.code == api.EINVAL
+    done = []
+    while not done:
+        done = b.step(4)
+    b.close()
+    assert done[0][1]["iterations"] == rrep["iterations"]
+    assert np.array_equal(dp.get_vx(vx), rx) and np.array_equal(dp.get_vy(vy), ry)
+    m.close()
+    ctx2.close()

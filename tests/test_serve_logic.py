@@ -118,3 +118,46 @@ def test_poisson_arrivals_have_the_requested_rate():
     gaps = np.diff([0.0] + [r.arrival for r in reqs])
     assert gaps.mean() == pytest.approx(1 / 20.0, rel=0.05)
     assert all(r.arrival == 0.0 for r in serve.poisson_requests(5, float("inf"), [64], seed=4))
+
+
+class FakeAsyncBackend(FakeBackend):
+    """FakeBackend whose admission is asynchronous: a request's setup takes
+    `setup` seconds of clock from prepare() and only then can it join."""
+
+    def __init__(self, clock, dt=0.01, setup=0.05):
+        super().__init__(clock, dt)
+        self.setup = setup
+        self.step_times = []
+        self.joined = {}
+
+    def prepare(self, r):
+        return {"r": r, "ready_at": self.clock.t + self.setup}
+
+    def ready(self, token):
+        return self.clock.t >= token["ready_at"]
+
+    def join(self, token):
+        if self.clock.t < token["ready_at"]:  # the loop waits only when nothing else can run
+            self.clock.t = token["ready_at"]
+        self.joined[token["r"].rid] = self.clock.t
+        return self.admit(token["r"])
+
+    def step(self, iters):
+        self.step_times.append(self.clock.t)
+        return super().step(iters)
+
+
+def test_setup_of_an_admitted_request_does_not_stall_the_batch():
+    clk = FakeClock()
+    be = FakeAsyncBackend(clk, dt=0.01, setup=0.05)
+    reqs = [serve.Request(0, 0.0, 64 * 40, 0), serve.Request(1, 0.1, 64, 1), serve.Request(2, 0.1, 128, 2)]
+    res = serve.Server(be, 10 ** 9, iters_per_step=1, clock=clk, sleep=clk.sleep).run(reqs)
+    assert len(res.done) == 3
+    done = {d.rid: d for d in res.done}
+    # request 0 keeps stepping while 1 and 2 are being set up: steps between their arrival and their join
+    during = [t for t in be.step_times if 0.1 <= t < be.joined[1]]
+    assert len(during) >= 4, (be.joined, be.step_times[:20])
+    assert be.joined[1] >= 0.1 + 0.05 and be.joined[2] >= be.joined[1]
+    assert done[1].inflight_at_admission >= 1 and done[2].inflight_at_admission >= 1
+    # the first request had nothing to overlap with: its setup was waited for
+    assert be.joined[0] == pytest.approx(0.05)
