@@ -209,3 +209,94 @@ def random_shifts(n_outer: int, tile_x: int, tile_y: int, seed: int) -> np.ndarr
     s[:, 0] = rng.integers(0, tile_x, size=n_outer)
     s[:, 1] = rng.integers(0, tile_y, size=n_outer)
     return s
+
+
+# --------------------------------------------------------------------------
+# 3D problems (the paper's future-work extension): spherical sinkers in a
+# free-slip unit box, gravity along -z
+# --------------------------------------------------------------------------
+
+@dataclass
+class Problem3:
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    eta_c: np.ndarray   # (nz, ny, nx) cells
+    eta_xy: np.ndarray  # (nz, ny+1, nx+1) z-parallel edges
+    eta_xz: np.ndarray  # (nz+1, ny, nx+1) y-parallel edges
+    eta_yz: np.ndarray  # (nz+1, ny+1, nx) x-parallel edges
+    fx: np.ndarray = None  # (nz, ny, nx+1)
+    fy: np.ndarray = None  # (nz, ny+1, nx)
+    fz: np.ndarray = None  # (nz+1, ny, nx)
+    meta: dict = field(default_factory=dict)
+
+    def zeros_v(self):
+        nx, ny, nz = self.nx, self.ny, self.nz
+        return np.zeros((nz, ny, nx + 1)), np.zeros((nz, ny + 1, nx)), np.zeros((nz + 1, ny, nx))
+
+
+def edge_harmonic(eta_c: np.ndarray, axis: int) -> np.ndarray:
+    """Viscosity on the edges that run along array axis `axis` of the (z, y, x)
+    cell array (0: z-parallel, 1: y-parallel, 2: x-parallel edges): harmonic
+    mean of the 1, 2 or 4 cells that touch the edge.  Input construction only
+    (the workload's stated choice, as for the 2D nodes)."""
+    nz, ny, nx = eta_c.shape
+    inv = 1.0 / eta_c
+    # an edge parallel to `axis` sits between cells along the two other axes
+    shape = [nz + (axis != 0), ny + (axis != 1), nx + (axis != 2)]
+    s = np.zeros(shape)
+    n = np.zeros(shape)
+    others = [a for a in range(3) if a != axis]
+    for o0 in (0, 1):
+        for o1 in (0, 1):
+            sl = [slice(None)] * 3
+            for a, o in zip(others, (o0, o1)):
+                size = eta_c.shape[a]
+                sl[a] = slice(o, o + size)
+            s[tuple(sl)] += inv
+            n[tuple(sl)] += 1.0
+    return n / s
+
+
+def sinker_problem3d(nx: int, ny: int, nz: int, spheres, eta_in: float, eta_out: float, rho_in: float = 1.1,
+                     rho_out: float = 1.0, g: float = 1.0, meta: dict | None = None) -> Problem3:
+    """Spheres ``[(cx, cy, cz, r), ...]`` of viscosity eta_in and density rho_in
+    in a medium of eta_out, rho_out; fz = rho g at the vz faces (gravity -z)."""
+    dx, dy, dz = 1.0 / nx, 1.0 / ny, 1.0 / nz
+    xc = (np.arange(nx) + 0.5) * dx
+    yc = (np.arange(ny) + 0.5) * dy
+    zc = (np.arange(nz) + 0.5) * dz
+
+    def inside(x, y, z):
+        m = np.zeros((len(z), len(y), len(x)), bool)
+        for (cx, cy, cz, r) in spheres:
+            m |= ((x[None, None, :] - cx) ** 2 + (y[None, :, None] - cy) ** 2 + (z[:, None, None] - cz) ** 2) <= r * r
+        return m
+
+    eta_c = np.where(inside(xc, yc, zc), eta_in, eta_out).astype(np.float64)
+    rho = np.where(inside(xc, yc, np.arange(nz + 1) * dz), rho_in, rho_out)
+    return Problem3(nx, ny, nz, dx, dy, dz, eta_c, edge_harmonic(eta_c, 0), edge_harmonic(eta_c, 1),
+                    edge_harmonic(eta_c, 2), np.zeros((nz, ny, nx + 1)), np.zeros((nz, ny + 1, nx)),
+                    (rho * g).astype(np.float64), dict(meta or {}))
+
+
+def random_sinkers3d(n: int, count: int, seed: int, eta_in: float = 1e4, eta_out: float = 1.0,
+                     rmin: float = 0.05, rmax: float = 0.15) -> Problem3:
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.15, 0.85, size=(count, 3))
+    r = rng.uniform(rmin, rmax, size=count)
+    return sinker_problem3d(n, n, n, [(*map(float, c[q]), float(r[q])) for q in range(count)], eta_in, eta_out,
+                            meta=dict(workload="random_sinkers3d", n=n, count=count, seed=seed))
+
+
+def random_velocity3d(p: Problem3, seed: int, scale: float = 1.0):
+    """Random velocity state with the wall entries set to 0."""
+    rng = np.random.default_rng(seed)
+    vx, vy, vz = (rng.standard_normal(a.shape) * scale for a in p.zeros_v())
+    vx[:, :, 0] = vx[:, :, -1] = 0.0
+    vy[:, 0, :] = vy[:, -1, :] = 0.0
+    vz[0, :, :] = vz[-1, :, :] = 0.0
+    return vx, vy, vz
