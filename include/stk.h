@@ -453,6 +453,75 @@ int stk_uzawa_anderson(stk_mg* mg, const stk_grid* g, double* vx, double* vy, do
                        const double* eta_n, const double* fx, const double* fy, int depth,
                        const stk_uzawa_opts* opts, double* hist, stk_uzawa_report* rep);
 
+/* ----------------------------------------------------------------- 3D -- */
+
+/* The 3D extension (the paper's future work, Sec. 9): the staggered
+ * variable-viscosity operator in three dimensions, smoothed by damped Jacobi
+ * or by RAS-type temporal blocking of 3D tiles (Alg. 2 with snapshot
+ * semantics on T x T x T tiles: three space dimensions and the inner
+ * sweeps).  The paper gives only the 2D formulas; these follow them axis by
+ * axis:
+ *   cells (i,j,k) carry eta_c; vx(i,j,k) is the x-face at (i dx, (j+1/2) dy,
+ *   (k+1/2) dz), an unknown iff 1 <= i <= nx-1; vy, vz likewise along y, z;
+ *   the wall values are 0.  eta_xy lives on the z-parallel edges
+ *   (i dx, j dy, (k+1/2) dz), eta_xz on the y-parallel edges (i dx, (j+1/2) dy,
+ *   k dz), eta_yz on the x-parallel edges ((i+1/2) dx, j dy, k dz); shear
+ *   stresses vanish on boundary edges (free slip).
+ *   t_xx = 2 eta_c dvx/dx per cell (yy, zz alike); t_xy = eta_xy (dvx/dy +
+ *   dvy/dx) per interior z-parallel edge (xz, yz alike); (Mv)_x = dt_xx/dx +
+ *   dt_xy/dy + dt_xz/dz at the x-faces (y, z alike).
+ * Layout: every field is plane-major with one row stride ld and one plane
+ * stride lp (elements): element (i,j,k) at base[k*lp + j*ld + i].  Used
+ * extents (planes x rows x columns): vx nz x ny x (nx+1), vy nz x (ny+1) x nx,
+ * vz (nz+1) x ny x nx, eta_c nz x ny x nx, eta_xy nz x (ny+1) x (nx+1),
+ * eta_xz (nz+1) x ny x (nx+1), eta_yz (nz+1) x (ny+1) x nx.  All arrays are
+ * caller-owned DEVICE arrays of (nz+1) * lp elements of dtype dt.  The
+ * right-hand side b = (bx, by, bz) has the velocity layout (0 on walls). */
+typedef struct {
+    int nx, ny, nz;     /* cells, each >= 2 (nz + 1 <= 65535)                 */
+    int64_t ld, lp;     /* row stride >= nx + 1; plane stride >= (ny + 1) ld  */
+    double dx, dy, dz;  /* cell size, > 0                                     */
+} stk_grid3;
+
+typedef struct {
+    double omega;          /* damping in (0, 2) (default 0.7)                                    */
+    int tile;              /* RAS tile edge T in cells (default 8)                               */
+    int halo;              /* RAS overlap h >= 0; -1 (default) = k, which is Jacobi^k exactly    */
+    int k;                 /* RAS inner sweeps per outer iteration (default 2)                   */
+    const int32_t* shifts; /* HOST, 3 ints (x, y, z) per outer iteration; NULL: SplitMix64(seed),
+                              (z >> 32) mod T drawn x, y, z per outer iteration                  */
+    uint64_t seed;
+} stk_smooth3d_opts;
+
+void stk_smooth3d_opts_default(stk_smooth3d_opts* o);
+
+/* `sweeps` sweeps of damped Jacobi (STK_JACOBI_FUSED) or RAS-Jacobi
+ * (STK_RAS_JACOBI, the last outer iteration partial) on M v = b, in place.
+ * The RAS workgroup stages its tile grown by h plus a one-cell frozen ring in
+ * LDS (3 components, 2 buffers: 6 (T + 2h + 2)^3 words): STK_EUNSUPPORTED
+ * when that exceeds a workgroup's LDS.  Uses 6 fields of context scratch.
+ * Asynchronous. */
+int stk_smooth3d(stk_ctx* ctx, stk_dtype dt, const stk_grid3* g, void* vx, void* vy, void* vz, const void* eta_c,
+                 const void* eta_xy, const void* eta_xz, const void* eta_yz, const void* bx, const void* by,
+                 const void* bz, int sweeps, stk_variant variant, const stk_smooth3d_opts* opts);
+/* One 3D RAS outer iteration out of place with explicit shifts (outputs must
+ * not alias inputs; every velocity entry of the used extents is written, 0 on
+ * walls).  Asynchronous. */
+int stk_ras_outer3d(stk_ctx* ctx, stk_dtype dt, const stk_grid3* g, const void* vx, const void* vy, const void* vz,
+                    const void* eta_c, const void* eta_xy, const void* eta_xz, const void* eta_yz, const void* bx,
+                    const void* by, const void* bz, void* ox, void* oy, void* oz, double omega, int tile, int halo,
+                    int kt, int sx, int sy, int sz);
+/* r = b - M v on the unknowns, 0 on the walls.  Asynchronous. */
+int stk_residual3d(stk_ctx* ctx, stk_dtype dt, const stk_grid3* g, const void* vx, const void* vy, const void* vz,
+                   const void* eta_c, const void* eta_xy, const void* eta_xz, const void* eta_yz, const void* bx,
+                   const void* by, const void* bz, void* rx, void* ry, void* rz);
+/* Velocity energy norms (Sec. 6.4) with b = f: out = {N_v = sum r^2/d,
+ * N_f = sum f^2/d, E_v = sqrt(N_v/N_f)}, FP64 sums in a fixed order.  HOST
+ * out; synchronises. */
+int stk_energy_norm3d(stk_ctx* ctx, stk_dtype dt, const stk_grid3* g, const void* vx, const void* vy, const void* vz,
+                      const void* eta_c, const void* eta_xy, const void* eta_xz, const void* eta_yz, const void* fx,
+                      const void* fy, const void* fz, double out[3]);
+
 #ifdef __cplusplus
 }
 #endif

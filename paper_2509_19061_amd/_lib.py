@@ -44,6 +44,16 @@ class Report(C.Structure):
                 ("seconds", C.c_double)]
 
 
+class Grid3(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("ld", C.c_int64), ("lp", C.c_int64),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
+
+
+class Smooth3dOpts(C.Structure):
+    _fields_ = [("omega", C.c_double), ("tile", C.c_int), ("halo", C.c_int), ("k", C.c_int),
+                ("shifts", C.POINTER(C.c_int32)), ("seed", C.c_uint64)]
+
+
 class UzawaOpts(C.Structure):
     _fields_ = [("omega_p", C.c_double), ("vcycles", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int),
                 ("stages", C.c_int), ("stage_cycles", C.c_int), ("mode", C.c_int)]
@@ -81,6 +91,11 @@ _SIGS = {
     "stk_energy_norm": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, C.POINTER(C.c_double)], _I),
     "stk_energy_norm_noalloc": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _P], _I),
     "stk_stream_probe": ([_P, _I, _G, _P, _P, _P, _P, _P, _P, _P, _P], _I),
+    "stk_smooth3d_opts_default": ([C.POINTER(Smooth3dOpts)], None),
+    "stk_smooth3d": ([_P, _I, C.POINTER(Grid3)] + [_P] * 10 + [_I, _I, C.POINTER(Smooth3dOpts)], _I),
+    "stk_ras_outer3d": ([_P, _I, C.POINTER(Grid3)] + [_P] * 13 + [C.c_double, _I, _I, _I, _I, _I, _I], _I),
+    "stk_residual3d": ([_P, _I, C.POINTER(Grid3)] + [_P] * 13, _I),
+    "stk_energy_norm3d": ([_P, _I, C.POINTER(Grid3)] + [_P] * 10 + [C.POINTER(C.c_double)], _I),
     "stk_mg_opts_default": ([C.POINTER(MgOpts)], None),
     "stk_mg_create": ([_P, C.POINTER(_P), _G, _P, _P, C.POINTER(MgOpts)], _I),
     "stk_mg_destroy": ([_P], _I),

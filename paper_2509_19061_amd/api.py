@@ -19,7 +19,8 @@ from ._lib import (EHIP, EINVAL, ENOMEM, ENONFINITE, ENOTCONV, EUNSUPPORTED, F32
                    StkError, check)
 
 __all__ = ["Context", "Grid", "SmoothOpts", "StkError", "smooth", "ras_outer", "residual", "energy_norm", "ras_shifts",
-           "smooth_opts", "energy_norm_noalloc", "stream_probe", "F64", "F32", "JACOBI", "JACOBI_FUSED", "RAS_JACOBI", "RBGS", "VARIANTS", "OK", "EINVAL",
+           "smooth_opts", "energy_norm_noalloc", "stream_probe", "smooth3d", "ras_outer3d", "residual3d",
+           "energy_norm3d", "smooth3d_opts", "F64", "F32", "JACOBI", "JACOBI_FUSED", "RAS_JACOBI", "RBGS", "VARIANTS", "OK", "EINVAL",
            "ENOMEM", "EHIP", "ENOTCONV", "ENONFINITE", "EUNSUPPORTED", "dtype_code", "torch_dtype", "MG", "mg_opts",
            "mg_footprint", "mg_solve_batch", "SOLVE_F64", "SOLVE_F32_REFINED", "MODES", "Batch", "uzawa_opts",
            "litho_pressure", "uzawa_pressure", "uzawa_solve", "uzawa_anderson"]
@@ -388,3 +389,50 @@ def uzawa_anderson(mg, grid, vx, vy, p, eta_c, eta_n, fx, fy, depth=3, allow_not
         check(rc)
     rep = dict(cycles=r.cycles, converged=bool(r.converged), e=r.e, ev=r.ev, seconds=r.seconds)
     return rep, np.array(hist[:r.cycles + 1])
+
+
+# ------------------------------------------------------------------------ 3D --
+
+def smooth3d_opts(omega=0.7, tile=8, halo=-1, k=2, shifts=None, seed=0):
+    """Returns (Smooth3dOpts, keepalive); ``shifts`` is an (n_outer, 3) int array."""
+    o = L.Smooth3dOpts()
+    L.lib.stk_smooth3d_opts_default(C.byref(o))
+    o.omega, o.tile, o.halo, o.k, o.seed = float(omega), int(tile), int(halo), int(k), C.c_uint64(seed).value
+    keep = None
+    if shifts is not None:
+        keep = np.ascontiguousarray(np.asarray(shifts, dtype=np.int32).ravel())
+        o.shifts = keep.ctypes.data_as(C.POINTER(C.c_int32))
+    return o, keep
+
+
+def _p3(ts, dt):
+    return [_ptr(t, dt) for t in ts]
+
+
+def smooth3d(ctx, dt, grid, v, eta, b, sweeps, variant="jacobi_fused", **opts):
+    """In place on v = (vx, vy, vz); eta = (eta_c, eta_xy, eta_xz, eta_yz); b = (bx, by, bz)."""
+    dt = dtype_code(dt)
+    o, keep = smooth3d_opts(**opts)
+    check(L.lib.stk_smooth3d(ctx.handle, dt, C.byref(grid), *_p3(v, dt), *_p3(eta, dt), *_p3(b, dt), int(sweeps),
+                             VARIANTS[variant] if isinstance(variant, str) else int(variant), C.byref(o)))
+    del keep
+
+
+def ras_outer3d(ctx, dt, grid, v, eta, b, out, omega, tile, halo, kt, shift):
+    dt = dtype_code(dt)
+    check(L.lib.stk_ras_outer3d(ctx.handle, dt, C.byref(grid), *_p3(v, dt), *_p3(eta, dt), *_p3(b, dt),
+                                *_p3(out, dt), float(omega), int(tile), int(halo), int(kt), *[int(s) for s in shift]))
+
+
+def residual3d(ctx, dt, grid, v, eta, b, r):
+    dt = dtype_code(dt)
+    check(L.lib.stk_residual3d(ctx.handle, dt, C.byref(grid), *_p3(v, dt), *_p3(eta, dt), *_p3(b, dt), *_p3(r, dt)))
+
+
+def energy_norm3d(ctx, dt, grid, v, eta, f):
+    """(N_v, N_f, E_v) as a numpy array."""
+    dt = dtype_code(dt)
+    out = (C.c_double * 3)()
+    check(L.lib.stk_energy_norm3d(ctx.handle, dt, C.byref(grid), *_p3(v, dt), *_p3(eta, dt), *_p3(f, dt), out))
+    return np.array(out[:])
+

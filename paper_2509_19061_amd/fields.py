@@ -10,7 +10,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from ._lib import Grid
+from ._lib import Grid, Grid3
 
 
 def pad_ld(nx: int, align: int = 64) -> int:
@@ -68,3 +68,37 @@ class DeviceProblem:
 
     def get_cell(self, t):
         return download(t, (self.ny, self.nx))
+
+
+class DeviceProblem3:
+    """A 3D problem's viscosities and right-hand side on the device: every field
+    (nz+1) x (ny+1) x ld, plane stride lp = (ny+1) ld."""
+
+    def __init__(self, prob, dtype=torch.float64, device="cuda", align: int = 64):
+        self.prob = prob
+        self.nx, self.ny, self.nz = prob.nx, prob.ny, prob.nz
+        self.ld = pad_ld(prob.nx, align)
+        self.lp = (prob.ny + 1) * self.ld
+        self.dtype, self.device = dtype, device
+        self.grid = Grid3(prob.nx, prob.ny, prob.nz, self.ld, self.lp, float(prob.dx), float(prob.dy),
+                          float(prob.dz))
+        self.eta = tuple(self.field(a) for a in (prob.eta_c, prob.eta_xy, prob.eta_xz, prob.eta_yz))
+        self.f = tuple(self.field(a) for a in (prob.fx, prob.fy, prob.fz))
+
+    def field(self, a=None):
+        t = torch.zeros((self.nz + 1, self.ny + 1, self.ld), dtype=self.dtype)
+        if a is not None:
+            t[: a.shape[0], : a.shape[1], : a.shape[2]] = torch.from_numpy(
+                np.ascontiguousarray(a, dtype=np.float64)).to(self.dtype)
+        return t.to(self.device)
+
+    def velocity(self, v=None):
+        return tuple(self.field(None if v is None else a) for a in (v if v is not None else (None, None, None)))
+
+    def get(self, t, shape):
+        return t[: shape[0], : shape[1], : shape[2]].to(torch.float64).cpu().numpy()
+
+    def get_v(self, v):
+        nx, ny, nz = self.nx, self.ny, self.nz
+        return (self.get(v[0], (nz, ny, nx + 1)), self.get(v[1], (nz, ny + 1, nx)), self.get(v[2], (nz + 1, ny, nx)))
+
