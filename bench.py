@@ -43,9 +43,10 @@ multigrid solves:
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
 For profiling, ``--kernel-only L`` runs just L launches of the RAS
-outer-iteration kernel on the 4096^2 workload, followed by two copies of a
-512 MiB buffer (the calibration kernel for the HBM byte counters), and prints
-one JSON line with their timings.
+outer-iteration kernel on the 4096^2 workload, followed by two launches of the
+streaming probe with the same traffic pattern (6 planes read, 2 written; the
+calibration kernel for the HBM byte counters), and prints one JSON line with
+their timings.
 """
 import argparse
 import json
@@ -60,10 +61,11 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the streaming RAS kernel (4096^2, FP64, T = 64,
 # k = h = 4) from rocprofv3 FETCH_SIZE / WRITE_SIZE, each scaled by what the
-# counter reads for a copy of known size (profiles/k_ras_stream_4096_f64_k4.md).
+# counter reads for the stream probe k_stream6 of known size in the same run
+# (profiles/k_ras_stream_4096_f64_k4.md).
 # Valid only for the kernel code it was measured on: reported as null once the
 # hash of its sources (comments and blank space removed) differs.
-RAS_TRAFFIC = {"sources_sha256_16": "eabfb68239fe231e", "bytes_per_launch": 1.157e9, "n": 4096, "k": 4, "dtype": "f64"}
+RAS_TRAFFIC = {"sources_sha256_16": "eabfb68239fe231e", "bytes_per_launch": 1.152e9, "n": 4096, "k": 4, "dtype": "f64"}
 
 
 def ras_sources_hash():
@@ -100,6 +102,8 @@ def main():
     ap.add_argument("--config3-cap", type=int, default=600, help="iteration cap of the smooth-background solves")
     ap.add_argument("--config3-cap-iid", type=int, default=200, help="iteration cap of the i.i.d.-background solves")
     ap.add_argument("--cpu-seconds-1t", type=float, default=10.0, help="CPU oracle sample at 1 thread (s)")
+    ap.add_argument("--variants-n", type=int, default=1024, help="smoother-variant solve table size (0: skip)")
+    ap.add_argument("--n3d", type=int, default=256, help="3D extension size n^3 (0: skip)")
     ap.add_argument("--batch", default="default", help="'default' (64-instance mix), 'small' or 'none'")
     ap.add_argument("--kernel-only", type=int, default=0, help="profiling mode: L RAS launches + copy calibration")
     ap.add_argument("--serve", type=int, default=16, help="requests per serving run (0: skip)")
@@ -304,6 +308,8 @@ def main():
     solve = run_solves(ctx, args.solve_n) if args.solve_n > 0 else None
     config3 = (run_config3(ctx, args.config3_n, args.config3_cap, args.config3_cap_iid)
                if args.config3_n > 0 else None)
+    mgvar = run_variants_solve(ctx, args.variants_n) if args.variants_n > 0 else None
+    d3 = run_3d(ctx, args.n3d) if args.n3d > 0 else None
     batch = run_batch(ctx, args.batch) if args.batch != "none" else None
     loads = [float(x) for x in args.serve_loads.split(",") if x.strip()]
     served = run_serve(ctx, args.serve, loads=loads) if args.serve > 0 else None
@@ -338,6 +344,8 @@ def main():
         "wall_ms_per_step": round(wall / args.steps * 1e3, 4),
         "solve": solve,
         "config3": config3,
+        "smoother_variants_solve": mgvar,
+        "ext3d": d3,
         "batch": batch,
         "serve": served,
         "uzawa": uz,
@@ -371,14 +379,16 @@ def kernel_only(args):
                           *shifts[t])
 
     _, secs = _timed(launches)
-    copy_bytes = 512 << 20
-    a = torch.ones(copy_bytes // 8, dtype=torch.float64, device="cuda")
-    b = torch.empty_like(a)
-    _, csecs = _timed(lambda: (b.copy_(a), a.copy_(b)))
+    # calibration of the byte counters: the streaming pass with the same traffic pattern
+    # (6 planes read, 2 written, whole planes of (n+1) x ld elements), two launches
+    probe_in = [dp.eta_c, dp.eta_n, dp.fx, dp.fy, ax, ay]
+    _, csecs = _timed(lambda: [api.stream_probe(ctx, dt, dp.grid, probe_in, [cx, cy]) for _ in range(2)])
+    w = 8 if dt == torch.float64 else 4
     out = {"kernel": "k_ras_stream", "n": n, "k": k, "launches": args.kernel_only,
            "ms_per_launch": round(secs * 1e3 / args.kernel_only, 4),
-           "alg_bytes_per_launch": 8 * (8 if dt == torch.float64 else 4) * n * n,
-           "copy_bytes_each_way": copy_bytes, "copy_ms_per_launch": round(csecs * 1e3 / 2, 4)}
+           "alg_bytes_per_launch": 8 * w * n * n,
+           "calibration_kernel": "k_stream6", "calibration_read_bytes": 6 * w * (n + 1) * dp.ld,
+           "calibration_write_bytes": 2 * w * (n + 1) * dp.ld, "calibration_ms": round(csecs * 1e3 / 2, 4)}
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -645,6 +655,81 @@ def run_fp32_leg(ctx, prob, sweeps, ks=(2, 4, 8)):
                        "launch_ms": round(launch_ms, 4), "alg_bytes_per_launch": alg}
     log(f"[bench] fp32 k_ras_stream k=4: {launch_ms:.4f} ms/launch, {ach:.0f} GB/s effective")
     del ax, ay, cx, cy, dp
+    return out
+
+
+def run_variants_solve(ctx, n, tol=1e-8, max_iters=3000):
+    """The paper's smoother variants inside the V-cycle (Sec. 6.2, 6.3, 7.3) on
+    the refinement workload at n^2, FP64 FCG to E_v <= tol: the finest level
+    smoothed by RAS outer iterations of k inner sweeps (8 sweeps per stage, 64 x
+    64 tiles) with the full overlap h = k (exactly Jacobi^8) and the paper's
+    thin overlap h = 0, k = 1, 2, 4, 8; the mixed smoother (RAS 32 x 32, k = 4,
+    h = 0 on the coarse levels); the paper's schedule (5 + 5 sweeps growing by
+    2.5 per level, four levels, the last relaxed, mixed smoother)."""
+    import torch
+
+    from paper_2509_19061_amd import api, fields, inputs
+
+    prob = inputs.lognormal_background_workload(n)
+    dp = fields.DeviceProblem(prob, torch.float64)
+    runs = [("default_v22", dict())]
+    for kk in (1, 2, 4, 8):
+        for h in (kk, 0):
+            runs.append((f"fine_k{kk}_h{h}", dict(nu1=8, nu2=8, fine_k=kk, fine_halo=h)))
+    runs.append(("mixed_smoother", dict(coarse_smoother="ras", coarse_tile=32, coarse_k=4, coarse_halo=0)))
+    runs.append(("paper_schedule", dict(nu1=5, nu2=5, sweep_growth=2.5, max_levels=4, omega=0.5,
+                                        coarse_smoother="ras", coarse_tile=32, coarse_k=4, coarse_halo=0)))
+    out = {"workload": f"{n}x{n} refinement workload (16 sinkers eta 1e6, smooth log-uniform background), FP64 FCG "
+                       f"to E_v <= {tol:g}, at most {max_iters} iterations", "n": n, "runs": {}}
+    for name, opts in runs:
+        m = api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n, **opts)
+        vx, vy = dp.velocity()
+        m.solve("f64", vx, vy, None, dp.fx, dp.fy, tol=tol, max_iters=1, allow_notconv=True)  # buffers, plan
+        vx, vy = dp.velocity()
+        rep, secs = _timed(lambda: m.solve("f64", vx, vy, None, dp.fx, dp.fy, tol=tol, max_iters=max_iters,
+                                            allow_notconv=True))
+        its = max(1, rep["iterations"])
+        out["runs"][name] = {"options": opts, "converged": rep["converged"], "iterations": rep["iterations"],
+                             "seconds": round(secs, 4), "ms_per_iteration": round(secs * 1e3 / its, 3),
+                             "ev": rep["ev"]}
+        log(f"[bench] variants {name}: {rep['iterations']} iterations, {secs:.3f}s, E_v {rep['ev']:.2e}")
+        m.close()
+        del vx, vy
+    return out
+
+
+def run_3d(ctx, n, sweeps=20):
+    """The 3D extension at n^3 cells (4 spherical sinkers, eta 1e4 / 1): fused
+    Jacobi and 3D RAS (T = 8, h = k = 2) in FP64 and FP32, GLUP/s and the
+    effective HBM rate of the algorithmic bytes (13 words per LUP for Jacobi:
+    vx, vy, vz, eta_c, three edge viscosities, bx, by, bz read, vx, vy, vz
+    written; 13/k for RAS)."""
+    import torch
+
+    from paper_2509_19061_amd import api, fields, inputs
+
+    prob = inputs.random_sinkers3d(n, 4, 8)
+    out = {"workload": f"{n}^3 cells, 4 spherical sinkers eta 1e4 / 1, v = 0 start, {sweeps} sweeps", "n": n}
+    cells = n ** 3
+    for dts, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        dp = fields.DeviceProblem3(prob, dt)
+        w = 8 if dt == torch.float64 else 4
+        res = {}
+        for name, var, kw, words in (("jacobi_fused", "jacobi_fused", {}, 13.0),
+                                     ("ras_t8_k2", "ras", dict(tile=8, k=2, halo=2, seed=3), 13.0 / 2)):
+            v = dp.velocity()
+            api.smooth3d(ctx, dt, dp.grid, v, dp.eta, dp.f, 2, var, **kw)
+            _, secs = _timed(lambda: api.smooth3d(ctx, dt, dp.grid, v, dp.eta, dp.f, sweeps, var, **kw))
+            g = cells * sweeps / secs / 1e9
+            eff = g * words * w
+            res[name] = {"glups": round(g, 2), "ms_per_sweep": round(secs * 1e3 / sweeps, 4),
+                         "effective_gbs": round(eff, 1), "frac_hbm": round(eff / HBM_PEAK_GBS, 4),
+                         "words_per_lup": words}
+            log(f"[bench] 3d {dts} {name}: {g:.1f} GLUP/s, {eff:.0f} GB/s effective")
+            del v
+        out[dts] = res
+        del dp
+        torch.cuda.empty_cache()
     return out
 
 
