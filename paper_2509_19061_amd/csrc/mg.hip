@@ -599,7 +599,6 @@ static int vcycle(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o) {
             STK_TRY(d == 0 ? smooth_stage<T>(ctx, F, o, nu1) : coarse_stage<T>(ctx, F, P.fine_t[d], o, nu1));
             STK_TRY(mg_residual<T>(ctx, F));
         }
-        STK_TRY(mg_zero_coarse<T>(ctx, P.crs[d]));
         STK_TRY(mg_restrict<T>(ctx, P.crs[d]));
         if (d + 1 < (int)P.cjobs.size()) {
             STK_TRY(mg_coarse<T>(ctx, P.cjobs[d + 1], P.ncj[d + 1], P.maxcn));

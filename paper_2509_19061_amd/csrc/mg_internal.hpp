@@ -69,7 +69,7 @@ struct FcgState {
     double thr;     // stop when nv <= thr
     double tol2;    // tol^2 of this instance (thr = tol2 * nf)
     int active;     // 1 while this instance iterates
-    int pad;
+    int left;       // iterations left in its budget (PH_NV stops the instance at 0)
 };
 
 // ---- launchers (mg_kernels.hip) ----------------------------------------------
@@ -93,8 +93,8 @@ constexpr int SUM_CHUNK = 4096;
 
 template <typename T> int mg_jacobi(stk_ctx* ctx, const Batch& b, double omega, int dir);
 template <typename T> int mg_residual(stk_ctx* ctx, const Batch& b);
+// coarse right-hand side = R r, and the coarse iterate set to 0
 template <typename T> int mg_restrict(stk_ctx* ctx, const Batch& b_coarse_blocks);
-template <typename T> int mg_zero_coarse(stk_ctx* ctx, const Batch& b_coarse_blocks);
 template <typename T> int mg_prolong(stk_ctx* ctx, const Batch& b);
 template <typename T> int mg_coarse(stk_ctx* ctx, const void* jobs, int n, int max_unknowns);
 
@@ -125,8 +125,10 @@ enum VecOp {
     OP_INIT_P,      // p = z; acc0 += r.z
     OP_ZERO_Z       // z = 0
 };
-// phases of fcg_scalars
-enum { PH_NF = 0, PH_NV, PH_INIT, PH_ALPHA, PH_BETA };
+// phases of fcg_scalars: PH_NV ends a CG iteration (stop below the threshold
+// or when the budget runs out), PH_TRUE takes a recomputed true residual
+// (stop below the threshold only)
+enum { PH_NF = 0, PH_NV, PH_INIT, PH_ALPHA, PH_BETA, PH_TRUE };
 // Slot dtype T for the slots touched (R, Z, P, Q, X); partial sums land in
 // `part` (2 per block), then per-instance sums in `sums` (2 per instance).
 template <typename T>

@@ -212,7 +212,8 @@ __device__ __forceinline__ int w_tangent(int f, int nc, int* c, double* w) {
 }
 
 // coarse rhs = R r = P^T r / 4, gathered per coarse unknown from the fine
-// unknowns that prolongate from it.
+// unknowns that prolongate from it; the coarse iterate is set to 0 in the same
+// pass (the coarse problem is solved for the correction from 0).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
                                                     int n) {
@@ -241,6 +242,7 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restric
             }
         }
         J.cbx[k] = T(s);
+        J.cvx[k] = T(0);
     }
     if (i < NX) {  // coarse vy(I=i, J=j)
         double s = 0.0;
@@ -263,18 +265,8 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restric
             }
         }
         J.cby[k] = T(s);
+        J.cvy[k] = T(0);
     }
-}
-
-// coarse iterate = 0 (the coarse problem is solved for the correction from 0)
-template <typename T>
-__global__ __launch_bounds__(NT) void k_mg_zero_coarse(const LevelJob<T>* __restrict__ jobs,
-                                                       const int* __restrict__ pre, int n) {
-    STK_BATCH_INDEX(jobs, pre, n, COARSE_NX, COARSE_NY)
-    if (i > J.cnx || j > J.cny) return;
-    const int64_t k = (int64_t)j * J.cld + i;
-    if (j < J.cny) J.cvx[k] = T(0);
-    if (i < J.cnx) J.cvy[k] = T(0);
 }
 
 // v += P e_c on the fine unknowns.
@@ -596,6 +588,13 @@ __global__ void k_fcg_scalars(FcgState* __restrict__ st, const double* __restric
         case PH_NV:
             if (s.active) {
                 s.nv = s0;
+                s.left -= 1;
+                s.active = s0 > s.thr && s.left > 0;
+            }
+            break;
+        case PH_TRUE:
+            if (s.active) {
+                s.nv = s0;
                 s.active = s0 > s.thr;
             }
             break;
@@ -670,14 +669,6 @@ int mg_restrict(stk_ctx* ctx, const Batch& b) {
     return STK_OK;
 }
 template <typename T>
-int mg_zero_coarse(stk_ctx* ctx, const Batch& b) {
-    if (!b.n) return STK_OK;
-    hipLaunchKernelGGL(k_mg_zero_coarse<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
-                       static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n);
-    STK_LAUNCH_CHECK();
-    return STK_OK;
-}
-template <typename T>
 int mg_prolong(stk_ctx* ctx, const Batch& b) {
     if (!b.n) return STK_OK;
     hipLaunchKernelGGL(k_mg_prolong<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
@@ -701,8 +692,6 @@ template int mg_residual<double>(stk_ctx*, const Batch&);
 template int mg_residual<float>(stk_ctx*, const Batch&);
 template int mg_restrict<double>(stk_ctx*, const Batch&);
 template int mg_restrict<float>(stk_ctx*, const Batch&);
-template int mg_zero_coarse<double>(stk_ctx*, const Batch&);
-template int mg_zero_coarse<float>(stk_ctx*, const Batch&);
 template int mg_prolong<double>(stk_ctx*, const Batch&);
 template int mg_prolong<float>(stk_ctx*, const Batch&);
 template int mg_coarse<double>(stk_ctx*, const void*, int, int);

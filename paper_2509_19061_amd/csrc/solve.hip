@@ -71,6 +71,9 @@ struct stk_batch {
     bool dirty = true;
     bool have_opts = false;
     stk_mg_opts o{};       // V-cycle options shared by every instance of the batch
+    FcgState* pin = nullptr;  // pinned host copy of the member states, read once per iteration
+    int npin = 0;
+    hipEvent_t ev = nullptr;  // marks that copy in the stream
 };
 
 namespace stk {
@@ -87,6 +90,17 @@ int plans_for(stk_batch* b, const std::vector<int>& ids, PlanT** P, PlanT** P32)
             return rc;
         }
     }
+    return STK_OK;
+}
+
+int ensure_pinned(stk_batch* b, int n) {
+    if (!b->ev) STK_HIP(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
+    if (b->npin >= n) return STK_OK;
+    if (b->pin) STK_HIP(hipHostFree(b->pin));
+    b->pin = nullptr;
+    b->npin = 0;
+    STK_HIP(hipHostMalloc(reinterpret_cast<void**>(&b->pin), sizeof(FcgState) * (size_t)n, hipHostMallocDefault));
+    b->npin = n;
     return STK_OK;
 }
 
@@ -141,7 +155,7 @@ int start_phase(stk_batch* b, int* done, stk_report* reps, int* ndone) {
     for (auto& s : h) s.active = 1;
     if (int rc = write_states(ctx, *Q, h)) return fail(rc);
     if (int rc = vec_residual64_st(ctx, Q->vec, Q->st, Q->part, Q->sums)) return fail(rc);
-    if (int rc = fcg_scalars(ctx, Q->st, Q->sums, n, PH_NV)) return fail(rc);
+    if (int rc = fcg_scalars(ctx, Q->st, Q->sums, n, PH_TRUE)) return fail(rc);
     if (int rc = read_states(ctx, *Q, h)) return fail(rc);
     bool restart = false;
     for (int q = 0; q < n; ++q) {
@@ -153,6 +167,7 @@ int start_phase(stk_batch* b, int* done, stk_report* reps, int* ndone) {
             if (int rc = finish(b, ids[q], &reps[*ndone])) return fail(rc);
             ++*ndone;
         } else {
+            h[q].left = s.max_iters - s.its;  // the device stops the instance when its budget runs out
             restart = true;
         }
     }
@@ -195,36 +210,38 @@ int iterate_phase(stk_batch* b, int iters) {
     std::vector<FcgState> h(n);
     for (int q = 0; q < n; ++q) h[q] = b->slots[b->members[q]].fs;
     STK_TRY(write_states(ctx, P, h));
+    STK_TRY(ensure_pinned(b, n));
     for (int it = 0; it < iters; ++it) {
         STK_TRY(fcg_apply_pq(ctx, P.apply, P.applyr, P.st, P.part, P.sums));  // Q = A P and P . Q
         STK_TRY(fcg_scalars(ctx, P.st, P.sums, n, PH_ALPHA));
         STK_TRY(vec_op<double>(ctx, P.vec, OP_UPDATE, P.st, P.part, P.sums));
-        STK_TRY(fcg_scalars(ctx, P.st, P.sums, n, PH_NV));
-        std::vector<FcgState> prev = h;
-        STK_TRY(read_states(ctx, P, h));
-        bool any = false, stopped = false;
+        STK_TRY(fcg_scalars(ctx, P.st, P.sums, n, PH_NV));  // stop below tol or at the end of the budget
+        // The states go to the host while the rest of the iteration is queued
+        // behind them: the GPU never waits for the host between iterations.
+        // An instance that stopped here is skipped by the Krylov kernels, and
+        // its preconditioner output is recomputed before it is used again.
+        STK_HIP(hipMemcpyAsync(b->pin, P.st, sizeof(FcgState) * n, hipMemcpyDeviceToHost, ctx->stream));
+        STK_HIP(hipEventRecord(b->ev, ctx->stream));
+        STK_TRY(precondition(ctx, P, b->P32, o));
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_RZ_ZQ, P.st, P.part, P.sums, P.vec_z32));
+        STK_TRY(fcg_scalars(ctx, P.st, P.sums, n, PH_BETA));
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_XPBY, P.st, P.part, nullptr, P.vec_z32));
+        STK_HIP(hipEventSynchronize(b->ev));
+        bool any = false;
         for (int q = 0; q < n; ++q) {
             Slot& s = b->slots[b->members[q]];
-            if (!prev[q].active) continue;
+            const bool was = h[q].active != 0;
+            h[q] = b->pin[q];
+            if (!was) continue;
             ++s.its;
-            if (!h[q].active) {  // recurrence residual below tol: verify with the true one
-                s.state = SL_CHECK;
-                b->dirty = true;
-            } else if (s.its >= s.max_iters) {  // budget spent: stop here, report the true residual
-                h[q].active = 0;
-                stopped = true;
+            if (!h[q].active) {  // below tol (verify with the true residual) or budget spent
                 s.state = SL_CHECK;
                 b->dirty = true;
             } else {
                 any = true;
             }
         }
-        if (stopped) STK_TRY(write_states(ctx, P, h));
         if (!any) break;
-        STK_TRY(precondition(ctx, P, b->P32, o));
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_RZ_ZQ, P.st, P.part, P.sums, P.vec_z32));
-        STK_TRY(fcg_scalars(ctx, P.st, P.sums, n, PH_BETA));
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_XPBY, P.st, P.part, nullptr, P.vec_z32));
     }
     STK_TRY(read_states(ctx, P, h));
     for (int q = 0; q < n; ++q) b->slots[b->members[q]].fs = h[q];
@@ -257,6 +274,8 @@ int stk_batch_destroy(stk_batch* b) {
         if (s.m) s.m->busy = false;
     free_plan(b->P);
     free_plan(b->P32);
+    if (b->pin) (void)hipHostFree(b->pin);
+    if (b->ev) (void)hipEventDestroy(b->ev);
     delete b;
     return STK_OK;
 }
