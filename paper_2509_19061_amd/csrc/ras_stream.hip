@@ -71,6 +71,7 @@ enum { CF_EC = 0, CF_EN, CF_BX, CF_BY, CF_GX, CF_GY, CF_N };
 struct RasArgs {
     int Tx, Ty, h, kt, sx, sy;
     int NT;    // tiles per workgroup along y
+    int merge; // 1: the NT tiles are streamed as one tile (full overlap: the values do not depend on the cuts)
     int Wm;    // window width bound: min(Tx + 2h, nx) + 2
     int Vmax;  // virtual rows bound: NT * (min(Ty + 2h, ny) + 2)
     int ntx;   // tile columns (the grid is ntx x tile-row groups, flattened)
@@ -94,6 +95,19 @@ __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(
 // FP64 workgroup with T = 64, h = k <= 5 within a third of the CU's LDS (three
 // resident workgroups); wider windows take the wide one.
 constexpr int WS_NARROW = 76, WS_WIDE = 96;
+// A third stride for FP64 windows of many sweeps with full overlap (kt >= 6,
+// window <= 63 columns, so no remainder wave).  Its instances keep four
+// coefficient fields per row (A, N, bx, by).  The level waves compute the
+// Jacobi factors from the coefficients they already hold, in the feeders'
+// operation order, so the values are the same.  A kt = 8 workgroup then takes
+// 62 KB of LDS instead of 123 KB, and two fit in a CU.
+constexpr int WS_LG = 64;
+constexpr int LG_MIN_K = 6;  // FP64 full-overlap launches with at least this many sweeps use WS_LG
+__host__ __device__ constexpr bool level_factors(int WS) { return WS == WS_LG; }
+__host__ __device__ constexpr int cf_fields(int WS) { return level_factors(WS) ? 4 : CF_N; }
+// element stride of one coefficient row
+template <int WS>
+__host__ __device__ constexpr int cf_row() { return cf_fields(WS) * WS; }
 
 // level lanes: 64 per level for columns 0..63 (column 63 only as the right
 // neighbour of column 62), then a group per level for columns 63..Wm-1.
@@ -109,7 +123,7 @@ __host__ __device__ inline int level_waves(int Wm, int kt) { return (level_lanes
 // second component of a ring write)
 template <int WS>
 __host__ __device__ inline size_t stream_lds_elems(int kt) {
-    return (size_t)kt * RING * 2 * WS + (size_t)(2 * kt + 2) * CF_N * WS + 64 + WS;
+    return (size_t)kt * RING * 2 * WS + (size_t)(2 * kt + 2) * cf_fields(WS) * WS + 64 + WS;
 }
 template <typename T, int WS>
 size_t stream_lds_bytes(const RasArgs& a) {
@@ -147,6 +161,16 @@ __device__ __forceinline__ void store_row(T* __restrict__ ox, T* __restrict__ oy
     if (G.x1 == G.nx) buf_store(T(0), rox, rw_off);
     if (y == G.ny - 1)
         buf_store(T(0), buf_rsrc(oy + (int64_t)G.ny * G.ld, (size_t)G.nx * sizeof(T)), lane_off);
+}
+
+// diag(-M) of the scaled stencil from the coefficients around a cell: e0, e1
+// the normal-stress coefficients on either side (scaled by kl: 1 for vx, kap
+// for vy), n0, n1 the shear ones (scaled by rr).  The feeders and, in the
+// level-factor instances, the level waves evaluate this one expression, so
+// they produce the same bits.
+template <typename T>
+__device__ __forceinline__ T diag_scaled(T e0, T e1, T n0, T n1, T kl, T rr) {
+    return fmaT(n0 + n1, rr, e0 * kl + e1 * kl);
 }
 
 // ---------------------------------------------------------------- feeders --
@@ -224,16 +248,19 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
             const int t = t0 + u, q = u % PF;
             // (B, reads) coefficients around row t - 2, written at steps t - 3 .. t - 1
             const int sr = r2, sm = r3, sp = r1;
-            const T e0 = cf[(cy ? sm : sr) * CF_N * WS + off_e0];
-            const T e1 = cf[sr * CF_N * WS + CF_EC * WS + cq];
-            const T n0 = cf[sr * CF_N * WS + CF_EN * WS + cq];
-            const T n1 = cf[(cy ? sr : sp) * CF_N * WS + off_n1];
+            T e0 = T(0), e1 = T(0), n0 = T(0), n1 = T(0);
+            if constexpr (!level_factors(WS)) {
+                e0 = cf[(cy ? sm : sr) * cf_row<WS>() + off_e0];
+                e1 = cf[sr * cf_row<WS>() + CF_EC * WS + cq];
+                n0 = cf[sr * cf_row<WS>() + CF_EN * WS + cq];
+                n1 = cf[(cy ? sr : sp) * cf_row<WS>() + off_n1];
+            }
             __builtin_amdgcn_sched_barrier(0);
             const int ff_t = ff[q];  // flags of row t
             {  // (A) row t: FIFO -> LDS (slot 0 to the level-0 ring, the others to the
                //     coefficient row); loads of row t + PF
                 T* r0 = rings + (u % RING) * 2 * WS;
-                T* rc = cf + rA * CF_N * WS;
+                T* rc = cf + rA * cf_row<WS>();
                 const int y = (ff_t & YMASK) - 1;
 #pragma unroll
                 for (int m = 0; m < MM; ++m) {
@@ -248,12 +275,13 @@ __device__ __forceinline__ void feeder(const Grid<T>& g, const T* __restrict__ v
                 for (int m = 0; m < MM; ++m) fifo[q][m] = tbase[m][yo];
                 fn = t + PF + 1 < V ? vtab[t + PF + 1] : 0;
             }
-            {  // (B) omega / diag for row t - 2; 0 for a cell that is not relaxed, and for no
-               //     row (t < 2 or past the last row)
+            if constexpr (!level_factors(WS)) {  // (B) omega / diag for row t - 2; 0 for a cell
+                                                   //     that is not relaxed, and for no row
+                                                   //     (t < 2 or past the last row)
                 const int yr = (f2 & YMASK) - 1;
                 const bool upd = gcol && !(f2 & F_RING) && yr >= gylo && yr <= ny - 1;
-                const T d = fmaT(n0 + n1, rr, e0 * kl + e1 * kl);
-                T* dst = bl ? cf + sr * CF_N * WS + (cy ? CF_GY : CF_GX) * WS + cq : sink;
+                const T d = diag_scaled(e0, e1, n0, n1, kl, rr);
+                T* dst = bl ? cf + sr * cf_row<WS>() + (cy ? CF_GY : CF_GX) * WS + cq : sink;
                 const T gf = jac_factor(g.omega, d);  // not finite where d is 0: not selected
                 *dst = upd ? gf : T(0);
             }
@@ -295,6 +323,10 @@ __device__ __forceinline__ void level_loop(const Grid<T>& g, T* __restrict__ ox,
     int sa = RC - 1 - 2 * s;  // coefficient slot of row t - 1 - 2s at t = 0
     const unsigned lane_off = (c < 63 && i >= G.x0 && i < G.x1) ? (unsigned)i * (unsigned)sizeof(T) : OOB;
     const unsigned rw_off = (c < 63 && i == G.nx) ? (unsigned)i * (unsigned)sizeof(T) : OOB;
+    // level-factor instances: the lane's column may hold a relaxed vx / vy (the
+    // feeders' column test)
+    const bool colx = c >= 1 && c <= G.W - 2 && i >= 1 && i <= G.nx - 1;
+    const bool coly = c >= 1 && c <= G.W - 2 && i <= G.nx - 1;
 
     // window of level s-1 values at columns c-1, c, c+1: rows a-1, a, a+1
     T wx[3][3], wy[3][3];
@@ -303,16 +335,17 @@ __device__ __forceinline__ void level_loop(const Grid<T>& g, T* __restrict__ ox,
 #pragma unroll
         for (int q = 0; q < 3; ++q) wx[r][q] = wy[r][q] = T(0);
     T b_prev = T(0), n_prev = T(0);  // B(c, a-1), N(c, a)
+    T a_prev = T(0);                 // A(c, a-1) (level-factor instances)
     // A, bx, by of row a and N of row a + 1 are read one step ahead, before the barrier:
     // they were written two or more steps earlier, and their reads then stay out of the
     // burst of LDS reads that follows each barrier
     T qa, qbx, qby, qnt;
     {
-        const T* row = cfc + sa * (CF_N * WS);
+        const T* row = cfc + sa * cf_row<WS>();
         qa = row[CF_EC * WS];
         qbx = row[CF_BX * WS];
         qby = row[CF_BY * WS];
-        qnt = cfc[(sa + 1 == RC ? 0 : sa + 1) * (CF_N * WS) + CF_EN * WS];
+        qnt = cfc[(sa + 1 == RC ? 0 : sa + 1) * cf_row<WS>() + CF_EN * WS];
     }
 
     for (int t0 = 0; t0 < G.nsteps; t0 += U) {
@@ -328,11 +361,16 @@ __device__ __forceinline__ void level_loop(const Grid<T>& g, T* __restrict__ ox,
             }
             const T* p = pr[u % RING];
             const int sa1 = (sa + 1 == RC) ? 0 : sa + 1;
-            // row flags: only the level that stores the owned rows needs them
-            const int fl = TOP ? __builtin_amdgcn_readfirstlane(vtab[min(max(a2, 0), V - 1)]) : 0;
-            const T* row = cfc + sa * (CF_N * WS);
+            // row flags: the level that stores the owned rows needs them, and so do the
+            // levels that compute their Jacobi factors
+            const int fl = (TOP || level_factors(WS)) ? __builtin_amdgcn_readfirstlane(vtab[min(max(a2, 0), V - 1)]) : 0;
+            const T* row = cfc + sa * cf_row<WS>();
             const T xc = p[0], yc = p[WS];
-            const T gx = row[CF_GX * WS], gy = row[CF_GY * WS];  // level 1's are written in the last step
+            T gx = T(0), gy = T(0);
+            if constexpr (!level_factors(WS)) {
+                gx = row[CF_GX * WS];  // level 1's are written in the last step
+                gy = row[CF_GY * WS];
+            }
             const T aA = qa, bx = qbx, by = qby, nt = qnt;
             // every row is relaxed (a row outside the level's cone is never read), and the LDS
             // reads of the step are issued together, ahead of the arithmetic
@@ -352,6 +390,15 @@ __device__ __forceinline__ void level_loop(const Grid<T>& g, T* __restrict__ ox,
                                        wy[2][0], aL, aA, n_prev, nt, sc.ry);
             const T my = mvy_scaled<T>(wy[1][1], wy[1][0], wy[1][2], wy[0][1], wy[2][1], wx[1][1], wx[1][2], wx[0][1],
                                        wx[0][2], b_prev, bA, n_prev, nR, sc.rx);
+            if constexpr (level_factors(WS)) {  // omega / diag of row a, 0 where the feeders would store 0
+                const int fr = (a2 >= 0 && a2 < V) ? fl : 0;
+                const int y = (fr & YMASK) - 1;
+                const bool rok = !(fr & F_RING);
+                const T gfx = jac_factor(g.omega, diag_scaled(aL, aA, n_prev, nt, T(1), sc.ry));
+                const T gfy = jac_factor(g.omega, diag_scaled(a_prev, aA, n_prev, nR, sc.kap, sc.rx));
+                gx = (colx && rok && y >= 0 && y <= G.ny - 1) ? gfx : T(0);
+                gy = (coly && rok && y >= 1 && y <= G.ny - 1) ? gfy : T(0);
+            }
             const T ux = jac_step<T>(wx[1][1], gx, bx, mx);
             const T uy = jac_step<T>(wy[1][1], gy, by, my);
             if (!TOP) {
@@ -364,13 +411,14 @@ __device__ __forceinline__ void level_loop(const Grid<T>& g, T* __restrict__ ox,
             }
             b_prev = bA;
             n_prev = nt;
+            a_prev = aA;
             sa = sa1;
             {
-                const T* nrow = cfc + sa * (CF_N * WS);
+                const T* nrow = cfc + sa * cf_row<WS>();
                 qa = nrow[CF_EC * WS];
                 qbx = nrow[CF_BX * WS];
                 qby = nrow[CF_BY * WS];
-                qnt = cfc[(sa + 1 == RC ? 0 : sa + 1) * (CF_N * WS) + CF_EN * WS];
+                qnt = cfc[(sa + 1 == RC ? 0 : sa + 1) * cf_row<WS>() + CF_EN * WS];
             }
             lds_barrier();
         }
@@ -438,9 +486,9 @@ __device__ __forceinline__ void remainder_wave(const Grid<T>& g, T* __restrict__
             wy[2][1] = p[WS];
             wy[2][2] = p[WS + 1];
             const int sa1 = (sa + 1 == RC) ? 0 : sa + 1;
-            const T* row = cfc + sa * (CF_N * WS);
+            const T* row = cfc + sa * cf_row<WS>();
             const T aA = row[CF_EC * WS], aL = row[CF_EC * WS - 1], nR = row[CF_EN * WS + 1];
-            const T nt = cfc[sa1 * (CF_N * WS) + CF_EN * WS];
+            const T nt = cfc[sa1 * cf_row<WS>() + CF_EN * WS];
             const int ak = t0 + u - 1 - 2 * kt;  // the row of the level-kt lanes
             const int flk = __builtin_amdgcn_readfirstlane(vtab[min(max(ak, 0), V - 1)]);
             __builtin_amdgcn_sched_barrier(0);
@@ -488,18 +536,20 @@ __device__ __forceinline__ void ras_workgroup(const Grid<T>& g, const T* __restr
     int* vtab = reinterpret_cast<int*>(smem_raw);
     T* rings = reinterpret_cast<T*>(smem_raw + align16((size_t)(a.Vmax + 1) * sizeof(int)));
     T* cf = rings + kt * RING * 2 * WS;
-    T* sink = cf + (2 * kt + 2) * CF_N * WS + (tid & 63);  // this lane's sink for disabled LDS stores
+    T* sink = cf + (2 * kt + 2) * cf_row<WS>() + (tid & 63);  // this lane's sink for disabled LDS stores
 
     // ---- virtual row table: y + 1 and flags, tile after tile.
     // Tile ty of this workgroup contributes the rows y of [Y0 - 1, Y1] within D of its owned rows.
+    // Merged: the NT tiles as one tile of NT Ty rows.
     const int D = min(kt, a.h + 1);
     const int nty = (ny + a.Ty - 1) / a.Ty + 1;
     const int tyb = by * a.NT;
+    const int span = a.merge ? a.NT : 1;  // tiles per streamed tile
     int V = 0;
-    for (int q = 0; q < a.NT; ++q) {
+    for (int q = 0; q < a.NT; q += span) {
         const int ty = tyb + q;
         if (ty >= nty) break;
-        const int y0 = max(0, a.sy + (ty - 1) * a.Ty), y1 = min(ny, a.sy + ty * a.Ty);
+        const int y0 = max(0, a.sy + (ty - 1) * a.Ty), y1 = min(ny, a.sy + (ty + span - 1) * a.Ty);
         if (y0 >= y1) continue;
         const int Y0 = max(y0 - a.h, 0), Y1 = min(y1 + a.h, ny);
         const int lo = max(Y0 - 1, y0 - D), hi = min(Y1, y1 - 1 + D);
@@ -543,7 +593,8 @@ __device__ __forceinline__ void ras_workgroup(const Grid<T>& g, const T* __restr
         feeder<T, WS, MM>(g, vx, vy, G, rings, cf, sink, (wave - nlw) * 64 + lane);
     } else if (wave < kt) {
         level_wave<T, WS>(g, ox, oy, G, rings, cf, sink, wave + 1, lane);
-    } else {  // remainder: columns 63.. of every level
+    } else if constexpr (!level_factors(WS)) {  // remainder: columns 63.. of every level (level-factor
+                                                // windows have none)
         const int R = Wm - 63, GS = rem_group(Wm), j = (wave - kt) * 64 + lane;
         const int s = j / GS + 1, q = j % GS;
         remainder_wave<T, WS>(g, ox, oy, G, rings, cf, sink, s, s > kt ? 63 : 63 + min(q, R - 1), s > kt || q >= R);
@@ -553,12 +604,13 @@ __device__ __forceinline__ void ras_workgroup(const Grid<T>& g, const T* __restr
 // Waves per SIMD the register allocation must leave room for (at most 72
 // VGPRs each): an FP64 workgroup of up to 8 waves (k <= 4 with T = 64) is
 // resident three or four times per CU, 6 to 7 waves per SIMD, and the waves
-// of a workgroup do not always spread evenly over the SIMDs.  Other sizes are
-// bound by LDS or by their own wave count first.
-constexpr int ras_waves_per_simd(int nthr) { return nthr == 512 ? 7 : 1; }
+// of a workgroup do not always spread evenly over the SIMDs; so is a pair of
+// level-factor workgroups of up to 14 waves.  Other sizes are bound by LDS or
+// by their own wave count first.
+constexpr int ras_waves_per_simd(int nthr, int ws) { return (nthr == 512 || level_factors(ws)) ? 7 : 1; }
 
 template <typename T, int NTMAX, int MM, int WS>
-__global__ __launch_bounds__(NTMAX, ras_waves_per_simd(NTMAX)) void k_ras_stream(Grid<T> g, const T* __restrict__ vx, const T* __restrict__ vy,
+__global__ __launch_bounds__(NTMAX, ras_waves_per_simd(NTMAX, WS)) void k_ras_stream(Grid<T> g, const T* __restrict__ vx, const T* __restrict__ vy,
                                                       T* __restrict__ ox, T* __restrict__ oy, RasArgs a) {
     // tiles row-major, renumbered by XCD: tile columns side by side run on one
     // XCD at the same time and share the halo columns of their windows in L2
@@ -571,7 +623,7 @@ __global__ __launch_bounds__(NTMAX, ras_waves_per_simd(NTMAX)) void k_ras_stream
 // tiles per workgroup, window bound) is shared, the geometry is the
 // instance's, shifts are 0.
 template <typename T, int NTMAX, int MM, int WS>
-__global__ __launch_bounds__(NTMAX, ras_waves_per_simd(NTMAX)) void k_ras_batch(const RasJob<T>* __restrict__ jobs, const int* __restrict__ pre,
+__global__ __launch_bounds__(NTMAX, ras_waves_per_simd(NTMAX, WS)) void k_ras_batch(const RasJob<T>* __restrict__ jobs, const int* __restrict__ pre,
                                                      int n, RasArgs a, T omega) {
     const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     int lo = 0, hi = n - 1;
@@ -635,7 +687,8 @@ int stream_occupancy(int dev, int nthr, int mm, size_t lds) {
             if (e.dev == dev && e.nthr == nthr && e.mm == mm && e.lds == lds) return e.n;
     }
     int n;
-    if (nthr <= 256) n = occ_mm<T, 256, WS>(mm, nthr, lds);
+    if constexpr (level_factors(WS)) n = occ_mm<T, 1024, WS>(mm, nthr, lds);  // kt >= 6: over 512 threads
+    else if (nthr <= 256) n = occ_mm<T, 256, WS>(mm, nthr, lds);
     else if (nthr <= 512) n = occ_mm<T, 512, WS>(mm, nthr, lds);
     else n = occ_mm<T, 1024, WS>(mm, nthr, lds);
     std::lock_guard<std::mutex> lk(mu);
@@ -659,11 +712,16 @@ int try_stream_ws(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, RasArgs a,
     if (nthr > 1024) return STK_OK;
     const int mm = feeder_loads(a.Wm);  // 2 or 3 for Wm <= WS_WIDE
     const int ntx = (g->nx + Tx - 1) / Tx + 1, nty = (g->ny + Ty - 1) / Ty + 1;
-    // rows of a tile in the stream: at most Ty + 2 min(kt, h + 1), and at most the window's
+    // rows of a tile of height H in the stream: at most H + 2 min(kt, h + 1), and at most the window's
     const int D = std::min(kt, h + 1);
-    const int rows_per_tile = (int)std::min<int64_t>(std::min<int64_t>((int64_t)Ty + 2 * (int64_t)h, g->ny) + 2,
-                                                     std::min<int64_t>(Ty, g->ny) + 2 * D);
-    // Tiles per workgroup NT: a workgroup streams NT tiles (NT * rows + 2kt + 1 steps);
+    auto tile_rows = [&](int64_t H) {
+        return (int)std::min<int64_t>(std::min<int64_t>(H + 2 * (int64_t)h, g->ny) + 2, std::min<int64_t>(H, g->ny) + 2 * D);
+    };
+    // full overlap: the owned values do not depend on where the tiles are cut, so a
+    // workgroup's NT tiles are streamed as one (fewer overlap rows)
+    a.merge = h >= kt - 1 ? 1 : 0;
+    auto stream_rows = [&](int NT) { return a.merge ? tile_rows((int64_t)NT * Ty) : NT * tile_rows(Ty); };
+    // Tiles per workgroup NT: a workgroup streams NT tiles (stream rows + 2kt + 1 steps);
     // pick the NT that minimises (rounds of resident workgroups) x (steps per workgroup).
     // Residency counts LDS in 2 KiB granules against the CU's LDS as well as the
     // occupancy query: a workgroup just over a third of the LDS is resident only
@@ -674,7 +732,7 @@ int try_stream_ws(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, RasArgs a,
     for (int NT = 1; NT <= 8; ++NT) {
         RasArgs t = a;
         t.NT = NT;
-        t.Vmax = NT * rows_per_tile;
+        t.Vmax = stream_rows(NT);
         const size_t l = stream_lds_bytes<T, WS>(t);
         if (l > (size_t)ctx->lds_max) break;
         int per_cu = stream_occupancy<T, WS>(ctx->device, nthr, mm, l);
@@ -682,7 +740,7 @@ int try_stream_ws(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, RasArgs a,
         if (per_cu < 1) break;
         const int64_t nwg = (int64_t)ntx * ((nty + NT - 1) / NT);
         const int64_t slots = (int64_t)per_cu * std::max(ctx->num_cu, 1);
-        const double cost = (double)((nwg + slots - 1) / slots) * (NT * rows_per_tile + 2 * kt + 1);
+        const double cost = (double)((nwg + slots - 1) / slots) * (stream_rows(NT) + 2 * kt + 1);
         if (cost < best_cost) {
             best_cost = cost;
             best_nt = NT;
@@ -691,7 +749,7 @@ int try_stream_ws(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, RasArgs a,
     }
     if (best_cost >= 1e300) return STK_OK;
     a.NT = best_nt;
-    a.Vmax = best_nt * rows_per_tile;
+    a.Vmax = stream_rows(best_nt);
     a.ntx = ntx;
     a.nwg = ntx * ((nty + best_nt - 1) / best_nt);
     const dim3 grid((unsigned)a.nwg);
@@ -700,7 +758,8 @@ int try_stream_ws(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, RasArgs a,
     auto* b0 = static_cast<T*>(ox);
     auto* b1 = static_cast<T*>(oy);
     int rc;
-    if (nthr <= 256) rc = launch_mm<T, 256, WS>(ctx, mm, gg, a, nthr, lds, grid, a0, a1, b0, b1);
+    if constexpr (level_factors(WS)) rc = launch_mm<T, 1024, WS>(ctx, mm, gg, a, nthr, lds, grid, a0, a1, b0, b1);
+    else if (nthr <= 256) rc = launch_mm<T, 256, WS>(ctx, mm, gg, a, nthr, lds, grid, a0, a1, b0, b1);
     else if (nthr <= 512) rc = launch_mm<T, 512, WS>(ctx, mm, gg, a, nthr, lds, grid, a0, a1, b0, b1);
     else rc = launch_mm<T, 1024, WS>(ctx, mm, gg, a, nthr, lds, grid, a0, a1, b0, b1);
     if (rc == STK_OK) *done = true;
@@ -719,11 +778,23 @@ int try_stream(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, int Tx, int T
     a.kt = kt;
     a.sx = sx;
     a.sy = sy;
+    if constexpr (sizeof(T) == 8) {
+        // FP64, many sweeps, full overlap: tiles of 63 - 2kt columns, so that the window
+        // (63 columns) needs no remainder wave and the level-factor instance applies
+        // (the owned values do not depend on the cuts)
+        if (kt >= LG_MIN_K && h >= kt - 1 && 63 - 2 * kt >= 8) {
+            a.Tx = Tx = 63 - 2 * kt;
+            a.sx = sx % Tx;
+        }
+    }
     a.Wm = (int)std::min<int64_t>((int64_t)Tx + 2 * (int64_t)h, g->nx) + 2;
     // (the output stores address one row at a time through 32-bit buffer offsets)
     if (a.Wm > WS_WIDE || kt > 16 || g->ny + 1 > YMASK || (int64_t)(g->nx + 1) * (int64_t)sizeof(T) >= INT32_MAX ||
         (int64_t)g->ny * g->ld >= INT32_MAX)
         return STK_OK;
+    if constexpr (sizeof(T) == 8)
+        if (kt >= LG_MIN_K && h >= kt - 1 && a.Wm <= 63)
+            return try_stream_ws<T, WS_LG>(ctx, g, gg, a, vx, vy, ox, oy, done);
     if (a.Wm <= WS_NARROW) return try_stream_ws<T, WS_NARROW>(ctx, g, gg, a, vx, vy, ox, oy, done);
     return try_stream_ws<T, WS_WIDE>(ctx, g, gg, a, vx, vy, ox, oy, done);
 }
@@ -744,6 +815,7 @@ int launch_batch_t(stk_ctx* ctx, const RasShape& sh, const void* jobs, const int
     a.kt = sh.kt;
     a.sx = a.sy = sh.tile;  // cuts at multiples of the tile, the first tile at 0
     a.NT = sh.NT;
+    a.merge = sh.merge;
     a.Wm = sh.Wm;
     a.Vmax = sh.Vmax;
     hipLaunchKernelGGL((k_ras_batch<T, NTMAX, MM, WS>), dim3((unsigned)sh.nwg), dim3(sh.nthr), sh.lds, ctx->stream,
@@ -760,6 +832,7 @@ int launch_batch_mm(stk_ctx* ctx, const RasShape& sh, const void* jobs, const in
 }
 template <typename T, int WS>
 int launch_batch_ws(stk_ctx* ctx, const RasShape& sh, const void* jobs, const int* pre, int n, T omega) {
+    if constexpr (level_factors(WS)) return launch_batch_mm<T, 1024, WS>(ctx, sh, jobs, pre, n, omega);
     if (sh.nthr <= 256) return launch_batch_mm<T, 256, WS>(ctx, sh, jobs, pre, n, omega);
     if (sh.nthr <= 512) return launch_batch_mm<T, 512, WS>(ctx, sh, jobs, pre, n, omega);
     return launch_batch_mm<T, 1024, WS>(ctx, sh, jobs, pre, n, omega);
@@ -775,15 +848,24 @@ void batch_shape_ws(stk_ctx* ctx, const int* nx, const int* ny, int n, int tile,
     if (nthr > 1024) return;
     const int mm = feeder_loads(Wm);
     const int D = std::min(kt, h + 1);
-    int rows = 0;
-    for (int q = 0; q < n; ++q)
-        rows = std::max<int>(rows, (int)std::min<int64_t>(std::min<int64_t>((int64_t)tile + 2 * (int64_t)h, ny[q]) + 2,
-                                                          std::min<int64_t>(tile, ny[q]) + 2 * D));
+    const bool merge = h >= kt - 1;  // full overlap: a workgroup's tiles are streamed as one
+    // stream rows of NT tiles, the most over the instances
+    auto stream_rows = [&](int NT) {
+        int rows = 0;
+        for (int q = 0; q < n; ++q) {
+            auto tr = [&](int64_t H) {
+                return (int)std::min<int64_t>(std::min<int64_t>(H + 2 * (int64_t)h, ny[q]) + 2,
+                                              std::min<int64_t>(H, ny[q]) + 2 * D);
+            };
+            rows = std::max(rows, merge ? tr((int64_t)NT * tile) : NT * tr(tile));
+        }
+        return rows;
+    };
     double best_cost = 1e300;
     for (int NT = 1; NT <= 8; ++NT) {
         RasArgs t{};
         t.kt = kt;
-        t.Vmax = NT * rows;
+        t.Vmax = stream_rows(NT);
         const size_t l = stream_lds_bytes<T, WS>(t);
         if (l > (size_t)ctx->lds_max) break;
         int per_cu = stream_occupancy<T, WS>(ctx->device, nthr, mm, l);
@@ -795,11 +877,11 @@ void batch_shape_ws(stk_ctx* ctx, const int* nx, const int* ny, int n, int tile,
             nwg += (int64_t)ntx * ((nty + NT - 1) / NT);
         }
         const int64_t slots = (int64_t)per_cu * std::max(ctx->num_cu, 1);
-        const double cost = (double)((nwg + slots - 1) / slots) * (NT * rows + 2 * kt + 1);
+        const double cost = (double)((nwg + slots - 1) / slots) * (t.Vmax + 2 * kt + 1);
         if (cost < best_cost && nwg < INT32_MAX) {
             best_cost = cost;
             out->NT = NT;
-            out->Vmax = NT * rows;
+            out->Vmax = t.Vmax;
             out->lds = l;
             out->nwg = (int)nwg;
         }
@@ -808,6 +890,7 @@ void batch_shape_ws(stk_ctx* ctx, const int* nx, const int* ny, int n, int tile,
     out->tile = tile;
     out->h = h;
     out->kt = kt;
+    out->merge = merge ? 1 : 0;
     out->Wm = Wm;
     out->nthr = nthr;
     out->mm = mm;
@@ -835,15 +918,26 @@ void batch_shape(stk_ctx* ctx, const int* nx, const int* ny, const int64_t* ld, 
         Wm = std::max<int>(Wm, (int)std::min<int64_t>((int64_t)tile + 2 * (int64_t)h, nx[q]) + 2);
     }
     if (Wm > WS_WIDE) return;
+    if constexpr (sizeof(T) == 8)
+        if (kt >= LG_MIN_K && h >= kt - 1 && Wm <= 63)
+            return batch_shape_ws<T, WS_LG>(ctx, nx, ny, n, tile, h, kt, Wm, out, pre, ntx, ok);
     if (Wm <= WS_NARROW) batch_shape_ws<T, WS_NARROW>(ctx, nx, ny, n, tile, h, kt, Wm, out, pre, ntx, ok);
     else batch_shape_ws<T, WS_WIDE>(ctx, nx, ny, n, tile, h, kt, Wm, out, pre, ntx, ok);
 }
 
 }  // namespace
 
+// Overlap beyond kt - 1 cannot reach the owned cells: after kt sweeps an owned
+// value depends on the snapshot within kt cells, and a frozen ring at distance
+// kt (overlap kt - 1) enters only sweep-1 values at distance kt - 1, which
+// are exact.  Every overlap h >= kt - 1 therefore gives the same values (kt
+// Jacobi sweeps), and the narrowest window is streamed.
+inline int effective_halo(int h, int kt) { return std::min(h, std::max(kt - 1, 0)); }
+
 int launch_ras_stream(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const FieldPtrs& f, double omega, int tile_x,
                       int tile_y, int halo, int kt, int sx, int sy, const void* vx, const void* vy, void* ox, void* oy,
                       bool* done) {
+    halo = effective_halo(halo, kt);
     if (dt == STK_F64) {
         Grid<double> gg{static_cast<const double*>(f.eta_c), static_cast<const double*>(f.eta_n),
                         static_cast<const double*>(f.bx), static_cast<const double*>(f.by), g->ld, g->nx, g->ny,
@@ -862,6 +956,7 @@ namespace stk {
 
 int ras_batch_shape(stk_ctx* ctx, stk_dtype dt, const int* nx, const int* ny, const int64_t* ld, int n, int tile,
                     int h, int kt, RasShape* out, std::vector<int>* pre, std::vector<int>* ntx, bool* ok) {
+    h = effective_halo(h, kt);
     if (dt == STK_F64) batch_shape<double>(ctx, nx, ny, ld, n, tile, h, kt, out, pre, ntx, ok);
     else batch_shape<float>(ctx, nx, ny, ld, n, tile, h, kt, out, pre, ntx, ok);
     return STK_OK;
@@ -871,8 +966,9 @@ int ras_batch_launch(stk_ctx* ctx, stk_dtype dt, const RasShape& s, const void* 
                      double omega) {
     if (n < 1 || s.nwg < 1) return STK_OK;
     if (dt == STK_F64)
-        return s.ws == WS_NARROW ? launch_batch_ws<double, WS_NARROW>(ctx, s, jobs, pre, n, omega)
-                                 : launch_batch_ws<double, WS_WIDE>(ctx, s, jobs, pre, n, omega);
+        return s.ws == WS_LG       ? launch_batch_ws<double, WS_LG>(ctx, s, jobs, pre, n, omega)
+               : s.ws == WS_NARROW ? launch_batch_ws<double, WS_NARROW>(ctx, s, jobs, pre, n, omega)
+                                   : launch_batch_ws<double, WS_WIDE>(ctx, s, jobs, pre, n, omega);
     return s.ws == WS_NARROW ? launch_batch_ws<float, WS_NARROW>(ctx, s, jobs, pre, n, float(omega))
                              : launch_batch_ws<float, WS_WIDE>(ctx, s, jobs, pre, n, float(omega));
 }

@@ -94,6 +94,7 @@ struct RasJob {
 // Launch shape of a batched RAS outer iteration, shared by its instances.
 struct RasShape {
     int tile, h, kt, NT, Wm, Vmax, nthr, mm, ws, nwg;
+    int merge;  // full overlap: a workgroup's NT tiles are streamed as one
     size_t lds;
 };
 // Shape for instances of nx[i] x ny[i] cells (square tiles cut at multiples
