@@ -711,7 +711,9 @@ int try_stream_ws(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, RasArgs a,
     const int nthr = 64 * (level_waves(a.Wm, kt) + NF);
     if (nthr > 1024) return STK_OK;
     const int mm = feeder_loads(a.Wm);  // 2 or 3 for Wm <= WS_WIDE
-    const int ntx = (g->nx + Tx - 1) / Tx + 1, nty = (g->ny + Ty - 1) / Ty + 1;
+    // tiles cut at s + m T: one more tile column (row) for the partial tile before the
+    // first cut, none when the cuts fall on multiples of T (s == T)
+    const int ntx = (g->nx + Tx - 1) / Tx + (a.sx == Tx ? 0 : 1), nty = (g->ny + Ty - 1) / Ty + (a.sy == Ty ? 0 : 1);
     // rows of a tile of height H in the stream: at most H + 2 min(kt, h + 1), and at most the window's
     const int D = std::min(kt, h + 1);
     auto tile_rows = [&](int64_t H) {
@@ -786,6 +788,11 @@ int try_stream(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, int Tx, int T
             a.Tx = Tx = 63 - 2 * kt;
             a.sx = sx % Tx;
         }
+    }
+    if (h >= kt - 1) {  // full overlap: the shift does not matter either; cut at multiples of the
+                        // tile, the first tile at 0 (no partial tile column or row)
+        a.sx = a.Tx;
+        a.sy = a.Ty;
     }
     a.Wm = (int)std::min<int64_t>((int64_t)Tx + 2 * (int64_t)h, g->nx) + 2;
     // (the output stores address one row at a time through 32-bit buffer offsets)
