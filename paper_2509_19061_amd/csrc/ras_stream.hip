@@ -91,10 +91,13 @@ __device__ __forceinline__ void lds_barrier() {
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
 // LDS row stride WS (elements): a compile-time bound on the window width, so
-// that row offsets fold into the instructions.  The narrow stride keeps an
-// FP64 workgroup with T = 64, h = k <= 5 within a third of the CU's LDS (three
-// resident workgroups); wider windows take the wide one.
-constexpr int WS_NARROW = 76, WS_WIDE = 96;
+// that row offsets fold into the instructions.  The narrow stride takes the
+// windows of T = 64 with overlap up to 3 (full overlap up to k = 4, whose
+// overlap is streamed as k - 1) and keeps such an FP64 workgroup within a
+// third of the CU's LDS (three resident workgroups) with room for a row table
+// of some 350 rows (one tall tile per workgroup); wider windows take the wide
+// one.
+constexpr int WS_NARROW = 72, WS_WIDE = 96;
 // A third stride for FP64 windows of many sweeps with full overlap (kt >= 6,
 // window <= 63 columns, so no remainder wave).  Its instances keep four
 // coefficient fields per row (A, N, bx, by).  The level waves compute the
@@ -719,41 +722,77 @@ int try_stream_ws(stk_ctx* ctx, const stk_grid* g, const Grid<T>& gg, RasArgs a,
     auto tile_rows = [&](int64_t H) {
         return (int)std::min<int64_t>(std::min<int64_t>(H + 2 * (int64_t)h, g->ny) + 2, std::min<int64_t>(H, g->ny) + 2 * D);
     };
-    // full overlap: the owned values do not depend on where the tiles are cut, so a
-    // workgroup's NT tiles are streamed as one (fewer overlap rows)
-    a.merge = h >= kt - 1 ? 1 : 0;
-    auto stream_rows = [&](int NT) { return a.merge ? tile_rows((int64_t)NT * Ty) : NT * tile_rows(Ty); };
-    // Tiles per workgroup NT: a workgroup streams NT tiles (stream rows + 2kt + 1 steps);
-    // pick the NT that minimises (rounds of resident workgroups) x (steps per workgroup).
-    // Residency counts LDS in 2 KiB granules against the CU's LDS as well as the
-    // occupancy query: a workgroup just over a third of the LDS is resident only
-    // twice per CU, whatever the query says.
-    int best_nt = 1;
+    // Resident workgroups per CU: the occupancy query, and LDS counted in 2 KiB
+    // granules against the CU's LDS (a workgroup just over a third of the LDS is
+    // resident only twice per CU, whatever the query says).
+    auto slots_for = [&](size_t l, int occ) -> int64_t {
+        if (l > (size_t)ctx->lds_max) return 0;
+        int per_cu = occ;
+        if (ctx->lds_cu > 0) per_cu = std::min<int>(per_cu, ctx->lds_cu / (int)((l + 2047) & ~size_t(2047)));
+        return (int64_t)std::max(per_cu, 0) * std::max(ctx->num_cu, 1);
+    };
+    // Launch time model: (rounds of resident workgroups) x (row steps per workgroup).
     double best_cost = 1e300;
     size_t lds = 0;
-    for (int NT = 1; NT <= 8; ++NT) {
-        RasArgs t = a;
-        t.NT = NT;
-        t.Vmax = stream_rows(NT);
-        const size_t l = stream_lds_bytes<T, WS>(t);
-        if (l > (size_t)ctx->lds_max) break;
-        int per_cu = stream_occupancy<T, WS>(ctx->device, nthr, mm, l);
-        if (ctx->lds_cu > 0) per_cu = std::min<int>(per_cu, ctx->lds_cu / (int)((l + 2047) & ~size_t(2047)));
-        if (per_cu < 1) break;
-        const int64_t nwg = (int64_t)ntx * ((nty + NT - 1) / NT);
-        const int64_t slots = (int64_t)per_cu * std::max(ctx->num_cu, 1);
-        const double cost = (double)((nwg + slots - 1) / slots) * (stream_rows(NT) + 2 * kt + 1);
-        if (cost < best_cost) {
-            best_cost = cost;
-            best_nt = NT;
-            lds = l;
+    if (h >= kt - 1) {
+        // Full overlap: the owned values do not depend on where the tiles are cut, so each
+        // workgroup streams one tile of H rows (no overlap rows inside it), cut at multiples
+        // of H; H is chosen by the model, so that the workgroups fill whole rounds.
+        a.merge = 1;
+        a.NT = 1;
+        RasArgs t0 = a;
+        t0.Vmax = 0;
+        const int occ = stream_occupancy<T, WS>(ctx->device, nthr, mm, stream_lds_bytes<T, WS>(t0));
+        int best_h = 0, last_h = -1;
+        for (int r = 1; r <= std::max(1, g->ny / 16); ++r) {  // r tile rows (H >= 16)
+            const int H = (g->ny + r - 1) / r;
+            if (H == last_h) continue;
+            last_h = H;
+            RasArgs t = a;
+            t.Vmax = tile_rows(H);
+            const size_t l = stream_lds_bytes<T, WS>(t);
+            const int64_t slots = slots_for(l, occ);
+            if (slots < 1) continue;
+            const int64_t nwg = (int64_t)ntx * ((g->ny + H - 1) / H);
+            const double cost = (double)((nwg + slots - 1) / slots) * (tile_rows(H) + 2 * kt + 1);
+            if (cost < best_cost) {
+                best_cost = cost;
+                best_h = H;
+                lds = l;
+            }
         }
+        if (best_cost >= 1e300) return STK_OK;
+        a.Ty = a.sy = best_h;
+        a.Vmax = tile_rows(best_h);
+        a.ntx = ntx;
+        a.nwg = ntx * ((g->ny + best_h - 1) / best_h);
+    } else {
+        // Tiles per workgroup NT: a workgroup streams NT tiles (NT (rows of a tile) + 2kt + 1
+        // steps); pick the NT of least cost.
+        a.merge = 0;
+        int best_nt = 1;
+        for (int NT = 1; NT <= 8; ++NT) {
+            RasArgs t = a;
+            t.NT = NT;
+            t.Vmax = NT * tile_rows(Ty);
+            const size_t l = stream_lds_bytes<T, WS>(t);
+            if (l > (size_t)ctx->lds_max) break;
+            const int64_t slots = slots_for(l, stream_occupancy<T, WS>(ctx->device, nthr, mm, l));
+            if (slots < 1) break;
+            const int64_t nwg = (int64_t)ntx * ((nty + NT - 1) / NT);
+            const double cost = (double)((nwg + slots - 1) / slots) * (NT * tile_rows(Ty) + 2 * kt + 1);
+            if (cost < best_cost) {
+                best_cost = cost;
+                best_nt = NT;
+                lds = l;
+            }
+        }
+        if (best_cost >= 1e300) return STK_OK;
+        a.NT = best_nt;
+        a.Vmax = best_nt * tile_rows(Ty);
+        a.ntx = ntx;
+        a.nwg = ntx * ((nty + best_nt - 1) / best_nt);
     }
-    if (best_cost >= 1e300) return STK_OK;
-    a.NT = best_nt;
-    a.Vmax = stream_rows(best_nt);
-    a.ntx = ntx;
-    a.nwg = ntx * ((nty + best_nt - 1) / best_nt);
     const dim3 grid((unsigned)a.nwg);
     auto* a0 = static_cast<const T*>(vx);
     auto* a1 = static_cast<const T*>(vy);
