@@ -109,6 +109,9 @@ def main():
     ap.add_argument("--serve", type=int, default=16, help="requests per serving run (0: skip)")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95", help="Poisson loads as fractions of saturation")
     ap.add_argument("--uzawa-n", type=int, default=4096, help="Uzawa workload size (0: skip)")
+    ap.add_argument("--floor-n", type=int, default=0,
+                    help="FP64 floor of E_v: the n^2 contrast-1e6 sinker solve at growing iteration budgets (0: skip)")
+    ap.add_argument("--floor-budgets", default="250,500,1000,2000,4000")
     ap.add_argument("--uzawa-parts", default="all", choices=["all", "solve"],
                     help="'solve': only the contrast-1e2 solves (FP64 and FP32 V-cycle) and the pressure step")
     args = ap.parse_args()
@@ -314,6 +317,8 @@ def main():
     loads = [float(x) for x in args.serve_loads.split(",") if x.strip()]
     served = run_serve(ctx, args.serve, loads=loads) if args.serve > 0 else None
     uz = run_uzawa(ctx, args.uzawa_n, parts=args.uzawa_parts) if args.uzawa_n > 0 else None
+    floor = (run_floor(ctx, args.floor_n, [int(x) for x in args.floor_budgets.split(",") if x.strip()])
+             if args.floor_n > 0 else None)
 
     out = {
         "metric": "smoother GLUP/s + % HBM roofline (RAS-Jacobi)",
@@ -349,6 +354,7 @@ def main():
         "batch": batch,
         "serve": served,
         "uzawa": uz,
+        "fp64_floor": floor,
     }
     print(json.dumps(out), flush=True)
     if kctx is not ctx:
@@ -731,6 +737,34 @@ def run_3d(ctx, n, sweeps=20):
         del dp
         torch.cuda.empty_cache()
     return out
+
+
+def run_floor(ctx, n, budgets, tol=1e-12):
+    """The FP64 floor of the velocity energy residual: FCG solves of the n^2
+    smoother workload (8 sinkers, contrast 1e6) from zero with a tolerance
+    below what FP64 can reach, stopped at growing iteration budgets.  The
+    reported E_v is the true residual recomputed at the stop (the solve
+    restarts CG from its iterate whenever the recurrence residual falls below
+    tol while the true one does not)."""
+    import torch
+
+    from paper_2509_19061_amd import api, fields, inputs
+
+    prob = inputs.smoother_workload(n, 2)
+    dp = fields.DeviceProblem(prob, torch.float64)
+    m = api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n)
+    rows = []
+    for b in budgets:
+        vx, vy = dp.velocity()
+        rep, secs = _timed(lambda: m.solve("f64", vx, vy, None, dp.fx, dp.fy, tol=tol, max_iters=b,
+                                            allow_notconv=True))
+        ev = float(api.energy_norm(ctx, torch.float64, dp.grid, vx, vy, None, dp.eta_c, dp.eta_n, dp.fx, dp.fy)[4])
+        rows.append({"budget": b, "iterations": rep["iterations"], "ev_true": ev, "seconds": round(secs, 3)})
+        log(f"[bench] floor {n}^2: budget {b}: E_v {ev:.3e} after {rep['iterations']} iterations ({secs:.2f}s)")
+        del vx, vy
+    m.close()
+    return {"workload": f"{n}x{n} smoother workload (8 sinkers, eta 1e6 / 1), FP64 FCG + V(2,2), tol {tol}",
+            "n": n, "runs": rows}
 
 
 def run_config3(ctx, n, cap, cap_iid, tol=1e-8):
