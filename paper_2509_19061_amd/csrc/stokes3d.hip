@@ -20,6 +20,13 @@
 //                smoother and the residual call the same row functions, so
 //                RAS with an overlap >= k - 1 is bit-identical to k Jacobi
 //                sweeps.
+//   k_jacobi3d_z the same sweep with the velocity staged plane by plane: a
+//                64 x 4 workgroup walks up a segment of z-planes with a ring
+//                of four planes (the planes k - 1, k, k + 1 it reads, and
+//                k + 2, loaded meanwhile) of the three components in LDS,
+//                halo included; the coefficients come from global memory.
+//                Same operands, same row functions: the same values as
+//                k_jacobi3d.
 //   k_ras3d      one workgroup per T^3 tile: the tile grown by h plus the
 //                one-cell frozen ring is staged in LDS (three components,
 //                two buffers), k sweeps run there with a barrier between
@@ -33,6 +40,7 @@
 
 #include "stencil.hpp"
 #include "stk_internal.hpp"
+#include "wave.hpp"
 
 namespace stk {
 namespace {
@@ -166,6 +174,103 @@ __global__ __launch_bounds__(J3X* J3Y) void k_jacobi3d(Fields3<T> f, T omega, co
             o = jac_step<T>(vz[q], omega / d, f.bz[q], m);
         }
         oz[q] = o;
+    }
+}
+
+// --------------------------------------------- Jacobi (3D), plane streaming --
+constexpr int ZX = 64, ZY = 4, ZS = 32;               // tile columns, rows, planes per segment
+constexpr int ZWX = ZX + 2, ZWY = ZY + 2;              // staged window (one halo cell each side)
+constexpr int ZPL = ZWX * ZWY;                         // window cells of one plane
+constexpr int ZSLOT = 3 * ZPL;                         // one ring slot: three components
+constexpr int ZLOADS = (ZSLOT + ZX * ZY - 1) / (ZX * ZY);  // loads per thread per plane
+
+// Velocity loader of the staged ring: (c, i, j, k) -> the window cell, for
+// i0 - 1 <= i <= i0 + 64, j0 - 1 <= j <= j0 + 4 and any of the three planes
+// in the ring.
+template <typename T>
+struct RingV {
+    const T* w;
+    int i0, j0;
+    __device__ __forceinline__ T operator()(int c, int i, int j, int k) const {
+        return w[(k & 3) * ZSLOT + c * ZPL + (j - j0 + 1) * ZWX + (i - i0 + 1)];
+    }
+};
+
+// The window of plane k: the staged value of every cell, 0 for a wall or a
+// cell outside the arrays (the gather's operands).
+template <typename T>
+__device__ __forceinline__ void load_plane(const GlobalV<T>& g, int i0, int j0, int k, T (&r)[ZLOADS]) {
+#pragma unroll
+    for (int m = 0; m < ZLOADS; ++m) {
+        const int e = (int)threadIdx.x + m * ZX * ZY;
+        const int c = e / ZPL, rr = e - c * ZPL, wy = rr / ZWX, wx = rr - wy * ZWX;
+        r[m] = e < ZSLOT ? g(c, i0 - 1 + wx, j0 - 1 + wy, k) : T(0);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void store_plane(T* w, int k, const T (&r)[ZLOADS]) {
+#pragma unroll
+    for (int m = 0; m < ZLOADS; ++m) {
+        const int e = (int)threadIdx.x + m * ZX * ZY;
+        if (e < ZSLOT) w[(k & 3) * ZSLOT + e] = r[m];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(ZX* ZY) void k_jacobi3d_z(Fields3<T> f, T omega, const T* __restrict__ vx,
+                                                        const T* __restrict__ vy, const T* __restrict__ vz,
+                                                        T* __restrict__ ox, T* __restrict__ oy, T* __restrict__ oz,
+                                                        int ntx, int nty) {
+    __shared__ T ring[4 * ZSLOT];
+    const int nx = f.nx, ny = f.ny, nz = f.nz;
+    // tiles numbered x fastest, then y, then z segments, renumbered by XCD
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+    const int i0 = tx * ZX, j0 = ty * ZY, k0 = tz * ZS, k1 = min(k0 + ZS, nz + 1);
+    const int i = i0 + (int)(threadIdx.x % ZX), j = j0 + (int)(threadIdx.x / ZX);
+    const GlobalV<T> gv{vx, vy, vz, f.ld, f.lp, nx, ny, nz};
+    T r[ZLOADS];
+    load_plane<T>(gv, i0, j0, k0 - 1, r);
+    store_plane<T>(ring, k0 - 1, r);
+    load_plane<T>(gv, i0, j0, k0, r);
+    store_plane<T>(ring, k0, r);
+    load_plane<T>(gv, i0, j0, k0 + 1, r);
+    store_plane<T>(ring, k0 + 1, r);
+    __syncthreads();
+    const RingV<T> v{ring, i0, j0};
+    for (int k = k0; k < k1; ++k) {
+        load_plane<T>(gv, i0, j0, k + 2, r);  // in flight while plane k is relaxed
+        if (i <= nx && j <= ny) {
+            const int64_t q = at3(f, i, j, k);
+            T d;
+            if (k < nz && j < ny) {
+                T o = T(0);
+                if (vx_unknown3(nx, ny, nz, i, j, k)) {
+                    const T m = mvx3<T>(f, v, i, j, k, d);
+                    o = jac_step<T>(v(0, i, j, k), omega / d, f.bx[q], m);
+                }
+                ox[q] = o;
+            }
+            if (k < nz && i < nx) {
+                T o = T(0);
+                if (vy_unknown3(nx, ny, nz, i, j, k)) {
+                    const T m = mvy3<T>(f, v, i, j, k, d);
+                    o = jac_step<T>(v(1, i, j, k), omega / d, f.by[q], m);
+                }
+                oy[q] = o;
+            }
+            if (j < ny && i < nx) {
+                T o = T(0);
+                if (vz_unknown3(nx, ny, nz, i, j, k)) {
+                    const T m = mvz3<T>(f, v, i, j, k, d);
+                    o = jac_step<T>(v(2, i, j, k), omega / d, f.bz[q], m);
+                }
+                oz[q] = o;
+            }
+        }
+        // slot (k + 2) & 3 held plane k - 2, last read in the previous step
+        store_plane<T>(ring, k + 2, r);
+        __syncthreads();
     }
 }
 
@@ -388,9 +493,17 @@ int check_grid3(const stk_grid3* g) {
 template <typename T>
 int launch_jacobi3d(stk_ctx* ctx, const stk_grid3* g, const Fields3<T>& f, double omega, const void* vx,
                     const void* vy, const void* vz, void* ox, void* oy, void* oz) {
-    hipLaunchKernelGGL(k_jacobi3d<T>, grid3(g), dim3(J3X, J3Y), 0, ctx->stream, f, T(omega),
-                       static_cast<const T*>(vx), static_cast<const T*>(vy), static_cast<const T*>(vz),
-                       static_cast<T*>(ox), static_cast<T*>(oy), static_cast<T*>(oz));
+    const int ntx = (g->nx + 1 + ZX - 1) / ZX, nty = (g->ny + 1 + ZY - 1) / ZY, ntz = (g->nz + 1 + ZS - 1) / ZS;
+    const int64_t nwg = (int64_t)ntx * nty * ntz;
+    if (nwg < INT32_MAX) {
+        hipLaunchKernelGGL(k_jacobi3d_z<T>, dim3((unsigned)nwg), dim3(ZX * ZY), 0, ctx->stream, f, T(omega),
+                           static_cast<const T*>(vx), static_cast<const T*>(vy), static_cast<const T*>(vz),
+                           static_cast<T*>(ox), static_cast<T*>(oy), static_cast<T*>(oz), ntx, nty);
+    } else {
+        hipLaunchKernelGGL(k_jacobi3d<T>, grid3(g), dim3(J3X, J3Y), 0, ctx->stream, f, T(omega),
+                           static_cast<const T*>(vx), static_cast<const T*>(vy), static_cast<const T*>(vz),
+                           static_cast<T*>(ox), static_cast<T*>(oy), static_cast<T*>(oz));
+    }
     STK_HIP(hipGetLastError());
     return STK_OK;
 }
