@@ -92,31 +92,49 @@ __host__ __device__ __forceinline__ T stencil_coef(const T* st, int64_t plane, i
     return (pi >= 0 && pi <= nx && pj >= 0 && pj <= ny) ? st[src.plane * plane + (int64_t)pj * ld + pi] : T(0);
 }
 
-// (A v) at the unknown (a, i, j) from the stored stencil; also returns the
-// diagonal coefficient.  Fixed slot order.
-template <typename T>
-__device__ __forceinline__ T stencil_av(const T* __restrict__ st, int64_t plane, int a, const T* __restrict__ vx,
-                                        const T* __restrict__ vy, int64_t ld, int nx, int ny, int i, int j,
-                                        T& diag) {
+// (A v) at the unknown (a, i, j) from the stored stencil, with v(c, i, j)
+// given by the loader lv (component c, 0 outside the grid and on the walls);
+// also returns the diagonal coefficient.  Fixed slot order: every kernel that
+// applies a stored stencil goes through this function, so they agree bit for
+// bit.
+template <typename T, typename LV>
+__device__ __forceinline__ T stencil_av_l(const T* __restrict__ st, int64_t plane, int a, const LV& lv, int64_t ld,
+                                          int nx, int ny, int i, int j, T& diag) {
     T s = T(0);
     if (a == 0) {
 #pragma unroll
         for (int q = 0; q < NCOEF; ++q) {
-            const int dx = slot_dx(0, q), dy = slot_dy(0, q);
-            const T v = slot_comp(0, q) == 0 ? ldvx<T>(vx, ld, nx, ny, i + dx, j + dy) : ldvy<T>(vy, ld, nx, ny, i + dx, j + dy);
+            const T v = lv(slot_comp(0, q), i + slot_dx(0, q), j + slot_dy(0, q));
             s += stencil_coef<T>(st, plane, ld, nx, ny, 0, q, i, j) * v;
         }
         diag = st[(int64_t)j * ld + i];
     } else {
 #pragma unroll
         for (int q = 0; q < NCOEF; ++q) {
-            const int dx = slot_dx(1, q), dy = slot_dy(1, q);
-            const T v = slot_comp(1, q) == 0 ? ldvx<T>(vx, ld, nx, ny, i + dx, j + dy) : ldvy<T>(vy, ld, nx, ny, i + dx, j + dy);
+            const T v = lv(slot_comp(1, q), i + slot_dx(1, q), j + slot_dy(1, q));
             s += stencil_coef<T>(st, plane, ld, nx, ny, 1, q, i, j) * v;
         }
         diag = st[PL_VY * plane + (int64_t)j * ld + i];
     }
     return s;
+}
+
+// the velocity pair in global memory
+template <typename T>
+struct GlobalPair {
+    const T *vx, *vy;
+    int64_t ld;
+    int nx, ny;
+    __device__ __forceinline__ T operator()(int c, int i, int j) const {
+        return c == 0 ? ldvx<T>(vx, ld, nx, ny, i, j) : ldvy<T>(vy, ld, nx, ny, i, j);
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ T stencil_av(const T* __restrict__ st, int64_t plane, int a, const T* __restrict__ vx,
+                                        const T* __restrict__ vy, int64_t ld, int nx, int ny, int i, int j,
+                                        T& diag) {
+    return stencil_av_l<T>(st, plane, a, GlobalPair<T>{vx, vy, ld, nx, ny}, ld, nx, ny, i, j, diag);
 }
 
 }  // namespace stk

@@ -62,31 +62,80 @@ __device__ __forceinline__ Grid<T> job_grid(const LevelJob<T>& J, const T* bx, c
 }
 
 // ---------------------------------------------------------------- smoother --
+// Stored-stencil levels in FP64: the velocity of a workgroup's 64 x 4 patch,
+// grown by the stencil's reach of two cells, is staged in LDS (0 outside the
+// grid and on the walls, the operands of the global loaders), and the rows
+// read it from there; the coefficients come from global memory.  In FP64 this
+// cut a thread's registers from 196 to 128 VGPRs (twice the resident waves)
+// and the 2048^2 solve iteration from 1.49 to 1.39 ms.  In FP32 the staged
+// form (78 VGPRs) was slower than the gather (1.325 against 1.286 s for the
+// 2048^2 FP32 V-cycle solve, interleaved runs), so FP32 levels gather.  Same
+// row function (stencil_av_l) either way.
+constexpr int SWX = BX + 4, SWY = BY + 4;  // staged window
+template <typename T>
+struct PatchPair {
+    const T* win;
+    int i0, j0;  // cell of window element (0, 0)
+    __device__ __forceinline__ T operator()(int c, int i, int j) const {
+        return win[(c * SWY + (j - j0)) * SWX + (i - i0)];
+    }
+};
+template <typename T>
+__device__ __forceinline__ PatchPair<T> stage_patch(T* win, const T* vx, const T* vy, int64_t ld, int nx, int ny,
+                                                    int i, int j) {
+    const int i0 = i - (int)(threadIdx.x % BX) - 2, j0 = j - (int)(threadIdx.x / BX) - 2;
+    for (int e = threadIdx.x; e < 2 * SWY * SWX; e += NT) {
+        const int c = e / (SWY * SWX), r = (e / SWX) % SWY, x = e % SWX;
+        win[e] = c == 0 ? ldvx<T>(vx, ld, nx, ny, i0 + x, j0 + r) : ldvy<T>(vy, ld, nx, ny, i0 + x, j0 + r);
+    }
+    __syncthreads();
+    return PatchPair<T>{win, i0, j0};
+}
+
 // One damped Jacobi sweep (dir 0: v -> w, dir 1: w -> v), the shared update.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_jacobi(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
                                                   int n, T omega, int dir) {
     STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
-    if (i > J.nx || j > J.ny) return;
-    const Grid<T> g = job_grid(J, J.bx, J.by, omega);
     const T* sx = dir ? J.wx : J.vx;
     const T* sy = dir ? J.wy : J.vy;
     T* dx_ = dir ? J.vx : J.wx;
     T* dy_ = dir ? J.vy : J.wy;
     const int64_t k = (int64_t)j * J.ld + i;
-    if (J.st) {  // stored Galerkin stencil: m = M v = -(A v), g = omega / A_ii
-        for (int a = 0; a < 2; ++a) {
-            if (a == 0 ? j >= J.ny : i >= J.nx) continue;
-            T out = T(0);
-            if (a == 0 ? is_vx_unknown(J.nx, J.ny, i, j) : is_vy_unknown(J.nx, J.ny, i, j)) {
-                T d;
-                const T av = stencil_av<T>(J.st, J.plane, a, sx, sy, J.ld, J.nx, J.ny, i, j, d);
-                out = jac_step<T>((a == 0 ? sx : sy)[k], omega / d, (a == 0 ? J.bx : J.by)[k], -av);
+    if (J.st) {  // stored Galerkin stencil: m = M v = -(A v), g = omega / A_ii (the instance is the block's)
+        auto sweep = [&](const auto& lv) {
+            if (i > J.nx || j > J.ny) return;
+            for (int a = 0; a < 2; ++a) {
+                if (a == 0 ? j >= J.ny : i >= J.nx) continue;
+                T out = T(0);
+                if (a == 0 ? is_vx_unknown(J.nx, J.ny, i, j) : is_vy_unknown(J.nx, J.ny, i, j)) {
+                    T d;
+                    const T av = stencil_av_l<T>(J.st, J.plane, a, lv, J.ld, J.nx, J.ny, i, j, d);
+                    out = jac_step<T>(lv(a, i, j), omega / d, (a == 0 ? J.bx : J.by)[k], -av);
+                }
+                (a == 0 ? dx_ : dy_)[k] = out;
             }
-            (a == 0 ? dx_ : dy_)[k] = out;
+        };
+        if constexpr (sizeof(T) == 8) {
+            __shared__ T win[2 * SWY * SWX];
+            sweep(stage_patch<T>(win, sx, sy, J.ld, J.nx, J.ny, i, j));
+        } else {
+            if (i > J.nx || j > J.ny) return;
+            for (int a = 0; a < 2; ++a) {
+                if (a == 0 ? j >= J.ny : i >= J.nx) continue;
+                T out = T(0);
+                if (a == 0 ? is_vx_unknown(J.nx, J.ny, i, j) : is_vy_unknown(J.nx, J.ny, i, j)) {
+                    T d;
+                    const T av = stencil_av<T>(J.st, J.plane, a, sx, sy, J.ld, J.nx, J.ny, i, j, d);
+                    out = jac_step<T>((a == 0 ? sx : sy)[k], omega / d, (a == 0 ? J.bx : J.by)[k], -av);
+                }
+                (a == 0 ? dx_ : dy_)[k] = out;
+            }
         }
         return;
     }
+    if (i > J.nx || j > J.ny) return;
+    const Grid<T> g = job_grid(J, J.bx, J.by, omega);
     if (j < J.ny) dx_[k] = is_vx_unknown(J.nx, J.ny, i, j) ? jac_vx_global(g, sx, sy, i, j) : T(0);
     if (i < J.nx) dy_[k] = is_vy_unknown(J.nx, J.ny, i, j) ? jac_vy_global(g, sx, sy, i, j) : T(0);
 }
@@ -156,21 +205,39 @@ template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_residual(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
                                                     int n) {
     STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
-    if (i > J.nx || j > J.ny) return;
     const int nx = J.nx, ny = J.ny;
     const int64_t ld = J.ld, k = (int64_t)j * ld + i;
-    if (J.st) {  // r = b - M v = b + A v
-        for (int a = 0; a < 2; ++a) {
-            if (a == 0 ? j >= ny : i >= nx) continue;
-            T r = T(0);
-            if (a == 0 ? is_vx_unknown(nx, ny, i, j) : is_vy_unknown(nx, ny, i, j)) {
-                T d;
-                r = (a == 0 ? J.bx : J.by)[k] + stencil_av<T>(J.st, J.plane, a, J.vx, J.vy, ld, nx, ny, i, j, d);
+    if (J.st) {  // r = b - M v = b + A v (velocity staged in FP64, as in k_mg_jacobi)
+        auto resid = [&](const auto& lv) {
+            if (i > nx || j > ny) return;
+            for (int a = 0; a < 2; ++a) {
+                if (a == 0 ? j >= ny : i >= nx) continue;
+                T r = T(0);
+                if (a == 0 ? is_vx_unknown(nx, ny, i, j) : is_vy_unknown(nx, ny, i, j)) {
+                    T d;
+                    r = (a == 0 ? J.bx : J.by)[k] + stencil_av_l<T>(J.st, J.plane, a, lv, ld, nx, ny, i, j, d);
+                }
+                (a == 0 ? J.rx : J.ry)[k] = r;
             }
-            (a == 0 ? J.rx : J.ry)[k] = r;
+        };
+        if constexpr (sizeof(T) == 8) {
+            __shared__ T win[2 * SWY * SWX];
+            resid(stage_patch<T>(win, J.vx, J.vy, ld, nx, ny, i, j));
+        } else {
+            if (i > nx || j > ny) return;
+            for (int a = 0; a < 2; ++a) {
+                if (a == 0 ? j >= ny : i >= nx) continue;
+                T r = T(0);
+                if (a == 0 ? is_vx_unknown(nx, ny, i, j) : is_vy_unknown(nx, ny, i, j)) {
+                    T d;
+                    r = (a == 0 ? J.bx : J.by)[k] + stencil_av<T>(J.st, J.plane, a, J.vx, J.vy, ld, nx, ny, i, j, d);
+                }
+                (a == 0 ? J.rx : J.ry)[k] = r;
+            }
         }
         return;
     }
+    if (i > nx || j > ny) return;
     auto VX = [&](int a, int b) { return ldvx<T>(J.vx, ld, nx, ny, a, b); };
     auto VY = [&](int a, int b) { return ldvy<T>(J.vy, ld, nx, ny, a, b); };
     auto ENH = [&](int a, int b) { return (a >= 1 && a <= nx - 1 && b >= 1 && b <= ny - 1) ? J.en[(int64_t)b * ld + a] : T(0); };

@@ -34,20 +34,21 @@ __device__ __forceinline__ int find_tile_inst(const int* __restrict__ pre, int n
 
 // (A w) at the unknown (a, i, j) with w read from the LDS window (origin
 // (wx0, wy0), row stride ws; component c of buffer at base + c * plane_w),
-// coefficients from the stored planes; the slot order of stencil_av.
+// coefficients from the stored planes (stencil_av_l: the slot order of every
+// stored-stencil kernel).
+template <typename T>
+struct WindowPair {
+    const T* win;
+    int plane_w, ws, wx0, wy0;
+    __device__ __forceinline__ T operator()(int c, int i, int j) const {
+        return win[c * plane_w + (j - wy0) * ws + (i - wx0)];
+    }
+};
 template <typename T>
 __device__ __forceinline__ T stencil_av_window(const T* __restrict__ st, int64_t plane, int a, const T* win,
                                                int plane_w, int ws, int wx0, int wy0, int64_t ld, int nx, int ny,
                                                int i, int j, T& diag) {
-    T s = T(0);
-#pragma unroll
-    for (int q = 0; q < NCOEF; ++q) {
-        const int dx = slot_dx(a, q), dy = slot_dy(a, q);
-        const T v = win[slot_comp(a, q) * plane_w + (j + dy - wy0) * ws + (i + dx - wx0)];
-        s += stencil_coef<T>(st, plane, ld, nx, ny, a, q, i, j) * v;
-    }
-    diag = st[(a == 0 ? 0 : PL_VY) * plane + (int64_t)j * ld + i];
-    return s;
+    return stencil_av_l<T>(st, plane, a, WindowPair<T>{win, plane_w, ws, wx0, wy0}, ld, nx, ny, i, j, diag);
 }
 
 // dir 0: (v) -> (w); dir 1: (w) -> (v).  Tiles T x T cells cut at multiples
