@@ -118,7 +118,7 @@ int mg_galerkin(stk_ctx* ctx, const GalerkinArgs& g);
 
 // (q = A p and p.q are one fused pass: fcg_apply_pq)
 enum VecOp {
-    OP_UPDATE = 0,  // x += alpha p; r += alpha q; acc0 += r^2/d
+    OP_UPDATE = 0,  // x += alpha p; r += alpha q; acc0 += r^2/d; z = 0 (an FP64 Z slot)
     OP_RZ_ZQ,       // acc0 += r.z ; acc1 += z.q  (rho = -r: gamma = -acc0)
     OP_XPBY,        // p = z + beta p
     OP_FNORM,       // acc0 += f^2/d
@@ -135,11 +135,16 @@ template <typename T>
 // z32: the batch's Z slot holds FP32 vectors (the FP32 V-cycle's output, read
 // in place by the FP64 Krylov operations).
 int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* part, double* sums, bool z32 = false);
-// R = B - M X in FP64; sums[2i] = sum R^2 / d
+// R = B - M X in FP64; sums[2i] = sum R^2 / d (sums == nullptr: the block partials only)
 int vec_residual64_st(stk_ctx* ctx, const Batch& b, const FcgState* st, double* part, double* sums);
 // Per-instance scalar update from the reduced sums (one thread per instance);
 // PH_NF sets N_f and the stop threshold tol2 * N_f.
 int fcg_scalars(stk_ctx* ctx, FcgState* st, const double* sums, int n, int phase);
+// inst_sums + fcg_scalars in one launch over the reduction chunks of `red`
+// (the same bits); out != nullptr (device-visible pinned host memory): the
+// updated states are also copied there.
+int fcg_reduce(stk_ctx* ctx, const Batch& red, const double* part, double* sums, FcgState* st, int phase,
+               FcgState* out = nullptr);
 
 // Entry of the FP32 V-cycle preconditioner (active instances): r32 = (float)
 // r64 and z32 = 0 (its initial guess) in one pass.  Its output z32 is read in
@@ -156,7 +161,7 @@ int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st);
 int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums);
 // FP64 FCG, finest level: Q = A P and per-instance P . Q into sums (apply:
 // the operator batch with its row-streaming prefix; red: the reduction chunks
-// over that prefix)
+// over that prefix); sums == nullptr: the block partials only
 int fcg_apply_pq(stk_ctx* ctx, const Batch& apply, const Batch& red, const FcgState* st, double* part,
                  double* sums);
 template <typename T> int mg_copy_wv(stk_ctx* ctx, const Batch& b);

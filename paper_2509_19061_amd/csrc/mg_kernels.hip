@@ -12,6 +12,8 @@
 // Launch shape: a flat grid of 256-thread blocks; block b belongs to the
 // instance i with pre[i] <= b < pre[i+1] and covers a 64 x 4 patch of that
 // instance's (nx+1) x (ny+1) index box.
+#include <type_traits>
+
 #include "coarse_stencil.hpp"
 #include "mg_internal.hpp"
 #include "rowstream.hpp"
@@ -280,7 +282,11 @@ __device__ __forceinline__ int w_tangent(int f, int nc, int* c, double* w) {
 
 // coarse rhs = R r = P^T r / 4, gathered per coarse unknown from the fine
 // unknowns that prolongate from it; the coarse iterate is set to 0 in the same
-// pass (the coarse problem is solved for the correction from 0).
+// pass (the coarse problem is solved for the correction from 0).  The fine
+// values of a coarse unknown's 3 x 4 window are loaded first, all at once
+// (rows or columns outside the grid clamped onto it), and the terms whose
+// weights are nonzero are then added in window order, so a thread waits for
+// one round trip instead of one per term.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
                                                     int n) {
@@ -288,46 +294,70 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restric
     const int NX = J.cnx, NY = J.cny, nx = J.nx, ny = J.ny;
     if (i > NX || j > NY) return;
     const int64_t ld = J.ld, cld = J.cld, k = (int64_t)j * cld + i;
-    if (j < NY) {  // coarse vx(I=i, J=j)
+    if (j < NY) {  // coarse vx(I=i, J=j): fine columns 2i-1..2i+1 (normal), rows 2j-1..2j+2 (tangential)
         double s = 0.0;
         if (i >= 1 && i <= NX - 1) {
-            for (int fi = 2 * i - 1; fi <= 2 * i + 1; ++fi) {
+            double rv[3][4];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int fj = min(max(2 * j - 1 + b, 0), ny - 1);
+                    rv[a][b] = (double)J.rx[(int64_t)fj * ld + 2 * i - 1 + a];
+                }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int fi = 2 * i - 1 + a;
                 int ci[2];
                 double wi[2];
                 const int nci = w_normal(fi, ci, wi);
                 double wn = 0.0;
-                for (int a = 0; a < nci; ++a) wn += ci[a] == i ? wi[a] : 0.0;
-                for (int fj = 2 * j - 1; fj <= 2 * j + 2; ++fj) {
+                for (int q = 0; q < nci; ++q) wn += ci[q] == i ? wi[q] : 0.0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int fj = 2 * j - 1 + b;
                     if (fj < 0 || fj >= ny) continue;
                     int cj[2];
                     double wj[2];
                     const int ncj = w_tangent(fj, NY, cj, wj);
                     double wt = 0.0;
-                    for (int b = 0; b < ncj; ++b) wt += cj[b] == j ? wj[b] : 0.0;
-                    if (wn != 0.0 && wt != 0.0) s += 0.25 * wn * wt * (double)J.rx[(int64_t)fj * ld + fi];
+                    for (int q = 0; q < ncj; ++q) wt += cj[q] == j ? wj[q] : 0.0;
+                    if (wn != 0.0 && wt != 0.0) s += 0.25 * wn * wt * rv[a][b];
                 }
             }
         }
         J.cbx[k] = T(s);
         J.cvx[k] = T(0);
     }
-    if (i < NX) {  // coarse vy(I=i, J=j)
+    if (i < NX) {  // coarse vy(I=i, J=j): fine rows 2j-1..2j+1 (normal), columns 2i-1..2i+2 (tangential)
         double s = 0.0;
         if (j >= 1 && j <= NY - 1) {
-            for (int fj = 2 * j - 1; fj <= 2 * j + 1; ++fj) {
+            double rv[3][4];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int fi = min(max(2 * i - 1 + a, 0), nx - 1);
+                    rv[b][a] = (double)J.ry[(int64_t)(2 * j - 1 + b) * ld + fi];
+                }
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const int fj = 2 * j - 1 + b;
                 int cj[2];
                 double wj[2];
                 const int ncj = w_normal(fj, cj, wj);
                 double wn = 0.0;
-                for (int b = 0; b < ncj; ++b) wn += cj[b] == j ? wj[b] : 0.0;
-                for (int fi = 2 * i - 1; fi <= 2 * i + 2; ++fi) {
+                for (int q = 0; q < ncj; ++q) wn += cj[q] == j ? wj[q] : 0.0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int fi = 2 * i - 1 + a;
                     if (fi < 0 || fi >= nx) continue;
                     int ci[2];
                     double wi[2];
                     const int nci = w_tangent(fi, NX, ci, wi);
                     double wt = 0.0;
-                    for (int a = 0; a < nci; ++a) wt += ci[a] == i ? wi[a] : 0.0;
-                    if (wn != 0.0 && wt != 0.0) s += 0.25 * wn * wt * (double)J.ry[(int64_t)fj * ld + fi];
+                    for (int q = 0; q < nci; ++q) wt += ci[q] == i ? wi[q] : 0.0;
+                    if (wn != 0.0 && wt != 0.0) s += 0.25 * wn * wt * rv[b][a];
                 }
             }
         }
@@ -336,7 +366,22 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restric
     }
 }
 
-// v += P e_c on the fine unknowns.
+// Interpolation terms of one fine unknown: up to 2 x 2 coarse indices with
+// weights; absent terms repeat the first index and are masked out.
+struct Terms {
+    int ci[2], cj[2];
+    double wi[2], wj[2];
+    int na, nb;
+};
+__device__ __forceinline__ void pad_terms(Terms& t) {
+    if (t.na == 1) { t.ci[1] = t.ci[0]; t.wi[1] = 0.0; }
+    if (t.nb == 1) { t.cj[1] = t.cj[0]; t.wj[1] = 0.0; }
+}
+
+// v += P e_c on the fine unknowns.  The coarse values are loaded first, all
+// at once (their indices are inside the coarse arrays whether or not the
+// term is used), and the terms added in the same order as the weights list
+// them.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_prolong(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
                                                    int n) {
@@ -345,30 +390,46 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(const LevelJob<T>* __restrict
     if (i > nx || j > ny) return;
     const int64_t k = (int64_t)j * J.ld + i, cld = J.cld;
     if (is_vx_unknown(nx, ny, i, j)) {
-        int ci[2], cj[2];
-        double wi[2], wj[2];
-        const int a = w_normal(i, ci, wi), b = w_tangent(j, NY, cj, wj);
+        Terms t;
+        t.na = w_normal(i, t.ci, t.wi);
+        t.nb = w_tangent(j, NY, t.cj, t.wj);
+        pad_terms(t);
+        double c[2][2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) c[p][q] = (double)J.cvx[(int64_t)t.cj[q] * cld + t.ci[p]];
+        const T v = J.vx[k];
         double s = 0.0;
-        for (int p = 0; p < a; ++p)
-            for (int q = 0; q < b; ++q) {
-                const int I = ci[p], JJ = cj[q];
-                const double c = (I >= 1 && I <= NX - 1) ? (double)J.cvx[(int64_t)JJ * cld + I] : 0.0;
-                s += wi[p] * wj[q] * c;
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const double cv = (t.ci[p] >= 1 && t.ci[p] <= NX - 1) ? c[p][q] : 0.0;
+                if (p < t.na && q < t.nb) s += t.wi[p] * t.wj[q] * cv;
             }
-        J.vx[k] = J.vx[k] + T(s);
+        J.vx[k] = v + T(s);
     }
     if (is_vy_unknown(nx, ny, i, j)) {
-        int ci[2], cj[2];
-        double wi[2], wj[2];
-        const int a = w_tangent(i, NX, ci, wi), b = w_normal(j, cj, wj);
+        Terms t;
+        t.na = w_tangent(i, NX, t.ci, t.wi);
+        t.nb = w_normal(j, t.cj, t.wj);
+        pad_terms(t);
+        double c[2][2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) c[p][q] = (double)J.cvy[(int64_t)t.cj[q] * cld + t.ci[p]];
+        const T v = J.vy[k];
         double s = 0.0;
-        for (int p = 0; p < a; ++p)
-            for (int q = 0; q < b; ++q) {
-                const int I = ci[p], JJ = cj[q];
-                const double c = (JJ >= 1 && JJ <= NY - 1) ? (double)J.cvy[(int64_t)JJ * cld + I] : 0.0;
-                s += wi[p] * wj[q] * c;
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const double cv = (t.cj[q] >= 1 && t.cj[q] <= NY - 1) ? c[p][q] : 0.0;
+                if (p < t.na && q < t.nb) s += t.wi[p] * t.wj[q] * cv;
             }
-        J.vy[k] = J.vy[k] + T(s);
+        J.vy[k] = v + T(s);
     }
 }
 
@@ -470,6 +531,9 @@ __global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, con
                         R[k] = r;
                         a0 += (double)r * (double)r / (c == 0 ? dgx(J, i, j) : dgy(J, i, j));
                     }
+                    // the next V-cycle's initial guess (OP_ZERO_Z), when Z is this plan's own
+                    // FP64 slot; the FP32 one is zeroed by the cast that starts that V-cycle
+                    if constexpr (std::is_same<ZT, T>::value) Z[k] = ZT(0);
                     break;
                 case OP_XPBY:
                     P[k] = u ? T((double)Z[k] + be * (double)P[k]) : T(0);
@@ -640,11 +704,7 @@ __global__ void k_inst_sums(const int* __restrict__ cpre, int n, const double* _
     sums[2 * inst + 1] = s1;
 }
 
-__global__ void k_fcg_scalars(FcgState* __restrict__ st, const double* __restrict__ sums, int n, int phase) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    FcgState& s = st[q];
-    const double s0 = sums[2 * q], s1 = sums[2 * q + 1];
+__device__ __forceinline__ void fcg_update(FcgState& s, double s0, double s1, int phase) {
     switch (phase) {
         case PH_NF:  // N_f and the stop threshold
             if (s.active) {
@@ -683,6 +743,58 @@ __global__ void k_fcg_scalars(FcgState* __restrict__ st, const double* __restric
                 s.gamma = gnew;
             }
         }
+    }
+}
+__global__ void k_fcg_scalars(FcgState* __restrict__ st, const double* __restrict__ sums, int n, int phase) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    fcg_update(st[q], sums[2 * q], sums[2 * q + 1], phase);
+}
+
+// k_chunk_sums, k_inst_sums and k_fcg_scalars in one launch, one workgroup
+// per instance: the instance's chunks one after the other, each summed by
+// the same 256 threads in the same order as k_chunk_sums, the chunk sums
+// added in order as k_inst_sums does (the same bits), then the scalar update,
+// and optionally a copy of the updated state to `out` (pinned host memory).
+// Each of these launches costs about 5 us on the device however small, and
+// an iteration had nine of them.
+__global__ __launch_bounds__(256) void k_fcg_reduce(const int* __restrict__ pre, const int* __restrict__ cpre,
+                                                    const double* __restrict__ part, double* __restrict__ sums,
+                                                    FcgState* __restrict__ st, int phase, FcgState* out) {
+    const int inst = blockIdx.x;
+    __shared__ double red[2][256 / 64];
+    double t0 = 0.0, t1 = 0.0;
+    for (int c = cpre[inst]; c < cpre[inst + 1]; ++c) {
+        const int b0 = pre[inst] + (c - cpre[inst]) * SUM_CHUNK;
+        const int b1 = min(pre[inst + 1], b0 + SUM_CHUNK);
+        double s0 = 0.0, s1 = 0.0;
+        for (int b = b0 + (int)threadIdx.x; b < b1; b += 256) {
+            s0 += part[2 * b];
+            s1 += part[2 * b + 1];
+        }
+        s0 = wave_sum(s0);
+        s1 = wave_sum(s1);
+        if ((threadIdx.x & 63) == 0) {
+            red[0][threadIdx.x >> 6] = s0;
+            red[1][threadIdx.x >> 6] = s1;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double c0 = 0.0, c1 = 0.0;
+            for (int q = 0; q < 256 / 64; ++q) {
+                c0 += red[0][q];
+                c1 += red[1][q];
+            }
+            t0 += c0;
+            t1 += c1;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sums[2 * inst] = t0;
+        sums[2 * inst + 1] = t1;
+        fcg_update(st[inst], t0, t1, phase);
+        if (out) out[inst] = st[inst];
     }
 }
 
@@ -795,7 +907,7 @@ int fcg_apply_pq(stk_ctx* ctx, const Batch& apply, const Batch& red, const FcgSt
     hipLaunchKernelGGL(k_fcg_apply_rows, dim3(apply.rblocks), dim3(64 * rows::WPB), 0, ctx->stream,
                        static_cast<const LevelJob<double>*>(apply.jobs), apply.rpre, apply.n, st, part);
     STK_LAUNCH_CHECK();
-    return inst_sums(ctx, red, part, sums);
+    return sums ? inst_sums(ctx, red, part, sums) : STK_OK;
 }
 
 int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st) {
@@ -810,7 +922,16 @@ int vec_residual64_st(stk_ctx* ctx, const Batch& b, const FcgState* st, double* 
     hipLaunchKernelGGL(k_vec_res64, dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const VecJob*>(b.jobs), b.pre,
                        b.n, st, part);
     STK_LAUNCH_CHECK();
-    return inst_sums(ctx, b, part, sums);
+    return sums ? inst_sums(ctx, b, part, sums) : STK_OK;
+}
+int fcg_reduce(stk_ctx* ctx, const Batch& red, const double* part, double* sums, FcgState* st, int phase,
+               FcgState* out) {
+    if (!red.n) return STK_OK;
+    if (!red.cpre) return set_error(STK_EINVAL, "internal: batch without reduction chunks");
+    hipLaunchKernelGGL(k_fcg_reduce, dim3(red.n), dim3(256), 0, ctx->stream, red.pre, red.cpre, part, sums, st, phase,
+                       out);
+    STK_LAUNCH_CHECK();
+    return STK_OK;
 }
 int fcg_scalars(stk_ctx* ctx, FcgState* st, const double* sums, int n, int phase) {
     if (!n) return STK_OK;

@@ -45,10 +45,11 @@ struct Slot {
 };
 
 // Z = V-cycle(R) from zero for every active instance of P, in FP64 (P32 ==
-// nullptr) or in FP32 between the casts R -> R32 and Z32 -> Z.
-int precondition(stk_ctx* ctx, const PlanT& P, const PlanT* P32, const stk_mg_opts& o) {
+// nullptr) or in FP32 between the casts R -> R32 and Z32 -> Z.  z_zeroed: the
+// FP64 Z is already 0 (OP_UPDATE clears it).
+int precondition(stk_ctx* ctx, const PlanT& P, const PlanT* P32, const stk_mg_opts& o, bool z_zeroed) {
     if (!P32) {
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_ZERO_Z, P.st, P.part, nullptr));
+        if (!z_zeroed) STK_TRY(vec_op<double>(ctx, P.vec, OP_ZERO_Z, P.st, P.part, nullptr));
         return run_vcycle(ctx, P, o, 0);
     }
     // r32 = (float) r and z32 = 0, the FP32 V-cycle, whose z32 the Krylov steps read in place
@@ -77,7 +78,11 @@ struct stk_batch {
     // iteration ahead made a serving loop that sets requests up on another
     // stream meanwhile 35 % slower.
     bool lookahead = false;
-    FcgState* pin = nullptr;  // pinned host copy of the member states, read once per iteration
+    // pinned host copy of the member states, read once per iteration; the reduction
+    // kernel that updates them writes it on the solve's stream (a copy-engine
+    // transfer would queue behind unrelated uploads: requests being set up on
+    // another stream while the batch runs)
+    FcgState* pin = nullptr;
     FcgState* pin_dev = nullptr;  // its device-side address
     int npin = 0;
     hipEvent_t ev = nullptr;  // marks that copy in the stream
@@ -112,14 +117,6 @@ int ensure_pinned(stk_batch* b, int n) {
     return STK_OK;
 }
 
-// The member states to the pinned host buffer, written by a kernel on the
-// solve's stream: a copy-engine transfer would queue behind unrelated uploads
-// (requests being set up on another stream while the batch runs).
-static_assert(sizeof(FcgState) % sizeof(uint64_t) == 0, "FcgState is copied as 64-bit words");
-__global__ __launch_bounds__(256) void k_states_out(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst,
-                                                    int n) {
-    for (int q = threadIdx.x; q < n; q += blockDim.x) dst[q] = src[q];
-}
 
 // Write the solution to the caller's arrays and fill the report (the true
 // residual of the slot's last CHECK is in its state).
@@ -165,14 +162,14 @@ int start_phase(stk_batch* b, int* done, stk_report* reps, int* ndone) {
     }
     if (any_new) {
         if (int rc = write_states(ctx, *Q, h)) return fail(rc);
-        if (int rc = vec_op<double>(ctx, Q->vec, OP_FNORM, Q->st, Q->part, Q->sums)) return fail(rc);
-        if (int rc = fcg_scalars(ctx, Q->st, Q->sums, n, PH_NF)) return fail(rc);
+        if (int rc = vec_op<double>(ctx, Q->vec, OP_FNORM, Q->st, Q->part, nullptr)) return fail(rc);
+        if (int rc = fcg_reduce(ctx, Q->vec, Q->part, Q->sums, Q->st, PH_NF)) return fail(rc);
         if (int rc = read_states(ctx, *Q, h)) return fail(rc);
     }
     for (auto& s : h) s.active = 1;
     if (int rc = write_states(ctx, *Q, h)) return fail(rc);
-    if (int rc = vec_residual64_st(ctx, Q->vec, Q->st, Q->part, Q->sums)) return fail(rc);
-    if (int rc = fcg_scalars(ctx, Q->st, Q->sums, n, PH_TRUE)) return fail(rc);
+    if (int rc = vec_residual64_st(ctx, Q->vec, Q->st, Q->part, nullptr)) return fail(rc);
+    if (int rc = fcg_reduce(ctx, Q->vec, Q->part, Q->sums, Q->st, PH_TRUE)) return fail(rc);
     if (int rc = read_states(ctx, *Q, h)) return fail(rc);
     bool restart = false;
     for (int q = 0; q < n; ++q) {
@@ -190,9 +187,9 @@ int start_phase(stk_batch* b, int* done, stk_report* reps, int* ndone) {
     }
     if (restart) {  // Z = V(R), P = Z, gamma for the slots that go on
         if (int rc = write_states(ctx, *Q, h)) return fail(rc);
-        if (int rc = precondition(ctx, *Q, Q32, o)) return fail(rc);
-        if (int rc = vec_op<double>(ctx, Q->vec, OP_INIT_P, Q->st, Q->part, Q->sums, Q->vec_z32)) return fail(rc);
-        if (int rc = fcg_scalars(ctx, Q->st, Q->sums, n, PH_INIT)) return fail(rc);
+        if (int rc = precondition(ctx, *Q, Q32, o, false)) return fail(rc);
+        if (int rc = vec_op<double>(ctx, Q->vec, OP_INIT_P, Q->st, Q->part, nullptr, Q->vec_z32)) return fail(rc);
+        if (int rc = fcg_reduce(ctx, Q->vec, Q->part, Q->sums, Q->st, PH_INIT)) return fail(rc);
         if (int rc = read_states(ctx, *Q, h)) return fail(rc);
         for (int q = 0; q < n; ++q) {
             Slot& s = b->slots[ids[q]];
@@ -250,27 +247,26 @@ int iterate_phase(stk_batch* b, int iters) {
     };
     std::vector<FcgState> hn;
     for (int it = 0; it < iters; ++it) {
-        STK_TRY(fcg_apply_pq(ctx, P.apply, P.applyr, P.st, P.part, P.sums));  // Q = A P and P . Q
-        STK_TRY(fcg_scalars(ctx, P.st, P.sums, n, PH_ALPHA));
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_UPDATE, P.st, P.part, P.sums));
-        STK_TRY(fcg_scalars(ctx, P.st, P.sums, n, PH_NV));  // stop below tol or at the end of the budget
+        STK_TRY(fcg_apply_pq(ctx, P.apply, P.applyr, P.st, P.part, nullptr));  // Q = A P and P . Q
+        STK_TRY(fcg_reduce(ctx, P.applyr, P.part, P.sums, P.st, PH_ALPHA));
+        // (the Z slot's dtype selects the kernel: OP_UPDATE clears an FP64 Z)
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_UPDATE, P.st, P.part, nullptr, P.vec_z32));
+        // stop below tol or at the end of the budget
         if (b->lookahead) {
             // The states go to the host while the rest of the iteration is queued behind
             // them: the GPU does not wait for the host between iterations.  An instance
             // that stopped here is skipped by the Krylov kernels, and its preconditioner
             // output is recomputed before it is used again.
-            hipLaunchKernelGGL(k_states_out, dim3(1), dim3(256), 0, ctx->stream,
-                               reinterpret_cast<const uint64_t*>(P.st), reinterpret_cast<uint64_t*>(b->pin_dev),
-                               (int)(sizeof(FcgState) / sizeof(uint64_t)) * n);
-            STK_HIP(hipGetLastError());
+            STK_TRY(fcg_reduce(ctx, P.vec, P.part, P.sums, P.st, PH_NV, b->pin_dev));
             STK_HIP(hipEventRecord(b->ev, ctx->stream));
         } else {
+            STK_TRY(fcg_reduce(ctx, P.vec, P.part, P.sums, P.st, PH_NV));
             STK_TRY(read_states(ctx, P, hn));
             if (!take(hn.data())) break;
         }
-        STK_TRY(precondition(ctx, P, b->P32, o));
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_RZ_ZQ, P.st, P.part, P.sums, P.vec_z32));
-        STK_TRY(fcg_scalars(ctx, P.st, P.sums, n, PH_BETA));
+        STK_TRY(precondition(ctx, P, b->P32, o, true));
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_RZ_ZQ, P.st, P.part, nullptr, P.vec_z32));
+        STK_TRY(fcg_reduce(ctx, P.vec, P.part, P.sums, P.st, PH_BETA));
         STK_TRY(vec_op<double>(ctx, P.vec, OP_XPBY, P.st, P.part, nullptr, P.vec_z32));
         if (b->lookahead) {
             STK_HIP(hipEventSynchronize(b->ev));
