@@ -202,6 +202,27 @@ __global__ __launch_bounds__(64 * rows::WPB) void k_mg_residual_rows(const Level
 }
 
 // ---------------------------------------------------------------- residual --
+// r = b - M v at (i, j) of the matrix-free level (0 on walls and outside the
+// box of each component).
+template <typename T>
+__device__ __forceinline__ void mf_residual(const LevelJob<T>& J, int i, int j, T& rx, T& ry) {
+    const int nx = J.nx, ny = J.ny;
+    const int64_t ld = J.ld, k = (int64_t)j * ld + i;
+    auto VX = [&](int a, int b) { return ldvx<T>(J.vx, ld, nx, ny, a, b); };
+    auto VY = [&](int a, int b) { return ldvy<T>(J.vy, ld, nx, ny, a, b); };
+    auto ENH = [&](int a, int b) { return (a >= 1 && a <= nx - 1 && b >= 1 && b <= ny - 1) ? J.en[(int64_t)b * ld + a] : T(0); };
+    rx = T(0);
+    ry = T(0);
+    if (is_vx_unknown(nx, ny, i, j))
+        rx = J.bx[k] - mv_x<T>(VX(i, j), VX(i - 1, j), VX(i + 1, j), VX(i, j - 1), VX(i, j + 1), VY(i, j),
+                               VY(i - 1, j), VY(i, j + 1), VY(i - 1, j + 1), J.ec[k - 1], J.ec[k], ENH(i, j),
+                               ENH(i, j + 1), J.idx, J.idy);
+    if (is_vy_unknown(nx, ny, i, j))
+        ry = J.by[k] - mv_y<T>(VY(i, j), VY(i - 1, j), VY(i + 1, j), VY(i, j - 1), VY(i, j + 1), VX(i, j),
+                               VX(i + 1, j), VX(i, j - 1), VX(i + 1, j - 1), J.ec[k - ld], J.ec[k], ENH(i, j),
+                               ENH(i + 1, j), J.idx, J.idy);
+}
+
 // r = b - M v on the unknowns (0 on walls).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_residual(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
@@ -240,25 +261,10 @@ __global__ __launch_bounds__(NT) void k_mg_residual(const LevelJob<T>* __restric
         return;
     }
     if (i > nx || j > ny) return;
-    auto VX = [&](int a, int b) { return ldvx<T>(J.vx, ld, nx, ny, a, b); };
-    auto VY = [&](int a, int b) { return ldvy<T>(J.vy, ld, nx, ny, a, b); };
-    auto ENH = [&](int a, int b) { return (a >= 1 && a <= nx - 1 && b >= 1 && b <= ny - 1) ? J.en[(int64_t)b * ld + a] : T(0); };
-    if (j < ny) {
-        T r = T(0);
-        if (is_vx_unknown(nx, ny, i, j))
-            r = J.bx[k] - mv_x<T>(VX(i, j), VX(i - 1, j), VX(i + 1, j), VX(i, j - 1), VX(i, j + 1), VY(i, j),
-                                  VY(i - 1, j), VY(i, j + 1), VY(i - 1, j + 1), J.ec[k - 1], J.ec[k], ENH(i, j),
-                                  ENH(i, j + 1), J.idx, J.idy);
-        J.rx[k] = r;
-    }
-    if (i < nx) {
-        T r = T(0);
-        if (is_vy_unknown(nx, ny, i, j))
-            r = J.by[k] - mv_y<T>(VY(i, j), VY(i - 1, j), VY(i + 1, j), VY(i, j - 1), VY(i, j + 1), VX(i, j),
-                                  VX(i + 1, j), VX(i, j - 1), VX(i + 1, j - 1), J.ec[k - ld], J.ec[k], ENH(i, j),
-                                  ENH(i + 1, j), J.idx, J.idy);
-        J.ry[k] = r;
-    }
+    T rx, ry;
+    mf_residual<T>(J, i, j, rx, ry);
+    if (j < ny) J.rx[k] = rx;
+    if (i < nx) J.ry[k] = ry;
 }
 
 // --------------------------------------------------------------- transfers --
@@ -287,13 +293,12 @@ __device__ __forceinline__ int w_tangent(int f, int nc, int* c, double* w) {
 // (rows or columns outside the grid clamped onto it), and the terms whose
 // weights are nonzero are then added in window order, so a thread waits for
 // one round trip instead of one per term.
-template <typename T>
-__global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
-                                                    int n) {
-    STK_BATCH_INDEX(jobs, pre, n, COARSE_NX, COARSE_NY)
+// rf(c, fi, fj): the fine residual of component c (as double); (i, j) inside
+// the coarse (cnx+1) x (cny+1) box.
+template <typename T, typename RF>
+__device__ __forceinline__ void restrict_from(const LevelJob<T>& J, int i, int j, const RF& rf) {
     const int NX = J.cnx, NY = J.cny, nx = J.nx, ny = J.ny;
-    if (i > NX || j > NY) return;
-    const int64_t ld = J.ld, cld = J.cld, k = (int64_t)j * cld + i;
+    const int64_t cld = J.cld, k = (int64_t)j * cld + i;
     if (j < NY) {  // coarse vx(I=i, J=j): fine columns 2i-1..2i+1 (normal), rows 2j-1..2j+2 (tangential)
         double s = 0.0;
         if (i >= 1 && i <= NX - 1) {
@@ -302,8 +307,7 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restric
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    const int fj = min(max(2 * j - 1 + b, 0), ny - 1);
-                    rv[a][b] = (double)J.rx[(int64_t)fj * ld + 2 * i - 1 + a];
+                    rv[a][b] = rf(0, 2 * i - 1 + a, min(max(2 * j - 1 + b, 0), ny - 1));
                 }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -337,8 +341,7 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restric
             for (int b = 0; b < 3; ++b)
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
-                    const int fi = min(max(2 * i - 1 + a, 0), nx - 1);
-                    rv[b][a] = (double)J.ry[(int64_t)(2 * j - 1 + b) * ld + fi];
+                    rv[b][a] = rf(1, min(max(2 * i - 1 + a, 0), nx - 1), 2 * j - 1 + b);
                 }
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
@@ -364,6 +367,16 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restric
         J.cby[k] = T(s);
         J.cvy[k] = T(0);
     }
+}
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
+                                                    int n) {
+    STK_BATCH_INDEX(jobs, pre, n, COARSE_NX, COARSE_NY)
+    if (i > J.cnx || j > J.cny) return;
+    const int64_t ld = J.ld;
+    restrict_from<T>(J, i, j, [&](int c, int fi, int fj) {
+        return (double)(c == 0 ? J.rx : J.ry)[(int64_t)fj * ld + fi];
+    });
 }
 
 // Interpolation terms of one fine unknown: up to 2 x 2 coarse indices with
@@ -767,10 +780,22 @@ __global__ __launch_bounds__(256) void k_fcg_reduce(const int* __restrict__ pre,
     for (int c = cpre[inst]; c < cpre[inst + 1]; ++c) {
         const int b0 = pre[inst] + (c - cpre[inst]) * SUM_CHUNK;
         const int b1 = min(pre[inst + 1], b0 + SUM_CHUNK);
+        // a thread's SUM_CHUNK / 256 partials are loaded before they are added (in
+        // k_chunk_sums' order): one round trip per chunk instead of one per partial
+        double v0[SUM_CHUNK / 256], v1[SUM_CHUNK / 256];
+#pragma unroll
+        for (int q = 0; q < SUM_CHUNK / 256; ++q) {
+            const int b = min(b0 + (int)threadIdx.x + 256 * q, b1 - 1);  // a chunk is never empty
+            v0[q] = part[2 * b];
+            v1[q] = part[2 * b + 1];
+        }
         double s0 = 0.0, s1 = 0.0;
-        for (int b = b0 + (int)threadIdx.x; b < b1; b += 256) {
-            s0 += part[2 * b];
-            s1 += part[2 * b + 1];
+#pragma unroll
+        for (int q = 0; q < SUM_CHUNK / 256; ++q) {
+            if (b0 + (int)threadIdx.x + 256 * q < b1) {
+                s0 += v0[q];
+                s1 += v1[q];
+            }
         }
         s0 = wave_sum(s0);
         s1 = wave_sum(s1);
