@@ -281,6 +281,10 @@ static LevelJob<T> level_job(const stk_mg* m, size_t l, int t) {
         J.cby = (T*)C.b[t].y;
         J.cvx = (T*)C.v[t].x;
         J.cvy = (T*)C.v[t].y;
+        J.cwx = (T*)C.w[t].x;
+        J.cwy = (T*)C.w[t].y;
+        J.cst = t ? (const T*)C.st32 : (const T*)C.st64;
+        J.cplane = C.plane;
     }
     return J;
 }
@@ -308,6 +312,16 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P, 
     P->relax_t.assign(maxl, Batch{});
     const stk_mg_opts& o0 = mgs[0]->o;
     const bool cras = o0.coarse_smoother == 1;
+    // Does the restriction into level l (>= 1) also take its first smoothing
+    // sweep?  When it is smoothed by Jacobi from zero with at least one sweep
+    // before its residual, or is a relaxed last level; not the solved
+    // coarsest level, not with coarse RAS.  The V-cycle skips that sweep under
+    // the same conditions (first_sweep_done).
+    auto first_sweep = [&](const stk_mg* m, int l) {
+        if (cras) return 0;
+        if (l < (int)m->L.size() - 1) return level_sweeps(m->o.nu1, m->o.sweep_growth, l) >= 1 ? 1 : 0;
+        return m->relaxed ? 1 : 0;
+    };
     for (int d = 0; d < maxl; ++d) {
         std::vector<LevelJob<T>> jobs, rj;
         std::vector<int> pf{0}, pc{0}, pr{0}, pt{0}, rpf{0}, rpt{0};
@@ -317,6 +331,7 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P, 
             const int nl = (int)m->L.size();
             if (d < nl - 1) {
                 jobs.push_back(level_job<T>(m, d, t));
+                jobs.back().first = first_sweep(m, d + 1);
                 pf.push_back(pf.back() + blocks_of(m->L[d].nx, m->L[d].ny));
                 pr.push_back(pr.back() + rows::workgroups(m->L[d].nx, m->L[d].ny));
                 pc.push_back(pc.back() + blocks_of(m->L[d + 1].nx, m->L[d + 1].ny));
@@ -517,18 +532,26 @@ static const PlanT::RasK* ras_shape(stk_ctx* ctx, const PlanT& P, int kt, int h,
     return r.ok ? &P.ras_k.back() : nullptr;
 }
 
+// nu Jacobi sweeps v -> v; first_done: the first one (v -> w) was taken by the
+// restriction into this level (its iterate was 0).
 template <typename T>
-static int smooth_stage(stk_ctx* ctx, const Batch& F, const stk_mg_opts& o, int nu) {
-    for (int q = 0; q < nu; ++q) STK_TRY(mg_jacobi<T>(ctx, F, o.omega, q & 1));
+static int smooth_stage(stk_ctx* ctx, const Batch& F, const stk_mg_opts& o, int nu, bool first_done = false) {
+    for (int q = first_done ? 1 : 0; q < nu; ++q) STK_TRY(mg_jacobi<T>(ctx, F, o.omega, q & 1));
     if (nu & 1) STK_TRY(mg_copy_wv<T>(ctx, F));
     return STK_OK;
 }
 
+// The restriction into a coarse level took its first sweep (see first_sweep
+// in build_plan): the pre-smoothing of a level d >= 1 smoothed by Jacobi with
+// nu1 >= 1, or the relaxation of a relaxed last level.
+static bool first_sweep_done(const stk_mg_opts& o, int nu) { return o.coarse_smoother != 1 && nu >= 1; }
+
 // nu sweeps of a coarse level's smoother, v -> v: Jacobi, or (the mixed
 // smoother) RAS outer iterations of min(coarse_k, sweeps left) sweeps.
 template <typename T>
-static int coarse_stage(stk_ctx* ctx, const Batch& F, const Batch& Ft, const stk_mg_opts& o, int nu) {
-    if (o.coarse_smoother != 1) return smooth_stage<T>(ctx, F, o, nu);
+static int coarse_stage(stk_ctx* ctx, const Batch& F, const Batch& Ft, const stk_mg_opts& o, int nu,
+                        bool first_done = false) {
+    if (o.coarse_smoother != 1) return smooth_stage<T>(ctx, F, o, nu, first_done);
     int left = nu, q = 0;
     for (; left > 0; ++q) {
         const int kt = std::min(o.coarse_k, left);
@@ -596,15 +619,16 @@ static int vcycle(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o) {
             STK_TRY(fine_ras_stage<T>(ctx, P, o, nu1, false, &done));
             STK_TRY(mg_residual<T>(ctx, P.fine0w));
         } else {
-            STK_TRY(d == 0 ? smooth_stage<T>(ctx, F, o, nu1) : coarse_stage<T>(ctx, F, P.fine_t[d], o, nu1));
+            STK_TRY(d == 0 ? smooth_stage<T>(ctx, F, o, nu1)
+                           : coarse_stage<T>(ctx, F, P.fine_t[d], o, nu1, first_sweep_done(o, nu1)));
             STK_TRY(mg_residual<T>(ctx, F));
         }
-        STK_TRY(mg_restrict<T>(ctx, P.crs[d]));
+        STK_TRY(mg_restrict<T>(ctx, P.crs[d], o.omega));
         if (d + 1 < (int)P.cjobs.size()) {
             STK_TRY(mg_coarse<T>(ctx, P.cjobs[d + 1], P.ncj[d + 1], P.maxcn));
             if (P.relax[d + 1].n) {  // truncated hierarchies: the last level relaxed from 0
                 const int nr = level_sweeps(o.nu1, o.sweep_growth, d + 1) + level_sweeps(o.nu2, o.sweep_growth, d + 1);
-                STK_TRY(coarse_stage<T>(ctx, P.relax[d + 1], P.relax_t[d + 1], o, nr));
+                STK_TRY(coarse_stage<T>(ctx, P.relax[d + 1], P.relax_t[d + 1], o, nr, first_sweep_done(o, nr)));
             }
         }
     }

@@ -29,6 +29,12 @@ struct LevelJob {
     T *cvx, *cvy;  // coarse iterate
     const T* st;    // stored Galerkin stencil (coarse levels), nullptr on the finest
     int64_t plane;  // elements per stencil plane
+    // the restriction also takes the coarse level's first smoothing sweep from 0
+    // (damped Jacobi, written to cw*) when `first`; cst / cplane: its stencil
+    int first;
+    const T* cst;
+    int64_t cplane;
+    T *cwx, *cwy;
 };
 
 // Coarsest level of one instance: n unknowns, map[q] = (component << 30) |
@@ -93,8 +99,10 @@ constexpr int SUM_CHUNK = 4096;
 
 template <typename T> int mg_jacobi(stk_ctx* ctx, const Batch& b, double omega, int dir);
 template <typename T> int mg_residual(stk_ctx* ctx, const Batch& b);
-// coarse right-hand side = R r, and the coarse iterate set to 0
-template <typename T> int mg_restrict(stk_ctx* ctx, const Batch& b_coarse_blocks);
+// coarse right-hand side = R r, and the coarse iterate set to 0, or, for jobs
+// with `first`, the coarse level's first Jacobi sweep from 0 (damping omega)
+// written to its w
+template <typename T> int mg_restrict(stk_ctx* ctx, const Batch& b_coarse_blocks, double omega);
 template <typename T> int mg_prolong(stk_ctx* ctx, const Batch& b);
 template <typename T> int mg_coarse(stk_ctx* ctx, const void* jobs, int n, int max_unknowns);
 

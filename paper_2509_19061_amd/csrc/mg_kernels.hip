@@ -295,8 +295,16 @@ __device__ __forceinline__ int w_tangent(int f, int nc, int* c, double* w) {
 // one round trip instead of one per term.
 // rf(c, fi, fj): the fine residual of component c (as double); (i, j) inside
 // the coarse (cnx+1) x (cny+1) box.
+//
+// J.first: the coarse level's first smoothing sweep is taken here.  That
+// sweep starts from the zero iterate, so A v = 0 and each new value depends
+// only on the point's own right-hand side and diagonal: the damped Jacobi
+// update jac_step(0, omega / a_ii, b, -0), the same operation with the same
+// operands as in k_mg_jacobi (which sums the zero terms to +0).  It is written
+// to w, where that sweep writes, and v is not cleared (the next sweep, w -> v,
+// or the odd-count copy overwrites it before anything reads it).
 template <typename T, typename RF>
-__device__ __forceinline__ void restrict_from(const LevelJob<T>& J, int i, int j, const RF& rf) {
+__device__ __forceinline__ void restrict_from(const LevelJob<T>& J, int i, int j, const RF& rf, T omega) {
     const int NX = J.cnx, NY = J.cny, nx = J.nx, ny = J.ny;
     const int64_t cld = J.cld, k = (int64_t)j * cld + i;
     if (j < NY) {  // coarse vx(I=i, J=j): fine columns 2i-1..2i+1 (normal), rows 2j-1..2j+2 (tangential)
@@ -330,8 +338,12 @@ __device__ __forceinline__ void restrict_from(const LevelJob<T>& J, int i, int j
                 }
             }
         }
-        J.cbx[k] = T(s);
-        J.cvx[k] = T(0);
+        const T bc = T(s);
+        J.cbx[k] = bc;
+        if (J.first)
+            J.cwx[k] = (i >= 1 && i <= NX - 1) ? jac_step<T>(T(0), omega / J.cst[k], bc, -T(0)) : T(0);
+        else
+            J.cvx[k] = T(0);
     }
     if (i < NX) {  // coarse vy(I=i, J=j): fine rows 2j-1..2j+1 (normal), columns 2i-1..2i+2 (tangential)
         double s = 0.0;
@@ -364,19 +376,23 @@ __device__ __forceinline__ void restrict_from(const LevelJob<T>& J, int i, int j
                 }
             }
         }
-        J.cby[k] = T(s);
-        J.cvy[k] = T(0);
+        const T bc = T(s);
+        J.cby[k] = bc;
+        if (J.first)
+            J.cwy[k] = (j >= 1 && j <= NY - 1) ? jac_step<T>(T(0), omega / J.cst[PL_VY * J.cplane + k], bc, -T(0))
+                                               : T(0);
+        else
+            J.cvy[k] = T(0);
     }
 }
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
-                                                    int n) {
+                                                    int n, T omega) {
     STK_BATCH_INDEX(jobs, pre, n, COARSE_NX, COARSE_NY)
     if (i > J.cnx || j > J.cny) return;
     const int64_t ld = J.ld;
-    restrict_from<T>(J, i, j, [&](int c, int fi, int fj) {
-        return (double)(c == 0 ? J.rx : J.ry)[(int64_t)fj * ld + fi];
-    });
+    restrict_from<T>(
+        J, i, j, [&](int c, int fi, int fj) { return (double)(c == 0 ? J.rx : J.ry)[(int64_t)fj * ld + fi]; }, omega);
 }
 
 // Interpolation terms of one fine unknown: up to 2 x 2 coarse indices with
@@ -865,10 +881,10 @@ int mg_residual(stk_ctx* ctx, const Batch& b) {
     return STK_OK;
 }
 template <typename T>
-int mg_restrict(stk_ctx* ctx, const Batch& b) {
+int mg_restrict(stk_ctx* ctx, const Batch& b, double omega) {
     if (!b.n) return STK_OK;
     hipLaunchKernelGGL(k_mg_restrict<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
-                       static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n);
+                       static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n, T(omega));
     STK_LAUNCH_CHECK();
     return STK_OK;
 }
@@ -894,8 +910,8 @@ template int mg_copy_wv<double>(stk_ctx*, const Batch&);
 template int mg_copy_wv<float>(stk_ctx*, const Batch&);
 template int mg_residual<double>(stk_ctx*, const Batch&);
 template int mg_residual<float>(stk_ctx*, const Batch&);
-template int mg_restrict<double>(stk_ctx*, const Batch&);
-template int mg_restrict<float>(stk_ctx*, const Batch&);
+template int mg_restrict<double>(stk_ctx*, const Batch&, double);
+template int mg_restrict<float>(stk_ctx*, const Batch&, double);
 template int mg_prolong<double>(stk_ctx*, const Batch&);
 template int mg_prolong<float>(stk_ctx*, const Batch&);
 template int mg_coarse<double>(stk_ctx*, const void*, int, int);
