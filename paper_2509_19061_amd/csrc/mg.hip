@@ -532,8 +532,9 @@ static const PlanT::RasK* ras_shape(stk_ctx* ctx, const PlanT& P, int kt, int h,
     return r.ok ? &P.ras_k.back() : nullptr;
 }
 
-// nu Jacobi sweeps v -> v; first_done: the first one (v -> w) was taken by the
-// restriction into this level (its iterate was 0).
+// nu Jacobi sweeps v -> v; first_done: the first one (v -> w) was already
+// taken (by the restriction into this level, from its zero iterate, or with
+// the prolongation before the post-smoothing).
 template <typename T>
 static int smooth_stage(stk_ctx* ctx, const Batch& F, const stk_mg_opts& o, int nu, bool first_done = false) {
     for (int q = first_done ? 1 : 0; q < nu; ++q) STK_TRY(mg_jacobi<T>(ctx, F, o.omega, q & 1));
@@ -640,6 +641,10 @@ static int vcycle(stk_ctx* ctx, const PlanT& P, const stk_mg_opts& o) {
             STK_TRY(mg_prolong<T>(ctx, P.fine0w));
             bool done = false;
             STK_TRY(fine_ras_stage<T>(ctx, P, o, nu2, true, &done));
+        } else if (d >= 1 && o.coarse_smoother != 1 && nu2 >= 1) {
+            // the prolongation and the first post-sweep in one pass (v + P e -> w)
+            STK_TRY(mg_jacobi_prolonged<T>(ctx, F, o.omega));
+            STK_TRY(smooth_stage<T>(ctx, F, o, nu2, true));
         } else {
             STK_TRY(mg_prolong<T>(ctx, F));
             STK_TRY(d == 0 ? smooth_stage<T>(ctx, F, o, nu2) : coarse_stage<T>(ctx, F, P.fine_t[d], o, nu2));

@@ -104,6 +104,9 @@ template <typename T> int mg_residual(stk_ctx* ctx, const Batch& b);
 // written to its w
 template <typename T> int mg_restrict(stk_ctx* ctx, const Batch& b_coarse_blocks, double omega);
 template <typename T> int mg_prolong(stk_ctx* ctx, const Batch& b);
+// Stored-stencil levels: v + P e_c, then one Jacobi sweep of it into w, in one
+// pass (v itself is left as it was)
+template <typename T> int mg_jacobi_prolonged(stk_ctx* ctx, const Batch& b, double omega);
 template <typename T> int mg_coarse(stk_ctx* ctx, const void* jobs, int n, int max_unknowns);
 
 // Galerkin setup of one coarse level from the next finer one (galerkin.hip).

@@ -407,58 +407,112 @@ __device__ __forceinline__ void pad_terms(Terms& t) {
     if (t.nb == 1) { t.cj[1] = t.cj[0]; t.wj[1] = 0.0; }
 }
 
-// v += P e_c on the fine unknowns.  The coarse values are loaded first, all
-// at once (their indices are inside the coarse arrays whether or not the
-// term is used), and the terms added in the same order as the weights list
-// them.
+// (P e_c) at a fine vx / vy unknown (i, j), as double.  The coarse values are
+// loaded first, all at once (their indices are inside the coarse arrays
+// whether or not the term is used), and the terms added in the order the
+// weights list them.
+template <typename T>
+__device__ __forceinline__ double prolong_sx(const LevelJob<T>& J, int i, int j) {
+    Terms t;
+    t.na = w_normal(i, t.ci, t.wi);
+    t.nb = w_tangent(j, J.cny, t.cj, t.wj);
+    pad_terms(t);
+    double c[2][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) c[p][q] = (double)J.cvx[(int64_t)t.cj[q] * J.cld + t.ci[p]];
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double cv = (t.ci[p] >= 1 && t.ci[p] <= J.cnx - 1) ? c[p][q] : 0.0;
+            if (p < t.na && q < t.nb) s += t.wi[p] * t.wj[q] * cv;
+        }
+    return s;
+}
+template <typename T>
+__device__ __forceinline__ double prolong_sy(const LevelJob<T>& J, int i, int j) {
+    Terms t;
+    t.na = w_tangent(i, J.cnx, t.ci, t.wi);
+    t.nb = w_normal(j, t.cj, t.wj);
+    pad_terms(t);
+    double c[2][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) c[p][q] = (double)J.cvy[(int64_t)t.cj[q] * J.cld + t.ci[p]];
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double cv = (t.cj[q] >= 1 && t.cj[q] <= J.cny - 1) ? c[p][q] : 0.0;
+            if (p < t.na && q < t.nb) s += t.wi[p] * t.wj[q] * cv;
+        }
+    return s;
+}
+
+// v += P e_c on the fine unknowns.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_prolong(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
                                                    int n) {
     STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
-    const int nx = J.nx, ny = J.ny, NX = J.cnx, NY = J.cny;
+    const int nx = J.nx, ny = J.ny;
     if (i > nx || j > ny) return;
-    const int64_t k = (int64_t)j * J.ld + i, cld = J.cld;
+    const int64_t k = (int64_t)j * J.ld + i;
     if (is_vx_unknown(nx, ny, i, j)) {
-        Terms t;
-        t.na = w_normal(i, t.ci, t.wi);
-        t.nb = w_tangent(j, NY, t.cj, t.wj);
-        pad_terms(t);
-        double c[2][2];
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) c[p][q] = (double)J.cvx[(int64_t)t.cj[q] * cld + t.ci[p]];
         const T v = J.vx[k];
-        double s = 0.0;
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const double cv = (t.ci[p] >= 1 && t.ci[p] <= NX - 1) ? c[p][q] : 0.0;
-                if (p < t.na && q < t.nb) s += t.wi[p] * t.wj[q] * cv;
-            }
-        J.vx[k] = v + T(s);
+        J.vx[k] = v + T(prolong_sx(J, i, j));
     }
     if (is_vy_unknown(nx, ny, i, j)) {
-        Terms t;
-        t.na = w_tangent(i, NX, t.ci, t.wi);
-        t.nb = w_normal(j, t.cj, t.wj);
-        pad_terms(t);
-        double c[2][2];
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) c[p][q] = (double)J.cvy[(int64_t)t.cj[q] * cld + t.ci[p]];
         const T v = J.vy[k];
-        double s = 0.0;
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const double cv = (t.cj[q] >= 1 && t.cj[q] <= NY - 1) ? c[p][q] : 0.0;
-                if (p < t.na && q < t.nb) s += t.wi[p] * t.wj[q] * cv;
-            }
-        J.vy[k] = v + T(s);
+        J.vy[k] = v + T(prolong_sy(J, i, j));
+    }
+}
+
+// Stored-stencil levels: the prolongation and the first post-smoothing sweep
+// (v + P e_c -> w) in one pass.  The staged window holds the corrected
+// iterate, v + T(P e_c) on the unknowns and 0 elsewhere, which is what
+// k_mg_prolong stores and the loaders then read; it is not stored, since the
+// next sweep (w -> v) or the odd-count copy overwrites v.  Staged in both
+// precisions: the correction is computed where it is staged.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mg_jacobi_prolonged(const LevelJob<T>* __restrict__ jobs,
+                                                            const int* __restrict__ pre, int n, T omega) {
+    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    const int nx = J.nx, ny = J.ny;
+    const int64_t ld = J.ld;
+    __shared__ T win[2 * SWY * SWX];
+    const int i0 = i - (int)(threadIdx.x % BX) - 2, j0 = j - (int)(threadIdx.x / BX) - 2;
+    for (int e = threadIdx.x; e < 2 * SWY * SWX; e += NT) {
+        const int c = e / (SWY * SWX), r = (e / SWX) % SWY, x = e % SWX;
+        const int ii = i0 + x, jj = j0 + r;
+        const int64_t kk = (int64_t)jj * ld + ii;
+        T val = T(0);
+        if (c == 0 && is_vx_unknown(nx, ny, ii, jj)) {
+            const T v = J.vx[kk];
+            val = v + T(prolong_sx(J, ii, jj));
+        } else if (c == 1 && is_vy_unknown(nx, ny, ii, jj)) {
+            const T v = J.vy[kk];
+            val = v + T(prolong_sy(J, ii, jj));
+        }
+        win[e] = val;
+    }
+    __syncthreads();
+    const PatchPair<T> lv{win, i0, j0};
+    if (i > nx || j > ny) return;
+    const int64_t k = (int64_t)j * ld + i;
+    for (int a = 0; a < 2; ++a) {
+        if (a == 0 ? j >= ny : i >= nx) continue;
+        T out = T(0);
+        if (a == 0 ? is_vx_unknown(nx, ny, i, j) : is_vy_unknown(nx, ny, i, j)) {
+            T d;
+            const T av = stencil_av_l<T>(J.st, J.plane, a, lv, ld, nx, ny, i, j, d);
+            out = jac_step<T>(lv(a, i, j), omega / d, (a == 0 ? J.bx : J.by)[k], -av);
+        }
+        (a == 0 ? J.wx : J.wy)[k] = out;
     }
 }
 
@@ -897,6 +951,14 @@ int mg_prolong(stk_ctx* ctx, const Batch& b) {
     return STK_OK;
 }
 template <typename T>
+int mg_jacobi_prolonged(stk_ctx* ctx, const Batch& b, double omega) {
+    if (!b.n) return STK_OK;
+    hipLaunchKernelGGL(k_mg_jacobi_prolonged<T>, dim3(b.blocks), dim3(NT), 0, ctx->stream,
+                       static_cast<const LevelJob<T>*>(b.jobs), b.pre, b.n, T(omega));
+    STK_LAUNCH_CHECK();
+    return STK_OK;
+}
+template <typename T>
 int mg_coarse(stk_ctx* ctx, const void* jobs, int n, int max_unknowns) {
     if (!n) return STK_OK;
     hipLaunchKernelGGL(k_mg_coarse<T>, dim3(n), dim3(256), (size_t)max_unknowns * sizeof(double), ctx->stream,
@@ -914,6 +976,8 @@ template int mg_restrict<double>(stk_ctx*, const Batch&, double);
 template int mg_restrict<float>(stk_ctx*, const Batch&, double);
 template int mg_prolong<double>(stk_ctx*, const Batch&);
 template int mg_prolong<float>(stk_ctx*, const Batch&);
+template int mg_jacobi_prolonged<double>(stk_ctx*, const Batch&, double);
+template int mg_jacobi_prolonged<float>(stk_ctx*, const Batch&, double);
 template int mg_coarse<double>(stk_ctx*, const void*, int, int);
 template int mg_coarse<float>(stk_ctx*, const void*, int, int);
 
