@@ -40,6 +40,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <mutex>
+#include <set>
 #include <vector>
 
 #include "stencil.hpp"
@@ -856,10 +857,12 @@ int launch_batch_t(stk_ctx* ctx, const RasShape& sh, const void* jobs, const int
         attr_set[dev] = sh.lds;
     }
     RasArgs a{};
-    a.Tx = a.Ty = sh.tile;
+    a.Tx = sh.tile;
+    a.Ty = sh.ty;
     a.h = sh.h;
     a.kt = sh.kt;
-    a.sx = a.sy = sh.tile;  // cuts at multiples of the tile, the first tile at 0
+    a.sx = sh.tile;  // cuts at multiples of the tile (and of its height), the first tile at 0
+    a.sy = sh.ty;
     a.NT = sh.NT;
     a.merge = sh.merge;
     a.Wm = sh.Wm;
@@ -895,44 +898,81 @@ void batch_shape_ws(stk_ctx* ctx, const int* nx, const int* ny, int n, int tile,
     const int mm = feeder_loads(Wm);
     const int D = std::min(kt, h + 1);
     const bool merge = h >= kt - 1;  // full overlap: a workgroup's tiles are streamed as one
-    // stream rows of NT tiles, the most over the instances
-    auto stream_rows = [&](int NT) {
+    // stream rows of a tile of height H, the most over the instances
+    auto rows_h = [&](int64_t H) {
         int rows = 0;
-        for (int q = 0; q < n; ++q) {
-            auto tr = [&](int64_t H) {
-                return (int)std::min<int64_t>(std::min<int64_t>(H + 2 * (int64_t)h, ny[q]) + 2,
-                                              std::min<int64_t>(H, ny[q]) + 2 * D);
-            };
-            rows = std::max(rows, merge ? tr((int64_t)NT * tile) : NT * tr(tile));
-        }
+        for (int q = 0; q < n; ++q)
+            rows = std::max(rows, (int)std::min<int64_t>(std::min<int64_t>(H + 2 * (int64_t)h, ny[q]) + 2,
+                                                         std::min<int64_t>(H, ny[q]) + 2 * D));
         return rows;
     };
     double best_cost = 1e300;
-    for (int NT = 1; NT <= 8; ++NT) {
-        RasArgs t{};
-        t.kt = kt;
-        t.Vmax = stream_rows(NT);
-        const size_t l = stream_lds_bytes<T, WS>(t);
-        if (l > (size_t)ctx->lds_max) break;
-        int per_cu = stream_occupancy<T, WS>(ctx->device, nthr, mm, l);
-        if (ctx->lds_cu > 0) per_cu = std::min<int>(per_cu, ctx->lds_cu / (int)((l + 2047) & ~size_t(2047)));
-        if (per_cu < 1) break;
-        int64_t nwg = 0;
-        for (int q = 0; q < n; ++q) {
-            const int ntx = (nx[q] + tile - 1) / tile, nty = (ny[q] + tile - 1) / tile;
-            nwg += (int64_t)ntx * ((nty + NT - 1) / NT);
+    int best_ty = tile;
+    if (merge) {
+        // Full overlap, as in try_stream_ws: one tile of H rows per workgroup, cut at
+        // multiples of H, H chosen over the instances' heights ceil(ny / r) so that the
+        // workgroups fill whole rounds.  Resident workgroups per CU are capped at 3 in
+        // FP64 and 4 in FP32: in the 2048^2 V-cycle (k = 2) four FP64 workgroups of
+        // 64-row tiles per CU took 84 us a launch against 68 us for three of 86 rows,
+        // and five FP32 ones of 52 rows were slower than four of 64 (62 against 47 us),
+        // although the occupancy query allows them.
+        RasArgs t0{};
+        t0.kt = kt;
+        const int occ = std::min(stream_occupancy<T, WS>(ctx->device, nthr, mm, stream_lds_bytes<T, WS>(t0)),
+                                 sizeof(T) == 8 ? 3 : 4);
+        std::set<int> hs;
+        for (int q = 0; q < n; ++q)
+            for (int r = 1; r <= std::max(1, ny[q] / 16); ++r) hs.insert((ny[q] + r - 1) / r);
+        for (int H : hs) {
+            RasArgs t{};
+            t.kt = kt;
+            t.Vmax = rows_h(H);
+            const size_t l = stream_lds_bytes<T, WS>(t);
+            if (l > (size_t)ctx->lds_max) continue;
+            int per_cu = occ;
+            if (ctx->lds_cu > 0) per_cu = std::min<int>(per_cu, ctx->lds_cu / (int)((l + 2047) & ~size_t(2047)));
+            if (per_cu < 1) continue;
+            int64_t nwg = 0;
+            for (int q = 0; q < n; ++q) nwg += (int64_t)((nx[q] + tile - 1) / tile) * ((ny[q] + H - 1) / H);
+            const int64_t slots = (int64_t)per_cu * std::max(ctx->num_cu, 1);
+            const double cost = (double)((nwg + slots - 1) / slots) * (t.Vmax + 2 * kt + 1);
+            if (cost < best_cost && nwg < INT32_MAX) {
+                best_cost = cost;
+                best_ty = H;
+                out->NT = 1;
+                out->Vmax = t.Vmax;
+                out->lds = l;
+                out->nwg = (int)nwg;
+            }
         }
-        const int64_t slots = (int64_t)per_cu * std::max(ctx->num_cu, 1);
-        const double cost = (double)((nwg + slots - 1) / slots) * (t.Vmax + 2 * kt + 1);
-        if (cost < best_cost && nwg < INT32_MAX) {
-            best_cost = cost;
-            out->NT = NT;
-            out->Vmax = t.Vmax;
-            out->lds = l;
-            out->nwg = (int)nwg;
+    } else {
+        for (int NT = 1; NT <= 8; ++NT) {
+            RasArgs t{};
+            t.kt = kt;
+            t.Vmax = NT * rows_h(tile);  // NT tiles, each with its overlap rows
+            const size_t l = stream_lds_bytes<T, WS>(t);
+            if (l > (size_t)ctx->lds_max) break;
+            int per_cu = stream_occupancy<T, WS>(ctx->device, nthr, mm, l);
+            if (ctx->lds_cu > 0) per_cu = std::min<int>(per_cu, ctx->lds_cu / (int)((l + 2047) & ~size_t(2047)));
+            if (per_cu < 1) break;
+            int64_t nwg = 0;
+            for (int q = 0; q < n; ++q) {
+                const int ntx = (nx[q] + tile - 1) / tile, nty = (ny[q] + tile - 1) / tile;
+                nwg += (int64_t)ntx * ((nty + NT - 1) / NT);
+            }
+            const int64_t slots = (int64_t)per_cu * std::max(ctx->num_cu, 1);
+            const double cost = (double)((nwg + slots - 1) / slots) * (t.Vmax + 2 * kt + 1);
+            if (cost < best_cost && nwg < INT32_MAX) {
+                best_cost = cost;
+                out->NT = NT;
+                out->Vmax = t.Vmax;
+                out->lds = l;
+                out->nwg = (int)nwg;
+            }
         }
     }
     if (best_cost >= 1e300) return;
+    out->ty = best_ty;
     out->tile = tile;
     out->h = h;
     out->kt = kt;
@@ -944,7 +984,7 @@ void batch_shape_ws(stk_ctx* ctx, const int* nx, const int* ny, int n, int tile,
     pre->assign(1, 0);
     ntxv->clear();
     for (int q = 0; q < n; ++q) {
-        const int ntx = (nx[q] + tile - 1) / tile, nty = (ny[q] + tile - 1) / tile;
+        const int ntx = (nx[q] + tile - 1) / tile, nty = (ny[q] + best_ty - 1) / best_ty;
         ntxv->push_back(ntx);
         pre->push_back(pre->back() + ntx * ((nty + out->NT - 1) / out->NT));
     }

@@ -95,6 +95,7 @@ struct RasJob {
 struct RasShape {
     int tile, h, kt, NT, Wm, Vmax, nthr, mm, ws, nwg;
     int merge;  // full overlap: a workgroup's NT tiles are streamed as one
+    int ty;     // tile height: the tile, or (full overlap) the height that fills whole rounds
     size_t lds;
 };
 // Shape for instances of nx[i] x ny[i] cells (square tiles cut at multiples
