@@ -33,14 +33,24 @@ __device__ __forceinline__ int find_inst(const int* __restrict__ pre, int n, int
     return lo;
 }
 
-// (instance, i, j) of this thread for a box of (nx+1) x (ny+1) indices
-#define STK_BATCH_INDEX(JOBS, PRE, N, NXF, NYF)                                     \
-    const int inst = find_inst(PRE, N, (int)blockIdx.x);                             \
+// (instance, i, j) of this thread for a box of (nx+1) x (ny+1) indices, block
+// B of the flat grid
+#define STK_BATCH_INDEX_B(JOBS, PRE, N, NXF, NYF, B)                                \
+    const int inst = find_inst(PRE, N, (B));                                         \
     const auto& J = JOBS[inst];                                                      \
-    const int lb = (int)blockIdx.x - PRE[inst];                                      \
+    const int lb = (B) - PRE[inst];                                                  \
     const int gxb = (NXF(J) + 1 + BX - 1) / BX;                                      \
     const int i = (lb % gxb) * BX + (int)(threadIdx.x % BX);                         \
     const int j = (lb / gxb) * BY + (int)(threadIdx.x / BX);
+#define STK_BATCH_INDEX(JOBS, PRE, N, NXF, NYF) STK_BATCH_INDEX_B(JOBS, PRE, N, NXF, NYF, (int)blockIdx.x)
+// The same with the blocks renumbered by XCD (xcd_tile): the block above a
+// block (gxb further on) then runs on the same XCD at about the same time, and
+// the rows both read (the stencil's reach, the transfers' windows) come from
+// that XCD's L2.  In row order the level-1 Jacobi sweep of the 2048^2 solve
+// read 1.4 times its algorithmic bytes.  For the kernels without block
+// partials (their order would change the sums).
+#define STK_BATCH_INDEX_XCD(JOBS, PRE, N, NXF, NYF) \
+    STK_BATCH_INDEX_B(JOBS, PRE, N, NXF, NYF, xcd_tile((int)blockIdx.x, (int)gridDim.x))
 
 #define FINE_NX(J) (J).nx
 #define FINE_NY(J) (J).ny
@@ -98,7 +108,7 @@ __device__ __forceinline__ PatchPair<T> stage_patch(T* win, const T* vx, const T
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_jacobi(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
                                                   int n, T omega, int dir) {
-    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    STK_BATCH_INDEX_XCD(jobs, pre, n, FINE_NX, FINE_NY)
     const T* sx = dir ? J.wx : J.vx;
     const T* sy = dir ? J.wy : J.vy;
     T* dx_ = dir ? J.vx : J.wx;
@@ -227,7 +237,7 @@ __device__ __forceinline__ void mf_residual(const LevelJob<T>& J, int i, int j, 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_residual(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
                                                     int n) {
-    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    STK_BATCH_INDEX_XCD(jobs, pre, n, FINE_NX, FINE_NY)
     const int nx = J.nx, ny = J.ny;
     const int64_t ld = J.ld, k = (int64_t)j * ld + i;
     if (J.st) {  // r = b - M v = b + A v (velocity staged in FP64, as in k_mg_jacobi)
@@ -388,7 +398,7 @@ __device__ __forceinline__ void restrict_from(const LevelJob<T>& J, int i, int j
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_restrict(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
                                                     int n, T omega) {
-    STK_BATCH_INDEX(jobs, pre, n, COARSE_NX, COARSE_NY)
+    STK_BATCH_INDEX_XCD(jobs, pre, n, COARSE_NX, COARSE_NY)
     if (i > J.cnx || j > J.cny) return;
     const int64_t ld = J.ld;
     restrict_from<T>(
@@ -458,7 +468,7 @@ __device__ __forceinline__ double prolong_sy(const LevelJob<T>& J, int i, int j)
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_prolong(const LevelJob<T>* __restrict__ jobs, const int* __restrict__ pre,
                                                    int n) {
-    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    STK_BATCH_INDEX_XCD(jobs, pre, n, FINE_NX, FINE_NY)
     const int nx = J.nx, ny = J.ny;
     if (i > nx || j > ny) return;
     const int64_t k = (int64_t)j * J.ld + i;
@@ -481,7 +491,7 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(const LevelJob<T>* __restrict
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mg_jacobi_prolonged(const LevelJob<T>* __restrict__ jobs,
                                                             const int* __restrict__ pre, int n, T omega) {
-    STK_BATCH_INDEX(jobs, pre, n, FINE_NX, FINE_NY)
+    STK_BATCH_INDEX_XCD(jobs, pre, n, FINE_NX, FINE_NY)
     const int nx = J.nx, ny = J.ny;
     const int64_t ld = J.ld;
     __shared__ T win[2 * SWY * SWX];
