@@ -82,6 +82,10 @@ __host__ __device__ constexpr SlotSrc slot_src(int a, int s) {
 }
 
 // Full-row coefficient of slot s at row (a, i, j) of a level of nx x ny cells.
+// A neighbour outside the (nx+1) x (ny+1) box reads as 0: its load is clamped
+// onto the box and the value dropped, so no load sits under a branch and a
+// row's 31 loads are issued back to back (under branches each one waited for
+// the one before).
 template <typename T>
 __host__ __device__ __forceinline__ T stencil_coef(const T* st, int64_t plane, int64_t ld, int nx, int ny, int a, int s,
                                                    int i, int j) {
@@ -89,7 +93,10 @@ __host__ __device__ __forceinline__ T stencil_coef(const T* st, int64_t plane, i
     const int pi = i + src.ndx, pj = j + src.ndy;
     // (i, j) itself is inside every plane: no bounds check
     if (src.ndx == 0 && src.ndy == 0) return st[src.plane * plane + (int64_t)j * ld + i];
-    return (pi >= 0 && pi <= nx && pj >= 0 && pj <= ny) ? st[src.plane * plane + (int64_t)pj * ld + pi] : T(0);
+    const bool in = pi >= 0 && pi <= nx && pj >= 0 && pj <= ny;
+    const int ci = pi < 0 ? 0 : (pi > nx ? nx : pi), cj = pj < 0 ? 0 : (pj > ny ? ny : pj);
+    const T c = st[src.plane * plane + (int64_t)cj * ld + ci];
+    return in ? c : T(0);
 }
 
 // (A v) at the unknown (a, i, j) from the stored stencil, with v(c, i, j)
