@@ -6,7 +6,7 @@
 //           N_f = sum f^2/d.
 //
 // Both stream rows like the fused Jacobi kernel: a wave owns a strip of
-// SW = 62 columns and SR rows, its 64 lanes hold the strip and one neighbour
+// SW = 62 columns and seg_rows rows, its 64 lanes hold the strip and one neighbour
 // column on each side, each row of every field is loaded once (coalesced
 // buffer loads; walls and outside read as 0), three rows stay in registers
 // and the columns i +- 1 come from neighbouring lanes (DPP).  The energy sums
@@ -178,7 +178,7 @@ int launch_residual_to32(stk_ctx* ctx, const stk_grid* g, const double* vx, cons
     return STK_OK;
 }
 
-int64_t energy_partials(const stk_grid* g) { return (int64_t)strips(g->nx) * segments(g->ny); }
+int64_t energy_partials(const stk_grid* g) { return (int64_t)strips(g->nx) * segments(g->nx, g->ny); }
 
 int launch_energy(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const void* vx, const void* vy, const void* p,
                   const void* eta_c, const void* eta_n, const void* fx, const void* fy, double* dst) {

@@ -2,7 +2,7 @@
 // grid: fused Jacobi, residual, energy norms, and the finest level of the
 // batched V-cycle.
 //
-// A wave owns a strip of SW = 62 columns and a segment of SR rows.  Its 64
+// A wave owns a strip of SW = 62 columns and a segment of seg_rows rows.  Its 64
 // lanes hold the columns x0 - 1 .. x0 + 62 (the strip and one neighbour
 // column on each side); it walks up the rows, loading each row of every field
 // once with coalesced buffer loads, keeps a window of three rows in registers
@@ -27,14 +27,29 @@ namespace stk {
 namespace rows {
 
 constexpr int SW = 62;  // columns a wave owns
-constexpr int SR = 64;  // rows a wave walks
+constexpr int SR = 64;  // the most rows a wave walks
 constexpr int WPB = 4;  // waves per workgroup (independent)
+// Fewer waves than this (16 per CU of a 256-CU chip) leave the walk's latency
+// exposed: a grid whose 64-row segments give fewer is cut into 32- or 16-row
+// segments (each re-reads the two rows around it).  At 2048^2 (1122 waves of
+// 64 rows) 16-row segments made the FCG iteration 2.7 % faster, at 1024^2 5 %;
+// 4096^2 and larger keep 64.
+constexpr int64_t MIN_WAVES = 4096;
 
 __host__ __device__ inline int strips(int nx) { return (nx + 1 + SW - 1) / SW; }
-__host__ __device__ inline int segments(int ny) { return (ny + 1 + SR - 1) / SR; }
+// rows a wave walks on an nx x ny grid: SR, or SR / 2, SR / 4 (at least 16)
+__host__ __device__ inline int seg_rows(int nx, int ny) {
+    int r = SR;
+    while (r > 16 && (int64_t)strips(nx) * ((ny + 1 + r - 1) / r) < MIN_WAVES) r >>= 1;
+    return r;
+}
+__host__ __device__ inline int segments(int nx, int ny) {
+    const int r = seg_rows(nx, ny);
+    return (ny + 1 + r - 1) / r;
+}
 // workgroups for one (nx, ny) grid
 __host__ __device__ inline int workgroups(int nx, int ny) {
-    return (int)(((int64_t)strips(nx) * segments(ny) + WPB - 1) / WPB);
+    return (int)(((int64_t)strips(nx) * segments(nx, ny) + WPB - 1) / WPB);
 }
 
 // One grid row of the inputs at this lane's column: velocity, viscosities,
@@ -84,11 +99,11 @@ struct Place {
 };
 __device__ __forceinline__ Place place(int wv, int nx, int ny) {
     Place q;
-    const int nstrip = strips(nx), nseg = segments(ny), lane = threadIdx.x & 63;
+    const int sr = seg_rows(nx, ny), nstrip = strips(nx), nseg = (ny + 1 + sr - 1) / sr, lane = threadIdx.x & 63;
     const int strip = wv % nstrip, seg = wv / nstrip;
     q.i = strip * SW - 1 + lane;
-    q.y0 = seg * SR;
-    q.y1 = seg < nseg ? min(q.y0 + SR, ny + 1) : q.y0;
+    q.y0 = seg * sr;
+    q.y1 = seg < nseg ? min(q.y0 + sr, ny + 1) : q.y0;
     q.own = lane >= 1 && lane <= SW && q.i <= nx;
     return q;
 }
