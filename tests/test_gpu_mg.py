@@ -274,3 +274,30 @@ def test_footprint_covers_what_a_solve_holds(ctx):
         m.solve(mode, vx, vy, None, dq.fx, dq.fy, tol=1e-6, max_iters=200)
         held, fp = m.info()["bytes"], api.mg_footprint(dq.grid, mode)
         assert held <= fp <= 1.05 * held, (mode, held, fp)
+
+
+@pytest.mark.parametrize("nu1,nu2,growth,max_levels", [
+    (1, 1, 1.0, 0), (0, 2, 1.0, 0), (2, 0, 1.0, 0), (1, 3, 1.0, 0), (1, 2, 2.0, 0), (1, 1, 1.0, 3), (0, 1, 1.0, 3)])
+def test_vcycle_sweep_counts_match_oracle(ctx, nu1, nu2, growth, max_levels):
+    """Sweep counts at the edges of the passes folded into the transfers: the
+    restriction into a Jacobi-smoothed coarse level takes its first pre-sweep
+    (from zero), the prolongation onto a Galerkin level its first post-sweep.
+    One sweep (then the w -> v copy), none, growing counts, and a truncated
+    hierarchy whose relaxed last level gets its first sweep the same way,
+    against the oracle's V-cycle, which does none of this folding."""
+    from oracle import sparse as SP
+    p = sinkers(96, 64, 21, 1e2)
+    levels = OM.hierarchy_truncated(p, max_levels) if max_levels else OM.hierarchy(p, coarsest=8)
+    m, dp = gpu_mg(ctx, p, nu1=nu1, nu2=nu2, omega=0.6, sweep_growth=growth, max_levels=max_levels)
+    assert m.info()["levels"] == len(levels)
+    vx0, vy0 = I.random_velocity(p, 31, 1e-2)
+    rx, ry = I.random_velocity(p, 32, 1.0)
+    vx, vy = dp.velocity(vx0, vy0)
+    m.vcycle(torch.float64, vx, vy, dp.field(rx), dp.field(ry))
+    torch.cuda.synchronize()
+    L = levels[0]
+    x = SP.pack(L.nx, L.ny, vx0, vy0)
+    c = -SP.pack(L.nx, L.ny, rx, ry)
+    ox, oy = SP.unpack(L.nx, L.ny, OM.vcycle_general(levels, 0, x, c, nu1=nu1, nu2=nu2, omega=0.6, growth=growth,
+                                                     relax_coarsest=bool(max_levels)))
+    assert normwise(dp.get_vx(vx), ox) <= TOL_V and normwise(dp.get_vy(vy), oy) <= TOL_V
