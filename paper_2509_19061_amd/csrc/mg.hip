@@ -457,25 +457,17 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P, 
         std::vector<int> cp{0};
         for (int q = 0; q < n; ++q) cp.push_back(cp.back() + (pra[q + 1] - pra[q] + SUM_CHUNK - 1) / SUM_CHUNK);
         const void* dcp = nullptr;
-        void* p2 = nullptr;
         STK_TRY(upload(P, cp, &dcp, s));
-        STK_TRY(pdalloc(P, sizeof(double) * 2 * (size_t)std::max(1, cp.back()), &p2, s));
         P->applyr = Batch{nullptr, (const int*)dpra, n, pra.back()};
         P->applyr.cpre = static_cast<const int*>(dcp);
-        P->applyr.chunks = cp.back();
-        P->applyr.part2 = static_cast<double*>(p2);
     }
     P->vec = Batch{dvj, (const int*)dpa, n, pa.back()};
     {  // reduction chunks of the vector batch
         std::vector<int> cp{0};
         for (int q = 0; q < n; ++q) cp.push_back(cp.back() + (pa[q + 1] - pa[q] + SUM_CHUNK - 1) / SUM_CHUNK);
         const void* dcp = nullptr;
-        void* p2 = nullptr;
         STK_TRY(upload(P, cp, &dcp, s));
-        STK_TRY(pdalloc(P, sizeof(double) * 2 * (size_t)std::max(1, cp.back()), &p2, s));
         P->vec.cpre = static_cast<const int*>(dcp);
-        P->vec.chunks = cp.back();
-        P->vec.part2 = static_cast<double*>(p2);
     }
     if (t == 1) {  // casts between the FP64 Krylov slots and this plan's FP32 V-cycle slots
         STK_TRY(upload(P, xj, &dxj, s));

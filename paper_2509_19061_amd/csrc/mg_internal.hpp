@@ -85,11 +85,8 @@ struct Batch {       // a job array resident on the device plus its block prefix
     int n = 0;       // instances
     int blocks = 0;  // total blocks
     // reductions over the blocks (vector batches only): per-instance chunks of
-    // at most SUM_CHUNK block partials, chunk prefix cpre[0..n], partials of
-    // the chunks in part2 (2 per chunk)
+    // at most SUM_CHUNK block partials, chunk prefix cpre[0..n]
     const int* cpre = nullptr;
-    int chunks = 0;
-    double* part2 = nullptr;
     // finest (matrix-free) level: workgroup prefix of the row-streaming kernels
     // (rowstream.hpp); when set, smoothing and residual use them
     const int* rpre = nullptr;
@@ -136,23 +133,22 @@ enum VecOp {
     OP_INIT_P,      // p = z; acc0 += r.z
     OP_ZERO_Z       // z = 0
 };
-// phases of fcg_scalars: PH_NV ends a CG iteration (stop below the threshold
-// or when the budget runs out), PH_TRUE takes a recomputed true residual
-// (stop below the threshold only)
+// phases of the scalar update: PH_NF sets N_f and the stop threshold
+// tol2 * N_f, PH_NV ends a CG iteration (stop below the threshold or when the
+// budget runs out), PH_TRUE takes a recomputed true residual (stop below the
+// threshold only)
 enum { PH_NF = 0, PH_NV, PH_INIT, PH_ALPHA, PH_BETA, PH_TRUE };
 // Slot dtype T for the slots touched (R, Z, P, Q, X); partial sums land in
-// `part` (2 per block), then per-instance sums in `sums` (2 per instance).
+// `part` (2 per block), summed per instance by fcg_reduce.  z32: the batch's Z
+// slot holds FP32 vectors (the FP32 V-cycle's output, read in place by the
+// FP64 Krylov operations).
 template <typename T>
-// z32: the batch's Z slot holds FP32 vectors (the FP32 V-cycle's output, read
-// in place by the FP64 Krylov operations).
-int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* part, double* sums, bool z32 = false);
-// R = B - M X in FP64; sums[2i] = sum R^2 / d (sums == nullptr: the block partials only)
-int vec_residual64_st(stk_ctx* ctx, const Batch& b, const FcgState* st, double* part, double* sums);
-// Per-instance scalar update from the reduced sums (one thread per instance);
-// PH_NF sets N_f and the stop threshold tol2 * N_f.
-int fcg_scalars(stk_ctx* ctx, FcgState* st, const double* sums, int n, int phase);
-// inst_sums + fcg_scalars in one launch over the reduction chunks of `red`
-// (the same bits); out != nullptr (device-visible pinned host memory): the
+int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* part, bool z32 = false);
+// R = B - M X in FP64, block partials of sum R^2 / d in `part`
+int vec_residual64_st(stk_ctx* ctx, const Batch& b, const FcgState* st, double* part);
+// Per-instance sums of the block partials over the reduction chunks of `red`
+// (fixed order) into sums (2 per instance) and the scalar update of `phase`,
+// in one launch; out != nullptr (device-visible pinned host memory): the
 // updated states are also copied there.
 int fcg_reduce(stk_ctx* ctx, const Batch& red, const double* part, double* sums, FcgState* st, int phase,
                FcgState* out = nullptr);
@@ -168,13 +164,10 @@ struct XCastJob {
     float* z32[2];
 };
 int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st);
-// per-instance sums of the block partials, in a fixed order: chunk sums, then chunks in order
-int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums);
-// FP64 FCG, finest level: Q = A P and per-instance P . Q into sums (apply:
-// the operator batch with its row-streaming prefix; red: the reduction chunks
-// over that prefix); sums == nullptr: the block partials only
-int fcg_apply_pq(stk_ctx* ctx, const Batch& apply, const Batch& red, const FcgState* st, double* part,
-                 double* sums);
+// FP64 FCG, finest level: Q = A P and the block partials of P . Q (apply: the
+// operator batch with its row-streaming prefix; summed over its reduction
+// chunks by fcg_reduce)
+int fcg_apply_pq(stk_ctx* ctx, const Batch& apply, const FcgState* st, double* part);
 template <typename T> int mg_copy_wv(stk_ctx* ctx, const Batch& b);
 // Coarse-level RAS outer iteration (mg_ras.hip): kt sweeps per tile of the
 // stored stencil, tiles `tile` cells cut at multiples of it, overlap h; b's

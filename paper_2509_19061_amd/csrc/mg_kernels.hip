@@ -755,48 +755,6 @@ __global__ __launch_bounds__(NT) void k_vec_res64(const VecJob* __restrict__ job
     block_sum2(a0, 0.0, part);
 }
 
-// Per-instance sums of the per-block partials in a fixed order.  Stage 1:
-// chunk c (of instance inst) sums partials [pre[inst] + lc * SUM_CHUNK, ...)
-// with 256 threads; stage 2: one thread per instance adds its chunk sums in
-// order.  Both orders depend only on the instance's own block count.
-__global__ __launch_bounds__(256) void k_chunk_sums(const int* __restrict__ pre, const int* __restrict__ cpre, int n,
-                                                    const double* __restrict__ part, double* __restrict__ part2) {
-    const int c = blockIdx.x;
-    const int inst = find_inst(cpre, n, c);
-    const int b0 = pre[inst] + (c - cpre[inst]) * SUM_CHUNK;
-    const int b1 = min(pre[inst + 1], b0 + SUM_CHUNK);
-    __shared__ double red[2][256 / 64];
-    double s0 = 0.0, s1 = 0.0;
-    for (int b = b0 + (int)threadIdx.x; b < b1; b += 256) {
-        s0 += part[2 * b];
-        s1 += part[2 * b + 1];
-    }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = s0;
-        red[1][threadIdx.x >> 6] = s1;
-    }
-    __syncthreads();
-    if (threadIdx.x < 2) {
-        double s = 0.0;
-        for (int q = 0; q < 256 / 64; ++q) s += red[threadIdx.x][q];
-        part2[2 * c + threadIdx.x] = s;
-    }
-}
-__global__ void k_inst_sums(const int* __restrict__ cpre, int n, const double* __restrict__ part2,
-                            double* __restrict__ sums) {
-    const int inst = blockIdx.x * blockDim.x + threadIdx.x;
-    if (inst >= n) return;
-    double s0 = 0.0, s1 = 0.0;
-    for (int c = cpre[inst]; c < cpre[inst + 1]; ++c) {
-        s0 += part2[2 * c];
-        s1 += part2[2 * c + 1];
-    }
-    sums[2 * inst] = s0;
-    sums[2 * inst + 1] = s1;
-}
-
 __device__ __forceinline__ void fcg_update(FcgState& s, double s0, double s1, int phase) {
     switch (phase) {
         case PH_NF:  // N_f and the stop threshold
@@ -838,19 +796,16 @@ __device__ __forceinline__ void fcg_update(FcgState& s, double s0, double s1, in
         }
     }
 }
-__global__ void k_fcg_scalars(FcgState* __restrict__ st, const double* __restrict__ sums, int n, int phase) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    fcg_update(st[q], sums[2 * q], sums[2 * q + 1], phase);
-}
 
-// k_chunk_sums, k_inst_sums and k_fcg_scalars in one launch, one workgroup
-// per instance: the instance's chunks one after the other, each summed by
-// the same 256 threads in the same order as k_chunk_sums, the chunk sums
-// added in order as k_inst_sums does (the same bits), then the scalar update,
+// Per-instance sums of the per-block partials and the scalar update in one
+// launch, one workgroup per instance.  The order is fixed and depends only on
+// the instance's own block count: its partials come in chunks of SUM_CHUNK
+// blocks; in a chunk, thread t sums partials t, t + 256, ... in turn, the
+// waves reduce by shuffles, and the four wave sums are added in order; the
+// chunk sums are added in chunk order.  Then the scalar update of `phase`,
 // and optionally a copy of the updated state to `out` (pinned host memory).
-// Each of these launches costs about 5 us on the device however small, and
-// an iteration had nine of them.
+// This replaced three launches per dot product (chunk sums, instance sums,
+// scalar update), each about 5 us on the device however small.
 __global__ __launch_bounds__(256) void k_fcg_reduce(const int* __restrict__ pre, const int* __restrict__ cpre,
                                                     const double* __restrict__ part, double* __restrict__ sums,
                                                     FcgState* __restrict__ st, int phase, FcgState* out) {
@@ -861,7 +816,7 @@ __global__ __launch_bounds__(256) void k_fcg_reduce(const int* __restrict__ pre,
         const int b0 = pre[inst] + (c - cpre[inst]) * SUM_CHUNK;
         const int b1 = min(pre[inst + 1], b0 + SUM_CHUNK);
         // a thread's SUM_CHUNK / 256 partials are loaded before they are added (in
-        // k_chunk_sums' order): one round trip per chunk instead of one per partial
+        // the order above): one round trip per chunk instead of one per partial
         double v0[SUM_CHUNK / 256], v1[SUM_CHUNK / 256];
 #pragma unroll
         for (int q = 0; q < SUM_CHUNK / 256; ++q) {
@@ -992,7 +947,7 @@ template int mg_coarse<double>(stk_ctx*, const void*, int, int);
 template int mg_coarse<float>(stk_ctx*, const void*, int, int);
 
 template <typename T>
-int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* part, double* sums, bool z32) {
+int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* part, bool z32) {
     if (!b.n) return STK_OK;
     if (z32)
         hipLaunchKernelGGL((k_vec<T, float>), dim3(b.blocks), dim3(NT), 0, ctx->stream,
@@ -1001,28 +956,17 @@ int vec_op(stk_ctx* ctx, const Batch& b, int op, const FcgState* st, double* par
         hipLaunchKernelGGL((k_vec<T, T>), dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const VecJob*>(b.jobs),
                            b.pre, b.n, op, st, part);
     STK_LAUNCH_CHECK();
-    if (sums) return inst_sums(ctx, b, part, sums);
     return STK_OK;
 }
-template int vec_op<double>(stk_ctx*, const Batch&, int, const FcgState*, double*, double*, bool);
+template int vec_op<double>(stk_ctx*, const Batch&, int, const FcgState*, double*, bool);
 
-int inst_sums(stk_ctx* ctx, const Batch& b, const double* part, double* sums) {
-    if (!b.cpre || !b.part2) return set_error(STK_EINVAL, "internal: batch without reduction chunks");
-    hipLaunchKernelGGL(k_chunk_sums, dim3(b.chunks), dim3(256), 0, ctx->stream, b.pre, b.cpre, b.n, part, b.part2);
-    hipLaunchKernelGGL(k_inst_sums, dim3((b.n + 63) / 64), dim3(64), 0, ctx->stream, b.cpre, b.n,
-                       (const double*)b.part2, sums);
-    STK_LAUNCH_CHECK();
-    return STK_OK;
-}
-
-int fcg_apply_pq(stk_ctx* ctx, const Batch& apply, const Batch& red, const FcgState* st, double* part,
-                 double* sums) {
+int fcg_apply_pq(stk_ctx* ctx, const Batch& apply, const FcgState* st, double* part) {
     if (!apply.n) return STK_OK;
     if (!apply.rpre) return set_error(STK_EINVAL, "internal: operator batch without row-streaming prefix");
     hipLaunchKernelGGL(k_fcg_apply_rows, dim3(apply.rblocks), dim3(64 * rows::WPB), 0, ctx->stream,
                        static_cast<const LevelJob<double>*>(apply.jobs), apply.rpre, apply.n, st, part);
     STK_LAUNCH_CHECK();
-    return sums ? inst_sums(ctx, red, part, sums) : STK_OK;
+    return STK_OK;
 }
 
 int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st) {
@@ -1032,12 +976,12 @@ int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st) {
     STK_LAUNCH_CHECK();
     return STK_OK;
 }
-int vec_residual64_st(stk_ctx* ctx, const Batch& b, const FcgState* st, double* part, double* sums) {
+int vec_residual64_st(stk_ctx* ctx, const Batch& b, const FcgState* st, double* part) {
     if (!b.n) return STK_OK;
     hipLaunchKernelGGL(k_vec_res64, dim3(b.blocks), dim3(NT), 0, ctx->stream, static_cast<const VecJob*>(b.jobs), b.pre,
                        b.n, st, part);
     STK_LAUNCH_CHECK();
-    return sums ? inst_sums(ctx, b, part, sums) : STK_OK;
+    return STK_OK;
 }
 int fcg_reduce(stk_ctx* ctx, const Batch& red, const double* part, double* sums, FcgState* st, int phase,
                FcgState* out) {
@@ -1045,12 +989,6 @@ int fcg_reduce(stk_ctx* ctx, const Batch& red, const double* part, double* sums,
     if (!red.cpre) return set_error(STK_EINVAL, "internal: batch without reduction chunks");
     hipLaunchKernelGGL(k_fcg_reduce, dim3(red.n), dim3(256), 0, ctx->stream, red.pre, red.cpre, part, sums, st, phase,
                        out);
-    STK_LAUNCH_CHECK();
-    return STK_OK;
-}
-int fcg_scalars(stk_ctx* ctx, FcgState* st, const double* sums, int n, int phase) {
-    if (!n) return STK_OK;
-    hipLaunchKernelGGL(k_fcg_scalars, dim3((n + 63) / 64), dim3(64), 0, ctx->stream, st, sums, n, phase);
     STK_LAUNCH_CHECK();
     return STK_OK;
 }

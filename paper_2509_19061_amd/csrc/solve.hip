@@ -49,7 +49,7 @@ struct Slot {
 // FP64 Z is already 0 (OP_UPDATE clears it).
 int precondition(stk_ctx* ctx, const PlanT& P, const PlanT* P32, const stk_mg_opts& o, bool z_zeroed) {
     if (!P32) {
-        if (!z_zeroed) STK_TRY(vec_op<double>(ctx, P.vec, OP_ZERO_Z, P.st, P.part, nullptr));
+        if (!z_zeroed) STK_TRY(vec_op<double>(ctx, P.vec, OP_ZERO_Z, P.st, P.part));
         return run_vcycle(ctx, P, o, 0);
     }
     // r32 = (float) r and z32 = 0, the FP32 V-cycle, whose z32 the Krylov steps read in place
@@ -162,13 +162,13 @@ int start_phase(stk_batch* b, int* done, stk_report* reps, int* ndone) {
     }
     if (any_new) {
         if (int rc = write_states(ctx, *Q, h)) return fail(rc);
-        if (int rc = vec_op<double>(ctx, Q->vec, OP_FNORM, Q->st, Q->part, nullptr)) return fail(rc);
+        if (int rc = vec_op<double>(ctx, Q->vec, OP_FNORM, Q->st, Q->part)) return fail(rc);
         if (int rc = fcg_reduce(ctx, Q->vec, Q->part, Q->sums, Q->st, PH_NF)) return fail(rc);
         if (int rc = read_states(ctx, *Q, h)) return fail(rc);
     }
     for (auto& s : h) s.active = 1;
     if (int rc = write_states(ctx, *Q, h)) return fail(rc);
-    if (int rc = vec_residual64_st(ctx, Q->vec, Q->st, Q->part, nullptr)) return fail(rc);
+    if (int rc = vec_residual64_st(ctx, Q->vec, Q->st, Q->part)) return fail(rc);
     if (int rc = fcg_reduce(ctx, Q->vec, Q->part, Q->sums, Q->st, PH_TRUE)) return fail(rc);
     if (int rc = read_states(ctx, *Q, h)) return fail(rc);
     bool restart = false;
@@ -188,7 +188,7 @@ int start_phase(stk_batch* b, int* done, stk_report* reps, int* ndone) {
     if (restart) {  // Z = V(R), P = Z, gamma for the slots that go on
         if (int rc = write_states(ctx, *Q, h)) return fail(rc);
         if (int rc = precondition(ctx, *Q, Q32, o, false)) return fail(rc);
-        if (int rc = vec_op<double>(ctx, Q->vec, OP_INIT_P, Q->st, Q->part, nullptr, Q->vec_z32)) return fail(rc);
+        if (int rc = vec_op<double>(ctx, Q->vec, OP_INIT_P, Q->st, Q->part, Q->vec_z32)) return fail(rc);
         if (int rc = fcg_reduce(ctx, Q->vec, Q->part, Q->sums, Q->st, PH_INIT)) return fail(rc);
         if (int rc = read_states(ctx, *Q, h)) return fail(rc);
         for (int q = 0; q < n; ++q) {
@@ -247,10 +247,10 @@ int iterate_phase(stk_batch* b, int iters) {
     };
     std::vector<FcgState> hn;
     for (int it = 0; it < iters; ++it) {
-        STK_TRY(fcg_apply_pq(ctx, P.apply, P.applyr, P.st, P.part, nullptr));  // Q = A P and P . Q
+        STK_TRY(fcg_apply_pq(ctx, P.apply, P.st, P.part));  // Q = A P and P . Q
         STK_TRY(fcg_reduce(ctx, P.applyr, P.part, P.sums, P.st, PH_ALPHA));
         // (the Z slot's dtype selects the kernel: OP_UPDATE clears an FP64 Z)
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_UPDATE, P.st, P.part, nullptr, P.vec_z32));
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_UPDATE, P.st, P.part, P.vec_z32));
         // stop below tol or at the end of the budget
         if (b->lookahead) {
             // The states go to the host while the rest of the iteration is queued behind
@@ -265,9 +265,9 @@ int iterate_phase(stk_batch* b, int iters) {
             if (!take(hn.data())) break;
         }
         STK_TRY(precondition(ctx, P, b->P32, o, true));
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_RZ_ZQ, P.st, P.part, nullptr, P.vec_z32));
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_RZ_ZQ, P.st, P.part, P.vec_z32));
         STK_TRY(fcg_reduce(ctx, P.vec, P.part, P.sums, P.st, PH_BETA));
-        STK_TRY(vec_op<double>(ctx, P.vec, OP_XPBY, P.st, P.part, nullptr, P.vec_z32));
+        STK_TRY(vec_op<double>(ctx, P.vec, OP_XPBY, P.st, P.part, P.vec_z32));
         if (b->lookahead) {
             STK_HIP(hipEventSynchronize(b->ev));
             if (!take(b->pin)) break;
