@@ -24,9 +24,10 @@
 //                64 x 4 workgroup walks up a segment of z-planes with a ring
 //                of four planes (the planes k - 1, k, k + 1 it reads, and
 //                k + 2, loaded meanwhile) of the three components in LDS,
-//                halo included; the coefficients come from global memory.
-//                Same operands, same row functions: the same values as
-//                k_jacobi3d.
+//                halo included; the coefficients come from global memory,
+//                addressed by one 32-bit offset per plane.  Same operands,
+//                same row arithmetic: the same values as k_jacobi3d, which
+//                serves the arrays beyond 2^32 bytes.
 //   k_ras3d      one workgroup per T^3 tile: the tile grown by h plus the
 //                one-cell frozen ring is staged in LDS (three components,
 //                two buffers), k sweeps run there with a barrier between
@@ -97,11 +98,21 @@ __device__ __forceinline__ T eyz3(const Fields3<T>& f, int i, int j, int k) {
 // Velocity values by a loader V(c, i, j, k) (c: 0 vx, 1 vy, 2 vz) that
 // returns 0 for walls and anything outside the arrays.  The row functions
 // return (M v) at the unknown and the diagonal d = diag(-M).
+//
+// The coefficients of one row come in a Row3: the cell viscosities behind and
+// ahead of the face along its own axis (e0, e1), and the edge viscosities
+// behind and ahead along each of the two other axes, in x, y, z order
+// (s0, s1, t0, t1), boundary edges already 0.  The gathering forms below
+// (mvx3, ...) load them through Fields3; the plane-streaming sweep loads
+// them its own way and calls the same arithmetic (mvx3c, ...).
+template <typename T>
+struct Row3 {
+    T e0, e1, s0, s1, t0, t1;
+};
 template <typename T, typename V>
-__device__ __forceinline__ T mvx3(const Fields3<T>& f, const V& v, int i, int j, int k, T& d) {
+__device__ __forceinline__ T mvx3c(const Fields3<T>& f, const V& v, int i, int j, int k, const Row3<T>& w, T& d) {
     const T c = v(0, i, j, k);
-    const T e0 = f.ec[at3(f, i - 1, j, k)], e1 = f.ec[at3(f, i, j, k)];
-    const T s0 = exy3(f, i, j, k), s1 = exy3(f, i, j + 1, k), t0 = exz3(f, i, j, k), t1 = exz3(f, i, j, k + 1);
+    const T e0 = w.e0, e1 = w.e1, s0 = w.s0, s1 = w.s1, t0 = w.t0, t1 = w.t1;
     const T txx1 = T(2) * e1 * (v(0, i + 1, j, k) - c) * f.idx, txx0 = T(2) * e0 * (c - v(0, i - 1, j, k)) * f.idx;
     const T txy1 = s1 * ((v(0, i, j + 1, k) - c) * f.idy + (v(1, i, j + 1, k) - v(1, i - 1, j + 1, k)) * f.idx);
     const T txy0 = s0 * ((c - v(0, i, j - 1, k)) * f.idy + (v(1, i, j, k) - v(1, i - 1, j, k)) * f.idx);
@@ -111,10 +122,9 @@ __device__ __forceinline__ T mvx3(const Fields3<T>& f, const V& v, int i, int j,
     return (txx1 - txx0) * f.idx + (txy1 - txy0) * f.idy + (txz1 - txz0) * f.idz;
 }
 template <typename T, typename V>
-__device__ __forceinline__ T mvy3(const Fields3<T>& f, const V& v, int i, int j, int k, T& d) {
+__device__ __forceinline__ T mvy3c(const Fields3<T>& f, const V& v, int i, int j, int k, const Row3<T>& w, T& d) {
     const T c = v(1, i, j, k);
-    const T e0 = f.ec[at3(f, i, j - 1, k)], e1 = f.ec[at3(f, i, j, k)];
-    const T s0 = exy3(f, i, j, k), s1 = exy3(f, i + 1, j, k), t0 = eyz3(f, i, j, k), t1 = eyz3(f, i, j, k + 1);
+    const T e0 = w.e0, e1 = w.e1, s0 = w.s0, s1 = w.s1, t0 = w.t0, t1 = w.t1;
     const T tyy1 = T(2) * e1 * (v(1, i, j + 1, k) - c) * f.idy, tyy0 = T(2) * e0 * (c - v(1, i, j - 1, k)) * f.idy;
     const T txy1 = s1 * ((v(0, i + 1, j, k) - v(0, i + 1, j - 1, k)) * f.idy + (v(1, i + 1, j, k) - c) * f.idx);
     const T txy0 = s0 * ((v(0, i, j, k) - v(0, i, j - 1, k)) * f.idy + (c - v(1, i - 1, j, k)) * f.idx);
@@ -124,10 +134,9 @@ __device__ __forceinline__ T mvy3(const Fields3<T>& f, const V& v, int i, int j,
     return (tyy1 - tyy0) * f.idy + (txy1 - txy0) * f.idx + (tyz1 - tyz0) * f.idz;
 }
 template <typename T, typename V>
-__device__ __forceinline__ T mvz3(const Fields3<T>& f, const V& v, int i, int j, int k, T& d) {
+__device__ __forceinline__ T mvz3c(const Fields3<T>& f, const V& v, int i, int j, int k, const Row3<T>& w, T& d) {
     const T c = v(2, i, j, k);
-    const T e0 = f.ec[at3(f, i, j, k - 1)], e1 = f.ec[at3(f, i, j, k)];
-    const T s0 = exz3(f, i, j, k), s1 = exz3(f, i + 1, j, k), t0 = eyz3(f, i, j, k), t1 = eyz3(f, i, j + 1, k);
+    const T e0 = w.e0, e1 = w.e1, s0 = w.s0, s1 = w.s1, t0 = w.t0, t1 = w.t1;
     const T tzz1 = T(2) * e1 * (v(2, i, j, k + 1) - c) * f.idz, tzz0 = T(2) * e0 * (c - v(2, i, j, k - 1)) * f.idz;
     const T txz1 = s1 * ((v(0, i + 1, j, k) - v(0, i + 1, j, k - 1)) * f.idz + (v(2, i + 1, j, k) - c) * f.idx);
     const T txz0 = s0 * ((v(0, i, j, k) - v(0, i, j, k - 1)) * f.idz + (c - v(2, i - 1, j, k)) * f.idx);
@@ -135,6 +144,24 @@ __device__ __forceinline__ T mvz3(const Fields3<T>& f, const V& v, int i, int j,
     const T tyz0 = t0 * ((v(1, i, j, k) - v(1, i, j, k - 1)) * f.idz + (c - v(2, i, j - 1, k)) * f.idy);
     d = T(2) * (e0 + e1) * f.idz * f.idz + (s0 + s1) * f.idx * f.idx + (t0 + t1) * f.idy * f.idy;
     return (tzz1 - tzz0) * f.idz + (txz1 - txz0) * f.idx + (tyz1 - tyz0) * f.idy;
+}
+template <typename T, typename V>
+__device__ __forceinline__ T mvx3(const Fields3<T>& f, const V& v, int i, int j, int k, T& d) {
+    const Row3<T> w{f.ec[at3(f, i - 1, j, k)], f.ec[at3(f, i, j, k)], exy3(f, i, j, k), exy3(f, i, j + 1, k),
+                    exz3(f, i, j, k), exz3(f, i, j, k + 1)};
+    return mvx3c(f, v, i, j, k, w, d);
+}
+template <typename T, typename V>
+__device__ __forceinline__ T mvy3(const Fields3<T>& f, const V& v, int i, int j, int k, T& d) {
+    const Row3<T> w{f.ec[at3(f, i, j - 1, k)], f.ec[at3(f, i, j, k)], exy3(f, i, j, k), exy3(f, i + 1, j, k),
+                    eyz3(f, i, j, k), eyz3(f, i, j, k + 1)};
+    return mvy3c(f, v, i, j, k, w, d);
+}
+template <typename T, typename V>
+__device__ __forceinline__ T mvz3(const Fields3<T>& f, const V& v, int i, int j, int k, T& d) {
+    const Row3<T> w{f.ec[at3(f, i, j, k - 1)], f.ec[at3(f, i, j, k)], exz3(f, i, j, k), exz3(f, i + 1, j, k),
+                    eyz3(f, i, j, k), eyz3(f, i, j + 1, k)};
+    return mvz3c(f, v, i, j, k, w, d);
 }
 
 // Loader of the global velocity arrays: walls and outside read as 0.
@@ -191,11 +218,27 @@ __global__ __launch_bounds__(J3X* J3Y) void k_jacobi3d(Fields3<T> f, T omega, co
 }
 
 // --------------------------------------------- Jacobi (3D), plane streaming --
+// A 64 x 4 workgroup owns the cells [i0, i0 + 64) x [j0, j0 + 4) of a segment
+// of up to 32 planes and walks up it.  The three velocity components of the
+// window (the tile plus one halo cell on each side) live in an LDS ring of
+// four planes: k - 1, k, k + 1 are read while plane k is relaxed and k + 2 is
+// loaded into registers meanwhile.  The walls beyond the last cell, vx(nx),
+// vy(ny) and vz(nz), are written by the threads of the cells below them, so
+// no workgroup exists for them alone.
+//
+// Everything that depends on the thread but not on the plane is computed once:
+// the window cells it loads and whether each holds an unknown, and the
+// boundary tests of its edge viscosities.  Within a plane every address is one
+// 32-bit byte offset from a uniform base (the host keeps the arrays within
+// 2^32 bytes), and every load is made unconditionally from a place on the
+// arrays and its value dropped where it does not count, so no load waits under
+// a branch.  Same operands and same row arithmetic as the gathering kernel.
 constexpr int ZX = 64, ZY = 4, ZS = 32;               // tile columns, rows, planes per segment
+constexpr int ZNT = ZX * ZY;
 constexpr int ZWX = ZX + 2, ZWY = ZY + 2;              // staged window (one halo cell each side)
-constexpr int ZPL = ZWX * ZWY;                         // window cells of one plane
+constexpr int ZPL = ZWX * ZWY;                         // window cells of one component and plane
 constexpr int ZSLOT = 3 * ZPL;                         // one ring slot: three components
-constexpr int ZLOADS = (ZSLOT + ZX * ZY - 1) / (ZX * ZY);  // loads per thread per plane
+static_assert(ZPL > ZNT && ZPL <= 2 * ZNT, "two window loads per thread and component");
 
 // Velocity loader of the staged ring: (c, i, j, k) -> the window cell, for
 // i0 - 1 <= i <= i0 + 64, j0 - 1 <= j <= j0 + 4 and any of the three planes
@@ -209,80 +252,157 @@ struct RingV {
     }
 };
 
-// The window of plane k: the staged value of every cell, 0 for a wall or a
-// cell outside the arrays (the gather's operands).
 template <typename T>
-__device__ __forceinline__ void load_plane(const GlobalV<T>& g, int i0, int j0, int k, T (&r)[ZLOADS]) {
+__device__ __forceinline__ T at_b(const T* __restrict__ base, uint32_t off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void put_b(T* __restrict__ base, uint32_t off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
+// The window cells of one thread: cell e = tid + 256 m of each component's
+// window plane (m = 0, 1; the second only for e < ZPL), its byte offset within
+// a plane (clamped onto the array where the cell is outside it) and whether it
+// holds an unknown of vx, vy, vz in that plane's rows and columns.
+struct ZWin {
+    uint32_t off[2];
+    bool x[2], y[2], z[2];
+};
+
+template <typename T>
+__device__ __forceinline__ void zwin_load(const ZWin& w, const T* __restrict__ vx, const T* __restrict__ vy,
+                                          const T* __restrict__ vz, uint32_t pb, bool kxy, bool kz,
+                                          T (&r)[2][3]) {
 #pragma unroll
-    for (int m = 0; m < ZLOADS; ++m) {
-        const int e = (int)threadIdx.x + m * ZX * ZY;
-        const int c = e / ZPL, rr = e - c * ZPL, wy = rr / ZWX, wx = rr - wy * ZWX;
-        r[m] = e < ZSLOT ? g(c, i0 - 1 + wx, j0 - 1 + wy, k) : T(0);
+    for (int m = 0; m < 2; ++m) {
+        const T a = at_b(vx, w.off[m] + pb), b = at_b(vy, w.off[m] + pb), c = at_b(vz, w.off[m] + pb);
+        r[m][0] = w.x[m] && kxy ? a : T(0);
+        r[m][1] = w.y[m] && kxy ? b : T(0);
+        r[m][2] = w.z[m] && kz ? c : T(0);
     }
 }
 template <typename T>
-__device__ __forceinline__ void store_plane(T* w, int k, const T (&r)[ZLOADS]) {
+__device__ __forceinline__ void zwin_store(T* ring, int k, const T (&r)[2][3]) {
+    T* s = ring + (k & 3) * ZSLOT + threadIdx.x;
 #pragma unroll
-    for (int m = 0; m < ZLOADS; ++m) {
-        const int e = (int)threadIdx.x + m * ZX * ZY;
-        if (e < ZSLOT) w[(k & 3) * ZSLOT + e] = r[m];
+    for (int c = 0; c < 3; ++c) s[c * ZPL] = r[0][c];
+    if (threadIdx.x + ZNT < ZPL) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s[c * ZPL + ZNT] = r[1][c];
     }
 }
 
+// The coefficients of the thread's cell (i, j) in one plane k, raw (boundary
+// edges not yet dropped): eta_c at the cell and behind it along x, y, z;
+// eta_xy at (i, j), (i, j + 1), (i + 1, j); eta_xz at (i, k), (i, k + 1),
+// (i + 1, k); eta_yz at (j, k), (j, k + 1), (j + 1, k); b.  The loader
+// fetches all but ecz, b0 and c0, which the plane below already had.
 template <typename T>
-__global__ __launch_bounds__(ZX* ZY) void k_jacobi3d_z(Fields3<T> f, T omega, const T* __restrict__ vx,
-                                                        const T* __restrict__ vy, const T* __restrict__ vz,
-                                                        T* __restrict__ ox, T* __restrict__ oy, T* __restrict__ oz,
-                                                        int ntx, int nty) {
+struct Coef3 {
+    T ec, ecx, ecy, ecz, a0, a1, a2, b0, b1, b2, c0, c1, c2, bx, by, bz;
+};
+template <typename T>
+__device__ __forceinline__ Coef3<T> coef3_load(const Fields3<T>& f, uint32_t q, uint32_t dxm, uint32_t dym,
+                                               uint32_t sld, uint32_t slp) {
+    constexpr uint32_t es = sizeof(T);
+    Coef3<T> c;
+    c.ec = at_b(f.ec, q);
+    c.ecx = at_b(f.ec, q - dxm);
+    c.ecy = at_b(f.ec, q - dym);
+    c.a0 = at_b(f.exy, q);
+    c.a1 = at_b(f.exy, q + sld);
+    c.a2 = at_b(f.exy, q + es);
+    c.b1 = at_b(f.exz, q + slp);
+    c.b2 = at_b(f.exz, q + es);
+    c.c1 = at_b(f.eyz, q + slp);
+    c.c2 = at_b(f.eyz, q + sld);
+    c.bx = at_b(f.bx, q);
+    c.by = at_b(f.by, q);
+    c.bz = at_b(f.bz, q);
+    return c;
+}
+
+template <typename T>
+__global__ __launch_bounds__(ZNT) void k_jacobi3d_z(Fields3<T> f, T omega, const T* __restrict__ vx,
+                                                     const T* __restrict__ vy, const T* __restrict__ vz,
+                                                     T* __restrict__ ox, T* __restrict__ oy, T* __restrict__ oz,
+                                                     int ntx, int nty) {
     __shared__ T ring[4 * ZSLOT];
     const int nx = f.nx, ny = f.ny, nz = f.nz;
     // tiles numbered x fastest, then y, then z segments, renumbered by XCD
     const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
-    const int i0 = tx * ZX, j0 = ty * ZY, k0 = tz * ZS, k1 = min(k0 + ZS, nz + 1);
+    const int i0 = tx * ZX, j0 = ty * ZY, k0 = tz * ZS, k1 = min(k0 + ZS, nz);
     const int i = i0 + (int)(threadIdx.x % ZX), j = j0 + (int)(threadIdx.x / ZX);
-    const GlobalV<T> gv{vx, vy, vz, f.ld, f.lp, nx, ny, nz};
-    T r[ZLOADS];
-    load_plane<T>(gv, i0, j0, k0 - 1, r);
-    store_plane<T>(ring, k0 - 1, r);
-    load_plane<T>(gv, i0, j0, k0, r);
-    store_plane<T>(ring, k0, r);
-    load_plane<T>(gv, i0, j0, k0 + 1, r);
-    store_plane<T>(ring, k0 + 1, r);
+    const bool act = i < nx && j < ny;
+    const int ic = min(i, nx - 1), jc = min(j, ny - 1);  // inactive threads load from the last cell
+    constexpr uint32_t es = sizeof(T);
+    const uint32_t sld = (uint32_t)f.ld * es, slp = (uint32_t)f.lp * es;
+
+    ZWin w;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int e = (int)threadIdx.x + m * ZNT, wy = e / ZWX, wx = e - wy * ZWX;
+        const int gi = i0 - 1 + wx, gj = j0 - 1 + wy;
+        const bool in = e < ZPL, ix = gi >= 0 && gi < nx, jy = gj >= 0 && gj < ny;
+        w.off[m] = ((uint32_t)min(max(gj, 0), ny) * (uint32_t)f.ld + (uint32_t)min(max(gi, 0), nx)) * es;
+        w.x[m] = in && gi >= 1 && gi <= nx - 1 && jy;
+        w.y[m] = in && ix && gj >= 1 && gj <= ny - 1;
+        w.z[m] = in && ix && jy;
+    }
+    // plane kk of the window: clamped onto the array, dropped outside the unknowns
+    auto load = [&](int kk, T(&r)[2][3]) {
+        zwin_load<T>(w, vx, vy, vz, (uint32_t)min(max(kk, 0), nz) * slp, kk >= 0 && kk < nz, kk >= 1 && kk < nz, r);
+    };
+    T r[2][3];
+    load(k0 - 1, r);
+    zwin_store<T>(ring, k0 - 1, r);
+    load(k0, r);
+    zwin_store<T>(ring, k0, r);
+    load(k0 + 1, r);
+    zwin_store<T>(ring, k0 + 1, r);
     __syncthreads();
+
+    // boundary tests of the edges around the thread's cell (x and y parts)
+    const bool xi0 = ic >= 1, xi1 = ic <= nx - 2, yj0 = jc >= 1, yj1 = jc <= ny - 2;
+    const uint32_t dxm = xi0 ? es : 0u, dym = yj0 ? sld : 0u;  // the cell behind, or the cell itself at a wall
+    uint32_t q = (uint32_t)k0 * slp + (uint32_t)jc * sld + (uint32_t)ic * es;
+    // the coefficients of plane k0; those of plane k + 1 are loaded during
+    // step k, and the three that planes k and k + 1 share are carried
+    Coef3<T> c = coef3_load<T>(f, q, dxm, dym, sld, slp);
+    c.ecz = at_b(f.ec, q - (k0 >= 1 ? slp : 0u));
+    c.b0 = at_b(f.exz, q);
+    c.c0 = at_b(f.eyz, q);
     const RingV<T> v{ring, i0, j0};
-    for (int k = k0; k < k1; ++k) {
-        load_plane<T>(gv, i0, j0, k + 2, r);  // in flight while plane k is relaxed
-        if (i <= nx && j <= ny) {
-            const int64_t q = at3(f, i, j, k);
-            T d;
-            if (k < nz && j < ny) {
-                T o = T(0);
-                if (vx_unknown3(nx, ny, nz, i, j, k)) {
-                    const T m = mvx3<T>(f, v, i, j, k, d);
-                    o = jac_step<T>(v(0, i, j, k), omega / d, f.bx[q], m);
-                }
-                ox[q] = o;
-            }
-            if (k < nz && i < nx) {
-                T o = T(0);
-                if (vy_unknown3(nx, ny, nz, i, j, k)) {
-                    const T m = mvy3<T>(f, v, i, j, k, d);
-                    o = jac_step<T>(v(1, i, j, k), omega / d, f.by[q], m);
-                }
-                oy[q] = o;
-            }
-            if (j < ny && i < nx) {
-                T o = T(0);
-                if (vz_unknown3(nx, ny, nz, i, j, k)) {
-                    const T m = mvz3<T>(f, v, i, j, k, d);
-                    o = jac_step<T>(v(2, i, j, k), omega / d, f.bz[q], m);
-                }
-                oz[q] = o;
-            }
+    for (int k = k0; k < k1; ++k, q += slp) {
+        load(k + 2, r);  // in flight while plane k is relaxed
+        Coef3<T> n = coef3_load<T>(f, k + 1 < k1 ? q + slp : q, dxm, dym, sld, slp);
+        n.ecz = c.ec;
+        n.b0 = c.b1;
+        n.c0 = c.c1;
+        const bool kz0 = k >= 1, kz1 = k <= nz - 2;
+        const T sxy = xi0 && yj0 ? c.a0 : T(0), sxy_y = xi0 && yj1 ? c.a1 : T(0), sxy_x = xi1 && yj0 ? c.a2 : T(0);
+        const T sxz = xi0 && kz0 ? c.b0 : T(0), sxz_z = xi0 && kz1 ? c.b1 : T(0), sxz_x = xi1 && kz0 ? c.b2 : T(0);
+        const T syz = yj0 && kz0 ? c.c0 : T(0), syz_z = yj0 && kz1 ? c.c1 : T(0), syz_y = yj1 && kz0 ? c.c2 : T(0);
+        T d;
+        const T mx = mvx3c<T>(f, v, i, j, k, Row3<T>{c.ecx, c.ec, sxy, sxy_y, sxz, sxz_z}, d);
+        const T nvx = jac_step<T>(v(0, i, j, k), omega / d, c.bx, mx);
+        const T my = mvy3c<T>(f, v, i, j, k, Row3<T>{c.ecy, c.ec, sxy, sxy_x, syz, syz_z}, d);
+        const T nvy = jac_step<T>(v(1, i, j, k), omega / d, c.by, my);
+        const T mz = mvz3c<T>(f, v, i, j, k, Row3<T>{c.ecz, c.ec, sxz, sxz_x, syz, syz_y}, d);
+        const T nvz = jac_step<T>(v(2, i, j, k), omega / d, c.bz, mz);
+        if (act) {
+            put_b(ox, q, xi0 ? nvx : T(0));  // vx(0) is a wall
+            put_b(oy, q, yj0 ? nvy : T(0));  // vy(0)
+            put_b(oz, q, kz0 ? nvz : T(0));  // vz(0)
+            if (i == nx - 1) put_b(ox, q + es, T(0));
+            if (j == ny - 1) put_b(oy, q + sld, T(0));
+            if (k == nz - 1) put_b(oz, q + slp, T(0));
         }
+        c = n;
         // slot (k + 2) & 3 held plane k - 2, last read in the previous step
-        store_plane<T>(ring, k + 2, r);
+        zwin_store<T>(ring, k + 2, r);
         __syncthreads();
     }
 }
@@ -506,9 +626,10 @@ int check_grid3(const stk_grid3* g) {
 template <typename T>
 int launch_jacobi3d(stk_ctx* ctx, const stk_grid3* g, const Fields3<T>& f, double omega, const void* vx,
                     const void* vy, const void* vz, void* ox, void* oy, void* oz) {
-    const int ntx = (g->nx + 1 + ZX - 1) / ZX, nty = (g->ny + 1 + ZY - 1) / ZY, ntz = (g->nz + 1 + ZS - 1) / ZS;
+    const int ntx = (g->nx + ZX - 1) / ZX, nty = (g->ny + ZY - 1) / ZY, ntz = (g->nz + ZS - 1) / ZS;
     const int64_t nwg = (int64_t)ntx * nty * ntz;
-    if (nwg < INT32_MAX) {
+    // the plane-streaming sweep addresses each array by 32-bit byte offsets
+    if (nwg < INT32_MAX && (uint64_t)(g->nz + 1) * (uint64_t)g->lp * sizeof(T) <= UINT32_MAX) {
         hipLaunchKernelGGL(k_jacobi3d_z<T>, dim3((unsigned)nwg), dim3(ZX * ZY), 0, ctx->stream, f, T(omega),
                            static_cast<const T*>(vx), static_cast<const T*>(vy), static_cast<const T*>(vz),
                            static_cast<T*>(ox), static_cast<T*>(oy), static_cast<T*>(oz), ntx, nty);
