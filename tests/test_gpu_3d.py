@@ -56,7 +56,7 @@ def oracle_jacobi(p, v, sweeps, omega=0.7):
     return v
 
 
-@pytest.mark.parametrize("dims,sweeps", [((19, 14, 11), 3), ((8, 8, 8), 5), ((33, 9, 17), 2)])
+@pytest.mark.parametrize("dims,sweeps", [((19, 14, 11), 3), ((8, 8, 8), 5), ((33, 9, 17), 2), ((130, 9, 40), 2)])
 def test_jacobi3d_fp64_matches_oracle(ctx, dims, sweeps):
     p = problem(*dims, seed=sum(dims))
     v0 = I.random_velocity3d(p, 1, 1e-3)
@@ -84,7 +84,8 @@ def test_ras3d_matches_oracle(ctx, T, h, k, sweeps):
         assert normwise(g, r) <= TOL64
 
 
-@pytest.mark.parametrize("dims,T,k", [((40, 36, 30), 8, 2), ((64, 64, 64), 8, 2), ((50, 21, 33), 6, 3)])
+@pytest.mark.parametrize("dims,T,k", [((40, 36, 30), 8, 2), ((64, 64, 64), 8, 2), ((50, 21, 33), 6, 3),
+                                        ((130, 9, 40), 5, 2)])
 def test_ras3d_full_overlap_equals_jacobi_bitwise(ctx, dims, T, k):
     """Overlap h = k: every outer iteration is k Jacobi sweeps exactly; the
     streaming tiles must reproduce the fused kernel bit for bit (random shifts)."""
