@@ -260,30 +260,30 @@ static LevelJob<T> level_job(const stk_mg* m, size_t l, int t) {
     J.ld = L.ld;
     J.idx = T(1.0 / L.dx);
     J.idy = T(1.0 / L.dy);
-    J.ec = t ? (const T*)L.ec32 : (const T*)L.ec64;
-    J.en = t ? (const T*)L.en32 : (const T*)L.en64;
-    J.st = t ? (const T*)L.st32 : (const T*)L.st64;
+    J.ec = t ? (gptr<const T>)L.ec32 : (gptr<const T>)L.ec64;
+    J.en = t ? (gptr<const T>)L.en32 : (gptr<const T>)L.en64;
+    J.st = t ? (gptr<const T>)L.st32 : (gptr<const T>)L.st64;
     J.plane = L.plane;
-    J.vx = (T*)L.v[t].x;
-    J.vy = (T*)L.v[t].y;
-    J.wx = (T*)L.w[t].x;
-    J.wy = (T*)L.w[t].y;
-    J.bx = (T*)L.b[t].x;
-    J.by = (T*)L.b[t].y;
-    J.rx = (T*)L.r[t].x;
-    J.ry = (T*)L.r[t].y;
+    J.vx = (gptr<T>)L.v[t].x;
+    J.vy = (gptr<T>)L.v[t].y;
+    J.wx = (gptr<T>)L.w[t].x;
+    J.wy = (gptr<T>)L.w[t].y;
+    J.bx = (gptr<T>)L.b[t].x;
+    J.by = (gptr<T>)L.b[t].y;
+    J.rx = (gptr<T>)L.r[t].x;
+    J.ry = (gptr<T>)L.r[t].y;
     if (l + 1 < m->L.size()) {
         const MgLevel& C = m->L[l + 1];
         J.cnx = C.nx;
         J.cny = C.ny;
         J.cld = C.ld;
-        J.cbx = (T*)C.b[t].x;
-        J.cby = (T*)C.b[t].y;
-        J.cvx = (T*)C.v[t].x;
-        J.cvy = (T*)C.v[t].y;
-        J.cwx = (T*)C.w[t].x;
-        J.cwy = (T*)C.w[t].y;
-        J.cst = t ? (const T*)C.st32 : (const T*)C.st64;
+        J.cbx = (gptr<T>)C.b[t].x;
+        J.cby = (gptr<T>)C.b[t].y;
+        J.cvx = (gptr<T>)C.v[t].x;
+        J.cvy = (gptr<T>)C.v[t].y;
+        J.cwx = (gptr<T>)C.w[t].x;
+        J.cwy = (gptr<T>)C.w[t].y;
+        J.cst = t ? (gptr<const T>)C.st32 : (gptr<const T>)C.st64;
         J.cplane = C.plane;
     }
     return J;
@@ -342,8 +342,9 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P, 
                 rpt.push_back(rpt.back() + mg_ras_tiles(m->L[d].nx, m->L[d].ny, o0.coarse_tile));
             } else if (d == nl - 1) {
                 const MgLevel& L = m->L[d];
-                cj.push_back(CoarseJob<T>{m->cn, m->cmap, m->cainv, (const T*)L.b[t].x, (const T*)L.b[t].y,
-                                          (T*)L.v[t].x, (T*)L.v[t].y});
+                cj.push_back(CoarseJob<T>{m->cn, (gptr<const int>)m->cmap, (gptr<const double>)m->cainv,
+                                          (gptr<const T>)L.b[t].x, (gptr<const T>)L.b[t].y,
+                                          (gptr<T>)L.v[t].x, (gptr<T>)L.v[t].y});
             }
         }
         if (!rj.empty()) {
@@ -410,12 +411,12 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P, 
     for (int q = 0; q < n; ++q) {
         stk_mg* m = mgs[q];
         LevelJob<T> J = level_job<T>(m, 0, t);
-        J.vx = (T*)m->ks[t][VS_P].x;
-        J.vy = (T*)m->ks[t][VS_P].y;
-        J.bx = (T*)m->zero[t].x;
-        J.by = (T*)m->zero[t].y;
-        J.rx = (T*)m->ks[t][VS_Q].x;
-        J.ry = (T*)m->ks[t][VS_Q].y;
+        J.vx = (gptr<T>)m->ks[t][VS_P].x;
+        J.vy = (gptr<T>)m->ks[t][VS_P].y;
+        J.bx = (gptr<T>)m->zero[t].x;
+        J.by = (gptr<T>)m->zero[t].y;
+        J.rx = (gptr<T>)m->ks[t][VS_Q].x;
+        J.ry = (gptr<T>)m->ks[t][VS_Q].y;
         aj.push_back(J);
         pa.push_back(pa.back() + blocks_of(m->L[0].nx, m->L[0].ny));
         pra.push_back(pra.back() + rows::workgroups(m->L[0].nx, m->L[0].ny));
@@ -425,12 +426,12 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P, 
         V.ld = m->L[0].ld;
         V.idx = 1.0 / m->L[0].dx;
         V.idy = 1.0 / m->L[0].dy;
-        V.ec = m->L[0].ec64;
-        V.en = m->L[0].en64;
+        V.ec = (gptr<const double>)m->L[0].ec64;
+        V.en = (gptr<const double>)m->L[0].en64;
         for (int sl = 0; sl < VS_N; ++sl) {
             const int ts = sl == VS_Z && P->vec_z32 ? 1 : t;
-            V.v[sl][0] = m->ks[ts][sl].x;
-            V.v[sl][1] = m->ks[ts][sl].y;
+            V.v[sl][0] = (gptr<void>)m->ks[ts][sl].x;
+            V.v[sl][1] = (gptr<void>)m->ks[ts][sl].y;
         }
         vj.push_back(V);
         XCastJob X{};
@@ -438,9 +439,9 @@ static int build_plan(stk_ctx* ctx, stk_mg* const* mgs, int n, int t, PlanT* P, 
         X.ny = V.ny;
         X.ld = V.ld;
         for (int c = 0; c < 2; ++c) {
-            X.r64[c] = static_cast<const double*>(c ? m->ks[0][VS_R].y : m->ks[0][VS_R].x);
-            X.r32[c] = static_cast<float*>(c ? m->ks[1][VS_R].y : m->ks[1][VS_R].x);
-            X.z32[c] = static_cast<float*>(c ? m->ks[1][VS_Z].y : m->ks[1][VS_Z].x);
+            X.r64[c] = (gptr<const double>)(c ? m->ks[0][VS_R].y : m->ks[0][VS_R].x);
+            X.r32[c] = (gptr<float>)(c ? m->ks[1][VS_R].y : m->ks[1][VS_R].x);
+            X.z32[c] = (gptr<float>)(c ? m->ks[1][VS_Z].y : m->ks[1][VS_Z].x);
         }
         xj.push_back(X);
     }

@@ -17,24 +17,24 @@ struct LevelJob {
     int nx, ny;
     int64_t ld;
     T idx, idy;
-    const T* ec;
-    const T* en;
-    T *vx, *vy;  // level iterate
-    T *wx, *wy;  // ping-pong partner of the smoother
-    T *bx, *by;  // right-hand side
-    T *rx, *ry;  // residual scratch
+    gptr<const T> ec;
+    gptr<const T> en;
+    gptr<T> vx, vy;  // level iterate
+    gptr<T> wx, wy;  // ping-pong partner of the smoother
+    gptr<T> bx, by;  // right-hand side
+    gptr<T> rx, ry;  // residual scratch
     int cnx, cny;
     int64_t cld;
-    T *cbx, *cby;  // coarse right-hand side
-    T *cvx, *cvy;  // coarse iterate
-    const T* st;    // stored Galerkin stencil (coarse levels), nullptr on the finest
-    int64_t plane;  // elements per stencil plane
+    gptr<T> cbx, cby;  // coarse right-hand side
+    gptr<T> cvx, cvy;  // coarse iterate
+    gptr<const T> st;  // stored Galerkin stencil (coarse levels), nullptr on the finest
+    int64_t plane;     // elements per stencil plane
     // the restriction also takes the coarse level's first smoothing sweep from 0
     // (damped Jacobi, written to cw*) when `first`; cst / cplane: its stencil
     int first;
-    const T* cst;
+    gptr<const T> cst;
     int64_t cplane;
-    T *cwx, *cwy;
+    gptr<T> cwx, cwy;
 };
 
 // Coarsest level of one instance: n unknowns, map[q] = (component << 30) |
@@ -42,10 +42,10 @@ struct LevelJob {
 template <typename T>
 struct CoarseJob {
     int n;
-    const int* map;
-    const double* ainv;
-    const T *bx, *by;
-    T *vx, *vy;
+    gptr<const int> map;
+    gptr<const double> ainv;
+    gptr<const T> bx, by;
+    gptr<T> vx, vy;
 };
 
 // Krylov vectors of one instance on its finest level (FP64): X, R, Z, P, Q =
@@ -57,9 +57,9 @@ struct VecJob {
     int nx, ny;
     int64_t ld;
     double idx, idy;
-    const double* ec;  // FP64 viscosities for the diag(-M) energy weights
-    const double* en;
-    void* v[VS_N][2];  // slot -> (x component, y component)
+    gptr<const double> ec;  // FP64 viscosities for the diag(-M) energy weights
+    gptr<const double> en;
+    gptr<void> v[VS_N][2];  // slot -> (x component, y component)
 };
 
 // Per-instance scalars of flexible CG (device resident).
@@ -159,9 +159,9 @@ int fcg_reduce(stk_ctx* ctx, const Batch& red, const double* part, double* sums,
 struct XCastJob {
     int nx, ny;
     int64_t ld;
-    const double* r64[2];
-    float* r32[2];
-    float* z32[2];
+    gptr<const double> r64[2];
+    gptr<float> r32[2];
+    gptr<float> z32[2];
 };
 int prec_cast(stk_ctx* ctx, const Batch& b, const FcgState* st);
 // FP64 FCG, finest level: Q = A P and the block partials of P . Q (apply: the

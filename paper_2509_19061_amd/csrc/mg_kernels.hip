@@ -147,7 +147,7 @@ __global__ __launch_bounds__(NT) void k_mg_jacobi(const LevelJob<T>* __restrict_
         return;
     }
     if (i > J.nx || j > J.ny) return;
-    const Grid<T> g = job_grid(J, J.bx, J.by, omega);
+    const Grid<T> g = job_grid<T>(J, J.bx, J.by, omega);
     if (j < J.ny) dx_[k] = is_vx_unknown(J.nx, J.ny, i, j) ? jac_vx_global(g, sx, sy, i, j) : T(0);
     if (i < J.nx) dy_[k] = is_vy_unknown(J.nx, J.ny, i, j) ? jac_vy_global(g, sx, sy, i, j) : T(0);
 }
@@ -611,11 +611,11 @@ __global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, con
             const bool u = c == 0 ? is_vx_unknown(J.nx, J.ny, i, j) : is_vy_unknown(J.nx, J.ny, i, j);
             const bool inbox = c == 0 ? j < J.ny : i < J.nx;
             if (!inbox) continue;
-            T* X = static_cast<T*>(J.v[VS_X][c]);
-            T* R = static_cast<T*>(J.v[VS_R][c]);
-            ZT* Z = static_cast<ZT*>(J.v[VS_Z][c]);
-            T* P = static_cast<T*>(J.v[VS_P][c]);
-            T* Q = static_cast<T*>(J.v[VS_Q][c]);
+            T* X = (T*)(J.v[VS_X][c]);
+            T* R = (T*)(J.v[VS_R][c]);
+            ZT* Z = (ZT*)(J.v[VS_Z][c]);
+            T* P = (T*)(J.v[VS_P][c]);
+            T* Q = (T*)(J.v[VS_Q][c]);
             switch (op) {
                 case OP_UPDATE:
                     if (u) {
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(NT) void k_vec(const VecJob* __restrict__ jobs, con
                     }
                     break;
                 case OP_FNORM: {
-                    const double* F = static_cast<const double*>(J.v[VS_F][c]);
+                    const double* F = (const double*)(J.v[VS_F][c]);
                     if (u) a0 += F[k] * F[k] / (c == 0 ? dgx(J, i, j) : dgy(J, i, j));
                     break;
                 }
@@ -724,8 +724,8 @@ __global__ __launch_bounds__(NT) void k_vec_res64(const VecJob* __restrict__ job
     if (i <= J.nx && j <= J.ny && st[inst].active) {
         const int nx = J.nx, ny = J.ny;
         const int64_t ld = J.ld, k = (int64_t)j * ld + i;
-        const double* vx = static_cast<const double*>(J.v[VS_X][0]);
-        const double* vy = static_cast<const double*>(J.v[VS_X][1]);
+        const double* vx = (const double*)(J.v[VS_X][0]);
+        const double* vy = (const double*)(J.v[VS_X][1]);
         auto VX = [&](int a, int b) { return ldvx<double>(vx, ld, nx, ny, a, b); };
         auto VY = [&](int a, int b) { return ldvy<double>(vy, ld, nx, ny, a, b); };
         auto ENH = [&](int a, int b) { return (a >= 1 && a <= nx - 1 && b >= 1 && b <= ny - 1) ? J.en[(int64_t)b * ld + a] : 0.0; };
@@ -735,10 +735,10 @@ __global__ __launch_bounds__(NT) void k_vec_res64(const VecJob* __restrict__ job
                 const double m = mv_x<double>(VX(i, j), VX(i - 1, j), VX(i + 1, j), VX(i, j - 1), VX(i, j + 1), VY(i, j),
                                               VY(i - 1, j), VY(i, j + 1), VY(i - 1, j + 1), J.ec[k - 1], J.ec[k],
                                               ENH(i, j), ENH(i, j + 1), J.idx, J.idy);
-                r = static_cast<const double*>(J.v[VS_B][0])[k] - m;
+                r = ((const double*)J.v[VS_B][0])[k] - m;
                 a0 += r * r / dgx(J, i, j);
             }
-            static_cast<double*>(J.v[VS_R][0])[k] = r;
+            ((double*)J.v[VS_R][0])[k] = r;
         }
         if (i < nx) {
             double r = 0.0;
@@ -746,10 +746,10 @@ __global__ __launch_bounds__(NT) void k_vec_res64(const VecJob* __restrict__ job
                 const double m = mv_y<double>(VY(i, j), VY(i - 1, j), VY(i + 1, j), VY(i, j - 1), VY(i, j + 1), VX(i, j),
                                               VX(i + 1, j), VX(i, j - 1), VX(i + 1, j - 1), J.ec[k - ld], J.ec[k],
                                               ENH(i, j), ENH(i + 1, j), J.idx, J.idy);
-                r = static_cast<const double*>(J.v[VS_B][1])[k] - m;
+                r = ((const double*)J.v[VS_B][1])[k] - m;
                 a0 += r * r / dgy(J, i, j);
             }
-            static_cast<double*>(J.v[VS_R][1])[k] = r;
+            ((double*)J.v[VS_R][1])[k] = r;
         }
     }
     block_sum2(a0, 0.0, part);

@@ -25,6 +25,21 @@ struct stk_ctx {
 
 namespace stk {
 
+// Device arrays named inside a job struct.  In device code they carry the
+// global address space: a kernel reads them from a job array in memory, and
+// without it the compiler cannot tell global from LDS and emits flat loads,
+// which count against the LDS wait counter too, so that every use of an LDS
+// value waited for all the loads in flight.  In host code they are plain
+// pointers of the same size (host code sets them with an explicit cast).
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <typename T>
+using gptr = T*;
+#endif
+
+
 int set_error(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 #define STK_HIP(call)                                      \
@@ -83,12 +98,12 @@ int launch_ras_stream(stk_ctx* ctx, stk_dtype dt, const stk_grid* g, const Field
 // snapshot and the result (device pointers, common row stride ld).
 template <typename T>
 struct RasJob {
-    const T *ec, *en, *bx, *by;
+    gptr<const T> ec, en, bx, by;
     int64_t ld;
     int nx, ny;
     T idx, idy;
-    const T *vx, *vy;
-    T *ox, *oy;
+    gptr<const T> vx, vy;
+    gptr<T> ox, oy;
     int ntx;  // tile columns
 };
 // Launch shape of a batched RAS outer iteration, shared by its instances.
