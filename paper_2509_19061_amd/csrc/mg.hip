@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "coarse_stencil.hpp"
@@ -97,8 +98,29 @@ static void host_apply_neg(const HostGrid& g, const std::vector<double>& vx, con
         }
 }
 
+// f(i) for i in [lo, hi) on up to hardware_concurrency host threads, in
+// contiguous chunks (each f(i) independent of the others).
+template <typename F>
+static void par_for(int lo, int hi, const F& f) {
+    const int n = hi - lo;
+    const int nt = std::max(1, std::min(n / 16, (int)std::thread::hardware_concurrency()));
+    if (nt <= 1) {
+        for (int i = lo; i < hi; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) {
+        const int a = lo + (int)((int64_t)n * t / nt), b = lo + (int)((int64_t)n * (t + 1) / nt);
+        th.emplace_back([&f, a, b] {
+            for (int i = a; i < b; ++i) f(i);
+        });
+    }
+    for (auto& x : th) x.join();
+}
+
 // Assemble A = -M on the coarsest level, invert it (Cholesky, A SPD) and
-// upload.  The coarsest level is the finest one (viscous stencil from the
+// upload the inverse column-major, so that the threads of the coarse solve
+// (one per row) read consecutive addresses.  The coarsest level is the finest one (viscous stencil from the
 // viscosities) when the grid is too small to coarsen, else a Galerkin level.
 static int build_coarse(stk_mg* m) {
     MgLevel& l = m->L.back();
@@ -156,34 +178,59 @@ static int build_coarse(stk_mg* m) {
             A[(size_t)r * n + c] = (map[r] >> 30) ? ay[o2] : ax[o2];
         }
     }
-    // Cholesky A = L L^T (lower, in place)
-    for (int j = 0; j < n; ++j) {
-        double d = A[(size_t)j * n + j];
-        for (int k = 0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
-        if (!(d > 0.0)) return set_error(STK_EINVAL, "coarsest operator not positive definite (check viscosities)");
-        const double Ljj = std::sqrt(d);
-        A[(size_t)j * n + j] = Ljj;
-        for (int i = j + 1; i < n; ++i) {
-            double s = A[(size_t)i * n + j];
-            for (int k = 0; k < j; ++k) s -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
-            A[(size_t)i * n + j] = s / Ljj;
-        }
+    // Cholesky A = L L^T (lower, in place), in panels of CPB columns: the
+    // panel's own rows first, then the rows below it in parallel.  Every entry
+    // is the same sum in the same order as column by column, L_ij = (A_ij -
+    // sum_{k<j} L_ik L_jk) / L_jj, so the factor does not depend on the split.
+    constexpr int CPB = 32;
+    bool spd = true;
+    auto entry = [&](int i, int j) {
+        double s = A[(size_t)i * n + j];
+        for (int k = 0; k < j; ++k) s -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+        return s;
+    };
+    for (int p0 = 0; p0 < n && spd; p0 += CPB) {
+        const int p1 = std::min(p0 + CPB, n);
+        for (int i = p0; i < p1 && spd; ++i)
+            for (int j = p0; j <= i; ++j) {
+                const double s = entry(i, j);
+                if (j < i) {
+                    A[(size_t)i * n + j] = s / A[(size_t)j * n + j];
+                } else if (s > 0.0) {
+                    A[(size_t)i * n + i] = std::sqrt(s);
+                } else {
+                    spd = false;
+                    break;
+                }
+            }
+        if (spd)
+            par_for(p1, n, [&](int i) {
+                for (int j = p0; j < p1; ++j) A[(size_t)i * n + j] = entry(i, j) / A[(size_t)j * n + j];
+            });
     }
-    // inverse: solve L L^T X = I column by column
-    std::vector<double> inv((size_t)n * n), y(n);
-    for (int c = 0; c < n; ++c) {
-        for (int i = 0; i < n; ++i) {
+    if (!spd) return set_error(STK_EINVAL, "coarsest operator not positive definite (check viscosities)");
+    // inverse: solve L L^T X = I column by column (columns in parallel).  Row c
+    // of the forward solve is the first nonzero; the backward solve reads L^T
+    // by rows.
+    std::vector<double> LT((size_t)n * n);
+    par_for(0, n, [&](int i) {
+        for (int k = 0; k <= i; ++k) LT[(size_t)k * n + i] = A[(size_t)i * n + k];
+    });
+    std::vector<double> inv((size_t)n * n);
+    par_for(0, n, [&](int c) {
+        double* y = &inv[(size_t)c * n];  // column c of the inverse, contiguous
+        for (int i = 0; i < c; ++i) y[i] = 0.0;
+        for (int i = c; i < n; ++i) {
             double s = (i == c) ? 1.0 : 0.0;
-            for (int k = 0; k < i; ++k) s -= A[(size_t)i * n + k] * y[k];
+            for (int k = c; k < i; ++k) s -= A[(size_t)i * n + k] * y[k];
             y[i] = s / A[(size_t)i * n + i];
         }
         for (int i = n - 1; i >= 0; --i) {
             double s = y[i];
-            for (int k = i + 1; k < n; ++k) s -= A[(size_t)k * n + i] * y[k];
+            for (int k = i + 1; k < n; ++k) s -= LT[(size_t)i * n + k] * y[k];
             y[i] = s / A[(size_t)i * n + i];
         }
-        for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = y[i];
-    }
+    });
     void *dm = nullptr, *di = nullptr;
     STK_TRY(dalloc(m, (size_t)n * sizeof(int), &dm));
     STK_TRY(dalloc(m, (size_t)n * n * sizeof(double), &di));

@@ -530,24 +530,41 @@ __global__ __launch_bounds__(NT) void k_mg_jacobi_prolonged(const LevelJob<T>* _
 // One workgroup per instance: dense FP64 solve x = A^{-1} (-b) of the coarsest
 // problem (A = -M assembled and inverted on the host at setup), gathered from
 // and scattered to the level layout through the unknown index map.
+// Coarsest solve v = A^-1 (-b).  A workgroup takes 64 rows (grid x) of one
+// instance (grid y); its CW waves each sum a contiguous chunk of the columns
+// for those rows, and the chunk sums are added in chunk order.  The inverse is
+// stored column by column, so a wave's loads of one column are contiguous, and
+// a large coarsest level spreads its inverse over many waves and CUs (a single
+// chain per row left the 1984-unknown solve of a 32^2 level latency-bound at
+// about 200 us).
+constexpr int CW = 16;
 template <typename T>
-__global__ __launch_bounds__(1024) void k_mg_coarse(const CoarseJob<T>* __restrict__ jobs) {
-    extern __shared__ double rhs[];
-    const CoarseJob<T>& J = jobs[blockIdx.x];
+__global__ __launch_bounds__(64 * CW) void k_mg_coarse(const CoarseJob<T>* __restrict__ jobs) {
+    extern __shared__ double csh[];  // CW x 64 chunk sums, then the right-hand side
+    double* part = csh;
+    double* rhs = csh + CW * 64;
+    const CoarseJob<T>& J = jobs[blockIdx.y];
     const int nu = J.n;
-    for (int q = threadIdx.x; q < nu; q += blockDim.x) {
-        const int code = J.map[q];  // (component << 30) | (j * ld + i) offset
+    if ((int)blockIdx.x * 64 >= nu) return;  // the whole workgroup: no rows of this instance
+    for (int r = threadIdx.x; r < nu; r += 64 * CW) {
+        const int code = J.map[r];  // (component << 30) | (j * ld + i) offset
         const int off = code & 0x3fffffff;
-        rhs[q] = -(double)((code >> 30) ? J.by[off] : J.bx[off]);
+        rhs[r] = -(double)((code >> 30) ? J.by[off] : J.bx[off]);
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < nu; q += blockDim.x) {
-        const double* row = J.ainv + (int64_t)q * nu;
-        double s = 0.0;
-        for (int c = 0; c < nu; ++c) s += row[c] * rhs[c];
+    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64, q = (int)blockIdx.x * 64 + lane;
+    const int c0 = (int)((int64_t)nu * w / CW), c1 = (int)((int64_t)nu * (w + 1) / CW);
+    double s = 0.0;
+    if (q < nu)
+        for (int c = c0; c < c1; ++c) s += J.ainv[(int64_t)c * nu + q] * rhs[c];
+    part[w * 64 + lane] = s;
+    __syncthreads();
+    if (w == 0 && q < nu) {
+        double t = part[lane];
+        for (int u = 1; u < CW; ++u) t += part[u * 64 + lane];
         const int code = J.map[q];
         const int off = code & 0x3fffffff;
-        if (code >> 30) J.vy[off] = T(s); else J.vx[off] = T(s);
+        if (code >> 30) J.vy[off] = T(t); else J.vx[off] = T(t);
     }
 }
 
@@ -926,7 +943,8 @@ int mg_jacobi_prolonged(stk_ctx* ctx, const Batch& b, double omega) {
 template <typename T>
 int mg_coarse(stk_ctx* ctx, const void* jobs, int n, int max_unknowns) {
     if (!n) return STK_OK;
-    hipLaunchKernelGGL(k_mg_coarse<T>, dim3(n), dim3(256), (size_t)max_unknowns * sizeof(double), ctx->stream,
+    hipLaunchKernelGGL(k_mg_coarse<T>, dim3((unsigned)((max_unknowns + 63) / 64), (unsigned)n), dim3(64 * CW),
+                       (size_t)(CW * 64 + max_unknowns) * sizeof(double), ctx->stream,
                        static_cast<const CoarseJob<T>*>(jobs));
     STK_LAUNCH_CHECK();
     return STK_OK;
