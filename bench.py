@@ -112,9 +112,12 @@ def main():
     ap.add_argument("--floor-n", type=int, default=0,
                     help="FP64 floor of E_v: the n^2 contrast-1e6 sinker solve at growing iteration budgets (0: skip)")
     ap.add_argument("--floor-budgets", default="250,500,1000,2000,4000")
+    ap.add_argument("--coarsest", type=int, default=32,
+                    help="coarsest grid of the solve workloads' hierarchies (solved exactly; the library default is 8)")
     ap.add_argument("--uzawa-parts", default="all", choices=["all", "solve"],
                     help="'solve': only the contrast-1e2 solves (FP64 and FP32 V-cycle) and the pressure step")
     args = ap.parse_args()
+    MG_OPTS["coarsest"] = args.coarsest
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -410,6 +413,12 @@ def _timed(fn):
     return r, e0.elapsed_time(e1) * 1e-3
 
 
+# Hierarchy options of the solve workloads (set from --coarsest): the coarsest
+# level is solved exactly, and at these contrasts a 32^2 coarsest level takes
+# about a third of the iterations of an 8^2 one for 0.4 s more setup.
+MG_OPTS = {"coarsest": 32}
+
+
 def run_solves(ctx, n, tol=1e-8, max_iters=4000):
     """FP64 vs FP32-refined solves of the refinement workload."""
     import torch
@@ -420,7 +429,7 @@ def run_solves(ctx, n, tol=1e-8, max_iters=4000):
     prob = inputs.lognormal_background_workload(n)
     log(f"[bench] solve workload {n}^2 generated in {time.time() - t0:.1f}s")
     dp = fields.DeviceProblem(prob, torch.float64)
-    m, setup_s = _timed(lambda: api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n))
+    m, setup_s = _timed(lambda: api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n, **MG_OPTS))
     info = m.info()
     log(f"[bench] hierarchy: {info['levels']} levels, {info['coarse_unknowns']} coarsest unknowns, "
         f"setup {setup_s:.3f}s")
@@ -471,7 +480,7 @@ def run_uzawa(ctx, n, tol=1e-8, max_cycles=1000, omega_p=0.6, reps=20, parts="al
 
     prob = inputs.random_sinkers(n, 8, 2, eta_in=1e2)
     dp = fields.DeviceProblem(prob, torch.float64)
-    m = api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n)
+    m = api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n, **MG_OPTS)
     vx, vy, p = dp.velocity() + (dp.field(),)
     api.uzawa_solve(m, dp.grid, vx, vy, p, dp.eta_c, dp.eta_n, dp.fx, dp.fy, allow_notconv=True,
                     max_cycles=1)  # buffers, plan
@@ -533,7 +542,7 @@ def run_uzawa(ctx, n, tol=1e-8, max_cycles=1000, omega_p=0.6, reps=20, parts="al
     # cycles, on the smoother workload (contrast 1e6)
     cprob = inputs.smoother_workload(n)
     cdp = fields.DeviceProblem(cprob, torch.float64)
-    cm = api.MG(ctx, cdp.grid, cdp.eta_c, cdp.eta_n)
+    cm = api.MG(ctx, cdp.grid, cdp.eta_c, cdp.eta_n, **MG_OPTS)
     cvx, cvy, cp = cdp.velocity() + (cdp.field(),)
 
     def csolve():
@@ -752,7 +761,7 @@ def run_floor(ctx, n, budgets, tol=1e-12):
 
     prob = inputs.smoother_workload(n, 2)
     dp = fields.DeviceProblem(prob, torch.float64)
-    m = api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n)
+    m = api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n, **MG_OPTS)
     rows = []
     for b in budgets:
         vx, vy = dp.velocity()
@@ -786,7 +795,7 @@ def run_config3(ctx, n, cap, cap_iid, tol=1e-8):
         prob = gen(n)
         dp = fields.DeviceProblem(prob, torch.float64)
         del prob
-        m, setup_s = _timed(lambda: api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n))
+        m, setup_s = _timed(lambda: api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n, **MG_OPTS))
         log(f"[bench] config3 {name} {n}^2 ready in {time.time() - t0:.1f}s (hierarchy {setup_s:.2f}s)")
         res, sols = {}, {}
         for mode in ("f64", "f32_refined"):
@@ -859,7 +868,7 @@ def run_serve(ctx, count, sizes=(128, 256, 512, 1024, 2048, 4096), budget=64 << 
                 rate = ld * res["saturation"]["solves_per_s"]
                 arr = serve.poisson_requests(count, rate, [0], seed=7)
                 reqs = [serve.Request(r.rid, a.arrival, r.n, r.seed, payload[r.rid]) for r, a in zip(base, arr)]
-            be = serve.GpuBackend(ctx, mode, 64, tol=tol, max_iters=max_iters)
+            be = serve.GpuBackend(ctx, mode, 64, tol=tol, max_iters=max_iters, mg_opts=MG_OPTS)
             summ = serve.Server(be, budget, max_slots=64, iters_per_step=4).run(reqs).summary()
             be.close()
             if ld is not None:
@@ -884,7 +893,7 @@ def run_batch(ctx, which, tol=1e-8, max_iters=3000):
     t0 = time.time()
     probs = inputs.batch_mix(5, sizes)
     dps = [fields.DeviceProblem(q, torch.float64) for q in probs]
-    mgs = [api.MG(ctx, d.grid, d.eta_c, d.eta_n) for d in dps]
+    mgs = [api.MG(ctx, d.grid, d.eta_c, d.eta_n, **MG_OPTS) for d in dps]
     cells = sum(q.nx * q.ny for q in probs)
     log(f"[bench] batch of {len(probs)} instances ({cells / 1e6:.1f} M cells) ready in {time.time() - t0:.1f}s")
     out = {"workload": f"{len(probs)} sinker problems " + ", ".join(f"{c} x {n}^2" for n, c in sizes)

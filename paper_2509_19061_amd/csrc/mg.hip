@@ -13,8 +13,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
+
+#include <sched.h>
 #include <vector>
 
 #include "coarse_stencil.hpp"
@@ -100,10 +103,29 @@ static void host_apply_neg(const HostGrid& g, const std::vector<double>& vx, con
 
 // f(i) for i in [lo, hi) on up to hardware_concurrency host threads, in
 // contiguous chunks (each f(i) independent of the others).
+// Host threads for setup work: the CPUs this process may run on, at most
+// OMP_NUM_THREADS when that is set (a machine's core count can far exceed a
+// job's share of it, and oversubscribed threads also stall the caller's own).
+static int host_threads() {
+    static const int nt = [] {
+        int c = (int)std::thread::hardware_concurrency();
+        cpu_set_t set;
+        if (sched_getaffinity(0, sizeof(set), &set) == 0) c = std::min(c, (int)CPU_COUNT(&set));
+        if (const char* e = std::getenv("OMP_NUM_THREADS")) {
+            const int v = std::atoi(e);
+            if (v > 0) c = std::min(c, v);
+        }
+        return std::max(1, c);
+    }();
+    return nt;
+}
+
+// f(i) for i in [lo, hi) on up to host_threads() threads, in contiguous
+// chunks (each f(i) independent of the others).
 template <typename F>
 static void par_for(int lo, int hi, const F& f) {
     const int n = hi - lo;
-    const int nt = std::max(1, std::min(n / 16, (int)std::thread::hardware_concurrency()));
+    const int nt = std::max(1, std::min(n / 16, host_threads()));
     if (nt <= 1) {
         for (int i = lo; i < hi; ++i) f(i);
         return;
@@ -137,11 +159,15 @@ static int build_coarse(stk_mg* m) {
         STK_HIP(hipMemcpyAsync(en.data(), l.en64, cnt * 8, hipMemcpyDeviceToHost, m->ctx->stream));
     }
     STK_HIP(hipStreamSynchronize(m->ctx->stream));
+    // unknowns numbered by grid row, then column, vx before vy: every coupling
+    // then reaches at most two grid rows, so A is banded (about 4 (nx + 1)
+    // wide) and its Cholesky factor stays inside A's envelope
     std::vector<int> map;
     for (int j = 0; j < l.ny; ++j)
-        for (int i = 1; i <= l.nx - 1; ++i) map.push_back((int)((int64_t)j * l.ld + i));
-    for (int j = 1; j <= l.ny - 1; ++j)
-        for (int i = 0; i < l.nx; ++i) map.push_back((1 << 30) | (int)((int64_t)j * l.ld + i));
+        for (int i = 0; i <= l.nx; ++i) {
+            if (i >= 1 && i <= l.nx - 1) map.push_back((int)((int64_t)j * l.ld + i));
+            if (j >= 1 && i < l.nx) map.push_back((1 << 30) | (int)((int64_t)j * l.ld + i));
+        }
     const int n = (int)map.size();
     if (n > 4096)
         return set_error(STK_EUNSUPPORTED, "coarsest level %dx%d has %d unknowns (> 4096): choose sizes divisible by powers of 2",
@@ -178,21 +204,42 @@ static int build_coarse(stk_mg* m) {
             A[(size_t)r * n + c] = (map[r] >> 30) ? ay[o2] : ax[o2];
         }
     }
+    // Envelope of A: first[i] = the first column of row i that is not 0.  The
+    // Cholesky factor has the same envelope, so every sum below starts there;
+    // the terms it skips are exact zeros.
+    std::vector<int> first(n), last(n);
+    for (int i = 0; i < n; ++i) {
+        int f = i;
+        for (int k = 0; k < i; ++k)
+            if (A[(size_t)i * n + k] != 0.0) {
+                f = k;
+                break;
+            }
+        first[i] = f;
+    }
+    // last[i] = the last row whose envelope reaches column i
+    for (int i = 0, k = 0; i < n; ++i) {
+        last[i] = i;
+        for (k = n - 1; k > i; --k)
+            if (first[k] <= i) {
+                last[i] = k;
+                break;
+            }
+    }
     // Cholesky A = L L^T (lower, in place), in panels of CPB columns: the
-    // panel's own rows first, then the rows below it in parallel.  Every entry
-    // is the same sum in the same order as column by column, L_ij = (A_ij -
-    // sum_{k<j} L_ik L_jk) / L_jj, so the factor does not depend on the split.
+    // panel's own rows first, then the rows below it in parallel (each entry
+    // the same sum in the same order however the work is split).
     constexpr int CPB = 32;
     bool spd = true;
     auto entry = [&](int i, int j) {
         double s = A[(size_t)i * n + j];
-        for (int k = 0; k < j; ++k) s -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+        for (int k = std::max(first[i], first[j]); k < j; ++k) s -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
         return s;
     };
     for (int p0 = 0; p0 < n && spd; p0 += CPB) {
         const int p1 = std::min(p0 + CPB, n);
         for (int i = p0; i < p1 && spd; ++i)
-            for (int j = p0; j <= i; ++j) {
+            for (int j = std::max(p0, first[i]); j <= i; ++j) {
                 const double s = entry(i, j);
                 if (j < i) {
                     A[(size_t)i * n + j] = s / A[(size_t)j * n + j];
@@ -205,31 +252,41 @@ static int build_coarse(stk_mg* m) {
             }
         if (spd)
             par_for(p1, n, [&](int i) {
-                for (int j = p0; j < p1; ++j) A[(size_t)i * n + j] = entry(i, j) / A[(size_t)j * n + j];
+                for (int j = std::max(p0, first[i]); j < p1; ++j) A[(size_t)i * n + j] = entry(i, j) / A[(size_t)j * n + j];
             });
     }
     if (!spd) return set_error(STK_EINVAL, "coarsest operator not positive definite (check viscosities)");
     // inverse: solve L L^T X = I column by column (columns in parallel).  Row c
-    // of the forward solve is the first nonzero; the backward solve reads L^T
-    // by rows.
+    // of the forward solve is the first nonzero (the rows above it stay 0, and
+    // the terms with them are exact zeros).  The inverse is symmetric, so
+    // column c is solved backward only down to row c (its rows below the
+    // diagonal need no others) and its upper part is copied from the rows of
+    // the columns before it.  The backward solve reads L^T by rows, over the
+    // rows whose envelope reaches its column.
     std::vector<double> LT((size_t)n * n);
     par_for(0, n, [&](int i) {
-        for (int k = 0; k <= i; ++k) LT[(size_t)k * n + i] = A[(size_t)i * n + k];
+        for (int k = first[i]; k <= i; ++k) LT[(size_t)k * n + i] = A[(size_t)i * n + k];
     });
     std::vector<double> inv((size_t)n * n);
     par_for(0, n, [&](int c) {
         double* y = &inv[(size_t)c * n];  // column c of the inverse, contiguous
-        for (int i = 0; i < c; ++i) y[i] = 0.0;
-        for (int i = c; i < n; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int k = c; k < i; ++k) s -= A[(size_t)i * n + k] * y[k];
-            y[i] = s / A[(size_t)i * n + i];
+        // forward, column-oriented: each y_i still takes its terms L_ik y_k in
+        // ascending k, but the updates of one step k are independent
+        for (int i = c; i < n; ++i) y[i] = (i == c) ? 1.0 : 0.0;
+        for (int k = c; k < n; ++k) {
+            const double yk = y[k] / A[(size_t)k * n + k];
+            y[k] = yk;
+            const double* lk = &LT[(size_t)k * n];
+            for (int i = k + 1; i <= last[k]; ++i) y[i] -= lk[i] * yk;
         }
-        for (int i = n - 1; i >= 0; --i) {
+        for (int i = n - 1; i >= c; --i) {
             double s = y[i];
-            for (int k = i + 1; k < n; ++k) s -= LT[(size_t)i * n + k] * y[k];
+            for (int k = i + 1; k <= last[i]; ++k) s -= LT[(size_t)i * n + k] * y[k];
             y[i] = s / A[(size_t)i * n + i];
         }
+    });
+    par_for(0, n, [&](int c) {
+        for (int i = 0; i < c; ++i) inv[(size_t)c * n + i] = inv[(size_t)i * n + c];
     });
     void *dm = nullptr, *di = nullptr;
     STK_TRY(dalloc(m, (size_t)n * sizeof(int), &dm));

@@ -173,7 +173,7 @@ class GpuBackend:
     context (``MG.bind``, which drains the setup stream); ``join`` adds it to
     the one ``api.Batch`` that the serving loop steps."""
 
-    def __init__(self, ctx, mode, max_slots, tol=1e-8, max_iters=3000, keep_results=False):
+    def __init__(self, ctx, mode, max_slots, tol=1e-8, max_iters=3000, keep_results=False, mg_opts=None):
         from concurrent.futures import ThreadPoolExecutor
 
         import torch
@@ -181,6 +181,7 @@ class GpuBackend:
         from . import api, fields
         self.api, self.fields, self.torch = api, fields, torch
         self.ctx, self.mode, self.tol, self.max_iters = ctx, mode, tol, max_iters
+        self.mg_opts = dict(mg_opts or {})  # hierarchy options of every request (api.MG keywords)
         self.batch = api.Batch(ctx, mode, max_slots)
         self.results = {} if keep_results else None  # rid -> (vx, vy) on the host
         self.setup_stream = torch.cuda.Stream(device=ctx.device)  # default priority
@@ -192,14 +193,14 @@ class GpuBackend:
         p = r.payload
         ld = self.fields.pad_ld(p.nx)
         g = self.api.Grid(p.nx, p.ny, ld, p.dx, p.dy)
-        return self.api.mg_footprint(g, self.mode) + 6 * (p.ny + 1) * ld * 8  # + eta_c, eta_n, fx, fy, vx, vy
+        return self.api.mg_footprint(g, self.mode, **self.mg_opts) + 6 * (p.ny + 1) * ld * 8  # + fields
 
     def _setup(self, r):
         torch = self.torch
         with torch.cuda.stream(self.setup_stream):
             dp = self.fields.DeviceProblem(r.payload, torch.float64)
             vx, vy = dp.velocity()
-        mg = self.api.MG(self.setup_ctx, dp.grid, dp.eta_c, dp.eta_n)
+        mg = self.api.MG(self.setup_ctx, dp.grid, dp.eta_c, dp.eta_n, **self.mg_opts)
         mg.bind(self.ctx, self.mode)  # the setup stream is drained here
         for t in (dp.eta_c, dp.eta_n, dp.fx, dp.fy, vx, vy):
             t.record_stream(self.serve_stream)  # used by the serving stream from now on
