@@ -536,7 +536,7 @@ __global__ __launch_bounds__(NT) void k_mg_jacobi_prolonged(const LevelJob<T>* _
 // stored column by column, so a wave's loads of one column are contiguous, and
 // a large coarsest level spreads its inverse over many waves and CUs (a single
 // chain per row left the 1984-unknown solve of a 32^2 level latency-bound at
-// about 200 us).
+// about 200 us; the chunks, each loaded one column at a time, at 63 us).
 constexpr int CW = 16;
 template <typename T>
 __global__ __launch_bounds__(64 * CW) void k_mg_coarse(const CoarseJob<T>* __restrict__ jobs) {
@@ -555,8 +555,19 @@ __global__ __launch_bounds__(64 * CW) void k_mg_coarse(const CoarseJob<T>* __res
     const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64, q = (int)blockIdx.x * 64 + lane;
     const int c0 = (int)((int64_t)nu * w / CW), c1 = (int)((int64_t)nu * (w + 1) / CW);
     double s = 0.0;
-    if (q < nu)
-        for (int c = c0; c < c1; ++c) s += J.ainv[(int64_t)c * nu + q] * rhs[c];
+    if (q < nu) {
+        // eight loads in flight before their products are added, in column order
+        const double* col = J.ainv + q;
+        int c = c0;
+        for (; c + 8 <= c1; c += 8) {
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = col[(int64_t)(c + u) * nu];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += a[u] * rhs[c + u];
+        }
+        for (; c < c1; ++c) s += col[(int64_t)c * nu] * rhs[c];
+    }
     part[w * 64 + lane] = s;
     __syncthreads();
     if (w == 0 && q < nu) {

@@ -28,14 +28,14 @@ pytestmark = pytest.mark.gpu
 TOL_V = 1e-12
 
 
-def ulp_sensitivity(p, vx0, vy0, rx, ry, trials=3, seed=0, **opts):
+def ulp_sensitivity(p, vx0, vy0, rx, ry, trials=3, seed=0, coarsest=8, **opts):
     """Largest normwise change of the oracle V-cycle when every coupling of
     every coarse operator is scaled by (1 + u eps), u ~ U(-1, 1), symmetric."""
-    ref = OM.vcycle(OM.hierarchy(p, coarsest=8), 0, vx0, vy0, rx, ry, **opts)
+    ref = OM.vcycle(OM.hierarchy(p, coarsest=coarsest), 0, vx0, vy0, rx, ry, **opts)
     rng = np.random.default_rng(seed)
     worst = 0.0
     for _ in range(trials):
-        lv = OM.hierarchy(p, coarsest=8)
+        lv = OM.hierarchy(p, coarsest=coarsest)
         for L in lv[1:]:
             U = sp.triu(L.A, 1).tocoo()
             Up = sp.coo_matrix((U.data * (1 + 2.2e-16 * rng.uniform(-1, 1, U.data.shape)), (U.row, U.col)),
@@ -87,6 +87,27 @@ def test_vcycle_fp64_matches_oracle(ctx, nx, ny, contrast):
     torch.cuda.synchronize()
     ox, oy = OM.vcycle(levels, 0, vx0, vy0, rx, ry)
     tol = max(TOL_V, 16 * ulp_sensitivity(p, vx0, vy0, rx, ry))
+    assert normwise(dp.get_vx(vx), ox) <= tol and normwise(dp.get_vy(vy), oy) <= tol
+
+
+@pytest.mark.parametrize("nx,ny,contrast", [(128, 128, 1e2), (192, 128, 1e3)])
+def test_vcycle_large_coarsest_matches_oracle(ctx, nx, ny, contrast):
+    """A 32^2 (48 x 32) coarsest level: 1984 (2992) unknowns solved exactly,
+    so the coarse solve runs on many workgroups with full column chunks, and
+    the host builds the inverse from the banded (row-numbered) operator."""
+    p = sinkers(nx, ny, nx + 3 * ny, contrast)
+    levels = OM.hierarchy(p, coarsest=32)
+    m, dp = gpu_mg(ctx, p, coarsest=32)
+    info = m.info()
+    assert info["levels"] == len(levels) == 3
+    assert info["coarse_unknowns"] == (1984 if ny == nx else 2992)
+    vx0, vy0 = I.random_velocity(p, 5, 1e-2)
+    rx, ry = I.random_velocity(p, 6, 1.0)
+    vx, vy = dp.velocity(vx0, vy0)
+    m.vcycle(torch.float64, vx, vy, dp.field(rx), dp.field(ry))
+    torch.cuda.synchronize()
+    ox, oy = OM.vcycle(levels, 0, vx0, vy0, rx, ry)
+    tol = max(TOL_V, 16 * ulp_sensitivity(p, vx0, vy0, rx, ry, coarsest=32))
     assert normwise(dp.get_vx(vx), ox) <= tol and normwise(dp.get_vy(vy), oy) <= tol
 
 
