@@ -22,10 +22,10 @@ def problems():
     return [I.instance_problem(n, rng) for n in (64, 128, 96, 64)]
 
 
-def alone(ctx, p, mode, tol=1e-8):
+def alone(ctx, p, mode, tol=1e-8, **opts):
     from paper_2509_19061_amd import api, fields
     dp = fields.DeviceProblem(p, torch.float64)
-    m = api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n)
+    m = api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n, **opts)
     vx, vy = dp.velocity()
     rep = m.solve(mode, vx, vy, None, dp.fx, dp.fy, tol=tol, max_iters=2000)
     out = (dp.get_vx(vx), dp.get_vy(vy), rep)
@@ -33,14 +33,17 @@ def alone(ctx, p, mode, tol=1e-8):
     return out
 
 
+@pytest.mark.parametrize("coarsest", [8, 32])
 @pytest.mark.parametrize("mode", ["f64", "f32_refined"])
-def test_solves_joining_midway_match_alone(ctx, mode):
+def test_solves_joining_midway_match_alone(ctx, mode, coarsest):
+    """With coarsest 32 the batch mixes coarsest levels of 1984 (64^2, 128^2)
+    and 1104 (96^2 -> 24^2) unknowns in one coarse-solve launch."""
     from paper_2509_19061_amd import api, fields
     probs = problems()
-    ref = [alone(ctx, p, mode) for p in probs]
+    ref = [alone(ctx, p, mode, coarsest=coarsest) for p in probs]
     b = api.Batch(ctx, mode, 3)
     dps = [fields.DeviceProblem(p, torch.float64) for p in probs]
-    mgs = [api.MG(ctx, d.grid, d.eta_c, d.eta_n) for d in dps]
+    mgs = [api.MG(ctx, d.grid, d.eta_c, d.eta_n, coarsest=coarsest) for d in dps]
     vs = [d.velocity() for d in dps]
     results, slot_of = {}, {}
 
