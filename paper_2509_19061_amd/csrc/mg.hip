@@ -131,11 +131,16 @@ static void par_for(int lo, int hi, const F& f) {
         return;
     }
     std::vector<std::thread> th;
-    for (int t = 0; t < nt; ++t) {
-        const int a = lo + (int)((int64_t)n * t / nt), b = lo + (int)((int64_t)n * (t + 1) / nt);
-        th.emplace_back([&f, a, b] {
-            for (int i = a; i < b; ++i) f(i);
-        });
+    int t = 0;
+    try {  // a thread that cannot be started leaves its chunk (and the rest) to this one
+        for (; t < nt; ++t) {
+            const int a = lo + (int)((int64_t)n * t / nt), b = lo + (int)((int64_t)n * (t + 1) / nt);
+            th.emplace_back([&f, a, b] {
+                for (int i = a; i < b; ++i) f(i);
+            });
+        }
+    } catch (...) {
+        for (int i = lo + (int)((int64_t)n * t / nt); i < hi; ++i) f(i);
     }
     for (auto& x : th) x.join();
 }
