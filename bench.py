@@ -468,7 +468,8 @@ def run_solves(ctx, n, tol=1e-8, max_iters=4000):
     log(f"[bench] refined vs FP64: relative energy-norm difference {rel:.3e}")
     return {"workload": f"{n}x{n} cells, 16 sinkers eta 1e6 over a smooth background with log10(eta) ~ U(-2, 4), "
                         f"V(2,2)-preconditioned flexible CG to E_v <= {tol:g}",
-            "n": n, "tol": tol, "levels": info["levels"], "setup_s": round(setup_s, 4),
+            "n": n, "tol": tol, "levels": info["levels"], "coarsest": MG_OPTS["coarsest"],
+            "coarse_unknowns": info["coarse_unknowns"], "setup_s": round(setup_s, 4),
             "f64": res["f64"], "f32_refined": res["f32_refined"],
             "refined_speedup": round(res["f64"]["seconds"] / res["f32_refined"]["seconds"], 3),
             "refined_vs_f64_energy_rel": rel}
@@ -791,7 +792,7 @@ def run_config3(ctx, n, cap, cap_f32, cap_iid, tol=1e-8):
 
     from paper_2509_19061_amd import api, fields, inputs
 
-    out = {"n": n, "tol": tol}
+    out = {"n": n, "tol": tol, "coarsest": MG_OPTS["coarsest"]}
     for name, gen, caps in (("smooth_background", inputs.lognormal_background_workload,
                               {"f64": cap, "f32_refined": cap_f32}),
                              ("iid_background", inputs.iid_log_uniform_workload,
@@ -903,7 +904,8 @@ def run_batch(ctx, which, tol=1e-8, max_iters=3000):
     cells = sum(q.nx * q.ny for q in probs)
     log(f"[bench] batch of {len(probs)} instances ({cells / 1e6:.1f} M cells) ready in {time.time() - t0:.1f}s")
     out = {"workload": f"{len(probs)} sinker problems " + ", ".join(f"{c} x {n}^2" for n, c in sizes)
-                       + f", contrast 10^U(2,6), E_v <= {tol:g}", "instances": len(probs), "cells": cells}
+                       + f", contrast 10^U(2,6), E_v <= {tol:g}", "instances": len(probs), "cells": cells,
+           "coarsest": MG_OPTS["coarsest"]}
     for mode in ("f64", "f32_refined"):
         vs = [d.velocity() for d in dps]
         reps, secs = _timed(lambda: api.mg_solve_batch(ctx, mgs, mode, [v[0] for v in vs], [v[1] for v in vs], None,
