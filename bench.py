@@ -116,10 +116,13 @@ def main():
     ap.add_argument("--floor-budgets", default="250,500,1000,2000,4000")
     ap.add_argument("--coarsest", type=int, default=32,
                     help="coarsest grid of the solve workloads' hierarchies (solved exactly; the library default is 8)")
+    ap.add_argument("--stall-checks", type=int, default=3,
+                    help="solves end after this many true-residual checks without halving N_v (0: never)")
     ap.add_argument("--uzawa-parts", default="all", choices=["all", "solve"],
                     help="'solve': only the contrast-1e2 solves (FP64 and FP32 V-cycle) and the pressure step")
     args = ap.parse_args()
     MG_OPTS["coarsest"] = args.coarsest
+    MG_OPTS["stall_checks"] = args.stall_checks
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -415,10 +418,12 @@ def _timed(fn):
     return r, e0.elapsed_time(e1) * 1e-3
 
 
-# Hierarchy options of the solve workloads (set from --coarsest): the coarsest
-# level is solved exactly, and at these contrasts a 32^2 coarsest level takes
-# about a third of the iterations of an 8^2 one for 0.4 s more setup.
-MG_OPTS = {"coarsest": 32}
+# Hierarchy options of the solve workloads (set from --coarsest and
+# --stall-checks): the coarsest level is solved exactly, and at these
+# contrasts a 32^2 coarsest level takes about a third of the iterations of an
+# 8^2 one; a solve whose tolerance lies below its FP64 floor ends once
+# restarts stop gaining.
+MG_OPTS = {"coarsest": 32, "stall_checks": 3}
 
 
 def run_solves(ctx, n, tol=1e-8, max_iters=4000):

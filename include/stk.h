@@ -258,6 +258,12 @@ typedef struct {
                           at most L levels, and when that stops the coarsening early the last
                           level is relaxed by its pre- plus post-sweeps instead of solved (the
                           paper runs four levels)                                                 */
+    int stall_checks;  /* 0 (default): a solve runs to tol or max_iters.  N >= 1: a solve also
+                          stops, not converged, after N consecutive true-residual checks that
+                          each fail to halve N_v against the check before (the recurrence
+                          residual reached tol, the true one did not, and restarts no longer
+                          gain): E_v is then at its FP64 floor, set by the rounding of the
+                          solution itself                                                        */
 } stk_mg_opts;
 
 /* Both modes run the same FP64 outer iteration: flexible conjugate gradients

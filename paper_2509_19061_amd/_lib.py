@@ -36,7 +36,7 @@ class MgOpts(C.Structure):
     _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("omega", C.c_double), ("coarsest", C.c_int),
                 ("fine_k", C.c_int), ("fine_halo", C.c_int), ("coarse_smoother", C.c_int), ("coarse_tile", C.c_int),
                 ("coarse_k", C.c_int), ("coarse_halo", C.c_int), ("sweep_growth", C.c_double),
-                ("max_levels", C.c_int)]
+                ("max_levels", C.c_int), ("stall_checks", C.c_int)]
 
 
 class Report(C.Structure):

@@ -195,7 +195,7 @@ def ras_shifts(seed, n_outer, tile_x, tile_y):
 # ------------------------------------------------------------------ multigrid --
 
 def mg_opts(nu1=2, nu2=2, omega=0.7, coarsest=8, fine_k=0, fine_halo=-1, coarse_smoother=0, coarse_tile=32,
-            coarse_k=4, coarse_halo=0, sweep_growth=1.0, max_levels=0):
+            coarse_k=4, coarse_halo=0, sweep_growth=1.0, max_levels=0, stall_checks=0):
     """stk_mg_opts; coarse_smoother 'jacobi' / 'ras' (or 0 / 1)."""
     o = MgOpts()
     L.lib.stk_mg_opts_default(C.byref(o))
@@ -204,6 +204,7 @@ def mg_opts(nu1=2, nu2=2, omega=0.7, coarsest=8, fine_k=0, fine_halo=-1, coarse_
     o.coarse_smoother = {"jacobi": 0, "ras": 1}.get(coarse_smoother, coarse_smoother)
     o.coarse_tile, o.coarse_k, o.coarse_halo = int(coarse_tile), int(coarse_k), int(coarse_halo)
     o.sweep_growth, o.max_levels = float(sweep_growth), int(max_levels)
+    o.stall_checks = int(stall_checks)
     return o
 
 

@@ -816,6 +816,7 @@ void stk_mg_opts_default(stk_mg_opts* o) {
     o->coarse_halo = 0;
     o->sweep_growth = 1.0;
     o->max_levels = 0;
+    o->stall_checks = 0;
 }
 
 static int check_mg_opts(const stk_mg_opts& o) {
@@ -833,6 +834,7 @@ static int check_mg_opts(const stk_mg_opts& o) {
     if (!(o.sweep_growth >= 1.0 && o.sweep_growth <= 16.0))
         return set_error(STK_EINVAL, "sweep_growth must be in [1, 16]");
     if (o.max_levels < 0 || o.max_levels == 1) return set_error(STK_EINVAL, "max_levels must be 0 or >= 2");
+    if (o.stall_checks < 0) return set_error(STK_EINVAL, "stall_checks must be >= 0");
     return STK_OK;
 }
 

@@ -40,6 +40,8 @@ struct Slot {
     int max_iters = 0;
     int its = 0;
     int state = SL_FREE;
+    double last_nv = -1.0;  // N_v of the previous true-residual check (-1: none yet)
+    int stalls = 0;         // consecutive checks that did not halve it
     FcgState fs{};
     std::chrono::steady_clock::time_point t0;
 };
@@ -175,7 +177,13 @@ int start_phase(stk_batch* b, int* done, stk_report* reps, int* ndone) {
     for (int q = 0; q < n; ++q) {
         Slot& s = b->slots[ids[q]];
         s.fs = h[q];
-        if (!h[q].active || s.its >= s.max_iters) {
+        bool stalled = false;  // restarts no longer gain: E_v is at its FP64 floor
+        if (h[q].active && s.m->o.stall_checks > 0) {
+            s.stalls = (s.last_nv >= 0.0 && !(h[q].nv <= 0.5 * s.last_nv)) ? s.stalls + 1 : 0;
+            s.last_nv = h[q].nv;
+            stalled = s.stalls >= s.m->o.stall_checks;
+        }
+        if (!h[q].active || s.its >= s.max_iters || stalled) {
             h[q].active = 0;
             done[*ndone] = ids[q];
             if (int rc = finish(b, ids[q], &reps[*ndone])) return fail(rc);

@@ -322,3 +322,24 @@ def test_vcycle_sweep_counts_match_oracle(ctx, nu1, nu2, growth, max_levels):
     ox, oy = SP.unpack(L.nx, L.ny, OM.vcycle_general(levels, 0, x, c, nu1=nu1, nu2=nu2, omega=0.6, growth=growth,
                                                      relax_coarsest=bool(max_levels)))
     assert normwise(dp.get_vx(vx), ox) <= TOL_V and normwise(dp.get_vy(vy), oy) <= TOL_V
+
+
+def test_solve_stall_stop_at_the_fp64_floor(ctx):
+    """stall_checks: with a tolerance below the FP64 floor of E_v (8e-12 for
+    this workload at 128^2, the rounding of the solution itself), the solve
+    ends once restarts stop halving N_v, where the full budget ends as well."""
+    from paper_2509_19061_amd import api, fields
+    prob = I.lognormal_background_workload(128)
+    dp = fields.DeviceProblem(prob, torch.float64)
+    res = {}
+    for stall in (0, 3):
+        m = api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n, coarsest=32, stall_checks=stall)
+        vx, vy = dp.velocity()
+        res[stall] = m.solve("f64", vx, vy, None, dp.fx, dp.fy, tol=1e-14, max_iters=1500, allow_notconv=True)
+        m.close()
+    full, stopped = res[0], res[3]
+    assert not full["converged"] and full["iterations"] == 1500
+    assert not stopped["converged"] and stopped["iterations"] < 1500
+    assert stopped["ev"] <= 2.0 * full["ev"] and full["ev"] < 1e-10
+    with pytest.raises(api.StkError):
+        api.MG(ctx, dp.grid, dp.eta_c, dp.eta_n, stall_checks=-1)
