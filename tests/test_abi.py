@@ -93,3 +93,18 @@ def test_uzawa_option_defaults(L):
     L.lib.stk_uzawa_opts_default(C.byref(o))
     assert (o.omega_p, o.vcycles, o.tol, o.max_cycles, o.stages, o.stage_cycles, o.mode) == \
         (0.6, 1, 1e-8, 1000, 0, 25, L.SOLVE_F64)
+
+
+def test_mg_option_defaults(L):
+    """The binding's struct and the library agree on every field, the last
+    one (stall_checks) included: a sentinel behind it stays untouched."""
+    class Padded(C.Structure):
+        _fields_ = [("o", L.MgOpts), ("sentinel", C.c_int64)]
+    p = Padded()
+    p.sentinel = 0x5A5A5A5A
+    p.o.stall_checks = 77
+    L.lib.stk_mg_opts_default(C.byref(p.o))
+    o = p.o
+    assert (o.nu1, o.nu2, o.omega, o.coarsest, o.fine_k, o.fine_halo, o.coarse_smoother, o.max_levels,
+            o.sweep_growth, o.stall_checks) == (2, 2, 0.7, 8, 0, -1, 0, 0, 1.0, 0)
+    assert p.sentinel == 0x5A5A5A5A
